@@ -1,0 +1,176 @@
+/*
+ * cqfp.h - C ABI of the MI355X (gfx950) convolution-quadrature solver for the
+ * two-state fractional Fokker-Planck system.
+ *
+ * Method: Sun, Nie & Deng, "Fast algorithms for convolution quadrature of
+ * Riemann-Liouville fractional derivative". The problem is the decoupled
+ * form (2.1) of system (1.1):
+ *   dG1/dt + a D^{1-alpha1} G1 + D^{1-alpha1} A G1 = a D^{1-alpha2} G2,
+ *   dG2/dt + a D^{1-alpha2} G2 + D^{1-alpha2} A G2 = a D^{1-alpha1} G1,
+ * with a = (1-m)/(2m-1) (m of the transition matrix (1.2)), A = -Laplacian
+ * with zero Dirichlet data, discretised in space by the 3-point (1D) or
+ * 5-point (2D) finite-difference stencil on a uniform grid of interior nodes.
+ * Time: backward-Euler CQ, scheme (4.1), or BDF2 (SBD) CQ with the starting
+ * correction, scheme (4.7); the CQ history is summed directly (O(N^2)) or by
+ * the fast sum-of-geometric-sequences form, schemes (4.3) and (4.8).
+ *
+ * Conventions for every entry point:
+ *  - All arrays are IEEE fp64, contiguous, owned by the caller. "dev" marks a
+ *    device pointer on the current HIP device, "host" a host pointer.
+ *  - A field G is laid out [2][M]: component 1 then component 2, each with
+ *    M = nx*ny nodes, x fastest (node (i,j) at index j*nx + i).
+ *  - Device work is enqueued on the caller's hipStream_t (passed as void*;
+ *    NULL means the default stream). Entry points that return data to the
+ *    host synchronise that stream.
+ *  - Entry points never abort and never throw; they return a status code
+ *    below. cq_last_error() returns a message for the last failure on the
+ *    calling thread.
+ */
+#ifndef CQFP_H
+#define CQFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define CQ_OK 0
+#define CQ_EINVAL -1      /* an argument is out of range or NULL                */
+#define CQ_ESINGULAR -2   /* the implicit step operator is not positive definite */
+#define CQ_ENOMEM -3      /* host or device allocation failed                    */
+#define CQ_EHIP -4        /* a HIP runtime call failed (or no GPU is present)    */
+#define CQ_ETOL -5        /* the fast rule cannot reach fast_tol within np_max   */
+#define CQ_ENONFINITE -6  /* G0 holds a NaN or an infinity                       */
+
+/* Grid: Omega = (0,lx) (dim 1) or (0,lx)x(0,ly) (dim 2); nx, ny interior
+ * nodes; h = l/(n+1). For dim 1, ny must be 1. */
+typedef struct {
+    int32_t dim;
+    int32_t nx, ny;
+    double lx, ly;
+} cq_grid;
+
+/* Problem and method parameters (Sections 3-4).
+ *  alpha1, alpha2 in (0,1): the CQ orders are beta_k = 1 - alpha_k.
+ *  m in [0,1] without 1/2 (m = 0 gives a = -1 as in Tables 3-5; m = 1 gives
+ *    a = 0, the decoupled case).
+ *  T > 0 and N >= 1: tau = T/N.
+ *  scheme: 1 = backward Euler (4.1), 2 = BDF2 with the correction (4.7).
+ *  method: 0 = direct history sum, 1 = fast history (3.10) / (3.18).
+ *  fast_tol: target relative error of the fast solution against the direct
+ *    one (0 selects 1e-8); the node count np is chosen by scanning the weight
+ *    errors eps_i of (3.8)/(3.16) unless np > 0 is given.
+ *  np: Gauss-Jacobi nodes (BE) or N_{p,2} (BDF2); 0 = choose by the scan.
+ *  np1: N_{p,1} for BDF2 (0 selects 16). ns: N_s for BDF2 (0 selects 30;
+ *    must be >= 3). np_max: scan limit (0 selects 1024).
+ *  block_B: direct method, time-block length of the Toeplitz far-field
+ *    update (0 = automatic; otherwise a multiple of 16 up to 256). */
+typedef struct {
+    double alpha1, alpha2;
+    double m;
+    double T;
+    int64_t N;
+    int32_t scheme;
+    int32_t method;
+    double fast_tol;
+    int32_t np;
+    int32_t np1;
+    int32_t ns;
+    int32_t np_max;
+    int32_t block_B;
+} cq_params;
+
+/* What a solver handle chose (filled by fp_info). */
+typedef struct {
+    int64_t n;            /* steps taken so far                               */
+    int64_t N;            /* total steps                                      */
+    int32_t np_total;     /* fast nodes per component (N_p, or N_p1 + N_p2)   */
+    int32_t lag;          /* first lag covered by the fast rule (2 or N_s)    */
+    double max_eps;       /* max_i |eps_i| / d_0 over both components          */
+    double theta[2];      /* eigenvalues of the 2x2 step coupling matrix       */
+    int32_t block_B;      /* direct: time-block length                        */
+    int32_t ksplit;       /* direct: K-split of the far-field update           */
+    size_t device_bytes;  /* device memory held by the handle                 */
+    size_t state_bytes;   /* bytes of fp_get_state                            */
+} cq_info;
+
+/* CQ weights d_i, i = 0..n, of order beta: Taylor coefficients of
+ * ((1-zeta)/tau)^beta (scheme 1, eqs. (3.3)-(3.4)) or of
+ * (((1-zeta) + (1-zeta)^2/2)/tau)^beta (scheme 2, eqs. (3.11)-(3.12)).
+ * d_out: host, n+1 doubles. beta in (0,1), tau > 0, n >= 0. Host only. */
+int cq_weights(int32_t scheme, double beta, double tau, int64_t n, double* d_out);
+
+/* Fast rule of Section 3: the families of geometric sequences with
+ *   d_i ~ sum_j coef_j * ratio_j^(i - lag),   i >= lag,
+ * from the Gauss-Jacobi rule of (3.6) (scheme 1, lag = 2) or the two rules
+ * of (3.14)-(3.16) with the real-part remark (scheme 2, lag = ns). coef_j
+ * folds in the paper's w_j and dbar(lag)(s_j). When np == 0 the node count
+ * is the smallest on an internal ladder with max_{lag<=i<=N} |eps_i| <=
+ * tol*|d_0|/(10 N); with np > 0 that count is used as given.
+ * ratio_out, coef_out: host arrays of capacity `cap`; count_out receives the
+ * number of terms (np, or np1 + np2), lag_out the lag, max_eps_out the
+ * measured max |eps_i| / |d_0| over lag <= i <= N. Host only.
+ * Returns CQ_ETOL if the scan cannot meet tol with np <= np_max and
+ * CQ_EINVAL if cap is too small. */
+int cq_fast_rule(int32_t scheme, double beta, double tau, int64_t N, double tol,
+                 int32_t np, int32_t np1, int32_t ns, int32_t np_max, int32_t cap,
+                 double* ratio_out, double* coef_out, int32_t* count_out,
+                 int32_t* lag_out, double* max_eps_out);
+
+/* CQ history sum S = sum_{i=1}^{n-1} d_i G^{n-i} (the convolution of
+ * (3.8)/(3.17) without the i = 0 term and without G^0, as it enters the
+ * schemes (4.1) and (4.7)), with d_i the weights of cq_weights(scheme, beta,
+ * tau, .). G_hist: dev [n][M] time-major (level 0 is G^0, unused);
+ * S_out: dev [M]. n >= 1, M >= 1. The sum runs as one row of the blocked
+ * Toeplitz product (FP64 MFMA) on the device. Synchronises the stream. */
+int cq_history(int32_t scheme, double beta, double tau, const double* G_hist,
+               int64_t n, int64_t M, double* S_out, void* hip_stream);
+
+/* Create a solver for one problem, starting from G0 (dev [2][M], copied).
+ * Allocates every device buffer the run needs (the full history [N+1][2][M]
+ * for method 0; the compressed state [2][np_total][M] and an N_s-level
+ * window for method 1). Validates the arguments (CQ_EINVAL, CQ_ENONFINITE),
+ * checks that the step operator is positive definite (CQ_ESINGULAR) and, for
+ * method 1 with np == 0, that the fast rule meets fast_tol (CQ_ETOL).
+ * *handle receives the solver; free it with fp_destroy. */
+int fp_create(const cq_grid* grid, const cq_params* prm, const double* G0,
+              void* hip_stream, void** handle);
+
+/* Advance by nsteps time steps (not beyond N), asynchronously on the
+ * handle's stream. Allocates nothing. */
+int fp_step(void* handle, int64_t nsteps);
+
+/* Copy the current solution G^n to G_out (dev [2][M]); *n_out receives n.
+ * Asynchronous on the handle's stream. */
+int fp_current(void* handle, double* G_out, int64_t* n_out);
+
+/* Report what the handle chose (node counts, block sizes, memory). */
+int fp_info(void* handle, cq_info* info);
+
+/* Save / restore the solver state (step index, time levels still needed,
+ * compressed history) to / from a host buffer. fp_get_state with dst NULL
+ * stores the needed size in *bytes. Restoring into a handle created with the
+ * same grid and parameters and then stepping gives the same result as never
+ * stopping. Both synchronise the stream. */
+int fp_get_state(void* handle, void* dst, size_t* bytes);
+int fp_set_state(void* handle, const void* src, size_t bytes);
+
+/* Release a handle and all its device memory. NULL is accepted. */
+int fp_destroy(void* handle);
+
+/* One-call solve: create, take all N steps, write G^N to GN (dev [2][M]),
+ * destroy. Synchronises the stream. */
+int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double* GN,
+             void* hip_stream);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* cq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CQFP_H */

@@ -50,3 +50,52 @@ def run_modes(dim, nx, ny, modes, alpha1, alpha2, m, T, N, G0, scheme, method,
     lam = mode_eigenvalues(dim, nx, ny, modes)
     c0 = project(G0, dim, nx, ny, modes)
     return run(ModalOps(lam), alpha1, alpha2, m, T, N, c0, scheme, method, np_, np1, ns)
+
+
+def sine_matrix(n):
+    """S[p-1][i-1] = sin(p pi i/(n+1)); symmetric, S S = (n+1)/2 I."""
+    k = np.arange(1, n + 1)
+    return np.sin(np.pi * np.outer(k, k) / (n + 1))
+
+
+def to_modes(G, dim, nx, ny):
+    """All sine-mode coefficients of G ([2][M]); layout [2][ny][nx] flattened
+    (row = y-mode, column = x-mode), so that G = sum c phi exactly."""
+    G = np.asarray(G, dtype=np.float64).reshape(2, -1)
+    Sx = sine_matrix(nx)
+    if dim == 1:
+        return (2.0 / (nx + 1)) * (G @ Sx)
+    Sy = sine_matrix(ny)
+    out = np.empty_like(G)
+    for k in range(2):
+        out[k] = ((4.0 / ((nx + 1) * (ny + 1))) * (Sy @ G[k].reshape(ny, nx) @ Sx)).reshape(-1)
+    return out
+
+
+def from_modes(c, dim, nx, ny):
+    c = np.asarray(c).reshape(2, -1)
+    Sx = sine_matrix(nx)
+    if dim == 1:
+        return c @ Sx
+    Sy = sine_matrix(ny)
+    return np.stack([(Sy @ c[k].reshape(ny, nx) @ Sx).reshape(-1) for k in range(2)])
+
+
+def all_eigenvalues(dim, nx, ny):
+    lx = grid.eigenvalues_1d(nx)
+    if dim == 1:
+        return lx
+    ly = grid.eigenvalues_1d(ny)
+    return (ly[:, None] + lx[None, :]).reshape(-1)
+
+
+def reference(dim, nx, ny, alpha1, alpha2, m, T, N, G0, scheme, method, np_=None, np1=16, ns=30):
+    """G^N of the nodal scheme, computed mode by mode over every mode.
+
+    The same numbers as stepper.solve in exact arithmetic; in fp64 the per-mode
+    form avoids the conditioning kappa = lambda_max/(lambda_min + theta) of the
+    nodal stencil and sparse solve, so it is the reference on large grids."""
+    lam = all_eigenvalues(dim, nx, ny)
+    c0 = to_modes(G0, dim, nx, ny)
+    cN = run(ModalOps(lam), alpha1, alpha2, m, T, N, c0, scheme, method, np_, np1, ns)
+    return from_modes(cN, dim, nx, ny)

@@ -1,0 +1,49 @@
+// Internal declarations shared by the host setup, the kernels and the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cqfp.h"
+
+namespace cqfp {
+
+// ---- error reporting (thread-local message behind cq_last_error) ----
+int fail(int code, const char* fmt, ...);
+void clear_error();
+
+// ---- host setup (setup.cpp) ----
+
+// Weights d_i, i = 0..n, of ((1-z)/tau)^beta (scheme 1) or
+// (((1-z)+(1-z)^2/2)/tau)^beta (scheme 2), by first-order recurrences.
+void weights(int scheme, double beta, double tau, int64_t n, double* d);
+
+// Gauss-Jacobi nodes s_j (ascending) and weights lam_j for the weight
+// (1-s)^a (1+s)^b on [-1,1]: eigenvalues of the Jacobi matrix by Sturm
+// bisection, Newton polish, Christoffel weights 1/sum_k p_k(s_j)^2.
+void gauss_jacobi(int n, double a, double b, std::vector<double>& s, std::vector<double>& lam);
+
+struct FastRule {
+    std::vector<double> ratio;  // r_j
+    std::vector<double> coef;   // coefficient of r_j^(i - lag)
+    int lag = 2;
+    double max_eps = 0.0;       // max |eps_i| / |d_0| over lag <= i <= N
+};
+
+// Build the rule for a given node count (np for BE, np1 + np2 for BDF2).
+void build_rule(int scheme, double beta, double tau, int np, int np1, int ns, FastRule& out);
+// max_{lag <= i <= N} |d_i - sum_j coef_j r_j^(i-lag)| / |d_0|
+double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N);
+// Node-count scan; returns CQ_OK or CQ_ETOL.
+int choose_rule(int scheme, double beta, double tau, int64_t N, double tol, int np_max, int np1,
+                int ns, FastRule& out);
+
+// Eigen-decomposition of the 2x2 coupling K (real eigenvalues, since
+// K12*K21 >= 0): K = V diag(theta) V^{-1}.
+void eig2(const double K[2][2], double theta[2], double V[2][2], double Vinv[2][2]);
+
+// ---- kernel launchers (kernels.hip) ----
+struct DevSolver;  // defined in runtime.cpp
+
+}  // namespace cqfp

@@ -1,0 +1,482 @@
+// HIP kernels (gfx950) of the CQ solver's per-step hot path.
+//
+// Every kernel here is one stage of a time step n of scheme (4.1) or (4.7):
+//   history  S_k = sum_{i=1}^{n-1} d_k,i G_k^{n-i}      (direct or fast form)
+//   rhs      r_k = E_k - (a + A) S'_k + a S'_k'        (E: time-difference part,
+//            S' = S + d_k,n-1 G_k^0 / 2 for BDF2)
+//   solve    [[c + d_1,0 (a+A), -a d_2,0], [-a d_1,0, c + d_2,0 (a+A)]] G^n = r
+//            (evaluated as G^n = K^-1 (E + c Delta^-1 S') - Delta^-1 S', below)
+// Field layout: [2][M] component-major, x fastest. Time levels live in a
+// "level store": level l at slot (l mod Lr) of a [Lr][2][M] array (Lr = N+1
+// keeps the whole history for the direct form; Lr = window length for the
+// fast form).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace cqfp {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Fast history (3.10)/(3.18), one component per blockIdx.z, a slice of nodes
+// per blockIdx.y. For lag L, the state H_j(n) = sum_{l=1}^{n-L} r_j^(n-L-l) G^l
+// obeys H_j(n) = r_j H_j(n-1) + G^{n-L} (n >= L+1, H_j(L) = 0), and
+//   S = sum_{i=1}^{min(L-1,n-1)} d_i G^{n-i} + sum_j coef_j H_j(n).
+// Layout H[2][np][M] (node-major: a wave streams 64 consecutive DOFs of one
+// node); the per-node ratio and coefficient are wave-uniform scalars.
+__global__ __launch_bounds__(256) void k_hist_fast(HistFastArgs p) {
+    const int k = blockIdx.z;
+    const int c = blockIdx.y;
+    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= p.M) return;
+    const int64_t twoM = 2 * p.M;
+    const double* __restrict__ lv = p.levels + int64_t(k) * p.M + x;
+    double S = 0.0;
+    if (c == 0) {
+        const int64_t top = (p.n - 1 < p.L - 1) ? p.n - 1 : p.L - 1;
+        const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+        for (int64_t i = 1; i <= top; ++i) {
+            const int64_t slot = (p.n - i) % p.Lr;
+            S = fma(dk[i], lv[slot * twoM], S);
+        }
+    }
+    if (p.n >= p.L + 1) {
+        const double g = lv[((p.n - p.L) % p.Lr) * twoM];
+        const int j0 = c * p.chunk;
+        const int j1 = (j0 + p.chunk < p.np) ? j0 + p.chunk : p.np;
+        double* __restrict__ h = p.H + (int64_t(k) * p.np) * p.M + x;
+        const double* __restrict__ r = p.ratio + k * p.np;
+        const double* __restrict__ w = p.coef + k * p.np;
+        double S2 = 0.0;
+        int j = j0;
+#pragma unroll 1
+        for (; j + 8 <= j1; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(h + int64_t(j + u) * p.M);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                v[u] = fma(r[j + u], v[u], g);
+                __builtin_nontemporal_store(v[u], h + int64_t(j + u) * p.M);
+                S2 = fma(w[j + u], v[u], S2);
+            }
+        }
+        for (; j < j1; ++j) {
+            double v = h[int64_t(j) * p.M];
+            v = fma(r[j], v, g);
+            h[int64_t(j) * p.M] = v;
+            S2 = fma(w[j], v, S2);
+        }
+        S += S2;
+    }
+    p.Spart[(int64_t(c) * 2 + k) * p.M + x] = S;
+}
+
+// ---------------------------------------------------------------------------
+// Direct history, near field: the far part for steps n0+1..n0+B was summed by
+// k_far_toeplitz into F[ks][B][2][M]; here the lags inside the block are added
+//   S = sum_q F[q][n-n0-1] + sum_{l=n0+1}^{n-1} d_{n-l} G^l.
+__global__ __launch_bounds__(256) void k_hist_direct(HistDirectArgs p) {
+    const int k = blockIdx.z;
+    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= p.M) return;
+    const int64_t twoM = 2 * p.M;
+    double S = 0.0;
+    if (p.n0 >= 1) {
+        const int64_t b = p.n - p.n0 - 1;
+        for (int q = 0; q < p.ks; ++q) S += p.F[((int64_t(q) * p.B + b) * 2 + k) * p.M + x];
+    }
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    const double* __restrict__ lv = p.levels + int64_t(k) * p.M + x;
+    double S2 = 0.0;
+    for (int64_t l = p.n0 + 1; l <= p.n - 1; ++l) S2 = fma(dk[p.n - l], lv[l * twoM], S2);
+    p.Spart[int64_t(k) * p.M + x] = S + S2;
+}
+
+// ---------------------------------------------------------------------------
+// Direct history, far field of one time block (FP64 MFMA):
+//   F[q][b][k][x] = sum_{l in chunk q} d_k[n0+1+b-l] G_k^l[x],  b < B, 1 <= l <= n0.
+// A lower-triangular Toeplitz block T[b][l] = d[n0+1+b-l] times the stored
+// levels. Workgroup: 4 waves share one 64-wide DOF tile; wave w owns rows
+// b in [16*BB*w, 16*BB*(w+1)). MFMA 16x16x4 f64 operands: A(16x4) lane L ->
+// (row L%16, k L/16); B(4x16) lane L -> (k L/16, col L%16); C: item i of
+// lane L is row L/16 + 4i, col L%16 (checked on gfx950). The Toeplitz A fragment is read straight from
+// the weight vector (a 4 KB window, cache resident).
+template <int BB>
+__global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
+    const int k = blockIdx.z;
+    const int q = blockIdx.y;
+    const int64_t x0 = int64_t(blockIdx.x) * 64;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t l_lo = 1 + int64_t(q) * p.mchunk;
+    const int64_t l_hi = (l_lo + p.mchunk < p.n0 + 1) ? l_lo + p.mchunk : p.n0 + 1;
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    const double* __restrict__ G = p.levels + int64_t(k) * p.M;
+    const int64_t ls = p.lstride;
+    const int brow0 = wave * 16 * BB;
+    d4 acc[BB][4];
+#pragma unroll
+    for (int bb = 0; bb < BB; ++bb)
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb) acc[bb][xb] = d4{0.0, 0.0, 0.0, 0.0};
+    bool xin[4];
+#pragma unroll
+    for (int xb = 0; xb < 4; ++xb) xin[xb] = (x0 + xb * 16 + li) < p.M;
+    for (int64_t l0 = l_lo; l0 < l_hi; l0 += 4) {
+        const int64_t l = l0 + lk;
+        const bool lin = l < l_hi;
+        double bv[4];
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb)
+            bv[xb] = (lin && xin[xb]) ? G[l * ls + x0 + xb * 16 + li] : 0.0;
+        double av[BB];
+#pragma unroll
+        for (int bb = 0; bb < BB; ++bb) {
+            const int b = brow0 + bb * 16 + li;
+            av[bb] = (lin && b < p.B) ? dk[p.n0 + 1 + b - l] : 0.0;
+        }
+#pragma unroll
+        for (int bb = 0; bb < BB; ++bb)
+#pragma unroll
+            for (int xb = 0; xb < 4; ++xb) acc[bb][xb] = mfma16x16x4(av[bb], bv[xb], acc[bb][xb]);
+    }
+#pragma unroll
+    for (int bb = 0; bb < BB; ++bb)
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb) {
+            const int64_t xx = x0 + xb * 16 + li;
+            if (xx >= p.M) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int b = brow0 + bb * 16 + lk + 4 * i;
+                if (b < p.B) p.F[((int64_t(q) * p.B + b) * p.ncomp + k) * p.M + xx] = acc[bb][xb][i];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Step solve. With L = a + A, D = [[L, -a], [-a, L]] and Delta = diag(d_1,0, d_2,0),
+// the step operator is K = c I + D Delta and the right-hand side is E - D S'.
+// Since K^-1 D = (I - c K^-1) Delta^-1, the new level is
+//   G^n = K^-1 (E + c Delta^-1 S') - Delta^-1 S',
+// so the stencil never acts on the (rough) history: every right-hand side
+// below is pointwise, and the only spatial coupling is inside K^-1.
+__device__ __forceinline__ double level_at(const double* lv, int64_t l, int64_t Lr, int64_t twoM) {
+    return lv[(l % Lr) * twoM];
+}
+
+// error-free transforms for the double-double residual
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double x) {
+    double s, e;
+    two_sum(hi, x, s, e);
+    hi = s;
+    lo += e;
+}
+
+// 1D: K = Delta (I (x) A + Kc (x) I) with the 2x2 coupling Kc = V diag(theta) V^-1,
+// so K^-1 w = V z with (A + theta_k I) z_k = (V^-1 Delta^-1 w)_k: two constant
+// tridiagonal systems T_k z = h^2 y, T_k = tridiag(-1, 2 + delta_k, -1),
+// delta_k = theta_k h^2, solved by parallel cyclic reduction (PCR) in LDS
+// (stride s: every row eliminates rows i-s and i+s; ceil(log2 M) levels).
+// One refinement step follows: the residual h^2 y - T z is summed in
+// double-double with the diagonal kept as 2 and delta apart (2 + delta is not
+// representable to the accuracy the smallest eigenvalue needs), and PCR
+// solves for the correction. One workgroup of 1024 threads; M <= 4096.
+constexpr int kNT1D = 1024;
+
+__device__ void pcr_solve(double* sa, double* sb, double* sc, double* sd, int64_t M, int64_t Mp,
+                          const double diag[2]) {
+    const int tid = threadIdx.x;
+    for (int64_t x = tid; x < M; x += kNT1D)
+        for (int k = 0; k < 2; ++k) {
+            sa[k * Mp + x] = (x > 0) ? -1.0 : 0.0;
+            sc[k * Mp + x] = (x + 1 < M) ? -1.0 : 0.0;
+            sb[k * Mp + x] = diag[k];
+        }
+    __syncthreads();
+    for (int64_t s = 1; s < M; s <<= 1) {
+        double na[8], nb[8], nc[8], nd[8];
+        int q = 0;
+        for (int64_t x = tid; x < M; x += kNT1D) {
+            for (int k = 0; k < 2; ++k, ++q) {
+                const int64_t o = k * Mp;
+                const double ai = sa[o + x], ci = sc[o + x];
+                double a2 = 0.0, c2 = 0.0, bb = sb[o + x], dd = sd[o + x];
+                if (x - s >= 0) {
+                    const double f = ai / sb[o + x - s];
+                    a2 = -sa[o + x - s] * f;
+                    bb -= sc[o + x - s] * f;
+                    dd -= sd[o + x - s] * f;
+                }
+                if (x + s < M) {
+                    const double g = ci / sb[o + x + s];
+                    c2 = -sc[o + x + s] * g;
+                    bb -= sa[o + x + s] * g;
+                    dd -= sd[o + x + s] * g;
+                }
+                na[q] = a2; nb[q] = bb; nc[q] = c2; nd[q] = dd;
+            }
+        }
+        __syncthreads();
+        q = 0;
+        for (int64_t x = tid; x < M; x += kNT1D) {
+            for (int k = 0; k < 2; ++k, ++q) {
+                const int64_t o = k * Mp;
+                sa[o + x] = na[q]; sb[o + x] = nb[q]; sc[o + x] = nc[q]; sd[o + x] = nd[q];
+            }
+        }
+        __syncthreads();
+    }
+    for (int64_t x = tid; x < M; x += kNT1D)
+        for (int k = 0; k < 2; ++k) sd[k * Mp + x] /= sb[k * Mp + x];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_solve_1d(Solve1DArgs p) {
+    extern __shared__ double sm[];
+    const int64_t M = p.M;
+    const int64_t Mp = p.Mpad;
+    double* sa = sm;             // [2][Mp]
+    double* sb = sm + 2 * Mp;    // [2][Mp]
+    double* sc = sm + 4 * Mp;    // [2][Mp]
+    double* sd = sm + 6 * Mp;    // [2][Mp]
+    const int64_t twoM = 2 * M;
+    const int tid = threadIdx.x;
+    // 1. S'_k (partials + BDF2 correction), w = E + c S'/d0, y = h^2 V^-1 Delta^-1 w
+    double rhs_y[2][4], qv[2][4];
+    int cnt = 0;
+    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
+        double u[2];
+        for (int k = 0; k < 2; ++k) {
+            double s = 0.0;
+            for (int c = 0; c < p.nsplit; ++c) s += p.Spart[(int64_t(c) * 2 + k) * M + x];
+            s = fma(p.corr[k], p.G0[k * M + x], s);
+            const double* lv = p.levels + int64_t(k) * M + x;
+            const double g1 = level_at(lv, p.n - 1, p.Lr, twoM);
+            double e;
+            if (p.scheme == 1) {
+                e = g1 * p.inv_tau;
+            } else {
+                const int64_t l2 = (p.n >= 2) ? p.n - 2 : 0;
+                e = (2.0 * g1 - 0.5 * level_at(lv, l2, p.Lr, twoM)) * p.inv_tau;
+            }
+            const double qk = s * p.inv_d0[k];
+            qv[k][cnt] = qk;
+            u[k] = (e + p.cdiag * qk) * p.inv_d0[k];
+        }
+        rhs_y[0][cnt] = (p.Vinv[0] * u[0] + p.Vinv[1] * u[1]) * p.h2;
+        rhs_y[1][cnt] = (p.Vinv[2] * u[0] + p.Vinv[3] * u[1]) * p.h2;
+        sd[x] = rhs_y[0][cnt];
+        sd[Mp + x] = rhs_y[1][cnt];
+    }
+    __syncthreads();
+    pcr_solve(sa, sb, sc, sd, M, Mp, p.diag);
+    // 2. residual r = h^2 y - T z in double-double, T = tridiag(-1, 2 + delta, -1)
+    cnt = 0;
+    double rr[2][4], zown[2][4];
+    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
+        for (int k = 0; k < 2; ++k) {
+            const int64_t o = k * Mp;
+            const double z = sd[o + x];
+            zown[k][cnt] = z;
+            const double zl = (x > 0) ? sd[o + x - 1] : 0.0;
+            const double zr = (x + 1 < M) ? sd[o + x + 1] : 0.0;
+            double hi = rhs_y[k][cnt], lo = 0.0;
+            dd_add(hi, lo, zl);
+            dd_add(hi, lo, zr);
+            dd_add(hi, lo, -2.0 * z);
+            const double pz = p.delta[k] * z;
+            const double pe = fma(p.delta[k], z, -pz);  // exact product error
+            dd_add(hi, lo, -pz);
+            lo -= pe;
+            rr[k][cnt] = hi + lo;
+        }
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
+        for (int k = 0; k < 2; ++k) sd[k * Mp + x] = rr[k][cnt];
+    }
+    __syncthreads();
+    pcr_solve(sa, sb, sc, sd, M, Mp, p.diag);
+    // 3. G^n = V (z + dz) - Delta^-1 S'
+    cnt = 0;
+    double* out = p.levels + (p.n % p.Lr) * twoM;
+    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
+        const double z0 = zown[0][cnt] + sd[x];
+        const double z1 = zown[1][cnt] + sd[Mp + x];
+        out[x] = p.V[0] * z0 + p.V[1] * z1 - qv[0][cnt];
+        out[M + x] = p.V[2] * z0 + p.V[3] * z1 - qv[1][cnt];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D: pointwise right-hand side w = E + c Delta^-1 S' and q = Delta^-1 S'
+// (the forward DST, per-mode solve and inverse DST follow; the last GEMM
+// subtracts q).
+__global__ __launch_bounds__(256) void k_prep_2d(Prep2DArgs p) {
+    const int64_t M = p.M;
+    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= M) return;
+    const int k = blockIdx.y;
+    const int64_t twoM = 2 * M;
+    double s = 0.0;
+    for (int c = 0; c < p.nsplit; ++c) s += p.Spart[(int64_t(c) * 2 + k) * M + x];
+    s = fma(p.corr[k], p.G0[k * M + x], s);
+    const double* lv = p.levels + int64_t(k) * M + x;
+    const double g1 = lv[((p.n - 1) % p.Lr) * twoM];
+    double e;
+    if (p.scheme == 1) {
+        e = g1 * p.inv_tau;
+    } else {
+        const int64_t l2 = (p.n >= 2) ? p.n - 2 : 0;
+        e = (2.0 * g1 - 0.5 * lv[(l2 % p.Lr) * twoM]) * p.inv_tau;
+    }
+    const double qk = s * p.inv_d0[k];
+    p.q[k * M + x] = qk;
+    p.w[k * M + x] = e + p.cdiag * qk;
+}
+
+// ---------------------------------------------------------------------------
+// Small dense GEMM pair for the 2D DST-I: C_k = A_k B_k, k = 0, 1, with
+// FP64 MFMA 16x16x4. One workgroup = one 16x16 output tile of both
+// components; its 4 waves split the K loop and reduce through LDS.
+// Epilogues: 0 plain store; 1 per-mode 2x2 solve (forward transform
+// finished); 2 store minus a field (inverse transform finished: G^n = K^-1 w - q).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
+    __shared__ double red[4][2][16][17];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+    const int row = r0 + li, col = c0 + li;
+    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = wave * 4; kk < p.K; kk += 16) {
+        const int kx = kk + lk;
+        const bool kin = kx < p.K;
+        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+        if (kin && row < p.R) {
+            // A is either a per-component field (row-major, lda) or a shared
+            // symmetric sine matrix (read transposed for coalescing)
+            if (p.A_shared) {
+                a0 = a1 = p.A0[int64_t(kx) * p.lda + row];
+            } else {
+                a0 = p.A0[int64_t(row) * p.lda + kx];
+                a1 = p.A1[int64_t(row) * p.lda + kx];
+            }
+        }
+        if (kin && col < p.C) {
+            if (p.B_shared) {
+                b0 = b1 = p.B0[int64_t(kx) * p.ldb + col];
+            } else {
+                b0 = p.B0[int64_t(kx) * p.ldb + col];
+                b1 = p.B1[int64_t(kx) * p.ldb + col];
+            }
+        }
+        acc0 = mfma16x16x4(a0, b0, acc0);
+        acc1 = mfma16x16x4(a1, b1, acc1);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        red[wave][0][lk + 4 * i][li] = acc0[i];
+        red[wave][1][lk + 4 * i][li] = acc1[i];
+    }
+    __syncthreads();
+    // 256 threads, one output element (i, j) of the 16x16 tile each
+    const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+    const int orow = r0 + ti, ocol = c0 + tj;
+    if (orow >= p.R || ocol >= p.C) return;
+    double v0 = red[0][0][ti][tj] + red[1][0][ti][tj] + red[2][0][ti][tj] + red[3][0][ti][tj];
+    double v1 = red[0][1][ti][tj] + red[1][1][ti][tj] + red[2][1][ti][tj] + red[3][1][ti][tj];
+    const int64_t o = int64_t(orow) * p.ldc + ocol;
+    if (EPI == 1) {
+        // per-mode solve: row = y-mode p, col = x-mode q
+        const double lam = p.lamy[orow] + p.lamx[ocol];
+        const double m11 = p.cdiag + p.dd0[0] * (p.a + lam);
+        const double m22 = p.cdiag + p.dd0[1] * (p.a + lam);
+        const double m12 = -p.a * p.dd0[1], m21 = -p.a * p.dd0[0];
+        const double det = m11 * m22 - m12 * m21;
+        const double s = p.scale / det;
+        const double g0 = (m22 * v0 - m12 * v1) * s;
+        const double g1 = (m11 * v1 - m21 * v0) * s;
+        v0 = g0;
+        v1 = g1;
+    } else if (EPI == 2) {
+        v0 -= p.sub0[o];
+        v1 -= p.sub1[o];
+    }
+    p.C0[o] = v0;
+    p.C1[o] = v1;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+void launch_hist_fast(const HistFastArgs& a, int nsplit, hipStream_t st) {
+    dim3 grid(unsigned((a.M + 255) / 256), unsigned(nsplit), 2);
+    hipLaunchKernelGGL(k_hist_fast, grid, dim3(256), 0, st, a);
+}
+
+void launch_hist_direct(const HistDirectArgs& a, hipStream_t st) {
+    dim3 grid(unsigned((a.M + 255) / 256), 1, 2);
+    hipLaunchKernelGGL(k_hist_direct, grid, dim3(256), 0, st, a);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_row(const double* __restrict__ F, int ks, int B, int64_t M,
+                                                    double* __restrict__ out) {
+    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= M) return;
+    double s = 0.0;
+    for (int q = 0; q < ks; ++q) s += F[int64_t(q) * B * M + x];
+    out[x] = s;
+}
+
+void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_row, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, F, ks, B, M, out);
+}
+
+void launch_far(const FarArgs& a, hipStream_t st) {
+    dim3 grid(unsigned((a.M + 63) / 64), unsigned(a.ks), unsigned(a.ncomp));
+    switch (a.B / 64) {
+        case 1: hipLaunchKernelGGL(k_far_toeplitz<1>, grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_far_toeplitz<2>, grid, dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL(k_far_toeplitz<3>, grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_far_toeplitz<4>, grid, dim3(256), 0, st, a); break;
+    }
+}
+
+void launch_solve_1d(const Solve1DArgs& a, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_solve_1d, dim3(1), dim3(kNT1D), lds, st, a);
+}
+
+void launch_prep_2d(const Prep2DArgs& a, hipStream_t st) {
+    dim3 grid(unsigned((a.M + 255) / 256), 2);
+    hipLaunchKernelGGL(k_prep_2d, grid, dim3(256), 0, st, a);
+}
+
+void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
+    dim3 grid(unsigned((a.C + 15) / 16), unsigned((a.R + 15) / 16));
+    if (epi == 1)
+        hipLaunchKernelGGL(k_dst_gemm<1>, grid, dim3(256), 0, st, a);
+    else if (epi == 2)
+        hipLaunchKernelGGL(k_dst_gemm<2>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_dst_gemm<0>, grid, dim3(256), 0, st, a);
+}
+
+const void* kernel_solve_1d() { return reinterpret_cast<const void*>(&k_solve_1d); }
+
+}  // namespace cqfp

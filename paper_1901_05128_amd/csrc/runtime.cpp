@@ -1,0 +1,689 @@
+// C ABI of the CQ solver: argument checks, solver set-up, device buffers and
+// the per-step launch sequence (see include/cqfp.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace cqfp {
+const char* last_error();
+}
+
+using namespace cqfp;
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(CQ_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
+
+struct Solver {
+    cq_grid g{};
+    cq_params p{};
+    int dim = 1, nx = 1, ny = 1;
+    int64_t M = 0, N = 0, n = 0;
+    double tau = 0, a = 0, beta[2] = {0, 0}, c = 0, hx = 0, hy = 0;
+    hipStream_t st = nullptr;
+    // fast
+    int L = 2, np = 0, nsplit = 1, chunk = 0;
+    double max_eps = 0;
+    // direct
+    int B = 0, ks = 1;
+    int64_t n0 = 0;
+    int64_t Lr = 0;
+    int64_t dstride = 0;
+    std::vector<double> dh[2];
+    FastRule rule[2];
+    double theta[2] = {0, 0}, V[2][2] = {{1, 0}, {0, 1}}, Vinv[2][2] = {{1, 0}, {0, 1}};
+    // device buffers
+    double *d_d = nullptr, *d_ratio = nullptr, *d_coef = nullptr, *G0 = nullptr, *levels = nullptr,
+           *H = nullptr, *Spart = nullptr, *F = nullptr, *rhs = nullptr, *T1 = nullptr, *T2 = nullptr,
+           *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr;
+    size_t lds = 0;
+    size_t dev_bytes = 0;
+    std::vector<void*> allocs;
+
+    ~Solver() {
+        for (void* q : allocs) (void)hipFree(q);
+    }
+};
+
+int dev_alloc(Solver& s, double** ptr, size_t count) {
+    void* q = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(double);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? CQ_ENOMEM : CQ_EHIP, "hipMalloc(%zu bytes): %s", bytes,
+                    hipGetErrorString(e));
+    }
+    s.allocs.push_back(q);
+    s.dev_bytes += bytes;
+    *ptr = static_cast<double*>(q);
+    return CQ_OK;
+}
+
+double lambda_1d(int n, double len, int p) {  // p = 1..n
+    const double h = len / (n + 1);
+    const double sn = std::sin(p * M_PI / (2.0 * (n + 1)));
+    return 4.0 / (h * h) * sn * sn;
+}
+
+int validate(const cq_grid* g, const cq_params* p) {
+    if (!g || !p) return fail(CQ_EINVAL, "grid and params must not be NULL");
+    if (g->dim != 1 && g->dim != 2) return fail(CQ_EINVAL, "dim must be 1 or 2 (got %d)", g->dim);
+    if (g->nx < 1 || g->ny < 1) return fail(CQ_EINVAL, "nx, ny must be >= 1");
+    if (g->dim == 1 && g->ny != 1) return fail(CQ_EINVAL, "dim 1 needs ny = 1");
+    if (g->dim == 1 && g->nx > 4096) return fail(CQ_EINVAL, "1D grids are limited to 4096 nodes (got %d)", g->nx);
+    if (!(g->lx > 0) || (g->dim == 2 && !(g->ly > 0))) return fail(CQ_EINVAL, "domain lengths must be > 0");
+    if (!(p->alpha1 > 0 && p->alpha1 < 1 && p->alpha2 > 0 && p->alpha2 < 1))
+        return fail(CQ_EINVAL, "alpha1, alpha2 must lie in (0,1)");
+    if (!(p->m >= 0 && p->m <= 1) || p->m == 0.5) return fail(CQ_EINVAL, "m must lie in [0,1] without 1/2");
+    if (!(p->T > 0) || !std::isfinite(p->T)) return fail(CQ_EINVAL, "T must be > 0");
+    if (p->N < 1) return fail(CQ_EINVAL, "N must be >= 1");
+    if (p->scheme != 1 && p->scheme != 2) return fail(CQ_EINVAL, "scheme must be 1 (BE) or 2 (BDF2)");
+    if (p->method != 0 && p->method != 1) return fail(CQ_EINVAL, "method must be 0 (direct) or 1 (fast)");
+    if (p->np < 0 || p->np1 < 0 || p->ns < 0 || p->np_max < 0 || p->block_B < 0 || p->fast_tol < 0)
+        return fail(CQ_EINVAL, "node counts, window, block and tolerance must be >= 0");
+    if (p->scheme == 2 && p->ns != 0 && p->ns < 3) return fail(CQ_EINVAL, "ns must be >= 3 (got %d)", p->ns);
+    if (p->block_B != 0 && (p->block_B % 64 != 0 || p->block_B > 256))
+        return fail(CQ_EINVAL, "block_B must be 64, 128, 192 or 256 (got %d)", p->block_B);
+    if (p->np > 4096 || p->np1 > 4096) return fail(CQ_EINVAL, "np, np1 must be <= 4096");
+    return CQ_OK;
+}
+
+int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) {
+    s.g = *g;
+    s.p = *p;
+    s.dim = g->dim;
+    s.nx = g->nx;
+    s.ny = g->dim == 2 ? g->ny : 1;
+    s.M = int64_t(s.nx) * s.ny;
+    s.N = p->N;
+    s.st = st;
+    s.tau = p->T / double(p->N);
+    s.a = (1.0 - p->m) / (2.0 * p->m - 1.0);
+    s.beta[0] = 1.0 - p->alpha1;
+    s.beta[1] = 1.0 - p->alpha2;
+    s.c = (p->scheme == 1 ? 1.0 : 1.5) / s.tau;
+    s.hx = g->lx / (s.nx + 1);
+    s.hy = s.dim == 2 ? g->ly / (s.ny + 1) : 1.0;
+    const int ns = p->ns ? p->ns : 30;
+    const int np1 = p->np1 ? p->np1 : 16;
+    const int np_max = p->np_max ? p->np_max : 1024;
+    const double tol = p->fast_tol > 0 ? p->fast_tol : 1e-8;
+
+    // direct block length and K-split (enough workgroups to fill 256 CUs)
+    if (p->method == 0) {
+        s.B = p->block_B ? p->block_B : (s.dim == 1 ? 64 : 128);
+        const int64_t tiles = 2 * ((s.M + 63) / 64);
+        s.ks = int(std::min<int64_t>(64, std::max<int64_t>(1, (1024 + tiles - 1) / tiles)));
+    }
+    s.dstride = s.N + 257 + 1;
+    for (int k = 0; k < 2; ++k) {
+        s.dh[k].assign(size_t(s.dstride), 0.0);
+        weights(p->scheme, s.beta[k], s.tau, s.dstride - 1, s.dh[k].data());
+    }
+
+    // step operator: diag(d0) (I x A + K x I), K as below; must be positive definite
+    const double d10 = s.dh[0][0], d20 = s.dh[1][0];
+    const double K[2][2] = {{s.c / d10 + s.a, -s.a * d20 / d10}, {-s.a * d10 / d20, s.c / d20 + s.a}};
+    eig2(K, s.theta, s.V, s.Vinv);
+    double lam_min = lambda_1d(s.nx, g->lx, 1);
+    if (s.dim == 2) lam_min += lambda_1d(s.ny, g->ly, 1);
+    for (int k = 0; k < 2; ++k)
+        if (!(s.theta[k] + lam_min > 0))
+            return fail(CQ_ESINGULAR,
+                        "step operator not positive definite: theta_%d = %.6g <= -lambda_min = %.6g "
+                        "(take a smaller tau or m further from 1/2)",
+                        k + 1, s.theta[k], -lam_min);
+
+    // fast rule: one node count for both components
+    FastRule rule[2];
+    if (p->method == 1) {
+        int npk[2];
+        for (int k = 0; k < 2; ++k) {
+            if (p->np > 0) {
+                build_rule(p->scheme, s.beta[k], s.tau, p->np, np1, ns, rule[k]);
+                std::vector<double> dk(s.dh[k].begin(), s.dh[k].begin() + s.N + 1);
+                rule[k].max_eps = rule_error(rule[k], dk, s.N);
+            } else {
+                int rc = choose_rule(p->scheme, s.beta[k], s.tau, s.N, tol, np_max, np1, ns, rule[k]);
+                if (rc != CQ_OK) return rc;
+            }
+            npk[k] = int(rule[k].ratio.size());
+        }
+        if (npk[0] != npk[1]) {  // rebuild the smaller one at the common size
+            const int k = npk[0] < npk[1] ? 0 : 1;
+            const int target = std::max(npk[0], npk[1]) - (p->scheme == 2 ? np1 : 0);
+            build_rule(p->scheme, s.beta[k], s.tau, target, np1, ns, rule[k]);
+            std::vector<double> dk(s.dh[k].begin(), s.dh[k].begin() + s.N + 1);
+            rule[k].max_eps = rule_error(rule[k], dk, s.N);
+        }
+        s.np = int(rule[0].ratio.size());
+        s.L = rule[0].lag;
+        s.max_eps = std::max(rule[0].max_eps, rule[1].max_eps);
+        const int64_t tiles = 2 * ((s.M + 255) / 256);
+        int want = int(std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
+        want = std::min(want, s.dim == 1 ? 16 : 4);
+        s.nsplit = std::max(1, std::min(want, s.np / 8 > 0 ? s.np / 8 : 1));
+        s.chunk = (s.np + s.nsplit - 1) / s.nsplit;
+        s.Lr = s.L;
+    } else {
+        s.Lr = s.N + 1;
+    }
+    s.rule[0] = rule[0];
+    s.rule[1] = rule[1];
+    return CQ_OK;
+}
+
+int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
+    const cq_params* p = &s.p;
+    const cq_grid* g = &s.g;
+    // device buffers
+    int rc;
+    const int64_t twoM = 2 * s.M;
+    if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
+    if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
+    if ((rc = dev_alloc(s, &s.Spart, size_t(s.nsplit * twoM)))) return rc;
+    HIPCHK(hipMemcpyAsync(s.d_d, s.dh[0].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
+                          st));
+    HIPCHK(hipMemcpyAsync(s.G0, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(s.levels, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (p->method == 1) {
+        if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * s.M)))) return rc;
+        if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
+        if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
+        HIPCHK(hipMemsetAsync(s.H, 0, size_t(2 * int64_t(s.np) * s.M) * sizeof(double), st));
+        std::vector<double> rr(size_t(2 * s.np)), cc(size_t(2 * s.np));
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < s.np; ++j) {
+                rr[size_t(k * s.np + j)] = s.rule[k].ratio[size_t(j)];
+                cc[size_t(k * s.np + j)] = s.rule[k].coef[size_t(j)];
+            }
+        HIPCHK(hipMemcpy(s.d_ratio, rr.data(), rr.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.d_coef, cc.data(), cc.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        if ((rc = dev_alloc(s, &s.F, size_t(int64_t(s.ks) * s.B * twoM)))) return rc;
+    }
+    if (s.dim == 1) {
+        s.lds = size_t(8) * size_t(s.M) * sizeof(double);
+        int dev = 0, maxlds = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (s.lds > size_t(maxlds))
+            return fail(CQ_EINVAL, "1D grid of %lld nodes needs %zu B of LDS, device allows %d", (long long)s.M,
+                        s.lds, maxlds);
+        if (s.lds > 65536)
+            HIPCHK(hipFuncSetAttribute(kernel_solve_1d(), hipFuncAttributeMaxDynamicSharedMemorySize, int(s.lds)));
+    } else {
+        if ((rc = dev_alloc(s, &s.rhs, size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.qbuf, size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.T2, size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.Sx, size_t(s.nx) * s.nx))) return rc;
+        if ((rc = dev_alloc(s, &s.Sy, size_t(s.ny) * s.ny))) return rc;
+        if ((rc = dev_alloc(s, &s.lamx, size_t(s.nx)))) return rc;
+        if ((rc = dev_alloc(s, &s.lamy, size_t(s.ny)))) return rc;
+        // DST-I: S[i][j] = sin(pi (i+1)(j+1)/(n+1)), symmetric, S S = (n+1)/2 I
+        auto sine = [](int n) {
+            std::vector<double> S(size_t(n) * n);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    // reduce the integer argument first: sin(pi k/(n+1)), k mod 2(n+1)
+                    const int64_t kk = (int64_t(i + 1) * (j + 1)) % (2 * int64_t(n + 1));
+                    S[size_t(i) * n + j] = std::sin(M_PI * double(kk) / double(n + 1));
+                }
+            return S;
+        };
+        std::vector<double> sx = sine(s.nx), sy = sine(s.ny), lx(size_t(s.nx)), ly(size_t(s.ny));
+        for (int q = 0; q < s.nx; ++q) lx[size_t(q)] = lambda_1d(s.nx, g->lx, q + 1);
+        for (int q = 0; q < s.ny; ++q) ly[size_t(q)] = lambda_1d(s.ny, g->ly, q + 1);
+        HIPCHK(hipMemcpy(s.Sx, sx.data(), sx.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.Sy, sy.data(), sy.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.lamx, lx.data(), lx.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.lamy, ly.data(), ly.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return CQ_OK;
+}
+
+int check_finite_g0(const double* G0dev, int64_t count, hipStream_t st) {
+    std::vector<double> h(static_cast<size_t>(count));
+    HIPCHK(hipMemcpyAsync(h.data(), G0dev, size_t(count) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (double v : h)
+        if (!std::isfinite(v)) return fail(CQ_ENONFINITE, "G0 holds a non-finite value");
+    return CQ_OK;
+}
+
+void launch_far_block(Solver& s) {
+    FarArgs fa{};
+    fa.n0 = s.n0;
+    fa.M = s.M;
+    fa.dstride = s.dstride;
+    fa.lstride = 2 * s.M;
+    fa.B = s.B;
+    fa.ks = s.ks;
+    fa.ncomp = 2;
+    int64_t mc = (s.n0 + s.ks - 1) / s.ks;
+    fa.mchunk = ((mc + 3) / 4) * 4;
+    fa.levels = s.levels;
+    fa.d = s.d_d;
+    fa.F = s.F;
+    launch_far(fa, s.st);
+}
+
+// one time step n = s.n + 1
+void step_once(Solver& s) {
+    const int64_t n = ++s.n;
+    if (s.p.method == 0) {
+        if ((n - 1) % s.B == 0) {
+            s.n0 = n - 1;
+            if (s.n0 >= 1) launch_far_block(s);
+        }
+        HistDirectArgs ha{};
+        ha.n = n;
+        ha.n0 = s.n0;
+        ha.M = s.M;
+        ha.dstride = s.dstride;
+        ha.B = s.B;
+        ha.ks = s.ks;
+        ha.levels = s.levels;
+        ha.d = s.d_d;
+        ha.F = s.F;
+        ha.Spart = s.Spart;
+        launch_hist_direct(ha, s.st);
+    } else {
+        HistFastArgs ha{};
+        ha.n = n;
+        ha.L = s.L;
+        ha.Lr = s.Lr;
+        ha.M = s.M;
+        ha.np = s.np;
+        ha.chunk = s.chunk;
+        ha.dstride = s.dstride;
+        ha.levels = s.levels;
+        ha.H = s.H;
+        ha.ratio = s.d_ratio;
+        ha.coef = s.d_coef;
+        ha.d = s.d_d;
+        ha.Spart = s.Spart;
+        launch_hist_fast(ha, s.nsplit, s.st);
+    }
+    const int nsplit = s.p.method == 1 ? s.nsplit : 1;
+    double corr[2] = {0.0, 0.0};
+    if (s.p.scheme == 2)
+        for (int k = 0; k < 2; ++k) corr[k] = 0.5 * s.dh[k][size_t(n - 1)];
+    if (s.dim == 1) {
+        Solve1DArgs sa{};
+        sa.n = n;
+        sa.M = s.M;
+        sa.Mpad = s.M;
+        sa.Lr = s.Lr;
+        sa.nsplit = nsplit;
+        sa.scheme = s.p.scheme;
+        sa.inv_tau = 1.0 / s.tau;
+        sa.cdiag = s.c;
+        sa.h2 = s.hx * s.hx;
+        for (int k = 0; k < 2; ++k) {
+            sa.inv_d0[k] = 1.0 / s.dh[k][0];
+            sa.corr[k] = corr[k];
+            sa.delta[k] = s.theta[k] * s.hx * s.hx;
+            sa.diag[k] = 2.0 + sa.delta[k];
+        }
+        sa.V[0] = s.V[0][0]; sa.V[1] = s.V[0][1]; sa.V[2] = s.V[1][0]; sa.V[3] = s.V[1][1];
+        sa.Vinv[0] = s.Vinv[0][0]; sa.Vinv[1] = s.Vinv[0][1]; sa.Vinv[2] = s.Vinv[1][0]; sa.Vinv[3] = s.Vinv[1][1];
+        sa.Spart = s.Spart;
+        sa.G0 = s.G0;
+        sa.levels = s.levels;
+        launch_solve_1d(sa, s.lds, s.st);
+        return;
+    }
+    const int64_t M = s.M;
+    Prep2DArgs ra{};
+    ra.n = n;
+    ra.Lr = s.Lr;
+    ra.M = M;
+    ra.nsplit = nsplit;
+    ra.scheme = s.p.scheme;
+    ra.inv_tau = 1.0 / s.tau;
+    ra.cdiag = s.c;
+    for (int k = 0; k < 2; ++k) {
+        ra.inv_d0[k] = 1.0 / s.dh[k][0];
+        ra.corr[k] = corr[k];
+    }
+    ra.Spart = s.Spart;
+    ra.G0 = s.G0;
+    ra.levels = s.levels;
+    ra.w = s.rhs;
+    ra.q = s.qbuf;
+    launch_prep_2d(ra, s.st);
+    GemmArgs ga{};
+    // forward: T1 = w Sx ; T2 = solve(Sy T1)
+    ga.R = s.ny; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
+    ga.A_shared = 0; ga.B_shared = 1;
+    ga.A0 = s.rhs; ga.A1 = s.rhs + M; ga.B0 = s.Sx; ga.B1 = s.Sx; ga.C0 = s.T1; ga.C1 = s.T1 + M;
+    launch_gemm(ga, 0, s.st);
+    GemmArgs gb{};
+    gb.R = s.ny; gb.C = s.nx; gb.K = s.ny; gb.lda = s.ny; gb.ldb = s.nx; gb.ldc = s.nx;
+    gb.A_shared = 1; gb.B_shared = 0;
+    gb.A0 = s.Sy; gb.A1 = s.Sy; gb.B0 = s.T1; gb.B1 = s.T1 + M; gb.C0 = s.T2; gb.C1 = s.T2 + M;
+    gb.lamx = s.lamx; gb.lamy = s.lamy; gb.cdiag = s.c; gb.a = s.a;
+    gb.scale = 4.0 / (double(s.nx + 1) * double(s.ny + 1));
+    gb.dd0[0] = s.dh[0][0]; gb.dd0[1] = s.dh[1][0];
+    launch_gemm(gb, 1, s.st);
+    // inverse: T1 = T2 Sx ; G^n = Sy T1 - q
+    GemmArgs gc = ga;
+    gc.A0 = s.T2; gc.A1 = s.T2 + M; gc.C0 = s.T1; gc.C1 = s.T1 + M;
+    launch_gemm(gc, 0, s.st);
+    GemmArgs gd{};
+    gd.R = s.ny; gd.C = s.nx; gd.K = s.ny; gd.lda = s.ny; gd.ldb = s.nx; gd.ldc = s.nx;
+    gd.A_shared = 1; gd.B_shared = 0;
+    double* out = s.levels + (n % s.Lr) * 2 * M;
+    gd.A0 = s.Sy; gd.A1 = s.Sy; gd.B0 = s.T1; gd.B1 = s.T1 + M; gd.C0 = out; gd.C1 = out + M;
+    gd.sub0 = s.qbuf; gd.sub1 = s.qbuf + M;
+    launch_gemm(gd, 2, s.st);
+}
+
+size_t state_bytes(const Solver& s) {
+    const int64_t twoM = 2 * s.M;
+    size_t b = 4 * sizeof(uint64_t) + size_t(twoM) * sizeof(double);  // header, G^0
+    if (s.p.method == 0)
+        b += size_t(s.n + 1) * size_t(twoM) * sizeof(double);
+    else
+        b += (size_t(s.Lr) * size_t(twoM) + size_t(2) * size_t(s.np) * size_t(s.M)) * sizeof(double);
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cq_weights(int32_t scheme, double beta, double tau, int64_t n, double* d_out) {
+    clear_error();
+    if (scheme != 1 && scheme != 2) return fail(CQ_EINVAL, "scheme must be 1 or 2");
+    if (!(beta > 0 && beta < 1)) return fail(CQ_EINVAL, "beta must lie in (0,1)");
+    if (!(tau > 0) || !std::isfinite(tau)) return fail(CQ_EINVAL, "tau must be > 0");
+    if (n < 0) return fail(CQ_EINVAL, "n must be >= 0");
+    if (!d_out) return fail(CQ_EINVAL, "d_out is NULL");
+    weights(scheme, beta, tau, n, d_out);
+    return CQ_OK;
+}
+
+int cq_fast_rule(int32_t scheme, double beta, double tau, int64_t N, double tol, int32_t np, int32_t np1, int32_t ns,
+                 int32_t np_max, int32_t cap, double* ratio_out, double* coef_out, int32_t* count_out,
+                 int32_t* lag_out, double* max_eps_out) {
+    clear_error();
+    if (scheme != 1 && scheme != 2) return fail(CQ_EINVAL, "scheme must be 1 or 2");
+    if (!(beta > 0 && beta < 1)) return fail(CQ_EINVAL, "beta must lie in (0,1)");
+    if (!(tau > 0)) return fail(CQ_EINVAL, "tau must be > 0");
+    if (N < 1) return fail(CQ_EINVAL, "N must be >= 1");
+    if (np < 0 || np1 < 0 || ns < 0 || np_max < 0 || cap < 0 || tol < 0)
+        return fail(CQ_EINVAL, "negative count or tolerance");
+    if (scheme == 2 && ns != 0 && ns < 3) return fail(CQ_EINVAL, "ns must be >= 3");
+    if (!ratio_out || !coef_out || !count_out || !lag_out || !max_eps_out)
+        return fail(CQ_EINVAL, "output pointer is NULL");
+    if (np > 4096 || np1 > 4096) return fail(CQ_EINVAL, "np, np1 must be <= 4096");
+    const int ns_ = ns ? ns : 30, np1_ = np1 ? np1 : 16, npmax = np_max ? np_max : 1024;
+    const double tol_ = tol > 0 ? tol : 1e-8;
+    FastRule r;
+    try {
+        if (np > 0) {
+            build_rule(scheme, beta, tau, np, np1_, ns_, r);
+            std::vector<double> d(size_t(N) + 1);
+            weights(scheme, beta, tau, N, d.data());
+            r.max_eps = rule_error(r, d, N);
+        } else {
+            int rc = choose_rule(scheme, beta, tau, N, tol_, npmax, np1_, ns_, r);
+            if (rc != CQ_OK) return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(CQ_ENOMEM, "host allocation failed");
+    }
+    if (int(r.ratio.size()) > cap) return fail(CQ_EINVAL, "cap %d < %zu terms", cap, r.ratio.size());
+    for (size_t j = 0; j < r.ratio.size(); ++j) {
+        ratio_out[j] = r.ratio[j];
+        coef_out[j] = r.coef[j];
+    }
+    *count_out = int32_t(r.ratio.size());
+    *lag_out = r.lag;
+    *max_eps_out = r.max_eps;
+    return CQ_OK;
+}
+
+int cq_history(int32_t scheme, double beta, double tau, const double* G_hist, int64_t n, int64_t M, double* S_out,
+               void* hip_stream) {
+    clear_error();
+    if (scheme != 1 && scheme != 2) return fail(CQ_EINVAL, "scheme must be 1 or 2");
+    if (!(beta > 0 && beta < 1)) return fail(CQ_EINVAL, "beta must lie in (0,1)");
+    if (!(tau > 0)) return fail(CQ_EINVAL, "tau must be > 0");
+    if (n < 1 || M < 1) return fail(CQ_EINVAL, "n and M must be >= 1");
+    if (!G_hist || !S_out) return fail(CQ_EINVAL, "NULL array");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int B = 64;
+    const int64_t tiles = (M + 63) / 64;
+    const int ks = int(std::min<int64_t>(64, std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles,
+                                                                                     (n + 3) / 4))));
+    const int64_t dstride = n + B + 1;
+    std::vector<double> dh(static_cast<size_t>(dstride));
+    weights(scheme, beta, tau, dstride - 1, dh.data());
+    double *dd = nullptr, *F = nullptr;
+    HIPCHK(hipMalloc(&dd, size_t(dstride) * sizeof(double)));
+    hipError_t e = hipMalloc(&F, size_t(ks) * B * size_t(M) * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipFree(dd);
+        return fail(CQ_ENOMEM, "hipMalloc for history partials: %s", hipGetErrorString(e));
+    }
+    int rc = CQ_OK;
+    do {
+        e = hipMemcpyAsync(dd, dh.data(), size_t(dstride) * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) { rc = fail(CQ_EHIP, "copy weights: %s", hipGetErrorString(e)); break; }
+        if (n == 1) {
+            e = hipMemsetAsync(S_out, 0, size_t(M) * sizeof(double), st);
+            if (e != hipSuccess) { rc = fail(CQ_EHIP, "memset: %s", hipGetErrorString(e)); break; }
+        } else {
+            FarArgs fa{};
+            fa.n0 = n - 1;
+            fa.M = M;
+            fa.dstride = dstride;
+            fa.lstride = M;
+            fa.B = B;
+            fa.ks = ks;
+            fa.ncomp = 1;
+            const int64_t mc = (fa.n0 + ks - 1) / ks;
+            fa.mchunk = ((mc + 3) / 4) * 4;
+            fa.levels = G_hist;
+            fa.d = dd;
+            fa.F = F;
+            launch_far(fa, st);
+            launch_reduce_row(F, ks, B, M, S_out, st);
+            e = hipGetLastError();
+            if (e != hipSuccess) { rc = fail(CQ_EHIP, "launch: %s", hipGetErrorString(e)); break; }
+        }
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(CQ_EHIP, "sync: %s", hipGetErrorString(e));
+    } while (0);
+    (void)hipFree(dd);
+    (void)hipFree(F);
+    return rc;
+}
+
+int fp_create(const cq_grid* grid, const cq_params* prm, const double* G0, void* hip_stream, void** handle) {
+    clear_error();
+    if (!handle) return fail(CQ_EINVAL, "handle is NULL");
+    *handle = nullptr;
+    int rc = validate(grid, prm);
+    if (rc) return rc;
+    if (!G0) return fail(CQ_EINVAL, "G0 is NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t M = int64_t(grid->nx) * (grid->dim == 2 ? grid->ny : 1);
+    Solver* s = new (std::nothrow) Solver();
+    if (!s) return fail(CQ_ENOMEM, "host allocation failed");
+    try {
+        // host checks (operator definiteness, fast-rule tolerance) come first,
+        // so they are reported without touching the device
+        rc = setup_host(*s, grid, prm, st);
+        if (!rc) rc = check_finite_g0(G0, 2 * M, st);
+        if (!rc) rc = setup_device(*s, G0, st);
+    } catch (const std::bad_alloc&) {
+        rc = fail(CQ_ENOMEM, "host allocation failed");
+    }
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    *handle = s;
+    return CQ_OK;
+}
+
+int fp_step(void* handle, int64_t nsteps) {
+    clear_error();
+    if (!handle) return fail(CQ_EINVAL, "handle is NULL");
+    Solver& s = *static_cast<Solver*>(handle);
+    if (nsteps < 0 || s.n + nsteps > s.N)
+        return fail(CQ_EINVAL, "cannot take %lld steps from n = %lld (N = %lld)", (long long)nsteps, (long long)s.n,
+                    (long long)s.N);
+    for (int64_t i = 0; i < nsteps; ++i) step_once(s);
+    HIPCHK(hipGetLastError());
+    return CQ_OK;
+}
+
+int fp_current(void* handle, double* G_out, int64_t* n_out) {
+    clear_error();
+    if (!handle || !G_out) return fail(CQ_EINVAL, "NULL argument");
+    Solver& s = *static_cast<Solver*>(handle);
+    const double* src = s.levels + (s.n % s.Lr) * 2 * s.M;
+    HIPCHK(hipMemcpyAsync(G_out, src, size_t(2 * s.M) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    if (n_out) *n_out = s.n;
+    return CQ_OK;
+}
+
+int fp_info(void* handle, cq_info* info) {
+    clear_error();
+    if (!handle || !info) return fail(CQ_EINVAL, "NULL argument");
+    const Solver& s = *static_cast<const Solver*>(handle);
+    info->n = s.n;
+    info->N = s.N;
+    info->np_total = s.np;
+    info->lag = s.p.method == 1 ? s.L : 0;
+    info->max_eps = s.max_eps;
+    info->theta[0] = s.theta[0];
+    info->theta[1] = s.theta[1];
+    info->block_B = s.B;
+    info->ksplit = s.ks;
+    info->device_bytes = s.dev_bytes;
+    info->state_bytes = state_bytes(s);
+    return CQ_OK;
+}
+
+int fp_get_state(void* handle, void* dst, size_t* bytes) {
+    clear_error();
+    if (!handle || !bytes) return fail(CQ_EINVAL, "NULL argument");
+    Solver& s = *static_cast<Solver*>(handle);
+    const size_t need = state_bytes(s);
+    if (!dst) {
+        *bytes = need;
+        return CQ_OK;
+    }
+    if (*bytes < need) return fail(CQ_EINVAL, "state buffer of %zu bytes < %zu", *bytes, need);
+    HIPCHK(hipStreamSynchronize(s.st));
+    uint64_t* hdr = static_cast<uint64_t*>(dst);
+    hdr[0] = kStateMagic;
+    hdr[1] = uint64_t(s.n);
+    hdr[2] = uint64_t(s.M);
+    hdr[3] = uint64_t(s.np);
+    char* q = static_cast<char*>(dst) + 4 * sizeof(uint64_t);
+    const int64_t twoM = 2 * s.M;
+    HIPCHK(hipMemcpy(q, s.G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToHost));
+    q += size_t(twoM) * sizeof(double);
+    if (s.p.method == 0) {
+        const size_t b = size_t(s.n + 1) * size_t(twoM) * sizeof(double);
+        HIPCHK(hipMemcpy(q, s.levels, b, hipMemcpyDeviceToHost));
+    } else {
+        const size_t b1 = size_t(s.Lr) * size_t(twoM) * sizeof(double);
+        HIPCHK(hipMemcpy(q, s.levels, b1, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(q + b1, s.H, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    *bytes = need;
+    return CQ_OK;
+}
+
+int fp_set_state(void* handle, const void* src, size_t bytes) {
+    clear_error();
+    if (!handle || !src) return fail(CQ_EINVAL, "NULL argument");
+    Solver& s = *static_cast<Solver*>(handle);
+    if (bytes < 4 * sizeof(uint64_t)) return fail(CQ_EINVAL, "state too short");
+    const uint64_t* hdr = static_cast<const uint64_t*>(src);
+    if (hdr[0] != kStateMagic || hdr[2] != uint64_t(s.M) || hdr[3] != uint64_t(s.np))
+        return fail(CQ_EINVAL, "state does not belong to a solver of this shape");
+    const int64_t n = int64_t(hdr[1]);
+    if (n < 0 || n > s.N) return fail(CQ_EINVAL, "state step %lld out of range", (long long)n);
+    const int64_t save_n = s.n;
+    s.n = n;
+    const size_t need = state_bytes(s);
+    if (bytes < need) {
+        s.n = save_n;
+        return fail(CQ_EINVAL, "state of %zu bytes < %zu", bytes, need);
+    }
+    HIPCHK(hipStreamSynchronize(s.st));
+    const char* q = static_cast<const char*>(src) + 4 * sizeof(uint64_t);
+    const int64_t twoM = 2 * s.M;
+    HIPCHK(hipMemcpy(s.G0, q, size_t(twoM) * sizeof(double), hipMemcpyHostToDevice));
+    q += size_t(twoM) * sizeof(double);
+    if (s.p.method == 0) {
+        HIPCHK(hipMemcpy(s.levels, q, size_t(n + 1) * size_t(twoM) * sizeof(double), hipMemcpyHostToDevice));
+        // far field of the block that contains step n+1
+        s.n0 = (n / s.B) * s.B;
+        if (n % s.B != 0 && s.n0 >= 1) launch_far_block(s);
+    } else {
+        const size_t b1 = size_t(s.Lr) * size_t(twoM) * sizeof(double);
+        HIPCHK(hipMemcpy(s.levels, q, b1, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.H, q + b1, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipGetLastError());
+    return CQ_OK;
+}
+
+int fp_destroy(void* handle) {
+    clear_error();
+    if (!handle) return CQ_OK;
+    Solver* s = static_cast<Solver*>(handle);
+    (void)hipStreamSynchronize(s->st);
+    delete s;
+    return CQ_OK;
+}
+
+int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double* GN, void* hip_stream) {
+    void* h = nullptr;
+    int rc = fp_create(grid, prm, G0, hip_stream, &h);
+    if (rc) return rc;
+    if (!GN) {
+        fp_destroy(h);
+        return fail(CQ_EINVAL, "GN is NULL");
+    }
+    rc = fp_step(h, prm->N);
+    if (!rc) rc = fp_current(h, GN, nullptr);
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+        if (e != hipSuccess) rc = fail(CQ_EHIP, "sync: %s", hipGetErrorString(e));
+    }
+    fp_destroy(h);
+    return rc;
+}
+
+const char* cq_last_error(void) { return cqfp::last_error(); }
+
+}  // extern "C"

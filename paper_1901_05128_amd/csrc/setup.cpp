@@ -1,0 +1,286 @@
+// Host-side setup of the CQ solver: weights, Gauss-Jacobi rules, the fast
+// sum-of-geometric-sequences rules and their node-count scan, and the 2x2
+// coupling eigen-decomposition. Plain fp64 C++; runs once per solver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "internal.h"
+
+namespace cqfp {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Weights (eqs. (3.4) and (3.12)).
+// BE: (1-z)^beta = sum g_i z^i with g_i = g_{i-1} (1 - (1+beta)/i).
+// BDF2: p(z) = 3/2 - 2z + z^2/2 and f = p^beta satisfy p f' = beta p' f;
+// comparing coefficients of z^(i-1) gives, with p0 = 3/2, p1 = -2, p2 = 1/2,
+//   c_i = [ (beta - (i-1)) p1 c_{i-1} + (2 beta - (i-2)) p2 c_{i-2} ] / (p0 i).
+// Both recurrences only shrink errors (the parasitic solution of the
+// second decays like 3^-i), so they stay at rounding level for i ~ 1e5.
+void weights(int scheme, double beta, double tau, int64_t n, double* d) {
+    const double s = std::pow(tau, -beta);
+    if (scheme == 1) {
+        double g = 1.0;
+        d[0] = s;
+        for (int64_t i = 1; i <= n; ++i) {
+            g *= 1.0 - (1.0 + beta) / double(i);
+            d[i] = s * g;
+        }
+        return;
+    }
+    const double p0 = 1.5, p1 = -2.0, p2 = 0.5;
+    double cm2 = 0.0, cm1 = std::pow(p0, beta);
+    d[0] = s * cm1;
+    for (int64_t i = 1; i <= n; ++i) {
+        const double di = double(i);
+        double c = (beta - (di - 1.0)) * p1 * cm1;
+        if (i >= 2) c += (2.0 * beta - (di - 2.0)) * p2 * cm2;
+        c /= p0 * di;
+        d[i] = s * c;
+        cm2 = cm1;
+        cm1 = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Jacobi rule for (1-s)^a (1+s)^b.
+// Monic recurrence p_{k+1} = (s - al_k) p_k - be_k p_{k-1} with
+//   al_k = (b^2 - a^2) / ((2k+a+b)(2k+a+b+2))   (al_0 = (b-a)/(a+b+2)),
+//   be_k = 4k(k+a)(k+b)(k+a+b) / ((2k+a+b)^2 (2k+a+b+1)(2k+a+b-1)),  k >= 1,
+//   mu_0 = 2^(a+b+1) Gamma(a+1) Gamma(b+1) / Gamma(a+b+2).
+// The nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix
+// (diagonal al_k, off-diagonal sqrt(be_k)); each is isolated by bisection on
+// the Sturm count and refined by Newton on the orthonormal polynomial. The
+// weights are the Christoffel numbers 1 / sum_{k<n} q_k(s_j)^2 with q_k the
+// orthonormal polynomials (q_0 = 1/sqrt(mu_0)).
+namespace {
+
+struct JacobiRec {
+    std::vector<double> al, sq;  // al[k], sq[k] = sqrt(be_k) (sq[0] unused)
+    double mu0;
+};
+
+JacobiRec jacobi_rec(int n, double a, double b) {
+    JacobiRec r;
+    r.al.resize(n + 1);
+    r.sq.assign(n + 1, 0.0);
+    for (int k = 0; k <= n; ++k) {
+        const double t = 2.0 * k + a + b;
+        if (k == 0)
+            r.al[k] = (b - a) / (a + b + 2.0);
+        else
+            r.al[k] = (b * b - a * a) / (t * (t + 2.0));
+        if (k >= 1) {
+            const double be = 4.0 * k * (k + a) * (k + b) * (k + a + b) / (t * t * (t + 1.0) * (t - 1.0));
+            r.sq[k] = std::sqrt(be);
+        }
+    }
+    r.mu0 = std::exp((a + b + 1.0) * std::log(2.0) + std::lgamma(a + 1.0) + std::lgamma(b + 1.0) -
+                     std::lgamma(a + b + 2.0));
+    return r;
+}
+
+// number of eigenvalues of the leading n x n Jacobi matrix below x
+int sturm_count(const JacobiRec& r, int n, double x) {
+    int cnt = 0;
+    double q = r.al[0] - x;
+    if (q < 0) ++cnt;
+    for (int k = 1; k < n; ++k) {
+        const double qq = (q != 0.0) ? q : 1e-300;
+        q = (r.al[k] - x) - r.sq[k] * r.sq[k] / qq;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// orthonormal q_n(x) and its derivative
+void ortho_eval(const JacobiRec& r, int n, double x, double& qn, double& dqn, double& sumsq) {
+    double qm1 = 0.0, q = 1.0 / std::sqrt(r.mu0);
+    double dqm1 = 0.0, dq = 0.0;
+    sumsq = q * q;
+    for (int k = 0; k < n; ++k) {
+        const double sn = r.sq[k + 1];
+        const double skm = (k >= 1) ? r.sq[k] : 0.0;
+        const double qn1 = ((x - r.al[k]) * q - skm * qm1) / sn;
+        const double dqn1 = (q + (x - r.al[k]) * dq - skm * dqm1) / sn;
+        qm1 = q;
+        q = qn1;
+        dqm1 = dq;
+        dq = dqn1;
+        if (k + 1 < n) sumsq += q * q;
+    }
+    qn = q;
+    dqn = dq;
+}
+
+}  // namespace
+
+void gauss_jacobi(int n, double a, double b, std::vector<double>& s, std::vector<double>& lam) {
+    const JacobiRec r = jacobi_rec(n, a, b);
+    s.assign(n, 0.0);
+    lam.assign(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        // the (j+1)-th smallest eigenvalue lies where the count passes j
+        double lo = -1.0, hi = 1.0;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (sturm_count(r, n, mid) > j)
+                hi = mid;
+            else
+                lo = mid;
+        }
+        double x = 0.5 * (lo + hi);
+        for (int it = 0; it < 3; ++it) {
+            double qn, dqn, ss;
+            ortho_eval(r, n, x, qn, dqn, ss);
+            if (dqn == 0.0) break;
+            const double xn = x - qn / dqn;
+            if (!(xn > lo - 1e-12 && xn < hi + 1e-12)) break;  // keep the bracketed root
+            x = xn;
+        }
+        double qn, dqn, ss;
+        ortho_eval(r, n, x, qn, dqn, ss);
+        s[j] = x;
+        lam[j] = 1.0 / ss;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fast rules. With Gamma(beta) Gamma(1-beta) = pi / sin(pi beta):
+// BE (3.6)-(3.7): d_i ~ sum_j w_j ((s_j+1)/2)^(i-2), i >= 2,
+//   w_j = -lam_j sin(pi beta) / (4 pi tau^beta), nodes for (1-s)^beta (1+s)^(1-beta).
+// BDF2 (3.14)-(3.16), real parts as in the remark after (3.16), i >= 3:
+//   family 1: ratio (s+1)/(s+5), w = -2^(2+2beta) cos(pi beta) sin(pi beta)/pi
+//             tau^-beta lam_j, dbar_i = (s+5)^-4 ratio^(i-3);
+//   family 2: ratio (s+1)/2, w = -2^(-beta-3) sin(pi beta)/pi tau^-beta lam_j,
+//             dbar_i = Re(1+3s)^beta ratio^(i-3);
+//   both with nodes for (1-s)^beta (1+s)^(2-2beta). Only lags i >= ns use the
+//   rule, so coef_j = w_j dbar_ns(s_j) multiplies ratio^(i-ns).
+void build_rule(int scheme, double beta, double tau, int np, int np1, int ns, FastRule& out) {
+    out.ratio.clear();
+    out.coef.clear();
+    const double sb = std::sin(M_PI * beta) / M_PI;
+    const double tb = std::pow(tau, -beta);
+    std::vector<double> s, lam;
+    if (scheme == 1) {
+        out.lag = 2;
+        gauss_jacobi(np, beta, 1.0 - beta, s, lam);
+        for (int j = 0; j < np; ++j) {
+            out.ratio.push_back(0.5 * (s[j] + 1.0));
+            out.coef.push_back(-lam[j] * sb * tb / 4.0);
+        }
+        return;
+    }
+    out.lag = ns;
+    gauss_jacobi(np1, beta, 2.0 - 2.0 * beta, s, lam);
+    const double c1 = -std::pow(2.0, 2.0 + 2.0 * beta) * std::cos(M_PI * beta) * sb * tb;
+    for (int j = 0; j < np1; ++j) {
+        const double r = (s[j] + 1.0) / (s[j] + 5.0);
+        const double dbar = std::pow(s[j] + 5.0, -4.0) * std::pow(r, double(ns - 3));
+        out.ratio.push_back(r);
+        out.coef.push_back(c1 * lam[j] * dbar);
+    }
+    gauss_jacobi(np, beta, 2.0 - 2.0 * beta, s, lam);
+    const double c2 = -std::pow(2.0, -beta - 3.0) * sb * tb;
+    for (int j = 0; j < np; ++j) {
+        const double r = 0.5 * (s[j] + 1.0);
+        const double u = 1.0 + 3.0 * s[j];
+        const double re = std::pow(std::fabs(u), beta) * (u >= 0.0 ? 1.0 : std::cos(M_PI * beta));
+        const double dbar = re * std::pow(r, double(ns - 3));
+        out.ratio.push_back(r);
+        out.coef.push_back(c2 * lam[j] * dbar);
+    }
+}
+
+double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N) {
+    const int64_t L = r.lag;
+    if (N < L) return 0.0;
+    std::vector<double> acc(size_t(N - L + 1), 0.0);
+    for (size_t j = 0; j < r.ratio.size(); ++j) {
+        double p = r.coef[j];
+        const double q = r.ratio[j];
+        for (int64_t i = L; i <= N; ++i) {
+            acc[size_t(i - L)] += p;
+            p *= q;
+        }
+    }
+    double m = 0.0;
+    for (int64_t i = L; i <= N; ++i) m = std::max(m, std::fabs(d[size_t(i)] - acc[size_t(i - L)]));
+    return m / std::fabs(d[0]);
+}
+
+int choose_rule(int scheme, double beta, double tau, int64_t N, double tol, int np_max, int np1,
+                int ns, FastRule& out) {
+    static const int ladder[] = {8,   12,  16,  24,  32,  48,  64,  96,  128, 160, 192,
+                                 256, 320, 384, 448, 512, 576, 640, 768, 896, 1024, 1280, 1536, 2048};
+    std::vector<double> d(size_t(N) + 1);
+    weights(scheme, beta, tau, N, d.data());
+    // fast-vs-direct error grows at most like C n max eps (Section 4); the
+    // factor 10 N keeps the measured solution error below tol
+    const double target = tol / (10.0 * double(std::max<int64_t>(N, 1)));
+    const int lag = (scheme == 1) ? 2 : ns;
+    if (N < lag) {  // the window covers every lag: no quadrature needed
+        build_rule(scheme, beta, tau, 1, scheme == 2 ? 1 : 0, ns, out);
+        out.max_eps = 0.0;
+        return CQ_OK;
+    }
+    for (int np : ladder) {
+        if (np > np_max) break;
+        build_rule(scheme, beta, tau, np, np1, ns, out);
+        out.max_eps = rule_error(out, d, N);
+        if (out.max_eps <= target) return CQ_OK;
+    }
+    return fail(CQ_ETOL, "fast rule: max|eps_i|/d_0 = %.3e > %.3e with np <= %d (beta=%g, N=%lld)", out.max_eps,
+                target, np_max, beta, (long long)N);
+}
+
+// ---------------------------------------------------------------------------
+void eig2(const double K[2][2], double theta[2], double V[2][2], double Vinv[2][2]) {
+    const double tr2 = 0.5 * (K[0][0] + K[1][1]);
+    const double df2 = 0.5 * (K[0][0] - K[1][1]);
+    const double off = K[0][1] * K[1][0];  // >= 0 here (= a^2)
+    const double rad = std::sqrt(std::max(0.0, df2 * df2 + off));
+    if (off == 0.0) {
+        theta[0] = K[0][0];
+        theta[1] = K[1][1];
+        V[0][0] = 1; V[0][1] = 0; V[1][0] = 0; V[1][1] = 1;
+        Vinv[0][0] = 1; Vinv[0][1] = 0; Vinv[1][0] = 0; Vinv[1][1] = 1;
+        return;
+    }
+    // theta0 pairs with component 1 when K11 <= K22 (keeps V near identity)
+    const double sgn = (df2 >= 0.0) ? 1.0 : -1.0;
+    theta[0] = tr2 + sgn * rad;  // closest to K11
+    theta[1] = tr2 - sgn * rad;  // closest to K22
+    // eigenvector for theta0: (theta0 - K22, K21); for theta1: (K12, theta1 - K11)
+    double v0x = theta[0] - K[1][1], v0y = K[1][0];
+    double v1x = K[0][1], v1y = theta[1] - K[0][0];
+    const double n0 = std::hypot(v0x, v0y), n1 = std::hypot(v1x, v1y);
+    v0x /= n0; v0y /= n0; v1x /= n1; v1y /= n1;
+    V[0][0] = v0x; V[1][0] = v0y;  // columns are eigenvectors
+    V[0][1] = v1x; V[1][1] = v1y;
+    const double det = V[0][0] * V[1][1] - V[0][1] * V[1][0];
+    Vinv[0][0] = V[1][1] / det;
+    Vinv[0][1] = -V[0][1] / det;
+    Vinv[1][0] = -V[1][0] / det;
+    Vinv[1][1] = V[0][0] / det;
+}
+
+}  // namespace cqfp

@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+The reference is the oracle's scheme evaluated mode by mode over every sine
+mode (oracle.modal.reference): the same numbers as the nodal oracle in exact
+arithmetic, but free of the nodal form's fp64 conditioning (on 1023 nodes the
+nodal fp64 oracle itself drifts by 1e-12..1e-9 from a long-double evaluation).
+Tolerances: direct CQ relative L2 <= 1e-12; fast CQ <= 1e-8 against the
+direct reference (the fast algorithm's stated accuracy) and <= 1e-11 against
+the oracle's fast scheme with the same node counts (the two Gauss-Jacobi rules
+are computed independently)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1901_05128_amd as cq  # noqa: E402
+from oracle import modal, stepper  # noqa: E402
+from oracle.weights import weights  # noqa: E402
+from paper_1901_05128_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cq.lib()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+# ---------------------------------------------------------------- cq_history
+@pytest.mark.parametrize("n,M", [(1, 7), (2, 5), (5, 1), (64, 63), (65, 65), (333, 1000), (1000, 129),
+                                 (4097, 64)])
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_cq_history_matches_oracle(n, M, scheme):
+    print(f"cq_history n={n} M={M} scheme={scheme}", flush=True)
+    rng = np.random.default_rng(n * 7 + M)
+    G = rng.uniform(-1, 1, size=(n, M))
+    beta, tau = 0.35, 1.0 / 1000
+    S = cq.cq_history(scheme, beta, tau, dev(G)).cpu().numpy()
+    d = weights(scheme, beta, tau, n)
+    ref = stepper.cq_history(d, G)
+    if n == 1:
+        assert np.all(S == 0.0)
+    else:
+        assert np.max(np.abs(S - ref)) <= 1e-13 * np.max(np.abs(d[1:])) * n
+
+
+# ---------------------------------------------------------------- small solves
+SMALL = [
+    # dim, nx, ny, alpha1, alpha2, m, T, N
+    (1, 127, 1, 0.3, 0.7, 0.3, 1.0, 1000),      # configuration 1 in full
+    (1, 1023, 1, 0.4, 0.8, 0.45, 1.0 / 32, 512),  # configuration 2's grid and tau, 512 steps
+    (1, 100, 1, 0.25, 0.55, 0.7, 1.0, 150),     # ragged tiles and blocks
+    (1, 1, 1, 0.5, 0.5, 0.2, 1.0, 7),
+    (2, 31, 17, 0.2, 0.6, 0.55, 1.0, 100),      # ragged 2D tiles
+    (2, 63, 63, 0.35, 0.65, 0.0, 1.0, 160),     # a = -1
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0]}d{c[1]}x{c[2]}N{c[7]}")
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("method", [0, 1])
+def test_solve_matches_oracle(case, scheme, method):
+    dim, nx, ny, a1, a2, m, T, N = case
+    print(f"solve case={case} scheme={scheme} method={method}", flush=True)
+    G0 = wl.g0_intervals(nx, 2) if dim == 1 else wl.g0_rectangle(nx, ny, 3)
+    if nx == 1:
+        G0 = np.array([[1.0], [0.5]])
+    g = cq.make_grid(dim, nx, ny)
+    p = cq.make_params(a1, a2, m, T, N, scheme, method)
+    with cq.Solver(g, p, dev(G0)) as s:
+        info = s.info()
+        s.step(N)
+        out, n = s.current()
+        out = out.cpu().numpy()
+    assert n == N
+    ref = modal.reference(dim, nx, ny, a1, a2, m, T, N, G0, scheme, 0)
+    e = rel(out, ref)
+    print(f"  rel_l2 vs direct reference {e:.3e}", flush=True)
+    if method == 0:
+        assert e <= 1e-12, e
+    else:
+        assert e <= 1e-8, e
+        if N > info.lag:
+            np_ = info.np_total - (16 if scheme == 2 else 0)
+            ref_f = modal.reference(dim, nx, ny, a1, a2, m, T, N, G0, scheme, 1, np_=np_, ns=30)
+            ef = rel(out, ref_f)
+            print(f"  rel_l2 vs fast reference {ef:.3e}", flush=True)
+            assert ef <= 1e-11
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_one_step_and_block_boundaries(method, dim):
+    """N = 1, and N straddling direct blocks (B = 64) step by step."""
+    nx, ny = (40, 1) if dim == 1 else (20, 9)
+    G0 = wl.g0_random(nx * ny, 4)
+    for N in (1, 2, 64, 65, 129):
+        print(f"blocks dim={dim} method={method} N={N}", flush=True)
+        p = cq.make_params(0.45, 0.55, 0.65, 0.5, N, 2, method, block_B=64)
+        out = cq.fp_solve(cq.make_grid(dim, nx, ny), p, dev(G0)).cpu().numpy()
+        ref = modal.reference(dim, nx, ny, 0.45, 0.55, 0.65, 0.5, N, G0, 2, 0)
+        assert rel(out, ref) <= (1e-12 if method == 0 else 1e-8)
+
+
+@pytest.mark.parametrize("block_B", [64, 128, 192, 256])
+def test_direct_block_sizes(block_B):
+    nx, N = 70, 300
+    G0 = wl.g0_random(nx, 8)
+    p = cq.make_params(0.3, 0.6, 0.8, 1.0, N, 1, 0, block_B=block_B)
+    out = cq.fp_solve(cq.make_grid(1, nx), p, dev(G0)).cpu().numpy()
+    ref = modal.reference(1, nx, 1, 0.3, 0.6, 0.8, 1.0, N, G0, 1, 0)
+    assert rel(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_state_roundtrip_is_bitwise(method, dim):
+    nx, ny = (50, 1) if dim == 1 else (12, 10)
+    N, k = 140, 77
+    G0 = wl.g0_random(nx * ny, 12)
+    g, p = cq.make_grid(dim, nx, ny), cq.make_params(0.3, 0.7, 0.6, 1.0, N, 2, method, block_B=64)
+    with cq.Solver(g, p, dev(G0)) as s:
+        s.step(N)
+        full = s.current()[0].cpu().numpy()
+    with cq.Solver(g, p, dev(G0)) as s:
+        s.step(k)
+        state = s.get_state()
+    with cq.Solver(g, p, dev(np.zeros_like(G0))) as s2:
+        s2.set_state(state)
+        s2.step(N - k)
+        resumed = s2.current()[0].cpu().numpy()
+    assert np.array_equal(full, resumed)
+
+
+def test_nonfinite_g0_rejected():
+    G0 = np.zeros((2, 9))
+    G0[1, 3] = np.nan
+    with pytest.raises(cq.CQError) as e:
+        cq.Solver(cq.make_grid(1, 9), cq.make_params(0.3, 0.7, 0.3, 1.0, 4, 1, 0), dev(G0))
+    assert e.value.code == -6
+
+
+def test_step_past_end_rejected():
+    with cq.Solver(cq.make_grid(1, 9), cq.make_params(0.3, 0.7, 0.3, 1.0, 4, 1, 0), dev(np.ones((2, 9)))) as s:
+        s.step(3)
+        with pytest.raises(cq.CQError):
+            s.step(2)
