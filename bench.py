@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Throughput of the CQ Fokker-Planck solver on one MI355X.
+
+One bench step = one full solve (all N time steps, inputs resident in HBM) of
+every variant of the workload: BE and BDF2, each with the fast history and
+with the direct (blocked Toeplitz) history. The value is whole-job
+DOF*steps/s (DOF = 2 components x grid nodes) over all variants; per-variant
+rates, the fast-vs-direct difference, the dominant kernel's roofline and the
+CPU oracle's rate on a bounded sample are reported beside it.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload c2|c3|c1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and MFMA)
+
+WORKLOADS = {
+    # name: (description, dim, nx, ny, alpha1, alpha2, m, T, N, seed)
+    "c1": ("1D 127 nodes, N=1000", 1, 127, 1, 0.3, 0.7, 0.3, 1.0, 1000, 1),
+    "c2": ("1D 1023 nodes, N=2^14", 1, 1023, 1, 0.4, 0.8, 0.45, 1.0, 2 ** 14, 2),
+    "c3": ("2D 255x255 nodes, N=2^16", 2, 255, 255, 0.2, 0.6, 0.55, 1.0, 2 ** 16, 3),
+}
+VARIANTS = [(1, 1), (1, 0), (2, 1), (2, 0)]  # (scheme, method)
+VNAME = {(1, 1): "be_fast", (1, 0): "be_direct", (2, 1): "bdf2_fast", (2, 0): "bdf2_direct"}
+
+
+def g0_for(w):
+    from paper_1901_05128_amd import workloads as wl
+    _, dim, nx, ny, *_rest, seed = w
+    if nx == 127 and dim == 1:
+        return wl.g0_c1(nx, seed)
+    return wl.g0_intervals(nx, seed) if dim == 1 else wl.g0_rectangle(nx, ny, seed)
+
+
+def kernel_work(kind, w, scheme, method, info, M):
+    """Algorithmic (bytes, flops) summed over the launches of one solve."""
+    N = w[8]
+    twoM = 2 * M
+    if method == 1 and kind in ("hist_direct", "far_toeplitz"):
+        return 0, 0
+    if method == 0 and kind == "hist_fast":
+        return 0, 0
+    if kind == "hist_fast":
+        L, npn = info.lag, info.np_total
+        b = 0
+        for n in range(1, N + 1):
+            terms = min(L - 1, n - 1)
+            b += twoM * 8 * (terms + 1)                 # window reads + S write
+            if n >= L + 1:
+                b += twoM * (16 * npn + 8)              # state read+write, G^{n-L}
+        return b, 0
+    if kind == "far_toeplitz":
+        B = info.block_B
+        fl, by = 0, 0
+        for n0 in range(B, N, B):
+            fl += 2 * B * n0 * twoM
+            by += n0 * twoM * 8 + B * twoM * 8
+        return by, fl
+    if kind == "hist_direct":
+        B = info.block_B
+        by = 0
+        for n in range(1, N + 1):
+            n0 = ((n - 1) // B) * B
+            by += twoM * 8 * ((n - 1 - n0) + 1 + (1 if n0 >= 1 else 0))
+        return by, 0
+    if kind == "dst_gemm":
+        nx, ny = w[2], w[3]
+        return 0, N * 2 * (2 * ny * nx * nx + 2 * ny * ny * nx) * 2
+    if kind == "solve_1d":
+        return N * twoM * 8 * 4, 0
+    if kind == "prep_2d":
+        return N * twoM * 8 * 5, 0
+    return 0, 0
+
+
+def cpu_baseline(w, seconds_target=20.0):
+    """The oracle (nodal direct and fast steppers) on the first steps of the
+    same workload: same grid, tau and data, N_sample < N steps."""
+    import numpy as np
+    from oracle import stepper
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    desc, dim, nx, ny, a1, a2, m, T, N, seed = w
+    G0 = g0_for(w)
+    tau = T / N
+    M = nx * ny
+    ns = 64
+    done_dofsteps, spent = 0, 0.0
+    while True:
+        t0 = time.perf_counter()
+        for scheme, method in VARIANTS:
+            stepper.solve(dim, nx, ny, a1, a2, m, ns * tau, ns, G0, scheme, method,
+                          np_=(None if method == 0 else max(16, int(3 * N ** 0.5))), ns=30)
+        dt = time.perf_counter() - t0
+        done_dofsteps, spent = 4 * 2 * M * ns, dt
+        if dt * 2 > seconds_target or 2 * ns > N:
+            break
+        ns *= 2
+    return {"value": done_dofsteps / spent, "unit": "DOF*steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"first {ns} of the {N} steps of {desc} (same tau and G0), BE+BDF2 x direct+fast, "
+                      f"numpy/scipy fp64, {spent:.1f} s; the direct form's per-step cost grows with n, so "
+                      f"this overstates the oracle's full-run rate"}
+
+
+def load_traffic(kernel_name):
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary, or
+    None when it is missing or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1901_05128_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        ent = rec.get(kernel_name)
+        if not ent or ent.get("kernels_hip_sha256") != sha:
+            return None
+        return ent.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--variants", default="all", help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prof", action="store_true", help="do not time kernels with events")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this solver has no multi-GPU path "
+              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1901_05128_amd as cq
+
+    w = WORKLOADS[args.workload]
+    desc, dim, nx, ny, a1, a2, m, T, N, seed = w
+    M = nx * ny
+    variants = VARIANTS if args.variants == "all" else \
+        [v for v in VARIANTS if VNAME[v] in args.variants.split(",")]
+    torch.cuda.set_device(0)
+    G0 = torch.tensor(g0_for(w), dtype=torch.float64, device="cuda")
+    grid = cq.make_grid(dim, nx, ny)
+    solvers = {}
+    for v in variants:
+        solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1]), G0)
+    outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
+
+    def one_step(events=None):
+        for v in variants:
+            s = solvers[v]
+            if events is not None:
+                events[v][0].record()
+            s.reset(G0)
+            s.step(N)
+            s.current(outs[v])
+            if events is not None:
+                events[v][1].record()
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    if not args.no_prof:
+        cq.prof_enable(True)
+    ev = {v: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)] for v in variants}
+    per_var_ms = {v: 0.0 for v in variants}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step({v: ev[v][k] for v in variants})
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for v in variants:
+        per_var_ms[v] = sum(a.elapsed_time(b) for a, b in ev[v]) / args.steps
+    elapsed = t1 - t0
+    dofsteps = args.steps * len(variants) * 2 * M * N
+    value = dofsteps / elapsed
+
+    # kernel timing and roofline of the dominant kernel
+    kinds = ["hist_fast", "hist_direct", "far_toeplitz", "solve_1d", "prep_2d", "dst_gemm"]
+    ktime = {}
+    if not args.no_prof:
+        for kname in kinds:
+            n_l, ms = cq.prof_read(kname)
+            if n_l:
+                ktime[kname] = (n_l, ms)
+        cq.prof_enable(False)
+    roofline = None
+    if ktime:
+        dom = max(ktime, key=lambda k: ktime[k][1])
+        n_l, ms = ktime[dom]
+        tot_b, tot_f = 0, 0
+        for v in variants:
+            info = solvers[v].info()
+            b, f = kernel_work(dom, w, v[0], v[1], info, M)
+            tot_b += b * args.steps
+            tot_f += f * args.steps
+        avg_s = ms / 1e3 / n_l
+        if tot_f > 0:
+            ach = tot_f / n_l / avg_s / 1e12
+            roofline = {"bound": "mfma" if dom in ("far_toeplitz", "dst_gemm") else "alu", "achieved": ach,
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS}
+        else:
+            ach = tot_b / n_l / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS}
+        roofline["kernel"] = dom
+        roofline["avg_launch_us"] = avg_s * 1e6
+        roofline["launches"] = n_l
+        roofline["traffic"] = load_traffic(dom)
+
+    # fast vs direct on the GPU (the metric's accuracy side)
+    fvd = {}
+    for scheme in (1, 2):
+        if (scheme, 1) in outs and (scheme, 0) in outs:
+            f, d = outs[(scheme, 1)], outs[(scheme, 0)]
+            fvd[f"scheme{scheme}"] = float(torch.linalg.norm(f - d) / torch.linalg.norm(d))
+
+    info_np = {VNAME[v]: solvers[v].info().np_total for v in variants if v[1] == 1}
+    breakdown = {VNAME[v]: {"ms": per_var_ms[v], "dofsteps_per_s": 2 * M * N / (per_var_ms[v] / 1e3)}
+                 for v in variants}
+    for s in solvers.values():
+        s.close()
+
+    rec = {
+        "metric": "DOF*steps/s (fast and direct CQ solves)",
+        "value": value,
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded indicator initial data)",
+        "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
+                   "variants": [VNAME[v] for v in variants], "dof": 2 * M, "N": N,
+                   "fast_nodes": info_np},
+        "breakdown": breakdown,
+        "fast_vs_direct_rel_l2": fvd,
+        "kernels_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in ktime.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

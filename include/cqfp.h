@@ -158,6 +158,11 @@ int fp_info(void* handle, cq_info* info);
 int fp_get_state(void* handle, void* dst, size_t* bytes);
 int fp_set_state(void* handle, const void* src, size_t bytes);
 
+/* Restart the handle at n = 0 from a new G0 (dev [2][M], copied): clears
+ * the compressed history and the level store on the device, reusing every
+ * buffer (allocates nothing). Asynchronous on the handle's stream. */
+int fp_reset(void* handle, const double* G0);
+
 /* Release a handle and all its device memory. NULL is accepted. */
 int fp_destroy(void* handle);
 
@@ -165,6 +170,17 @@ int fp_destroy(void* handle);
  * destroy. Synchronises the stream. */
 int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double* GN,
              void* hip_stream);
+
+/* Kernel timing (opt-in). While enabled, every kernel launch of the library
+ * is bracketed by a pair of HIP events on the stream it runs on. The kernels
+ * are grouped by kind: 0 fast history, 1 direct near field, 2 Toeplitz far
+ * field (FP64 MFMA), 3 1D right-hand side + PCR solve, 4 2D right-hand side,
+ * 5 DST GEMM (forward/inverse and per-mode solve), 6 standalone history
+ * reduction. cq_prof_read synchronises the recorded events and returns, for
+ * one kind, the launch count and the summed duration in milliseconds.
+ * cq_prof_enable(1) also clears earlier records. Not thread safe. */
+int cq_prof_enable(int32_t on);
+int cq_prof_read(int32_t kind, int64_t* launches, double* total_ms);
 
 /* Message describing the last failure on this thread ("" if none). */
 const char* cq_last_error(void);

@@ -22,7 +22,10 @@ STATUS_NAMES = {0: "CQ_OK", -1: "CQ_EINVAL", -2: "CQ_ESINGULAR", -3: "CQ_ENOMEM"
 
 # every entry point the header declares
 EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "fp_current", "fp_info",
-           "fp_get_state", "fp_set_state", "fp_destroy", "fp_solve", "cq_last_error"]
+           "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "cq_prof_enable", "cq_prof_read",
+           "cq_last_error"]
+PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
+              "reduce_row": 6}
 
 
 class CQError(RuntimeError):
@@ -73,7 +76,10 @@ def lib() -> C.CDLL:
     L.fp_info.argtypes = [VP, P(Info)]
     L.fp_get_state.argtypes = [VP, VP, P(C.c_size_t)]
     L.fp_set_state.argtypes = [VP, VP, C.c_size_t]
+    L.fp_reset.argtypes = [VP, VP]
     L.fp_destroy.argtypes = [VP]
+    L.cq_prof_enable.argtypes = [I32]
+    L.cq_prof_read.argtypes = [I32, P(I64), P(D)]
     L.fp_solve.argtypes = [P(Grid), P(Params), VP, VP, VP]
     L.cq_last_error.argtypes = []
     L.cq_last_error.restype = C.c_char_p
@@ -182,6 +188,9 @@ class Solver:
         buf = C.create_string_buffer(state, len(state))
         _check(lib().fp_set_state(self._h, buf, len(state)))
 
+    def reset(self, G0):
+        _check(lib().fp_reset(self._h, _dev(G0, "G0")))
+
     def close(self):
         if self._h:
             _check(lib().fp_destroy(self._h))
@@ -198,6 +207,18 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def prof_enable(on: bool = True):
+    _check(lib().cq_prof_enable(1 if on else 0))
+
+
+def prof_read(kind) -> tuple:
+    """(launches, total_ms) for a kernel kind (name or number)."""
+    k = PROF_KINDS[kind] if isinstance(kind, str) else int(kind)
+    n, ms = C.c_int64(), C.c_double()
+    _check(lib().cq_prof_read(k, C.byref(n), C.byref(ms)))
+    return n.value, ms.value
 
 
 def fp_solve(grid: Grid, params: Params, G0, GN=None):

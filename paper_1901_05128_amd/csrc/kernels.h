@@ -93,4 +93,8 @@ void launch_prep_2d(const Prep2DArgs& a, hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, hipStream_t st);
 const void* kernel_solve_1d();
 
+// kernel timing (runtime.cpp): no-ops unless cq_prof_enable(1)
+void prof_begin(int kind, hipStream_t st);
+void prof_end(int kind, hipStream_t st);
+
 }  // namespace cqfp

@@ -424,15 +424,19 @@ __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launchers (optionally bracketed by timing events, see prof_begin/prof_end)
 void launch_hist_fast(const HistFastArgs& a, int nsplit, hipStream_t st) {
     dim3 grid(unsigned((a.M + 255) / 256), unsigned(nsplit), 2);
+    prof_begin(0, st);
     hipLaunchKernelGGL(k_hist_fast, grid, dim3(256), 0, st, a);
+    prof_end(0, st);
 }
 
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st) {
     dim3 grid(unsigned((a.M + 255) / 256), 1, 2);
+    prof_begin(1, st);
     hipLaunchKernelGGL(k_hist_direct, grid, dim3(256), 0, st, a);
+    prof_end(1, st);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_row(const double* __restrict__ F, int ks, int B, int64_t M,
@@ -445,36 +449,46 @@ __global__ __launch_bounds__(256) void k_reduce_row(const double* __restrict__ F
 }
 
 void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st) {
+    prof_begin(6, st);
     hipLaunchKernelGGL(k_reduce_row, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, F, ks, B, M, out);
+    prof_end(6, st);
 }
 
 void launch_far(const FarArgs& a, hipStream_t st) {
     dim3 grid(unsigned((a.M + 63) / 64), unsigned(a.ks), unsigned(a.ncomp));
+    prof_begin(2, st);
     switch (a.B / 64) {
         case 1: hipLaunchKernelGGL(k_far_toeplitz<1>, grid, dim3(256), 0, st, a); break;
         case 2: hipLaunchKernelGGL(k_far_toeplitz<2>, grid, dim3(256), 0, st, a); break;
         case 3: hipLaunchKernelGGL(k_far_toeplitz<3>, grid, dim3(256), 0, st, a); break;
         default: hipLaunchKernelGGL(k_far_toeplitz<4>, grid, dim3(256), 0, st, a); break;
     }
+    prof_end(2, st);
 }
 
 void launch_solve_1d(const Solve1DArgs& a, size_t lds, hipStream_t st) {
+    prof_begin(3, st);
     hipLaunchKernelGGL(k_solve_1d, dim3(1), dim3(kNT1D), lds, st, a);
+    prof_end(3, st);
 }
 
 void launch_prep_2d(const Prep2DArgs& a, hipStream_t st) {
     dim3 grid(unsigned((a.M + 255) / 256), 2);
+    prof_begin(4, st);
     hipLaunchKernelGGL(k_prep_2d, grid, dim3(256), 0, st, a);
+    prof_end(4, st);
 }
 
 void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
     dim3 grid(unsigned((a.C + 15) / 16), unsigned((a.R + 15) / 16));
+    prof_begin(5, st);
     if (epi == 1)
         hipLaunchKernelGGL(k_dst_gemm<1>, grid, dim3(256), 0, st, a);
     else if (epi == 2)
         hipLaunchKernelGGL(k_dst_gemm<2>, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_dst_gemm<0>, grid, dim3(256), 0, st, a);
+    prof_end(5, st);
 }
 
 const void* kernel_solve_1d() { return reinterpret_cast<const void*>(&k_solve_1d); }

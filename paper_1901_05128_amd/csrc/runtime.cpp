@@ -410,7 +410,68 @@ size_t state_bytes(const Solver& s) {
 
 }  // namespace
 
+// ---- kernel timing ----
+namespace {
+constexpr int kProfKinds = 7;
+struct ProfRec {
+    hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_open[kProfKinds];
+std::vector<ProfRec> g_prof_done[kProfKinds];
+}  // namespace
+
+namespace cqfp {
+void prof_begin(int kind, hipStream_t st) {
+    if (!g_prof_on) return;
+    ProfRec r{};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, st);
+    g_prof_open[kind].push_back(r);
+}
+void prof_end(int kind, hipStream_t st) {
+    if (!g_prof_on || g_prof_open[kind].empty()) return;
+    ProfRec r = g_prof_open[kind].back();
+    g_prof_open[kind].pop_back();
+    (void)hipEventRecord(r.b, st);
+    g_prof_done[kind].push_back(r);
+}
+}  // namespace cqfp
+
+static void prof_clear() {
+    for (int k = 0; k < kProfKinds; ++k) {
+        for (auto& r : g_prof_done[k]) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        g_prof_done[k].clear();
+        g_prof_open[k].clear();
+    }
+}
+
 extern "C" {
+
+int cq_prof_enable(int32_t on) {
+    clear_error();
+    prof_clear();
+    g_prof_on = on != 0;
+    return CQ_OK;
+}
+
+int cq_prof_read(int32_t kind, int64_t* launches, double* total_ms) {
+    clear_error();
+    if (kind < 0 || kind >= kProfKinds || !launches || !total_ms) return fail(CQ_EINVAL, "bad kind or NULL output");
+    double tot = 0.0;
+    for (auto& r : g_prof_done[kind]) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        tot += ms;
+    }
+    *launches = int64_t(g_prof_done[kind].size());
+    *total_ms = tot;
+    return CQ_OK;
+}
 
 int cq_weights(int32_t scheme, double beta, double tau, int64_t n, double* d_out) {
     clear_error();
@@ -654,6 +715,21 @@ int fp_set_state(void* handle, const void* src, size_t bytes) {
         HIPCHK(hipMemcpy(s.H, q + b1, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), hipMemcpyHostToDevice));
     }
     HIPCHK(hipGetLastError());
+    return CQ_OK;
+}
+
+int fp_reset(void* handle, const double* G0) {
+    clear_error();
+    if (!handle || !G0) return fail(CQ_EINVAL, "NULL argument");
+    Solver& s = *static_cast<Solver*>(handle);
+    const int64_t twoM = 2 * s.M;
+    int rc = check_finite_g0(G0, twoM, s.st);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    HIPCHK(hipMemcpyAsync(s.levels, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    if (s.H) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
+    s.n = 0;
+    s.n0 = 0;
     return CQ_OK;
 }
 
