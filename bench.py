@@ -50,14 +50,16 @@ def kernel_work(kind, w, scheme, method, info, M):
     if method == 0 and kind == "hist_fast":
         return 0, 0
     if kind == "hist_fast":
-        L, npn = info.lag, info.np_total
-        b = 0
-        for n in range(1, N + 1):
-            terms = min(L - 1, n - 1)
-            b += twoM * 8 * (terms + 1)                 # window reads + S write
-            if n >= L + 1:
-                b += twoM * (16 * npn + 8)              # state read+write, G^{n-L}
-        return b, 0
+        # one launch per block of bt steps: state read + write once, the bt
+        # levels entering the state, bt history values out; 2 FMAs per node
+        # per step
+        L, npn, Bt = info.lag, info.np_total, info.block_B
+        b, f = 0, 0
+        for n in range(1, N + 1, Bt):
+            bt = min(Bt, N - n + 1)
+            b += twoM * 8 * (2 * npn + 2 * bt)
+            f += twoM * 4 * npn * bt
+        return b, f
     if kind == "far_toeplitz":
         B = info.block_B
         fl, by = 0, 0
@@ -75,10 +77,10 @@ def kernel_work(kind, w, scheme, method, info, M):
     if kind == "dst_gemm":
         nx, ny = w[2], w[3]
         return 0, N * 2 * (2 * ny * nx * nx + 2 * ny * ny * nx) * 2
-    if kind == "solve_1d":
-        return N * twoM * 8 * 4, 0
-    if kind == "prep_2d":
-        return N * twoM * 8 * 5, 0
+    if kind in ("solve_1d", "prep_2d"):
+        # window of exact weights (fast) or the partial sums, G^{n-1}, G^{n-2}, G0, output
+        win = (info.lag - 1) if method == 1 else 1
+        return N * twoM * 8 * (win + 5), 0
     return 0, 0
 
 
@@ -215,14 +217,17 @@ def main():
             tot_b += b * args.steps
             tot_f += f * args.steps
         avg_s = ms / 1e3 / n_l
-        if tot_f > 0:
+        f_frac = (tot_f / n_l / avg_s / 1e12) / FP64_PEAK_TFLOPS if tot_f else 0.0
+        b_frac = (tot_b / n_l / avg_s / 1e9) / HBM_PEAK_GBS if tot_b else 0.0
+        if f_frac >= b_frac:
             ach = tot_f / n_l / avg_s / 1e12
             roofline = {"bound": "mfma" if dom in ("far_toeplitz", "dst_gemm") else "alu", "achieved": ach,
-                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS}
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                        "hbm_frac": b_frac}
         else:
             ach = tot_b / n_l / avg_s / 1e9
             roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": ach / HBM_PEAK_GBS}
+                        "frac": ach / HBM_PEAK_GBS, "fp64_frac": f_frac}
         roofline["kernel"] = dom
         roofline["avg_launch_us"] = avg_s * 1e6
         roofline["launches"] = n_l

@@ -91,7 +91,7 @@ typedef struct {
     int32_t lag;          /* first lag covered by the fast rule (2 or N_s)    */
     double max_eps;       /* max_i |eps_i| / d_0 over both components          */
     double theta[2];      /* eigenvalues of the 2x2 step coupling matrix       */
-    int32_t block_B;      /* direct: time-block length                        */
+    int32_t block_B;      /* time-block length (direct far field / fast state) */
     int32_t ksplit;       /* direct: K-split of the far-field update           */
     size_t device_bytes;  /* device memory held by the handle                 */
     size_t state_bytes;   /* bytes of fp_get_state                            */

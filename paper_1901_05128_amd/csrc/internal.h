@@ -33,6 +33,8 @@ struct FastRule {
 
 // Build the rule for a given node count (np for BE, np1 + np2 for BDF2).
 void build_rule(int scheme, double beta, double tau, int np, int np1, int ns, FastRule& out);
+// Start the geometric families at a later lag (coef_j *= r_j^(lag - old lag)).
+void shift_lag(FastRule& r, int lag);
 // max_{lag <= i <= N} |d_i - sum_j coef_j r_j^(i-lag)| / |d_0|
 double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N);
 // Node-count scan; returns CQ_OK or CQ_ETOL.

@@ -7,20 +7,21 @@
 
 namespace cqfp {
 
-struct HistFastArgs {
-    int64_t n;            // step being computed (>= 1)
-    int64_t L;            // lag of the first quadrature term (2 or N_s)
-    int64_t Lr;           // slots in the level store
+struct HistBlockArgs {
+    int64_t n;            // first step of the block (>= 1)
+    int64_t L;            // lag of the first quadrature term
+    int64_t Lr;           // slots in the level store (>= L)
     int64_t M;            // nodes per component
     int np;               // fast nodes per component
     int chunk;            // nodes per blockIdx.y slice
-    int64_t dstride;      // stride between the two components' weights
+    int BT;               // template block length (>= bt)
+    int bt;               // steps in this block (<= L)
+    int64_t slot0;        // slot of level n - L: (n - L) mod Lr, in [0, Lr)
     const double* levels; // [Lr][2][M]
     double* H;            // [2][np][M]
     const double* ratio;  // [2][np]
     const double* coef;   // [2][np]
-    const double* d;      // [2][dstride]
-    double* Spart;        // [nsplit][2][M]
+    double* Sf;           // [nsplit][BT][2][M]
 };
 
 struct HistDirectArgs {
@@ -29,7 +30,7 @@ struct HistDirectArgs {
     int B, ks;
     const double* levels;  // [N+1][2][M]
     const double* d;       // [2][dstride]
-    const double* F;       // [ks][B][2][M]
+    const double* F;       // [B][2][M] (slice 0 of the reduced far field)
     double* Spart;         // [1][2][M]
 };
 
@@ -37,36 +38,38 @@ struct FarArgs {
     int64_t n0, M, mchunk, dstride;
     int64_t lstride;       // elements between time levels (2M for a solver)
     int B, ks, ncomp;      // ncomp components (blockIdx.z), offset M apart
+    int reduce;            // also sum the ks partials into slice 0
     const double* levels;  // level l of component k at levels[l*lstride + k*M]
     const double* d;       // [ncomp][dstride], dstride >= n0 + B + 1
     double* F;             // [ks][B][ncomp][M]
 };
 
-struct Solve1DArgs {
-    int64_t n, M, Mpad, Lr;
-    int nsplit, scheme;
-    double inv_tau, cdiag, h2;
-    double inv_d0[2];     // 1/d_k,0
+// Per-step right-hand side (and, in 1D, the step solve).
+struct StepArgs {
+    int64_t n, M, Lr;
+    int64_t slot1, slot2, slot_out;  // slots of levels n-1, max(n-2,0) and n
+    int scheme;
+    // history: S' = sum_c Sp[c*pstride + boff + k*M + x] + sum_{i<=win} d_i G^{n-i} + corr_k G0
+    const double* Sp;
+    int nsplit;
+    int64_t pstride, boff;
+    int win;
+    const double* d;      // [2][dstride]
+    int64_t dstride;
     double corr[2];       // BDF2: d_k,n-1 / 2; BE: 0
-    double diag[2];       // fl(2 + delta_k)
-    double delta[2];      // delta_k = theta_k h^2
-    double V[4], Vinv[4]; // row-major 2x2
-    const double* Spart;  // [nsplit][2][M]
     const double* G0;     // [2][M]
     double* levels;       // [Lr][2][M]
-};
-
-struct Prep2DArgs {
-    int64_t n, Lr, M;
-    int nsplit, scheme;
     double inv_tau, cdiag;
-    double inv_d0[2];
-    double corr[2];
-    const double* Spart;
-    const double* G0;
-    const double* levels;
-    double* w;  // [2][M]  E + c S'/d0
-    double* q;  // [2][M]  S'/d0
+    double inv_d0[2];     // 1/d_k,0
+    // 1D solve
+    double h2;
+    double delta[2];      // delta_k = theta_k h^2
+    int levels_pcr;       // ceil(log2 M)
+    const double *PF, *PG, *PRB;  // PCR multipliers (k_pcr_setup)
+    double V[4], Vinv[4]; // row-major 2x2
+    // 2D outputs
+    double* w;            // [2][M]  E + c S'/d0
+    double* q;            // [2][M]  S'/d0
 };
 
 struct GemmArgs {
@@ -83,15 +86,15 @@ struct GemmArgs {
     const double *sub0, *sub1;
 };
 
-void launch_hist_fast(const HistFastArgs& a, int nsplit, hipStream_t st);
+void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);
 // out[x] = sum_q F[q][0][0][x] (one history row of a single component)
 void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st);
-void launch_solve_1d(const Solve1DArgs& a, size_t lds, hipStream_t st);
-void launch_prep_2d(const Prep2DArgs& a, hipStream_t st);
+void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st);
+void launch_prep_2d(const StepArgs& a, hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, hipStream_t st);
-const void* kernel_solve_1d();
+const void* kernel_step_1d(int R);
 
 // kernel timing (runtime.cpp): no-ops unless cq_prof_enable(1)
 void prof_begin(int kind, hipStream_t st);

@@ -25,58 +25,73 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 }
 
 // ---------------------------------------------------------------------------
-// Fast history (3.10)/(3.18), one component per blockIdx.z, a slice of nodes
-// per blockIdx.y. For lag L, the state H_j(n) = sum_{l=1}^{n-L} r_j^(n-L-l) G^l
-// obeys H_j(n) = r_j H_j(n-1) + G^{n-L} (n >= L+1, H_j(L) = 0), and
-//   S = sum_{i=1}^{min(L-1,n-1)} d_i G^{n-i} + sum_j coef_j H_j(n).
-// Layout H[2][np][M] (node-major: a wave streams 64 consecutive DOFs of one
-// node); the per-node ratio and coefficient are wave-uniform scalars.
-__global__ __launch_bounds__(256) void k_hist_fast(HistFastArgs p) {
+// Fast history (3.10)/(3.18), time-blocked. For lag L the state
+//   H_j(m) = sum_{l=1}^{m-L} r_j^(m-L-l) G^l,   H_j(m) = r_j H_j(m-1) + G^{m-L},
+// and the fast part of the history sum is S_f(m) = sum_j coef_j H_j(m).
+// H_j(m) only involves levels up to m-L, so for the BT steps m = n..n+BT-1
+// (BT <= L) every level it needs is known before step n is solved. One pass
+// over the state therefore advances it by BT steps and emits S_f for all of
+// them: the state (the bulk of the bytes) is read and written once per BT
+// steps instead of once per step. blockIdx.z = component, blockIdx.y = slice
+// of the nodes (partial sums), one DOF per thread; H is [2][np][M] so a wave
+// streams 64 consecutive DOFs of one node; r_j and coef_j are wave-uniform.
+// Output Sf[slice][b][k][x].
+template <int BT>
+__global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
     const int k = blockIdx.z;
     const int c = blockIdx.y;
     const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (x >= p.M) return;
     const int64_t twoM = 2 * p.M;
     const double* __restrict__ lv = p.levels + int64_t(k) * p.M + x;
-    double S = 0.0;
-    if (c == 0) {
-        const int64_t top = (p.n - 1 < p.L - 1) ? p.n - 1 : p.L - 1;
-        const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
-        for (int64_t i = 1; i <= top; ++i) {
-            const int64_t slot = (p.n - i) % p.Lr;
-            S = fma(dk[i], lv[slot * twoM], S);
-        }
+    double g[BT], acc[BT];
+#pragma unroll
+    for (int b = 0; b < BT; ++b) {
+        const int64_t l = p.n + b - p.L;  // level entering the state at step n+b
+        int64_t sl = p.slot0 + b;         // its slot: (n - L + b) mod Lr
+        if (sl >= p.Lr) sl -= p.Lr;
+        g[b] = (b < p.bt && l >= 1) ? lv[sl * twoM] : 0.0;
+        acc[b] = 0.0;
     }
-    if (p.n >= p.L + 1) {
-        const double g = lv[((p.n - p.L) % p.Lr) * twoM];
-        const int j0 = c * p.chunk;
-        const int j1 = (j0 + p.chunk < p.np) ? j0 + p.chunk : p.np;
-        double* __restrict__ h = p.H + (int64_t(k) * p.np) * p.M + x;
-        const double* __restrict__ r = p.ratio + k * p.np;
-        const double* __restrict__ w = p.coef + k * p.np;
-        double S2 = 0.0;
-        int j = j0;
+    const int j0 = c * p.chunk;
+    const int j1 = (j0 + p.chunk < p.np) ? j0 + p.chunk : p.np;
+    double* __restrict__ h = p.H + (int64_t(k) * p.np) * p.M + x;
+    const double* __restrict__ r = p.ratio + k * p.np;
+    const double* __restrict__ w = p.coef + k * p.np;
+    int j = j0;
+    // two nodes per iteration: independent recurrences interleave
 #pragma unroll 1
-        for (; j + 8 <= j1; j += 8) {
-            double v[8];
+    for (; j + 2 <= j1; j += 2) {
+        double h0 = __builtin_nontemporal_load(h + int64_t(j) * p.M);
+        double h1 = __builtin_nontemporal_load(h + int64_t(j + 1) * p.M);
+        const double r0 = r[j], r1 = r[j + 1], w0 = w[j], w1 = w[j + 1];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(h + int64_t(j + u) * p.M);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                v[u] = fma(r[j + u], v[u], g);
-                __builtin_nontemporal_store(v[u], h + int64_t(j + u) * p.M);
-                S2 = fma(w[j + u], v[u], S2);
+        for (int b = 0; b < BT; ++b) {
+            if (b < p.bt) {
+                h0 = fma(r0, h0, g[b]);
+                h1 = fma(r1, h1, g[b]);
+                acc[b] = fma(w0, h0, acc[b]);
+                acc[b] = fma(w1, h1, acc[b]);
             }
         }
-        for (; j < j1; ++j) {
-            double v = h[int64_t(j) * p.M];
-            v = fma(r[j], v, g);
-            h[int64_t(j) * p.M] = v;
-            S2 = fma(w[j], v, S2);
-        }
-        S += S2;
+        __builtin_nontemporal_store(h0, h + int64_t(j) * p.M);
+        __builtin_nontemporal_store(h1, h + int64_t(j + 1) * p.M);
     }
-    p.Spart[(int64_t(c) * 2 + k) * p.M + x] = S;
+    for (; j < j1; ++j) {
+        double h0 = h[int64_t(j) * p.M];
+        const double r0 = r[j], w0 = w[j];
+#pragma unroll
+        for (int b = 0; b < BT; ++b) {
+            if (b < p.bt) {
+                h0 = fma(r0, h0, g[b]);
+                acc[b] = fma(w0, h0, acc[b]);
+            }
+        }
+        h[int64_t(j) * p.M] = h0;
+    }
+#pragma unroll
+    for (int b = 0; b < BT; ++b)
+        if (b < p.bt) p.Sf[((int64_t(c) * BT + b) * 2 + k) * p.M + x] = acc[b];
 }
 
 // ---------------------------------------------------------------------------
@@ -89,15 +104,31 @@ __global__ __launch_bounds__(256) void k_hist_direct(HistDirectArgs p) {
     if (x >= p.M) return;
     const int64_t twoM = 2 * p.M;
     double S = 0.0;
-    if (p.n0 >= 1) {
-        const int64_t b = p.n - p.n0 - 1;
-        for (int q = 0; q < p.ks; ++q) S += p.F[((int64_t(q) * p.B + b) * 2 + k) * p.M + x];
-    }
+    if (p.n0 >= 1) S = p.F[(int64_t(p.n - p.n0 - 1) * 2 + k) * p.M + x];  // reduced far field
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
     const double* __restrict__ lv = p.levels + int64_t(k) * p.M + x;
     double S2 = 0.0;
-    for (int64_t l = p.n0 + 1; l <= p.n - 1; ++l) S2 = fma(dk[p.n - l], lv[l * twoM], S2);
+    int64_t l = p.n0 + 1;
+    // eight levels per round: the loads are independent, the sum is not
+    for (; l + 8 <= p.n; l += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = lv[(l + u) * twoM];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) S2 = fma(dk[p.n - l - u], v[u], S2);
+    }
+    for (; l <= p.n - 1; ++l) S2 = fma(dk[p.n - l], lv[l * twoM], S2);
     p.Spart[int64_t(k) * p.M + x] = S + S2;
+}
+
+// Sum the K-split partials of the far field once per block, into slice 0:
+// F[0][b][k][x] = sum_q F[q][b][k][x].
+__global__ __launch_bounds__(256) void k_reduce_far(double* __restrict__ F, int ks, int64_t per) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= per) return;
+    double s = F[e];
+    for (int q = 1; q < ks; ++q) s += F[int64_t(q) * per + e];
+    F[e] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -170,10 +201,6 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
 //   G^n = K^-1 (E + c Delta^-1 S') - Delta^-1 S',
 // so the stencil never acts on the (rough) history: every right-hand side
 // below is pointwise, and the only spatial coupling is inside K^-1.
-__device__ __forceinline__ double level_at(const double* lv, int64_t l, int64_t Lr, int64_t twoM) {
-    return lv[(l % Lr) * twoM];
-}
-
 // error-free transforms for the double-double residual
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
     s = a + b;
@@ -187,140 +214,203 @@ __device__ __forceinline__ void dd_add(double& hi, double& lo, double x) {
     lo += e;
 }
 
+// History sum of step n at node x of component k, from the partial sums
+// (fast: Sf of this step's block; direct: the near/far kernel's output) plus
+// the exact-weight window sum_{i=1}^{win} d_i G^{n-i} (win <= 31; the loads
+// are issued before the sum) plus the BDF2 correction d_{n-1}/2 G^0.
+// Returns S'. Level n-i sits at slot s1 - (i-1) (mod Lr).
+__device__ __forceinline__ double history_at(const StepArgs& p, int k, int64_t x) {
+    const int64_t M = p.M;
+    double s = 0.0;
+    for (int c = 0; c < p.nsplit; ++c) s += p.Sp[int64_t(c) * p.pstride + p.boff + k * M + x];
+    if (p.win > 0) {
+        const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+        const double* __restrict__ lv = p.levels + int64_t(k) * M + x;
+        const int64_t twoM = 2 * M;
+        double v[32];
+#pragma unroll
+        for (int i = 1; i <= 31; ++i) {
+            int64_t sl = p.slot1 - (i - 1);
+            if (sl < 0) sl += p.Lr;
+            v[i] = (i <= p.win) ? lv[sl * twoM] : 0.0;
+        }
+        double s2 = 0.0;
+#pragma unroll
+        for (int i = 1; i <= 31; ++i)
+            if (i <= p.win) s2 = fma(dk[i], v[i], s2);
+        s += s2;
+    }
+    return fma(p.corr[k], p.G0[k * M + x], s);
+}
+
+// Time-difference part E_k of the right-hand side (BE: G^{n-1}/tau; BDF2:
+// (2 G^{n-1} - G^{n-2}/2)/tau with G^{-1} = G^0 at n = 1).
+__device__ __forceinline__ double time_part(const StepArgs& p, int k, int64_t x) {
+    const int64_t twoM = 2 * p.M;
+    const double* lv = p.levels + int64_t(k) * p.M + x;
+    const double g1 = lv[p.slot1 * twoM];
+    if (p.scheme == 1) return g1 * p.inv_tau;
+    return (2.0 * g1 - 0.5 * lv[p.slot2 * twoM]) * p.inv_tau;
+}
+
+
 // 1D: K = Delta (I (x) A + Kc (x) I) with the 2x2 coupling Kc = V diag(theta) V^-1,
 // so K^-1 w = V z with (A + theta_k I) z_k = (V^-1 Delta^-1 w)_k: two constant
 // tridiagonal systems T_k z = h^2 y, T_k = tridiag(-1, 2 + delta_k, -1),
 // delta_k = theta_k h^2, solved by parallel cyclic reduction (PCR) in LDS
-// (stride s: every row eliminates rows i-s and i+s; ceil(log2 M) levels).
-// One refinement step follows: the residual h^2 y - T z is summed in
+// (stride s: every row eliminates rows i-s and i+s; ceil(log2 M) levels),
+// with the eliminations precomputed once per run (k_pcr_setup). One
+// refinement step follows: the residual h^2 y - T z is summed in
 // double-double with the diagonal kept as 2 and delta apart (2 + delta is not
 // representable to the accuracy the smallest eigenvalue needs), and PCR
-// solves for the correction. One workgroup of 1024 threads; M <= 4096.
+// solves for the correction. One workgroup of 1024 threads, R rows each.
 constexpr int kNT1D = 1024;
 
-__device__ void pcr_solve(double* sa, double* sb, double* sc, double* sd, int64_t M, int64_t Mp,
-                          const double diag[2]) {
+// The matrices T_k never change within a run, so the PCR eliminations do not
+// either: the set-up (host, once per run) runs PCR on (a, b, c) and stores,
+// per level l and row i, the multipliers f = a_i / b_{i-s} and g = c_i / b_{i+s}
+// and finally 1/b_i. A solve is then the right-hand-side recurrence alone,
+//   d_i <- d_i - f d_{i-s} - g d_{i+s},   x_i = d_i / b_i,
+// (two FMAs and two LDS reads per row and level). Multipliers: PF, PG
+// [levels][2][M]; PRB [2][M]. Rows per thread: at most 4 (M <= 4096).
+// Right-hand-side recurrence of PCR with the stored multipliers; sd holds d
+// on entry and x on exit. The next level's multipliers are loaded before the
+// barrier of the current one.
+
+template <int R>
+__device__ void pcr_apply(double* sd, int64_t M, int levels, const double* __restrict__ PF,
+                          const double* __restrict__ PG, const double* __restrict__ PRB) {
     const int tid = threadIdx.x;
-    for (int64_t x = tid; x < M; x += kNT1D)
+    double fc[R][2], gc[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t x = tid + int64_t(r) * kNT1D;
+#pragma unroll
         for (int k = 0; k < 2; ++k) {
-            sa[k * Mp + x] = (x > 0) ? -1.0 : 0.0;
-            sc[k * Mp + x] = (x + 1 < M) ? -1.0 : 0.0;
-            sb[k * Mp + x] = diag[k];
+            fc[r][k] = (x < M && levels > 0) ? PF[k * M + x] : 0.0;
+            gc[r][k] = (x < M && levels > 0) ? PG[k * M + x] : 0.0;
         }
-    __syncthreads();
-    for (int64_t s = 1; s < M; s <<= 1) {
-        double na[8], nb[8], nc[8], nd[8];
-        int q = 0;
-        for (int64_t x = tid; x < M; x += kNT1D) {
-            for (int k = 0; k < 2; ++k, ++q) {
-                const int64_t o = k * Mp;
-                const double ai = sa[o + x], ci = sc[o + x];
-                double a2 = 0.0, c2 = 0.0, bb = sb[o + x], dd = sd[o + x];
-                if (x - s >= 0) {
-                    const double f = ai / sb[o + x - s];
-                    a2 = -sa[o + x - s] * f;
-                    bb -= sc[o + x - s] * f;
-                    dd -= sd[o + x - s] * f;
+    }
+    int64_t s = 1;
+    for (int lvl = 0; lvl < levels; ++lvl, s <<= 1) {
+        double nd[R][2], fn[R][2], gn[R][2];
+        const bool more = lvl + 1 < levels;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t x = tid + int64_t(r) * kNT1D;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t o = k * M;
+                double dd = 0.0;
+                if (x < M) {
+                    dd = sd[o + x];
+                    if (x - s >= 0) dd = fma(-fc[r][k], sd[o + x - s], dd);
+                    if (x + s < M) dd = fma(-gc[r][k], sd[o + x + s], dd);
                 }
-                if (x + s < M) {
-                    const double g = ci / sb[o + x + s];
-                    c2 = -sc[o + x + s] * g;
-                    bb -= sa[o + x + s] * g;
-                    dd -= sd[o + x + s] * g;
-                }
-                na[q] = a2; nb[q] = bb; nc[q] = c2; nd[q] = dd;
+                nd[r][k] = dd;
+                fn[r][k] = (more && x < M) ? PF[(int64_t(lvl + 1) * 2 + k) * M + x] : 0.0;
+                gn[r][k] = (more && x < M) ? PG[(int64_t(lvl + 1) * 2 + k) * M + x] : 0.0;
             }
         }
         __syncthreads();
-        q = 0;
-        for (int64_t x = tid; x < M; x += kNT1D) {
-            for (int k = 0; k < 2; ++k, ++q) {
-                const int64_t o = k * Mp;
-                sa[o + x] = na[q]; sb[o + x] = nb[q]; sc[o + x] = nc[q]; sd[o + x] = nd[q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t x = tid + int64_t(r) * kNT1D;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (x < M) sd[k * M + x] = nd[r][k];
+                fc[r][k] = fn[r][k];
+                gc[r][k] = gn[r][k];
             }
         }
         __syncthreads();
     }
-    for (int64_t x = tid; x < M; x += kNT1D)
-        for (int k = 0; k < 2; ++k) sd[k * Mp + x] /= sb[k * Mp + x];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t x = tid + int64_t(r) * kNT1D;
+        if (x < M) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) sd[k * M + x] *= PRB[k * M + x];
+        }
+    }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void k_solve_1d(Solve1DArgs p) {
+template <int R>
+__global__ __launch_bounds__(1024) void k_step_1d(StepArgs p) {
     extern __shared__ double sm[];
     const int64_t M = p.M;
-    const int64_t Mp = p.Mpad;
-    double* sa = sm;             // [2][Mp]
-    double* sb = sm + 2 * Mp;    // [2][Mp]
-    double* sc = sm + 4 * Mp;    // [2][Mp]
-    double* sd = sm + 6 * Mp;    // [2][Mp]
+    double* sd = sm;  // [2][M]
     const int64_t twoM = 2 * M;
     const int tid = threadIdx.x;
-    // 1. S'_k (partials + BDF2 correction), w = E + c S'/d0, y = h^2 V^-1 Delta^-1 w
-    double rhs_y[2][4], qv[2][4];
-    int cnt = 0;
-    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
-        double u[2];
-        for (int k = 0; k < 2; ++k) {
-            double s = 0.0;
-            for (int c = 0; c < p.nsplit; ++c) s += p.Spart[(int64_t(c) * 2 + k) * M + x];
-            s = fma(p.corr[k], p.G0[k * M + x], s);
-            const double* lv = p.levels + int64_t(k) * M + x;
-            const double g1 = level_at(lv, p.n - 1, p.Lr, twoM);
-            double e;
-            if (p.scheme == 1) {
-                e = g1 * p.inv_tau;
-            } else {
-                const int64_t l2 = (p.n >= 2) ? p.n - 2 : 0;
-                e = (2.0 * g1 - 0.5 * level_at(lv, l2, p.Lr, twoM)) * p.inv_tau;
+    // 1. w = E + c S'/d0, q = S'/d0, y = h^2 V^-1 Delta^-1 w
+    double ry[R][2], qv[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t x = tid + int64_t(r) * kNT1D;
+        if (x < M) {
+            double u[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const double qk = history_at(p, k, x) * p.inv_d0[k];
+                qv[r][k] = qk;
+                u[k] = (time_part(p, k, x) + p.cdiag * qk) * p.inv_d0[k];
             }
-            const double qk = s * p.inv_d0[k];
-            qv[k][cnt] = qk;
-            u[k] = (e + p.cdiag * qk) * p.inv_d0[k];
-        }
-        rhs_y[0][cnt] = (p.Vinv[0] * u[0] + p.Vinv[1] * u[1]) * p.h2;
-        rhs_y[1][cnt] = (p.Vinv[2] * u[0] + p.Vinv[3] * u[1]) * p.h2;
-        sd[x] = rhs_y[0][cnt];
-        sd[Mp + x] = rhs_y[1][cnt];
-    }
-    __syncthreads();
-    pcr_solve(sa, sb, sc, sd, M, Mp, p.diag);
-    // 2. residual r = h^2 y - T z in double-double, T = tridiag(-1, 2 + delta, -1)
-    cnt = 0;
-    double rr[2][4], zown[2][4];
-    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
-        for (int k = 0; k < 2; ++k) {
-            const int64_t o = k * Mp;
-            const double z = sd[o + x];
-            zown[k][cnt] = z;
-            const double zl = (x > 0) ? sd[o + x - 1] : 0.0;
-            const double zr = (x + 1 < M) ? sd[o + x + 1] : 0.0;
-            double hi = rhs_y[k][cnt], lo = 0.0;
-            dd_add(hi, lo, zl);
-            dd_add(hi, lo, zr);
-            dd_add(hi, lo, -2.0 * z);
-            const double pz = p.delta[k] * z;
-            const double pe = fma(p.delta[k], z, -pz);  // exact product error
-            dd_add(hi, lo, -pz);
-            lo -= pe;
-            rr[k][cnt] = hi + lo;
+            ry[r][0] = (p.Vinv[0] * u[0] + p.Vinv[1] * u[1]) * p.h2;
+            ry[r][1] = (p.Vinv[2] * u[0] + p.Vinv[3] * u[1]) * p.h2;
+            sd[x] = ry[r][0];
+            sd[M + x] = ry[r][1];
         }
     }
     __syncthreads();
-    cnt = 0;
-    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
-        for (int k = 0; k < 2; ++k) sd[k * Mp + x] = rr[k][cnt];
+    pcr_apply<R>(sd, M, p.levels_pcr, p.PF, p.PG, p.PRB);
+    // 2. residual in double-double
+    double rr[R][2], zown[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t x = tid + int64_t(r) * kNT1D;
+        if (x < M) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t o = k * M;
+                const double z = sd[o + x];
+                zown[r][k] = z;
+                const double zl = (x > 0) ? sd[o + x - 1] : 0.0;
+                const double zr = (x + 1 < M) ? sd[o + x + 1] : 0.0;
+                double hi = ry[r][k], lo = 0.0;
+                dd_add(hi, lo, zl);
+                dd_add(hi, lo, zr);
+                dd_add(hi, lo, -2.0 * z);
+                const double pz = p.delta[k] * z;
+                const double pe = fma(p.delta[k], z, -pz);
+                dd_add(hi, lo, -pz);
+                lo -= pe;
+                rr[r][k] = hi + lo;
+            }
+        }
     }
     __syncthreads();
-    pcr_solve(sa, sb, sc, sd, M, Mp, p.diag);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t x = tid + int64_t(r) * kNT1D;
+        if (x < M) {
+            sd[x] = rr[r][0];
+            sd[M + x] = rr[r][1];
+        }
+    }
+    __syncthreads();
+    pcr_apply<R>(sd, M, p.levels_pcr, p.PF, p.PG, p.PRB);
     // 3. G^n = V (z + dz) - Delta^-1 S'
-    cnt = 0;
-    double* out = p.levels + (p.n % p.Lr) * twoM;
-    for (int64_t x = tid; x < M; x += kNT1D, ++cnt) {
-        const double z0 = zown[0][cnt] + sd[x];
-        const double z1 = zown[1][cnt] + sd[Mp + x];
-        out[x] = p.V[0] * z0 + p.V[1] * z1 - qv[0][cnt];
-        out[M + x] = p.V[2] * z0 + p.V[3] * z1 - qv[1][cnt];
+    double* out = p.levels + p.slot_out * twoM;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t x = tid + int64_t(r) * kNT1D;
+        if (x < M) {
+            const double z0 = zown[r][0] + sd[x];
+            const double z1 = zown[r][1] + sd[M + x];
+            out[x] = p.V[0] * z0 + p.V[1] * z1 - qv[r][0];
+            out[M + x] = p.V[2] * z0 + p.V[3] * z1 - qv[r][1];
+        }
     }
 }
 
@@ -328,27 +418,14 @@ __global__ __launch_bounds__(1024) void k_solve_1d(Solve1DArgs p) {
 // 2D: pointwise right-hand side w = E + c Delta^-1 S' and q = Delta^-1 S'
 // (the forward DST, per-mode solve and inverse DST follow; the last GEMM
 // subtracts q).
-__global__ __launch_bounds__(256) void k_prep_2d(Prep2DArgs p) {
+__global__ __launch_bounds__(256) void k_prep_2d(StepArgs p) {
     const int64_t M = p.M;
     const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (x >= M) return;
     const int k = blockIdx.y;
-    const int64_t twoM = 2 * M;
-    double s = 0.0;
-    for (int c = 0; c < p.nsplit; ++c) s += p.Spart[(int64_t(c) * 2 + k) * M + x];
-    s = fma(p.corr[k], p.G0[k * M + x], s);
-    const double* lv = p.levels + int64_t(k) * M + x;
-    const double g1 = lv[((p.n - 1) % p.Lr) * twoM];
-    double e;
-    if (p.scheme == 1) {
-        e = g1 * p.inv_tau;
-    } else {
-        const int64_t l2 = (p.n >= 2) ? p.n - 2 : 0;
-        e = (2.0 * g1 - 0.5 * lv[(l2 % p.Lr) * twoM]) * p.inv_tau;
-    }
-    const double qk = s * p.inv_d0[k];
+    const double qk = history_at(p, k, x) * p.inv_d0[k];
     p.q[k * M + x] = qk;
-    p.w[k * M + x] = e + p.cdiag * qk;
+    p.w[k * M + x] = time_part(p, k, x) + p.cdiag * qk;
 }
 
 // ---------------------------------------------------------------------------
@@ -425,10 +502,15 @@ __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
 
 // ---------------------------------------------------------------------------
 // launchers (optionally bracketed by timing events, see prof_begin/prof_end)
-void launch_hist_fast(const HistFastArgs& a, int nsplit, hipStream_t st) {
+void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st) {
     dim3 grid(unsigned((a.M + 255) / 256), unsigned(nsplit), 2);
     prof_begin(0, st);
-    hipLaunchKernelGGL(k_hist_fast, grid, dim3(256), 0, st, a);
+    if (a.BT <= 8)
+        hipLaunchKernelGGL(k_hist_block<8>, grid, dim3(256), 0, st, a);
+    else if (a.BT <= 16)
+        hipLaunchKernelGGL(k_hist_block<16>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_hist_block<32>, grid, dim3(256), 0, st, a);
     prof_end(0, st);
 }
 
@@ -463,16 +545,26 @@ void launch_far(const FarArgs& a, hipStream_t st) {
         case 3: hipLaunchKernelGGL(k_far_toeplitz<3>, grid, dim3(256), 0, st, a); break;
         default: hipLaunchKernelGGL(k_far_toeplitz<4>, grid, dim3(256), 0, st, a); break;
     }
+    if (a.ks > 1 && a.reduce) {
+        const int64_t per = int64_t(a.B) * a.ncomp * a.M;
+        hipLaunchKernelGGL(k_reduce_far, dim3(unsigned((per + 255) / 256)), dim3(256), 0, st, a.F, a.ks, per);
+    }
     prof_end(2, st);
 }
 
-void launch_solve_1d(const Solve1DArgs& a, size_t lds, hipStream_t st) {
+void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st) {
     prof_begin(3, st);
-    hipLaunchKernelGGL(k_solve_1d, dim3(1), dim3(kNT1D), lds, st, a);
+    const int R = int((a.M + kNT1D - 1) / kNT1D);
+    switch (R) {
+        case 1: hipLaunchKernelGGL(k_step_1d<1>, dim3(1), dim3(kNT1D), lds, st, a); break;
+        case 2: hipLaunchKernelGGL(k_step_1d<2>, dim3(1), dim3(kNT1D), lds, st, a); break;
+        case 3: hipLaunchKernelGGL(k_step_1d<3>, dim3(1), dim3(kNT1D), lds, st, a); break;
+        default: hipLaunchKernelGGL(k_step_1d<4>, dim3(1), dim3(kNT1D), lds, st, a); break;
+    }
     prof_end(3, st);
 }
 
-void launch_prep_2d(const Prep2DArgs& a, hipStream_t st) {
+void launch_prep_2d(const StepArgs& a, hipStream_t st) {
     dim3 grid(unsigned((a.M + 255) / 256), 2);
     prof_begin(4, st);
     hipLaunchKernelGGL(k_prep_2d, grid, dim3(256), 0, st, a);
@@ -491,6 +583,13 @@ void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
     prof_end(5, st);
 }
 
-const void* kernel_solve_1d() { return reinterpret_cast<const void*>(&k_solve_1d); }
+const void* kernel_step_1d(int R) {
+    switch (R) {
+        case 1: return reinterpret_cast<const void*>(&k_step_1d<1>);
+        case 2: return reinterpret_cast<const void*>(&k_step_1d<2>);
+        case 3: return reinterpret_cast<const void*>(&k_step_1d<3>);
+        default: return reinterpret_cast<const void*>(&k_step_1d<4>);
+    }
+}
 
 }  // namespace cqfp

@@ -35,7 +35,7 @@ struct Solver {
     double tau = 0, a = 0, beta[2] = {0, 0}, c = 0, hx = 0, hy = 0;
     hipStream_t st = nullptr;
     // fast
-    int L = 2, np = 0, nsplit = 1, chunk = 0;
+    int L = 2, np = 0, nsplit = 1, chunk = 0, Bt = 1, BTt = 8;
     double max_eps = 0;
     // direct
     int B = 0, ks = 1;
@@ -48,7 +48,8 @@ struct Solver {
     // device buffers
     double *d_d = nullptr, *d_ratio = nullptr, *d_coef = nullptr, *G0 = nullptr, *levels = nullptr,
            *H = nullptr, *Spart = nullptr, *F = nullptr, *rhs = nullptr, *T1 = nullptr, *T2 = nullptr,
-           *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr;
+           *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr, *Sf = nullptr, *PF = nullptr, *PG = nullptr, *PRB = nullptr;
+    int levels_pcr = 0;
     size_t lds = 0;
     size_t dev_bytes = 0;
     std::vector<void*> allocs;
@@ -100,6 +101,51 @@ int validate(const cq_grid* g, const cq_params* p) {
         return fail(CQ_EINVAL, "block_B must be 64, 128, 192 or 256 (got %d)", p->block_B);
     if (p->np > 4096 || p->np1 > 4096) return fail(CQ_EINVAL, "np, np1 must be <= 4096");
     return CQ_OK;
+}
+
+// PCR eliminations of T_k = tridiag(-1, fl(2 + theta_k h^2), -1), k = 0, 1:
+// per level l (stride 2^l) and row i the multipliers f = a_i/b_{i-s},
+// g = c_i/b_{i+s}; after the last level 1/b_i. Layout [levels][2][M], [2][M].
+void pcr_multipliers(int64_t M, int levels, const double theta[2], double h, std::vector<double>& pf,
+                     std::vector<double>& pg, std::vector<double>& prb) {
+    const size_t nl = size_t(std::max(1, levels));
+    pf.assign(nl * 2 * size_t(M), 0.0);
+    pg.assign(nl * 2 * size_t(M), 0.0);
+    prb.assign(2 * size_t(M), 0.0);
+    for (int k = 0; k < 2; ++k) {
+        const size_t Mz = static_cast<size_t>(M);
+        std::vector<double> a(Mz), b(Mz), c(Mz), na(Mz), nb(Mz), nc(Mz);
+        for (int64_t i = 0; i < M; ++i) {
+            a[size_t(i)] = i > 0 ? -1.0 : 0.0;
+            c[size_t(i)] = i + 1 < M ? -1.0 : 0.0;
+            b[size_t(i)] = 2.0 + theta[k] * h * h;
+        }
+        int64_t s = 1;
+        for (int l = 0; l < levels; ++l, s <<= 1) {
+            for (int64_t i = 0; i < M; ++i) {
+                double a2 = 0.0, c2 = 0.0, bb = b[size_t(i)], f = 0.0, g = 0.0;
+                if (i - s >= 0) {
+                    f = a[size_t(i)] / b[size_t(i - s)];
+                    a2 = -a[size_t(i - s)] * f;
+                    bb -= c[size_t(i - s)] * f;
+                }
+                if (i + s < M) {
+                    g = c[size_t(i)] / b[size_t(i + s)];
+                    c2 = -c[size_t(i + s)] * g;
+                    bb -= a[size_t(i + s)] * g;
+                }
+                pf[(size_t(l) * 2 + k) * size_t(M) + size_t(i)] = f;
+                pg[(size_t(l) * 2 + k) * size_t(M) + size_t(i)] = g;
+                na[size_t(i)] = a2;
+                nb[size_t(i)] = bb;
+                nc[size_t(i)] = c2;
+            }
+            a.swap(na);
+            b.swap(nb);
+            c.swap(nc);
+        }
+        for (int64_t i = 0; i < M; ++i) prb[size_t(k) * size_t(M) + size_t(i)] = 1.0 / b[size_t(i)];
+    }
 }
 
 int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) {
@@ -170,8 +216,19 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
             std::vector<double> dk(s.dh[k].begin(), s.dh[k].begin() + s.N + 1);
             rule[k].max_eps = rule_error(rule[k], dk, s.N);
         }
+        // BE: the Gauss-Jacobi rule is exact for lags 2..2np+1, so summing lags
+        // below L' with the exact weights and the rest with the rule is the
+        // same fast scheme; a window of up to 32 lets the state advance in
+        // blocks of up to 32 steps
+        if (p->scheme == 1) {
+            const int Lw = std::min(32, 2 * int(rule[0].ratio.size()) + 2);
+            shift_lag(rule[0], Lw);
+            shift_lag(rule[1], Lw);
+        }
         s.np = int(rule[0].ratio.size());
         s.L = rule[0].lag;
+        s.Bt = std::min(s.L, 32);
+        s.BTt = s.Bt <= 8 ? 8 : (s.Bt <= 16 ? 16 : 32);
         s.max_eps = std::max(rule[0].max_eps, rule[1].max_eps);
         const int64_t tiles = 2 * ((s.M + 255) / 256);
         int want = int(std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
@@ -196,7 +253,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
     if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
     if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
-    if ((rc = dev_alloc(s, &s.Spart, size_t(s.nsplit * twoM)))) return rc;
+    if (p->method == 0 && (rc = dev_alloc(s, &s.Spart, size_t(twoM)))) return rc;
     HIPCHK(hipMemcpyAsync(s.d_d, s.dh[0].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
                           st));
@@ -204,6 +261,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(s.levels, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (p->method == 1) {
         if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * s.M)))) return rc;
+        if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
         if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
         HIPCHK(hipMemsetAsync(s.H, 0, size_t(2 * int64_t(s.np) * s.M) * sizeof(double), st));
@@ -219,15 +277,24 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
         if ((rc = dev_alloc(s, &s.F, size_t(int64_t(s.ks) * s.B * twoM)))) return rc;
     }
     if (s.dim == 1) {
-        s.lds = size_t(8) * size_t(s.M) * sizeof(double);
+        s.levels_pcr = 0;
+        while ((int64_t(1) << s.levels_pcr) < s.M) ++s.levels_pcr;
+        const size_t nl = size_t(std::max(1, s.levels_pcr));
+        if ((rc = dev_alloc(s, &s.PF, nl * size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.PG, nl * size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.PRB, size_t(twoM)))) return rc;
+        s.lds = size_t(2) * size_t(s.M) * sizeof(double);
         int dev = 0, maxlds = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         if (s.lds > size_t(maxlds))
             return fail(CQ_EINVAL, "1D grid of %lld nodes needs %zu B of LDS, device allows %d", (long long)s.M,
                         s.lds, maxlds);
-        if (s.lds > 65536)
-            HIPCHK(hipFuncSetAttribute(kernel_solve_1d(), hipFuncAttributeMaxDynamicSharedMemorySize, int(s.lds)));
+        std::vector<double> pf, pg, prb;
+        pcr_multipliers(s.M, s.levels_pcr, s.theta, s.hx, pf, pg, prb);
+        HIPCHK(hipMemcpy(s.PF, pf.data(), pf.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.PG, pg.data(), pg.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.PRB, prb.data(), prb.size() * sizeof(double), hipMemcpyHostToDevice));
     } else {
         if ((rc = dev_alloc(s, &s.rhs, size_t(twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.qbuf, size_t(twoM)))) return rc;
@@ -283,12 +350,32 @@ void launch_far_block(Solver& s) {
     fa.levels = s.levels;
     fa.d = s.d_d;
     fa.F = s.F;
+    fa.reduce = 1;
     launch_far(fa, s.st);
 }
 
 // one time step n = s.n + 1
 void step_once(Solver& s) {
     const int64_t n = ++s.n;
+    const int64_t twoM = 2 * s.M;
+    StepArgs sa{};
+    sa.n = n;
+    sa.M = s.M;
+    sa.Lr = s.Lr;
+    sa.slot1 = (n - 1) % s.Lr;
+    sa.slot2 = (n >= 2 ? n - 2 : 0) % s.Lr;
+    sa.slot_out = n % s.Lr;
+    sa.scheme = s.p.scheme;
+    sa.d = s.d_d;
+    sa.dstride = s.dstride;
+    sa.G0 = s.G0;
+    sa.levels = s.levels;
+    sa.inv_tau = 1.0 / s.tau;
+    sa.cdiag = s.c;
+    for (int k = 0; k < 2; ++k) {
+        sa.inv_d0[k] = 1.0 / s.dh[k][0];
+        sa.corr[k] = s.p.scheme == 2 ? 0.5 * s.dh[k][size_t(n - 1)] : 0.0;
+    }
     if (s.p.method == 0) {
         if ((n - 1) % s.B == 0) {
             s.n0 = n - 1;
@@ -306,71 +393,52 @@ void step_once(Solver& s) {
         ha.F = s.F;
         ha.Spart = s.Spart;
         launch_hist_direct(ha, s.st);
+        sa.Sp = s.Spart;
+        sa.nsplit = 1;
+        sa.pstride = 0;
+        sa.boff = 0;
+        sa.win = 0;
     } else {
-        HistFastArgs ha{};
-        ha.n = n;
-        ha.L = s.L;
-        ha.Lr = s.Lr;
-        ha.M = s.M;
-        ha.np = s.np;
-        ha.chunk = s.chunk;
-        ha.dstride = s.dstride;
-        ha.levels = s.levels;
-        ha.H = s.H;
-        ha.ratio = s.d_ratio;
-        ha.coef = s.d_coef;
-        ha.d = s.d_d;
-        ha.Spart = s.Spart;
-        launch_hist_fast(ha, s.nsplit, s.st);
-    }
-    const int nsplit = s.p.method == 1 ? s.nsplit : 1;
-    double corr[2] = {0.0, 0.0};
-    if (s.p.scheme == 2)
-        for (int k = 0; k < 2; ++k) corr[k] = 0.5 * s.dh[k][size_t(n - 1)];
-    if (s.dim == 1) {
-        Solve1DArgs sa{};
-        sa.n = n;
-        sa.M = s.M;
-        sa.Mpad = s.M;
-        sa.Lr = s.Lr;
-        sa.nsplit = nsplit;
-        sa.scheme = s.p.scheme;
-        sa.inv_tau = 1.0 / s.tau;
-        sa.cdiag = s.c;
-        sa.h2 = s.hx * s.hx;
-        for (int k = 0; k < 2; ++k) {
-            sa.inv_d0[k] = 1.0 / s.dh[k][0];
-            sa.corr[k] = corr[k];
-            sa.delta[k] = s.theta[k] * s.hx * s.hx;
-            sa.diag[k] = 2.0 + sa.delta[k];
+        if ((n - 1) % s.Bt == 0) {
+            HistBlockArgs hb{};
+            hb.n = n;
+            hb.L = s.L;
+            hb.Lr = s.Lr;
+            hb.M = s.M;
+            hb.np = s.np;
+            hb.chunk = s.chunk;
+            hb.BT = s.BTt;
+            hb.bt = int(std::min<int64_t>(s.Bt, s.N - n + 1));
+            hb.slot0 = ((n - s.L) % s.Lr + s.Lr) % s.Lr;
+            hb.levels = s.levels;
+            hb.H = s.H;
+            hb.ratio = s.d_ratio;
+            hb.coef = s.d_coef;
+            hb.Sf = s.Sf;
+            launch_hist_block(hb, s.nsplit, s.st);
         }
+        sa.Sp = s.Sf;
+        sa.nsplit = s.nsplit;
+        sa.pstride = int64_t(s.BTt) * twoM;
+        sa.boff = ((n - 1) % s.Bt) * twoM;
+        sa.win = int(std::min<int64_t>(s.L - 1, n - 1));
+    }
+    if (s.dim == 1) {
+        sa.h2 = s.hx * s.hx;
+        for (int k = 0; k < 2; ++k) sa.delta[k] = s.theta[k] * s.hx * s.hx;
+        sa.levels_pcr = s.levels_pcr;
+        sa.PF = s.PF;
+        sa.PG = s.PG;
+        sa.PRB = s.PRB;
         sa.V[0] = s.V[0][0]; sa.V[1] = s.V[0][1]; sa.V[2] = s.V[1][0]; sa.V[3] = s.V[1][1];
         sa.Vinv[0] = s.Vinv[0][0]; sa.Vinv[1] = s.Vinv[0][1]; sa.Vinv[2] = s.Vinv[1][0]; sa.Vinv[3] = s.Vinv[1][1];
-        sa.Spart = s.Spart;
-        sa.G0 = s.G0;
-        sa.levels = s.levels;
-        launch_solve_1d(sa, s.lds, s.st);
+        launch_step_1d(sa, s.lds, s.st);
         return;
     }
     const int64_t M = s.M;
-    Prep2DArgs ra{};
-    ra.n = n;
-    ra.Lr = s.Lr;
-    ra.M = M;
-    ra.nsplit = nsplit;
-    ra.scheme = s.p.scheme;
-    ra.inv_tau = 1.0 / s.tau;
-    ra.cdiag = s.c;
-    for (int k = 0; k < 2; ++k) {
-        ra.inv_d0[k] = 1.0 / s.dh[k][0];
-        ra.corr[k] = corr[k];
-    }
-    ra.Spart = s.Spart;
-    ra.G0 = s.G0;
-    ra.levels = s.levels;
-    ra.w = s.rhs;
-    ra.q = s.qbuf;
-    launch_prep_2d(ra, s.st);
+    sa.w = s.rhs;
+    sa.q = s.qbuf;
+    launch_prep_2d(sa, s.st);
     GemmArgs ga{};
     // forward: T1 = w Sx ; T2 = solve(Sy T1)
     ga.R = s.ny; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
@@ -404,7 +472,8 @@ size_t state_bytes(const Solver& s) {
     if (s.p.method == 0)
         b += size_t(s.n + 1) * size_t(twoM) * sizeof(double);
     else
-        b += (size_t(s.Lr) * size_t(twoM) + size_t(2) * size_t(s.np) * size_t(s.M)) * sizeof(double);
+        b += (size_t(s.Lr) * size_t(twoM) + size_t(2) * size_t(s.np) * size_t(s.M) +
+              size_t(s.nsplit) * size_t(s.BTt) * size_t(twoM)) * sizeof(double);
     return b;
 }
 
@@ -569,6 +638,7 @@ int cq_history(int32_t scheme, double beta, double tau, const double* G_hist, in
             fa.levels = G_hist;
             fa.d = dd;
             fa.F = F;
+            fa.reduce = 0;
             launch_far(fa, st);
             launch_reduce_row(F, ks, B, M, S_out, st);
             e = hipGetLastError();
@@ -643,7 +713,7 @@ int fp_info(void* handle, cq_info* info) {
     info->max_eps = s.max_eps;
     info->theta[0] = s.theta[0];
     info->theta[1] = s.theta[1];
-    info->block_B = s.B;
+    info->block_B = s.p.method == 1 ? s.Bt : s.B;
     info->ksplit = s.ks;
     info->device_bytes = s.dev_bytes;
     info->state_bytes = state_bytes(s);
@@ -676,7 +746,10 @@ int fp_get_state(void* handle, void* dst, size_t* bytes) {
     } else {
         const size_t b1 = size_t(s.Lr) * size_t(twoM) * sizeof(double);
         HIPCHK(hipMemcpy(q, s.levels, b1, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(q + b1, s.H, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), hipMemcpyDeviceToHost));
+        const size_t b2 = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
+        HIPCHK(hipMemcpy(q + b1, s.H, b2, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(q + b1 + b2, s.Sf, size_t(s.nsplit) * s.BTt * size_t(twoM) * sizeof(double),
+                         hipMemcpyDeviceToHost));
     }
     *bytes = need;
     return CQ_OK;
@@ -712,7 +785,10 @@ int fp_set_state(void* handle, const void* src, size_t bytes) {
     } else {
         const size_t b1 = size_t(s.Lr) * size_t(twoM) * sizeof(double);
         HIPCHK(hipMemcpy(s.levels, q, b1, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.H, q + b1, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), hipMemcpyHostToDevice));
+        const size_t b2 = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
+        HIPCHK(hipMemcpy(s.H, q + b1, b2, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.Sf, q + b1 + b2, size_t(s.nsplit) * s.BTt * size_t(twoM) * sizeof(double),
+                         hipMemcpyHostToDevice));
     }
     HIPCHK(hipGetLastError());
     return CQ_OK;

@@ -210,6 +210,11 @@ void build_rule(int scheme, double beta, double tau, int np, int np1, int ns, Fa
     }
 }
 
+void shift_lag(FastRule& r, int lag) {
+    for (size_t j = 0; j < r.ratio.size(); ++j) r.coef[j] *= std::pow(r.ratio[j], double(lag - r.lag));
+    r.lag = lag;
+}
+
 double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N) {
     const int64_t L = r.lag;
     if (N < L) return 0.0;
