@@ -67,7 +67,13 @@ typedef struct {
  *  np1: N_{p,1} for BDF2 (0 selects 16). ns: N_s for BDF2 (0 selects 30;
  *    must be >= 3). np_max: scan limit (0 selects 1024).
  *  block_B: direct method, time-block length of the Toeplitz far-field
- *    update (0 = automatic; otherwise a multiple of 16 up to 256). */
+ *    update (0 = automatic; otherwise 64, 128, 192 or 256).
+ *  solver: 0 = nodal: every step assembles the right-hand side on the grid
+ *    and solves the coupled system (cyclic reduction in 1D, sine transform
+ *    with a 2x2 solve per mode in 2D); 1 = modal: the sine transform is
+ *    applied once to G0 and once per read-out, and every mode advances by
+ *    its own 2x2 recurrence (same scheme, no per-step global coupling; the
+ *    fast form then needs lag <= 64 and at most 1024 nodes per component). */
 typedef struct {
     double alpha1, alpha2;
     double m;
@@ -81,6 +87,7 @@ typedef struct {
     int32_t ns;
     int32_t np_max;
     int32_t block_B;
+    int32_t solver;
 } cq_params;
 
 /* What a solver handle chose (filled by fp_info). */
@@ -176,7 +183,7 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
  * are grouped by kind: 0 fast history, 1 direct near field, 2 Toeplitz far
  * field (FP64 MFMA), 3 1D right-hand side + PCR solve, 4 2D right-hand side,
  * 5 DST GEMM (forward/inverse and per-mode solve), 6 standalone history
- * reduction. cq_prof_read synchronises the recorded events and returns, for
+ * reduction, 7 modal fast steps, 8 modal direct near field + solve. cq_prof_read synchronises the recorded events and returns, for
  * one kind, the launch count and the summed duration in milliseconds.
  * cq_prof_enable(1) also clears earlier records. Not thread safe. */
 int cq_prof_enable(int32_t on);

@@ -25,7 +25,7 @@ EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "
            "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "cq_prof_enable", "cq_prof_read",
            "cq_last_error"]
 PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
-              "reduce_row": 6}
+              "reduce_row": 6, "modal_fast": 7, "modal_near": 8}
 
 
 class CQError(RuntimeError):
@@ -42,7 +42,7 @@ class Params(C.Structure):
     _fields_ = [("alpha1", C.c_double), ("alpha2", C.c_double), ("m", C.c_double), ("T", C.c_double),
                 ("N", C.c_int64), ("scheme", C.c_int32), ("method", C.c_int32), ("fast_tol", C.c_double),
                 ("np", C.c_int32), ("np1", C.c_int32), ("ns", C.c_int32), ("np_max", C.c_int32),
-                ("block_B", C.c_int32)]
+                ("block_B", C.c_int32), ("solver", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -99,9 +99,12 @@ def make_grid(dim: int, nx: int, ny: int = 1, lx: float = 1.0, ly: float = 1.0) 
     return Grid(dim, nx, ny if dim == 2 else 1, lx, ly)
 
 
+SOLVER_NODAL, SOLVER_MODAL = 0, 1
+
+
 def make_params(alpha1, alpha2, m, T, N, scheme, method, fast_tol=0.0, np_=0, np1=0, ns=0, np_max=0,
-                block_B=0) -> Params:
-    return Params(alpha1, alpha2, m, T, int(N), scheme, method, fast_tol, np_, np1, ns, np_max, block_B)
+                block_B=0, solver=SOLVER_NODAL) -> Params:
+    return Params(alpha1, alpha2, m, T, int(N), scheme, method, fast_tol, np_, np1, ns, np_max, block_B, solver)
 
 
 def params_of(p) -> tuple:

@@ -86,6 +86,40 @@ struct GemmArgs {
     const double *sub0, *sub1;
 };
 
+struct ModalFastArgs {
+    int64_t M;            // modes (nodes per component)
+    int64_t n0;           // steps already taken
+    int nsteps;
+    int np, L;            // nodes per component (<= 1024), lag (<= 64)
+    int scheme;
+    int64_t dstride;
+    double inv_tau, c, a;
+    double d0[2];
+    const double* lam;    // [M]
+    const double* ratio;  // [2][np]
+    const double* coef;   // [2][np]
+    const double* d;      // [2][dstride]
+    const double* g0;     // [2][M] sine coefficients of G^0
+    double* H;            // [2][np][M]
+    double* ring;         // [L][2][M], ring[i] = g^{n-1-i}
+};
+
+struct ModalNearArgs {
+    int64_t M, n0;        // time block of the far field: steps n0+1 .. n0+B
+    int64_t nfirst;       // first step taken here (n0 < nfirst <= n0 + B)
+    int bt, scheme;
+    int64_t dstride;
+    double inv_tau, c, a;
+    double d0[2];
+    const double* lam;
+    const double* d;
+    const double* g0;
+    const double* F;      // [B][2][M] reduced far field (n0 >= 1)
+    double* levels;       // [N+1][2][M] coefficients
+};
+
+void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
+void launch_modal_near(const ModalNearArgs& a, hipStream_t st);
 void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);

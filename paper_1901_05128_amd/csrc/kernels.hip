@@ -429,11 +429,173 @@ __global__ __launch_bounds__(256) void k_prep_2d(StepArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Modal solver. The uniform-grid Dirichlet Laplacian is diagonalised by the
+// sine transform, A_h = S diag(lambda) S^-1, and every stage of the schemes
+// applies A only as a multiplication, so the sine coefficients of G^n obey
+// the same scheme with A -> lambda_p, independently for every mode p:
+//   [[c + d_1,0 (a+l), -a d_2,0], [-a d_1,0, c + d_2,0 (a+l)]] g^n
+//       = E - [(a+l) S'_1 - a S'_2 ; (a+l) S'_2 - a S'_1].
+// With no coupling between modes there is no per-step global dependency:
+// the transform runs once at the start and once per read-out.
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Fast form, persistent: one wave per mode runs `nsteps` steps. Lane l holds
+// nodes j = l + 64 q (q < NPL) of both components (ratio, coefficient and
+// state H_j in registers) and the window level g^{n-1-l} (lane l < L): the
+// state input g^{n-L} is lane L-1, the exact-weight window is lanes
+// 0..min(L-1,n-1)-1 with weights d_1.., and after each step the levels move
+// up one lane. One wave reduction per component gives S; every lane then
+// solves the 2x2 system. State H[2][np][M] and window ring[L][2][M]
+// (ring[i] = g^{n-1-i}) are loaded at entry and stored at exit.
+template <int NPL>
+__global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t mode = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (mode >= p.M) return;  // uniform per wave
+    const int64_t M = p.M;
+    double r[2][NPL], w[2][NPL], h[2][NPL];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) {
+            const int j = lane + 64 * q;
+            const bool ok = j < p.np;
+            r[k][q] = ok ? p.ratio[k * p.np + j] : 0.0;
+            w[k][q] = ok ? p.coef[k * p.np + j] : 0.0;
+            h[k][q] = ok ? p.H[(int64_t(k) * p.np + j) * M + mode] : 0.0;
+        }
+    double dw[2], ring[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        dw[k] = (lane < p.L - 1) ? p.d[k * p.dstride + lane + 1] : 0.0;
+        ring[k] = (lane < p.L) ? p.ring[(int64_t(lane) * 2 + k) * M + mode] : 0.0;
+    }
+    const double lam = p.lam[mode];
+    const double g00 = p.g0[mode], g01 = p.g0[M + mode];
+    const double L1 = p.a + lam;
+    const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
+    const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    for (int t = 0; t < p.nsteps; ++t) {
+        const int64_t n = p.n0 + 1 + t;
+        double part[2] = {0.0, 0.0};
+        if (n >= p.L + 1) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const double gin = __shfl(ring[k], p.L - 1, 64);
+                double pa = 0.0, pb = 0.0;
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) {
+                    h[k][q] = fma(r[k][q], h[k][q], gin);
+                    if (q & 1)
+                        pb = fma(w[k][q], h[k][q], pb);
+                    else
+                        pa = fma(w[k][q], h[k][q], pa);
+                }
+                part[k] = pa + pb;
+            }
+        }
+        const int64_t wn = (n - 1 < p.L - 1) ? n - 1 : p.L - 1;
+        if (lane < wn) {
+            part[0] = fma(dw[0], ring[0], part[0]);
+            part[1] = fma(dw[1], ring[1], part[1]);
+        }
+        double S0 = wave_sum(part[0]);
+        double S1 = wave_sum(part[1]);
+        const double gm10 = __shfl(ring[0], 0, 64), gm11 = __shfl(ring[1], 0, 64);
+        double E0, E1;
+        if (p.scheme == 1) {
+            E0 = gm10 * p.inv_tau;
+            E1 = gm11 * p.inv_tau;
+        } else {
+            const double gm20 = __shfl(ring[0], 1, 64), gm21 = __shfl(ring[1], 1, 64);
+            E0 = (2.0 * gm10 - 0.5 * gm20) * p.inv_tau;
+            E1 = (2.0 * gm11 - 0.5 * gm21) * p.inv_tau;
+            S0 = fma(0.5 * p.d[n - 1], g00, S0);
+            S1 = fma(0.5 * p.d[p.dstride + n - 1], g01, S1);
+        }
+        const double r0 = E0 - (L1 * S0 - p.a * S1);
+        const double r1 = E1 - (L1 * S1 - p.a * S0);
+        const double gn0 = (m22 * r0 - m12 * r1) * idet;
+        const double gn1 = (m11 * r1 - m21 * r0) * idet;
+        const double up0 = __shfl_up(ring[0], 1, 64), up1 = __shfl_up(ring[1], 1, 64);
+        ring[0] = (lane == 0) ? gn0 : up0;
+        ring[1] = (lane == 0) ? gn1 : up1;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) {
+            const int j = lane + 64 * q;
+            if (j < p.np) p.H[(int64_t(k) * p.np + j) * M + mode] = h[k][q];
+        }
+        if (lane < p.L) p.ring[(int64_t(lane) * 2 + k) * M + mode] = ring[k];
+    }
+}
+
+// Direct form, part of one time block: thread per mode takes the steps
+// n = nfirst .. nfirst+bt-1 (inside the block n0+1 .. n0+B) in order. S = F[b] (far field of the block, summed over
+// the K-split by k_reduce_far) + sum_{l=n0+1}^{n-1} d_{n-l} g^l (the levels
+// of this block, written by this same thread).
+__global__ __launch_bounds__(256) void k_modal_near(ModalNearArgs p) {
+    const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (mode >= p.M) return;
+    const int64_t M = p.M, twoM = 2 * M;
+    const double lam = p.lam[mode];
+    const double g00 = p.g0[mode], g01 = p.g0[M + mode];
+    const double L1 = p.a + lam;
+    const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
+    const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    double* __restrict__ lv = p.levels + mode;
+    const double* __restrict__ d0p = p.d;
+    const double* __restrict__ d1p = p.d + p.dstride;
+    for (int t = 0; t < p.bt; ++t) {
+        const int64_t n = p.nfirst + t;
+        const int64_t b = n - p.n0 - 1;
+        double S0 = 0.0, S1 = 0.0;
+        if (p.n0 >= 1) {
+            S0 = p.F[(int64_t(b) * 2 + 0) * M + mode];
+            S1 = p.F[(int64_t(b) * 2 + 1) * M + mode];
+        }
+        double a0 = 0.0, a1 = 0.0;
+        for (int64_t l = p.n0 + 1; l <= n - 1; ++l) {
+            a0 = fma(d0p[n - l], lv[l * twoM], a0);
+            a1 = fma(d1p[n - l], lv[l * twoM + M], a1);
+        }
+        S0 += a0;
+        S1 += a1;
+        const double gm10 = lv[(n - 1) * twoM], gm11 = lv[(n - 1) * twoM + M];
+        double E0, E1;
+        if (p.scheme == 1) {
+            E0 = gm10 * p.inv_tau;
+            E1 = gm11 * p.inv_tau;
+        } else {
+            const int64_t l2 = (n >= 2) ? n - 2 : 0;
+            E0 = (2.0 * gm10 - 0.5 * lv[l2 * twoM]) * p.inv_tau;
+            E1 = (2.0 * gm11 - 0.5 * lv[l2 * twoM + M]) * p.inv_tau;
+            S0 = fma(0.5 * d0p[n - 1], g00, S0);
+            S1 = fma(0.5 * d1p[n - 1], g01, S1);
+        }
+        const double r0 = E0 - (L1 * S0 - p.a * S1);
+        const double r1 = E1 - (L1 * S1 - p.a * S0);
+        lv[n * twoM] = (m22 * r0 - m12 * r1) * idet;
+        lv[n * twoM + M] = (m11 * r1 - m21 * r0) * idet;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Small dense GEMM pair for the 2D DST-I: C_k = A_k B_k, k = 0, 1, with
 // FP64 MFMA 16x16x4. One workgroup = one 16x16 output tile of both
 // components; its 4 waves split the K loop and reduce through LDS.
 // Epilogues: 0 plain store; 1 per-mode 2x2 solve (forward transform
-// finished); 2 store minus a field (inverse transform finished: G^n = K^-1 w - q).
+// finished); 2 store minus a field (inverse transform finished: G^n = K^-1 w - q);
+// 3 scaled store (sine coefficients of a field).
 template <int EPI>
 __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
     __shared__ double red[4][2][16][17];
@@ -495,6 +657,9 @@ __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
     } else if (EPI == 2) {
         v0 -= p.sub0[o];
         v1 -= p.sub1[o];
+    } else if (EPI == 3) {
+        v0 *= p.scale;
+        v1 *= p.scale;
     }
     p.C0[o] = v0;
     p.C1[o] = v1;
@@ -578,9 +743,36 @@ void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
         hipLaunchKernelGGL(k_dst_gemm<1>, grid, dim3(256), 0, st, a);
     else if (epi == 2)
         hipLaunchKernelGGL(k_dst_gemm<2>, grid, dim3(256), 0, st, a);
+    else if (epi == 3)
+        hipLaunchKernelGGL(k_dst_gemm<3>, grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_dst_gemm<0>, grid, dim3(256), 0, st, a);
     prof_end(5, st);
+}
+
+void launch_modal_fast(const ModalFastArgs& a, hipStream_t st) {
+    dim3 grid(unsigned((a.M + 3) / 4));
+    const int npl = (a.np + 63) / 64;
+    prof_begin(7, st);
+    if (npl <= 1)
+        hipLaunchKernelGGL(k_modal_fast<1>, grid, dim3(256), 0, st, a);
+    else if (npl <= 2)
+        hipLaunchKernelGGL(k_modal_fast<2>, grid, dim3(256), 0, st, a);
+    else if (npl <= 4)
+        hipLaunchKernelGGL(k_modal_fast<4>, grid, dim3(256), 0, st, a);
+    else if (npl <= 8)
+        hipLaunchKernelGGL(k_modal_fast<8>, grid, dim3(256), 0, st, a);
+    else if (npl <= 12)
+        hipLaunchKernelGGL(k_modal_fast<12>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_modal_fast<16>, grid, dim3(256), 0, st, a);
+    prof_end(7, st);
+}
+
+void launch_modal_near(const ModalNearArgs& a, hipStream_t st) {
+    prof_begin(8, st);
+    hipLaunchKernelGGL(k_modal_near, dim3(unsigned((a.M + 255) / 256)), dim3(256), 0, st, a);
+    prof_end(8, st);
 }
 
 const void* kernel_step_1d(int R) {

@@ -48,7 +48,8 @@ struct Solver {
     // device buffers
     double *d_d = nullptr, *d_ratio = nullptr, *d_coef = nullptr, *G0 = nullptr, *levels = nullptr,
            *H = nullptr, *Spart = nullptr, *F = nullptr, *rhs = nullptr, *T1 = nullptr, *T2 = nullptr,
-           *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr, *Sf = nullptr, *PF = nullptr, *PG = nullptr, *PRB = nullptr;
+           *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr, *Sf = nullptr, *PF = nullptr, *PG = nullptr, *PRB = nullptr, *lam = nullptr,
+           *g0c = nullptr, *ring = nullptr;
     int levels_pcr = 0;
     size_t lds = 0;
     size_t dev_bytes = 0;
@@ -100,6 +101,7 @@ int validate(const cq_grid* g, const cq_params* p) {
     if (p->block_B != 0 && (p->block_B % 64 != 0 || p->block_B > 256))
         return fail(CQ_EINVAL, "block_B must be 64, 128, 192 or 256 (got %d)", p->block_B);
     if (p->np > 4096 || p->np1 > 4096) return fail(CQ_EINVAL, "np, np1 must be <= 4096");
+    if (p->solver != 0 && p->solver != 1) return fail(CQ_EINVAL, "solver must be 0 (nodal) or 1 (modal)");
     return CQ_OK;
 }
 
@@ -227,6 +229,9 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
         }
         s.np = int(rule[0].ratio.size());
         s.L = rule[0].lag;
+        if (p->solver == 1 && (s.L > 64 || s.np > 1024))
+            return fail(CQ_EINVAL, "modal fast solver needs lag <= 64 and <= 1024 nodes (lag %d, nodes %d)", s.L,
+                        s.np);
         s.Bt = std::min(s.L, 32);
         s.BTt = s.Bt <= 8 ? 8 : (s.Bt <= 16 ? 16 : 32);
         s.max_eps = std::max(rule[0].max_eps, rule[1].max_eps);
@@ -244,24 +249,108 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     return CQ_OK;
 }
 
+// sine tables: S[i][j] = sin(pi (i+1)(j+1)/(n+1)) (symmetric, S S = (n+1)/2 I)
+// and eigenvalues lambda_q of the 3-point Dirichlet Laplacian
+std::vector<double> sine_matrix(int n) {
+    std::vector<double> S(size_t(n) * size_t(n));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            // reduce the integer argument first: sin(pi k/(n+1)), k mod 2(n+1)
+            const int64_t kk = (int64_t(i + 1) * (j + 1)) % (2 * int64_t(n + 1));
+            S[size_t(i) * size_t(n) + size_t(j)] = std::sin(M_PI * double(kk) / double(n + 1));
+        }
+    return S;
+}
+
+int upload(double* dst, const std::vector<double>& v) {
+    HIPCHK(hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    return CQ_OK;
+}
+
+int setup_tables(Solver& s) {
+    int rc;
+    const cq_grid* g = &s.g;
+    if ((rc = dev_alloc(s, &s.Sx, size_t(s.nx) * s.nx))) return rc;
+    if ((rc = dev_alloc(s, &s.lamx, size_t(s.nx)))) return rc;
+    std::vector<double> lx(size_t(s.nx));
+    for (int q = 0; q < s.nx; ++q) lx[size_t(q)] = lambda_1d(s.nx, g->lx, q + 1);
+    if ((rc = upload(s.Sx, sine_matrix(s.nx)))) return rc;
+    if ((rc = upload(s.lamx, lx))) return rc;
+    std::vector<double> ly(1, 0.0);
+    if (s.dim == 2) {
+        if ((rc = dev_alloc(s, &s.Sy, size_t(s.ny) * s.ny))) return rc;
+        if ((rc = dev_alloc(s, &s.lamy, size_t(s.ny)))) return rc;
+        ly.assign(size_t(s.ny), 0.0);
+        for (int q = 0; q < s.ny; ++q) ly[size_t(q)] = lambda_1d(s.ny, g->ly, q + 1);
+        if ((rc = upload(s.Sy, sine_matrix(s.ny)))) return rc;
+        if ((rc = upload(s.lamy, ly))) return rc;
+    }
+    if (s.p.solver == 1) {  // eigenvalue of every mode, layout [ny][nx] (row y-mode, column x-mode)
+        if ((rc = dev_alloc(s, &s.lam, size_t(s.M)))) return rc;
+        std::vector<double> lm(size_t(s.M));
+        for (int j = 0; j < s.ny; ++j)
+            for (int i = 0; i < s.nx; ++i) lm[size_t(j) * size_t(s.nx) + size_t(i)] = ly[size_t(j)] + lx[size_t(i)];
+        if ((rc = upload(s.lam, lm))) return rc;
+    }
+    return CQ_OK;
+}
+
+// sine coefficients: out = S G (1D, scaled 2/(n+1)) or S_y G S_x (2D, scaled
+// 4/((nx+1)(ny+1))); both components. tmp: [2][M] (2D).
+void transform(Solver& s, const double* G, double* out, bool forward) {
+    const int64_t M = s.M;
+    if (s.dim == 1) {
+        GemmArgs ga{};
+        ga.R = 1; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
+        ga.A_shared = 0; ga.B_shared = 1;
+        ga.A0 = G; ga.A1 = G + M; ga.B0 = s.Sx; ga.B1 = s.Sx; ga.C0 = out; ga.C1 = out + M;
+        ga.scale = forward ? 2.0 / double(s.nx + 1) : 1.0;
+        launch_gemm(ga, 3, s.st);
+        return;
+    }
+    GemmArgs ga{};
+    ga.R = s.ny; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
+    ga.A_shared = 0; ga.B_shared = 1;
+    ga.A0 = G; ga.A1 = G + M; ga.B0 = s.Sx; ga.B1 = s.Sx; ga.C0 = s.T1; ga.C1 = s.T1 + M;
+    launch_gemm(ga, 0, s.st);
+    GemmArgs gb{};
+    gb.R = s.ny; gb.C = s.nx; gb.K = s.ny; gb.lda = s.ny; gb.ldb = s.nx; gb.ldc = s.nx;
+    gb.A_shared = 1; gb.B_shared = 0;
+    gb.A0 = s.Sy; gb.A1 = s.Sy; gb.B0 = s.T1; gb.B1 = s.T1 + M; gb.C0 = out; gb.C1 = out + M;
+    gb.scale = forward ? 4.0 / (double(s.nx + 1) * double(s.ny + 1)) : 1.0;
+    launch_gemm(gb, 3, s.st);
+}
+
+// (re)start a modal solver from G0 (already in s.G0): coefficients of G0,
+// zero state, level 0 (and the BDF2 level -1 := 0) in place
+int modal_start(Solver& s) {
+    const int64_t twoM = 2 * s.M;
+    transform(s, s.G0, s.g0c, true);
+    if (s.p.method == 1) {
+        HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
+        HIPCHK(hipMemsetAsync(s.ring, 0, size_t(s.L) * size_t(twoM) * sizeof(double), s.st));
+        HIPCHK(hipMemcpyAsync(s.ring, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+        HIPCHK(hipMemcpyAsync(s.ring + twoM, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    } else {
+        HIPCHK(hipMemcpyAsync(s.levels, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    }
+    HIPCHK(hipGetLastError());
+    return CQ_OK;
+}
+
 int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
     const cq_params* p = &s.p;
-    const cq_grid* g = &s.g;
-    // device buffers
     int rc;
     const int64_t twoM = 2 * s.M;
+    const bool modal = p->solver == 1;
     if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
     if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
-    if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
-    if (p->method == 0 && (rc = dev_alloc(s, &s.Spart, size_t(twoM)))) return rc;
     HIPCHK(hipMemcpyAsync(s.d_d, s.dh[0].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
                           st));
     HIPCHK(hipMemcpyAsync(s.G0, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(s.levels, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (p->method == 1) {
         if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * s.M)))) return rc;
-        if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
         if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
         HIPCHK(hipMemsetAsync(s.H, 0, size_t(2 * int64_t(s.np) * s.M) * sizeof(double), st));
@@ -271,11 +360,30 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
                 rr[size_t(k * s.np + j)] = s.rule[k].ratio[size_t(j)];
                 cc[size_t(k * s.np + j)] = s.rule[k].coef[size_t(j)];
             }
-        HIPCHK(hipMemcpy(s.d_ratio, rr.data(), rr.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.d_coef, cc.data(), cc.size() * sizeof(double), hipMemcpyHostToDevice));
-    } else {
+        if ((rc = upload(s.d_ratio, rr))) return rc;
+        if ((rc = upload(s.d_coef, cc))) return rc;
+    }
+    if (p->method == 0) {
         if ((rc = dev_alloc(s, &s.F, size_t(int64_t(s.ks) * s.B * twoM)))) return rc;
     }
+    if (modal) {
+        if ((rc = setup_tables(s))) return rc;
+        if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
+        if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
+        if (p->method == 1) {
+            if ((rc = dev_alloc(s, &s.ring, size_t(s.L) * size_t(twoM)))) return rc;
+        } else {
+            if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
+        }
+        if ((rc = modal_start(s))) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        return CQ_OK;
+    }
+    // nodal
+    if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
+    HIPCHK(hipMemcpyAsync(s.levels, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (p->method == 0 && (rc = dev_alloc(s, &s.Spart, size_t(twoM)))) return rc;
+    if (p->method == 1 && (rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
     if (s.dim == 1) {
         s.levels_pcr = 0;
         while ((int64_t(1) << s.levels_pcr) < s.M) ++s.levels_pcr;
@@ -292,36 +400,15 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
                         s.lds, maxlds);
         std::vector<double> pf, pg, prb;
         pcr_multipliers(s.M, s.levels_pcr, s.theta, s.hx, pf, pg, prb);
-        HIPCHK(hipMemcpy(s.PF, pf.data(), pf.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.PG, pg.data(), pg.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.PRB, prb.data(), prb.size() * sizeof(double), hipMemcpyHostToDevice));
+        if ((rc = upload(s.PF, pf))) return rc;
+        if ((rc = upload(s.PG, pg))) return rc;
+        if ((rc = upload(s.PRB, prb))) return rc;
     } else {
         if ((rc = dev_alloc(s, &s.rhs, size_t(twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.qbuf, size_t(twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.T2, size_t(twoM)))) return rc;
-        if ((rc = dev_alloc(s, &s.Sx, size_t(s.nx) * s.nx))) return rc;
-        if ((rc = dev_alloc(s, &s.Sy, size_t(s.ny) * s.ny))) return rc;
-        if ((rc = dev_alloc(s, &s.lamx, size_t(s.nx)))) return rc;
-        if ((rc = dev_alloc(s, &s.lamy, size_t(s.ny)))) return rc;
-        // DST-I: S[i][j] = sin(pi (i+1)(j+1)/(n+1)), symmetric, S S = (n+1)/2 I
-        auto sine = [](int n) {
-            std::vector<double> S(size_t(n) * n);
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j) {
-                    // reduce the integer argument first: sin(pi k/(n+1)), k mod 2(n+1)
-                    const int64_t kk = (int64_t(i + 1) * (j + 1)) % (2 * int64_t(n + 1));
-                    S[size_t(i) * n + j] = std::sin(M_PI * double(kk) / double(n + 1));
-                }
-            return S;
-        };
-        std::vector<double> sx = sine(s.nx), sy = sine(s.ny), lx(size_t(s.nx)), ly(size_t(s.ny));
-        for (int q = 0; q < s.nx; ++q) lx[size_t(q)] = lambda_1d(s.nx, g->lx, q + 1);
-        for (int q = 0; q < s.ny; ++q) ly[size_t(q)] = lambda_1d(s.ny, g->ly, q + 1);
-        HIPCHK(hipMemcpy(s.Sx, sx.data(), sx.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.Sy, sy.data(), sy.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.lamx, lx.data(), lx.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.lamy, ly.data(), ly.size() * sizeof(double), hipMemcpyHostToDevice));
+        if ((rc = setup_tables(s))) return rc;
     }
     HIPCHK(hipStreamSynchronize(st));
     return CQ_OK;
@@ -352,6 +439,67 @@ void launch_far_block(Solver& s) {
     fa.F = s.F;
     fa.reduce = 1;
     launch_far(fa, s.st);
+}
+
+// modal solver: advance by nsteps
+void modal_steps(Solver& s, int64_t nsteps) {
+    if (s.p.method == 1) {
+        while (nsteps > 0) {
+            const int chunk = int(std::min<int64_t>(nsteps, 8192));
+            ModalFastArgs a{};
+            a.M = s.M;
+            a.n0 = s.n;
+            a.nsteps = chunk;
+            a.np = s.np;
+            a.L = s.L;
+            a.scheme = s.p.scheme;
+            a.dstride = s.dstride;
+            a.inv_tau = 1.0 / s.tau;
+            a.c = s.c;
+            a.a = s.a;
+            a.d0[0] = s.dh[0][0];
+            a.d0[1] = s.dh[1][0];
+            a.lam = s.lam;
+            a.ratio = s.d_ratio;
+            a.coef = s.d_coef;
+            a.d = s.d_d;
+            a.g0 = s.g0c;
+            a.H = s.H;
+            a.ring = s.ring;
+            launch_modal_fast(a, s.st);
+            s.n += chunk;
+            nsteps -= chunk;
+        }
+        return;
+    }
+    while (nsteps > 0) {
+        const int64_t n0 = (s.n / s.B) * s.B;  // block of the next step
+        if (s.n == n0) {
+            s.n0 = n0;
+            if (n0 >= 1) launch_far_block(s);
+        }
+        const int bt = int(std::min<int64_t>(n0 + s.B - s.n, nsteps));
+        ModalNearArgs a{};
+        a.M = s.M;
+        a.n0 = n0;
+        a.nfirst = s.n + 1;
+        a.bt = bt;
+        a.scheme = s.p.scheme;
+        a.dstride = s.dstride;
+        a.inv_tau = 1.0 / s.tau;
+        a.c = s.c;
+        a.a = s.a;
+        a.d0[0] = s.dh[0][0];
+        a.d0[1] = s.dh[1][0];
+        a.lam = s.lam;
+        a.d = s.d_d;
+        a.g0 = s.g0c;
+        a.F = s.F;
+        a.levels = s.levels;
+        launch_modal_near(a, s.st);
+        s.n += bt;
+        nsteps -= bt;
+    }
 }
 
 // one time step n = s.n + 1
@@ -466,14 +614,35 @@ void step_once(Solver& s) {
     launch_gemm(gd, 2, s.st);
 }
 
+// device buffers that make up the state after step n, in order
+struct Seg {
+    double* p;
+    size_t bytes;
+};
+std::vector<Seg> state_segments(const Solver& s, int64_t n) {
+    const size_t twoM = size_t(2 * s.M) * sizeof(double);
+    std::vector<Seg> v;
+    v.push_back({s.G0, twoM});
+    if (s.p.solver == 1) v.push_back({s.g0c, twoM});
+    if (s.p.method == 0) {
+        v.push_back({s.levels, size_t(n + 1) * twoM});
+    } else {
+        const size_t hb = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
+        if (s.p.solver == 1) {
+            v.push_back({s.H, hb});
+            v.push_back({s.ring, size_t(s.L) * twoM});
+        } else {
+            v.push_back({s.levels, size_t(s.Lr) * twoM});
+            v.push_back({s.H, hb});
+            v.push_back({s.Sf, size_t(s.nsplit) * size_t(s.BTt) * twoM});
+        }
+    }
+    return v;
+}
+
 size_t state_bytes(const Solver& s) {
-    const int64_t twoM = 2 * s.M;
-    size_t b = 4 * sizeof(uint64_t) + size_t(twoM) * sizeof(double);  // header, G^0
-    if (s.p.method == 0)
-        b += size_t(s.n + 1) * size_t(twoM) * sizeof(double);
-    else
-        b += (size_t(s.Lr) * size_t(twoM) + size_t(2) * size_t(s.np) * size_t(s.M) +
-              size_t(s.nsplit) * size_t(s.BTt) * size_t(twoM)) * sizeof(double);
+    size_t b = 4 * sizeof(uint64_t);
+    for (const Seg& g : state_segments(s, s.n)) b += g.bytes;
     return b;
 }
 
@@ -481,7 +650,7 @@ size_t state_bytes(const Solver& s) {
 
 // ---- kernel timing ----
 namespace {
-constexpr int kProfKinds = 7;
+constexpr int kProfKinds = 9;
 struct ProfRec {
     hipEvent_t a, b;
 };
@@ -687,7 +856,10 @@ int fp_step(void* handle, int64_t nsteps) {
     if (nsteps < 0 || s.n + nsteps > s.N)
         return fail(CQ_EINVAL, "cannot take %lld steps from n = %lld (N = %lld)", (long long)nsteps, (long long)s.n,
                     (long long)s.N);
-    for (int64_t i = 0; i < nsteps; ++i) step_once(s);
+    if (s.p.solver == 1)
+        modal_steps(s, nsteps);
+    else
+        for (int64_t i = 0; i < nsteps; ++i) step_once(s);
     HIPCHK(hipGetLastError());
     return CQ_OK;
 }
@@ -696,6 +868,13 @@ int fp_current(void* handle, double* G_out, int64_t* n_out) {
     clear_error();
     if (!handle || !G_out) return fail(CQ_EINVAL, "NULL argument");
     Solver& s = *static_cast<Solver*>(handle);
+    if (s.p.solver == 1) {
+        const double* c = s.p.method == 1 ? s.ring : s.levels + s.n * 2 * s.M;
+        transform(s, c, G_out, false);
+        HIPCHK(hipGetLastError());
+        if (n_out) *n_out = s.n;
+        return CQ_OK;
+    }
     const double* src = s.levels + (s.n % s.Lr) * 2 * s.M;
     HIPCHK(hipMemcpyAsync(G_out, src, size_t(2 * s.M) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
     if (n_out) *n_out = s.n;
@@ -737,19 +916,9 @@ int fp_get_state(void* handle, void* dst, size_t* bytes) {
     hdr[2] = uint64_t(s.M);
     hdr[3] = uint64_t(s.np);
     char* q = static_cast<char*>(dst) + 4 * sizeof(uint64_t);
-    const int64_t twoM = 2 * s.M;
-    HIPCHK(hipMemcpy(q, s.G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToHost));
-    q += size_t(twoM) * sizeof(double);
-    if (s.p.method == 0) {
-        const size_t b = size_t(s.n + 1) * size_t(twoM) * sizeof(double);
-        HIPCHK(hipMemcpy(q, s.levels, b, hipMemcpyDeviceToHost));
-    } else {
-        const size_t b1 = size_t(s.Lr) * size_t(twoM) * sizeof(double);
-        HIPCHK(hipMemcpy(q, s.levels, b1, hipMemcpyDeviceToHost));
-        const size_t b2 = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
-        HIPCHK(hipMemcpy(q + b1, s.H, b2, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(q + b1 + b2, s.Sf, size_t(s.nsplit) * s.BTt * size_t(twoM) * sizeof(double),
-                         hipMemcpyDeviceToHost));
+    for (const Seg& g : state_segments(s, s.n)) {
+        HIPCHK(hipMemcpy(q, g.p, g.bytes, hipMemcpyDeviceToHost));
+        q += g.bytes;
     }
     *bytes = need;
     return CQ_OK;
@@ -774,21 +943,13 @@ int fp_set_state(void* handle, const void* src, size_t bytes) {
     }
     HIPCHK(hipStreamSynchronize(s.st));
     const char* q = static_cast<const char*>(src) + 4 * sizeof(uint64_t);
-    const int64_t twoM = 2 * s.M;
-    HIPCHK(hipMemcpy(s.G0, q, size_t(twoM) * sizeof(double), hipMemcpyHostToDevice));
-    q += size_t(twoM) * sizeof(double);
-    if (s.p.method == 0) {
-        HIPCHK(hipMemcpy(s.levels, q, size_t(n + 1) * size_t(twoM) * sizeof(double), hipMemcpyHostToDevice));
-        // far field of the block that contains step n+1
+    for (const Seg& g : state_segments(s, n)) {
+        HIPCHK(hipMemcpy(g.p, q, g.bytes, hipMemcpyHostToDevice));
+        q += g.bytes;
+    }
+    if (s.p.method == 0) {  // far field of the block that contains step n+1
         s.n0 = (n / s.B) * s.B;
         if (n % s.B != 0 && s.n0 >= 1) launch_far_block(s);
-    } else {
-        const size_t b1 = size_t(s.Lr) * size_t(twoM) * sizeof(double);
-        HIPCHK(hipMemcpy(s.levels, q, b1, hipMemcpyHostToDevice));
-        const size_t b2 = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
-        HIPCHK(hipMemcpy(s.H, q + b1, b2, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(s.Sf, q + b1 + b2, size_t(s.nsplit) * s.BTt * size_t(twoM) * sizeof(double),
-                         hipMemcpyHostToDevice));
     }
     HIPCHK(hipGetLastError());
     return CQ_OK;
@@ -802,10 +963,11 @@ int fp_reset(void* handle, const double* G0) {
     int rc = check_finite_g0(G0, twoM, s.st);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
-    HIPCHK(hipMemcpyAsync(s.levels, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
-    if (s.H) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
     s.n = 0;
     s.n0 = 0;
+    if (s.p.solver == 1) return modal_start(s);
+    HIPCHK(hipMemcpyAsync(s.levels, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    if (s.H) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
     return CQ_OK;
 }
 

@@ -69,14 +69,15 @@ SMALL = [
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0]}d{c[1]}x{c[2]}N{c[7]}")
 @pytest.mark.parametrize("scheme", [1, 2])
 @pytest.mark.parametrize("method", [0, 1])
-def test_solve_matches_oracle(case, scheme, method):
+@pytest.mark.parametrize("solver", [0, 1], ids=["nodal", "modal"])
+def test_solve_matches_oracle(case, scheme, method, solver):
     dim, nx, ny, a1, a2, m, T, N = case
-    print(f"solve case={case} scheme={scheme} method={method}", flush=True)
+    print(f"solve case={case} scheme={scheme} method={method} solver={solver}", flush=True)
     G0 = wl.g0_intervals(nx, 2) if dim == 1 else wl.g0_rectangle(nx, ny, 3)
     if nx == 1:
         G0 = np.array([[1.0], [0.5]])
     g = cq.make_grid(dim, nx, ny)
-    p = cq.make_params(a1, a2, m, T, N, scheme, method)
+    p = cq.make_params(a1, a2, m, T, N, scheme, method, solver=solver)
     with cq.Solver(g, p, dev(G0)) as s:
         info = s.info()
         s.step(N)
@@ -100,13 +101,14 @@ def test_solve_matches_oracle(case, scheme, method):
 
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("dim", [1, 2])
-def test_one_step_and_block_boundaries(method, dim):
+@pytest.mark.parametrize("solver", [0, 1], ids=["nodal", "modal"])
+def test_one_step_and_block_boundaries(method, dim, solver):
     """N = 1, and N straddling direct blocks (B = 64) step by step."""
     nx, ny = (40, 1) if dim == 1 else (20, 9)
     G0 = wl.g0_random(nx * ny, 4)
     for N in (1, 2, 64, 65, 129):
-        print(f"blocks dim={dim} method={method} N={N}", flush=True)
-        p = cq.make_params(0.45, 0.55, 0.65, 0.5, N, 2, method, block_B=64)
+        print(f"blocks dim={dim} method={method} solver={solver} N={N}", flush=True)
+        p = cq.make_params(0.45, 0.55, 0.65, 0.5, N, 2, method, block_B=64, solver=solver)
         out = cq.fp_solve(cq.make_grid(dim, nx, ny), p, dev(G0)).cpu().numpy()
         ref = modal.reference(dim, nx, ny, 0.45, 0.55, 0.65, 0.5, N, G0, 2, 0)
         assert rel(out, ref) <= (1e-12 if method == 0 else 1e-8)
@@ -124,11 +126,13 @@ def test_direct_block_sizes(block_B):
 
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("dim", [1, 2])
-def test_state_roundtrip_is_bitwise(method, dim):
+@pytest.mark.parametrize("solver", [0, 1], ids=["nodal", "modal"])
+def test_state_roundtrip_is_bitwise(method, dim, solver):
     nx, ny = (50, 1) if dim == 1 else (12, 10)
     N, k = 140, 77
     G0 = wl.g0_random(nx * ny, 12)
-    g, p = cq.make_grid(dim, nx, ny), cq.make_params(0.3, 0.7, 0.6, 1.0, N, 2, method, block_B=64)
+    g, p = cq.make_grid(dim, nx, ny), cq.make_params(0.3, 0.7, 0.6, 1.0, N, 2, method, block_B=64,
+                                                     solver=solver)
     with cq.Solver(g, p, dev(G0)) as s:
         s.step(N)
         full = s.current()[0].cpu().numpy()
@@ -148,6 +152,26 @@ def test_nonfinite_g0_rejected():
     with pytest.raises(cq.CQError) as e:
         cq.Solver(cq.make_grid(1, 9), cq.make_params(0.3, 0.7, 0.3, 1.0, 4, 1, 0), dev(G0))
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_modal_and_nodal_agree_stepwise(method, dim):
+    """Read out after every few steps: both solvers give the same levels."""
+    nx, ny = (33, 1) if dim == 1 else (17, 15)
+    N = 90
+    G0 = wl.g0_random(nx * ny, 21)
+    g = cq.make_grid(dim, nx, ny)
+    outs = []
+    for solver in (0, 1):
+        with cq.Solver(g, cq.make_params(0.25, 0.75, 0.7, 1.0, N, 1, method, solver=solver), dev(G0)) as s:
+            seq = []
+            for chunk in (1, 2, 29, 58):
+                s.step(chunk)
+                seq.append(s.current()[0].cpu().numpy())
+            outs.append(seq)
+    for a, b in zip(*outs):
+        assert rel(a, b) <= 1e-12
 
 
 def test_step_past_end_rejected():
