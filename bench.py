@@ -31,6 +31,7 @@ WORKLOADS = {
 }
 VARIANTS = [(1, 1), (1, 0), (2, 1), (2, 0)]  # (scheme, method)
 VNAME = {(1, 1): "be_fast", (1, 0): "be_direct", (2, 1): "bdf2_fast", (2, 0): "bdf2_direct"}
+SOLVERS = {"nodal": 0, "modal": 1}
 
 
 def g0_for(w):
@@ -139,6 +140,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--variants", default="all", help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct")
+    ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
+                    help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="do not time kernels with events")
     args = ap.parse_args()
@@ -163,7 +166,7 @@ def main():
     grid = cq.make_grid(dim, nx, ny)
     solvers = {}
     for v in variants:
-        solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1]), G0)
+        solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1], solver=SOLVERS[args.solver]), G0)
     outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
 
     def one_step(events=None):
@@ -198,7 +201,8 @@ def main():
     value = dofsteps / elapsed
 
     # kernel timing and roofline of the dominant kernel
-    kinds = ["hist_fast", "hist_direct", "far_toeplitz", "solve_1d", "prep_2d", "dst_gemm"]
+    kinds = ["hist_fast", "hist_direct", "far_toeplitz", "solve_1d", "prep_2d", "dst_gemm", "modal_fast",
+             "modal_near"]
     ktime = {}
     if not args.no_prof:
         for kname in kinds:
@@ -260,6 +264,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded indicator initial data)",
         "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
+                   "solver": args.solver,
                    "variants": [VNAME[v] for v in variants], "dof": 2 * M, "N": N,
                    "fast_nodes": info_np},
         "breakdown": breakdown,

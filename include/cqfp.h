@@ -67,7 +67,8 @@ typedef struct {
  *  np1: N_{p,1} for BDF2 (0 selects 16). ns: N_s for BDF2 (0 selects 30;
  *    must be >= 3). np_max: scan limit (0 selects 1024).
  *  block_B: direct method, time-block length of the Toeplitz far-field
- *    update (0 = automatic; otherwise 64, 128, 192 or 256).
+ *    update (0 = automatic; otherwise 64, 128, 192 or 256; the modal solver
+ *    always uses 64).
  *  solver: 0 = nodal: every step assembles the right-hand side on the grid
  *    and solves the coupled system (cyclic reduction in 1D, sine transform
  *    with a 2x2 solve per mode in 2D); 1 = modal: the sine transform is

@@ -118,8 +118,28 @@ struct ModalNearArgs {
     double* levels;       // [N+1][2][M] coefficients
 };
 
+struct ModalWinArgs {
+    int64_t M;
+    int64_t nfirst;       // first step taken here
+    int64_t nblk;         // first step of the block whose Sf is in the buffer
+    int bt;               // steps taken here (within that block)
+    int L;                // lag (<= 32)
+    int64_t Lr;           // slots of the level store (= L)
+    int nsplit, BT;       // Sf[nsplit][BT][2][M]
+    int scheme;
+    int64_t dstride;
+    double inv_tau, c, a;
+    double d0[2];
+    const double* lam;
+    const double* d;
+    const double* g0;
+    const double* Sf;
+    double* levels;       // [Lr][2][M] coefficients, level l at slot l mod Lr
+};
+
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
-void launch_modal_near(const ModalNearArgs& a, hipStream_t st);
+void launch_modal_win(const ModalWinArgs& a, hipStream_t st);
+void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st);
 void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);

@@ -538,10 +538,109 @@ __global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
     }
 }
 
+// Fast form for many modes: the compressed state streams through
+// k_hist_block (time-blocked, exactly as for the nodal solver, here on the
+// sine coefficients), and this kernel takes the steps of the block: thread
+// per mode, S = sum of the block's partial sums Sf[.][b] + the exact-weight
+// window sum_{i<min(L-1,n-1)} d_{i+1} g^{n-1-i} from a register ring
+// (ring[i] = g^{n-1-i}, levels below 0 read as g^0 for BDF2's g^{-1}), then
+// the 2x2 solve; the new level goes to its slot of the level store (the
+// state pass of the next block reads it there).
+template <int LW>
+__global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
+    const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (mode >= p.M) return;
+    const int64_t M = p.M, twoM = 2 * M;
+    const double lam = p.lam[mode];
+    const double g00 = p.g0[mode], g01 = p.g0[M + mode];
+    const double L1 = p.a + lam;
+    const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
+    const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    const double* __restrict__ d0p = p.d;
+    const double* __restrict__ d1p = p.d + p.dstride;
+    double* __restrict__ lv = p.levels + mode;
+    double ring0[LW], ring1[LW];
+#pragma unroll
+    for (int i = 0; i < LW; ++i) {
+        int64_t l = p.nfirst - 1 - i;
+        if (l < 0) l = 0;
+        const bool ok = i < p.L && l >= p.nfirst - p.L;  // still in the store
+        const int64_t sl = l % p.Lr;
+        ring0[i] = ok ? lv[sl * twoM] : 0.0;
+        ring1[i] = ok ? lv[sl * twoM + M] : 0.0;
+    }
+    // partial sums of the next step are loaded one step ahead
+    auto sf = [&](int64_t b, int k) {
+        double v = 0.0;
+        for (int c = 0; c < p.nsplit; ++c) v += p.Sf[((int64_t(c) * p.BT + b) * 2 + k) * M + mode];
+        return v;
+    };
+    double f0 = 0.0, f1 = 0.0;
+    if (p.bt > 0) {
+        f0 = sf(p.nfirst - p.nblk, 0);
+        f1 = sf(p.nfirst - p.nblk, 1);
+    }
+    for (int t = 0; t < p.bt; ++t) {
+        const int64_t n = p.nfirst + t;
+        const int64_t b = n - p.nblk;
+        double S0 = f0, S1 = f1;
+        if (t + 1 < p.bt) {
+            f0 = sf(b + 1, 0);
+            f1 = sf(b + 1, 1);
+        }
+        const int64_t wn = (n - 1 < p.L - 1) ? n - 1 : p.L - 1;
+        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int i = 0; i + 1 < LW; i += 2) {
+            if (i < wn) {
+                a0 = fma(d0p[i + 1], ring0[i], a0);
+                a1 = fma(d1p[i + 1], ring1[i], a1);
+            }
+            if (i + 1 < wn) {
+                c0 = fma(d0p[i + 2], ring0[i + 1], c0);
+                c1 = fma(d1p[i + 2], ring1[i + 1], c1);
+            }
+        }
+        S0 += a0 + c0;
+        S1 += a1 + c1;
+        double E0, E1;
+        if (p.scheme == 1) {
+            E0 = ring0[0] * p.inv_tau;
+            E1 = ring1[0] * p.inv_tau;
+        } else {
+            E0 = (2.0 * ring0[0] - 0.5 * ring0[1]) * p.inv_tau;
+            E1 = (2.0 * ring1[0] - 0.5 * ring1[1]) * p.inv_tau;
+            S0 = fma(0.5 * d0p[n - 1], g00, S0);
+            S1 = fma(0.5 * d1p[n - 1], g01, S1);
+        }
+        const double r0 = E0 - (L1 * S0 - p.a * S1);
+        const double r1 = E1 - (L1 * S1 - p.a * S0);
+        const double gn0 = (m22 * r0 - m12 * r1) * idet;
+        const double gn1 = (m11 * r1 - m21 * r0) * idet;
+        const int64_t so = n % p.Lr;
+        lv[so * twoM] = gn0;
+        lv[so * twoM + M] = gn1;
+#pragma unroll
+        for (int i = LW - 1; i > 0; --i) {
+            ring0[i] = ring0[i - 1];
+            ring1[i] = ring1[i - 1];
+        }
+        ring0[0] = gn0;
+        ring1[0] = gn1;
+    }
+}
+
 // Direct form, part of one time block: thread per mode takes the steps
-// n = nfirst .. nfirst+bt-1 (inside the block n0+1 .. n0+B) in order. S = F[b] (far field of the block, summed over
-// the K-split by k_reduce_far) + sum_{l=n0+1}^{n-1} d_{n-l} g^l (the levels
-// of this block, written by this same thread).
+// n = nfirst .. nfirst+bt-1 (inside the block n0+1 .. n0+B) in order.
+// S = F[b] (far field of the block, summed over the K-split by
+// k_reduce_far) + sum_{l=n0+1}^{n-1} d_{n-l} g^l. The levels of this block
+// stay in registers: ring[i] = g^{n-1-i}, i < BB, zero for levels before the
+// block; a step shifts them by one. BDF2's time part keeps g^{n-1}, g^{n-2}
+// apart (they may belong to the previous block). The weights d_1..d_{BB-1}
+// are wave-uniform. A block that starts mid-way (a run resumed inside a
+// block) first reloads its earlier in-block levels from memory.
+template <int BB>
 __global__ __launch_bounds__(256) void k_modal_near(ModalNearArgs p) {
     const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (mode >= p.M) return;
@@ -555,37 +654,69 @@ __global__ __launch_bounds__(256) void k_modal_near(ModalNearArgs p) {
     double* __restrict__ lv = p.levels + mode;
     const double* __restrict__ d0p = p.d;
     const double* __restrict__ d1p = p.d + p.dstride;
+    double ring0[BB], ring1[BB];
+#pragma unroll
+    for (int i = 0; i < BB; ++i) {
+        const int64_t l = p.nfirst - 1 - i;  // in-block levels already taken
+        const bool in = l >= p.n0 + 1;
+        ring0[i] = in ? lv[l * twoM] : 0.0;
+        ring1[i] = in ? lv[l * twoM + M] : 0.0;
+    }
+    double gm1_0 = lv[(p.nfirst - 1) * twoM], gm1_1 = lv[(p.nfirst - 1) * twoM + M];
+    const int64_t l2i = (p.nfirst >= 2) ? p.nfirst - 2 : 0;
+    double gm2_0 = lv[l2i * twoM], gm2_1 = lv[l2i * twoM + M];
+    // far-field values of the next step are loaded one step ahead
+    double f0 = 0.0, f1 = 0.0;
+    if (p.n0 >= 1 && p.bt > 0) {
+        const int64_t b = p.nfirst - p.n0 - 1;
+        f0 = p.F[(b * 2 + 0) * M + mode];
+        f1 = p.F[(b * 2 + 1) * M + mode];
+    }
     for (int t = 0; t < p.bt; ++t) {
         const int64_t n = p.nfirst + t;
         const int64_t b = n - p.n0 - 1;
-        double S0 = 0.0, S1 = 0.0;
-        if (p.n0 >= 1) {
-            S0 = p.F[(int64_t(b) * 2 + 0) * M + mode];
-            S1 = p.F[(int64_t(b) * 2 + 1) * M + mode];
+        double S0 = f0, S1 = f1;
+        if (p.n0 >= 1 && t + 1 < p.bt) {
+            f0 = p.F[((b + 1) * 2 + 0) * M + mode];
+            f1 = p.F[((b + 1) * 2 + 1) * M + mode];
         }
-        double a0 = 0.0, a1 = 0.0;
-        for (int64_t l = p.n0 + 1; l <= n - 1; ++l) {
-            a0 = fma(d0p[n - l], lv[l * twoM], a0);
-            a1 = fma(d1p[n - l], lv[l * twoM + M], a1);
+        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int i = 0; i + 1 < BB; i += 2) {
+            a0 = fma(d0p[i + 1], ring0[i], a0);
+            a1 = fma(d1p[i + 1], ring1[i], a1);
+            c0 = fma(d0p[i + 2], ring0[i + 1], c0);
+            c1 = fma(d1p[i + 2], ring1[i + 1], c1);
         }
-        S0 += a0;
-        S1 += a1;
-        const double gm10 = lv[(n - 1) * twoM], gm11 = lv[(n - 1) * twoM + M];
+        S0 += a0 + c0;
+        S1 += a1 + c1;
         double E0, E1;
         if (p.scheme == 1) {
-            E0 = gm10 * p.inv_tau;
-            E1 = gm11 * p.inv_tau;
+            E0 = gm1_0 * p.inv_tau;
+            E1 = gm1_1 * p.inv_tau;
         } else {
-            const int64_t l2 = (n >= 2) ? n - 2 : 0;
-            E0 = (2.0 * gm10 - 0.5 * lv[l2 * twoM]) * p.inv_tau;
-            E1 = (2.0 * gm11 - 0.5 * lv[l2 * twoM + M]) * p.inv_tau;
+            E0 = (2.0 * gm1_0 - 0.5 * gm2_0) * p.inv_tau;
+            E1 = (2.0 * gm1_1 - 0.5 * gm2_1) * p.inv_tau;
             S0 = fma(0.5 * d0p[n - 1], g00, S0);
             S1 = fma(0.5 * d1p[n - 1], g01, S1);
         }
         const double r0 = E0 - (L1 * S0 - p.a * S1);
         const double r1 = E1 - (L1 * S1 - p.a * S0);
-        lv[n * twoM] = (m22 * r0 - m12 * r1) * idet;
-        lv[n * twoM + M] = (m11 * r1 - m21 * r0) * idet;
+        const double gn0 = (m22 * r0 - m12 * r1) * idet;
+        const double gn1 = (m11 * r1 - m21 * r0) * idet;
+        lv[n * twoM] = gn0;
+        lv[n * twoM + M] = gn1;
+#pragma unroll
+        for (int i = BB - 1; i > 0; --i) {
+            ring0[i] = ring0[i - 1];
+            ring1[i] = ring1[i - 1];
+        }
+        ring0[0] = gn0;
+        ring1[0] = gn1;
+        gm2_0 = gm1_0;
+        gm2_1 = gm1_1;
+        gm1_0 = gn0;
+        gm1_1 = gn1;
     }
 }
 
@@ -769,9 +900,23 @@ void launch_modal_fast(const ModalFastArgs& a, hipStream_t st) {
     prof_end(7, st);
 }
 
-void launch_modal_near(const ModalNearArgs& a, hipStream_t st) {
+void launch_modal_win(const ModalWinArgs& a, hipStream_t st) {
+    prof_begin(7, st);
+    hipLaunchKernelGGL(k_modal_win<32>, dim3(unsigned((a.M + 255) / 256)), dim3(256), 0, st, a);
+    prof_end(7, st);
+}
+
+void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st) {
+    const dim3 grid(unsigned((a.M + 255) / 256));
     prof_begin(8, st);
-    hipLaunchKernelGGL(k_modal_near, dim3(unsigned((a.M + 255) / 256)), dim3(256), 0, st, a);
+    if (B <= 64)
+        hipLaunchKernelGGL(k_modal_near<64>, grid, dim3(256), 0, st, a);
+    else if (B <= 128)
+        hipLaunchKernelGGL(k_modal_near<128>, grid, dim3(256), 0, st, a);
+    else if (B <= 192)
+        hipLaunchKernelGGL(k_modal_near<192>, grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_modal_near<256>, grid, dim3(256), 0, st, a);
     prof_end(8, st);
 }
 

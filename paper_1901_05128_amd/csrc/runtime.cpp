@@ -26,6 +26,7 @@ using namespace cqfp;
 namespace {
 
 constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
+constexpr int64_t kModalBlockedMin = 8192;      // modes
 
 struct Solver {
     cq_grid g{};
@@ -51,6 +52,7 @@ struct Solver {
            *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr, *Sf = nullptr, *PF = nullptr, *PG = nullptr, *PRB = nullptr, *lam = nullptr,
            *g0c = nullptr, *ring = nullptr;
     int levels_pcr = 0;
+    bool modal_blocked = false;  // modal fast form with the state streamed in time blocks
     size_t lds = 0;
     size_t dev_bytes = 0;
     std::vector<void*> allocs;
@@ -174,6 +176,7 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     // direct block length and K-split (enough workgroups to fill 256 CUs)
     if (p->method == 0) {
         s.B = p->block_B ? p->block_B : (s.dim == 1 ? 64 : 128);
+        if (p->solver == 1) s.B = 64;  // the modal near field keeps a 64-level ring in registers
         const int64_t tiles = 2 * ((s.M + 63) / 64);
         s.ks = int(std::min<int64_t>(64, std::max<int64_t>(1, (1024 + tiles - 1) / tiles)));
     }
@@ -326,7 +329,11 @@ void transform(Solver& s, const double* G, double* out, bool forward) {
 int modal_start(Solver& s) {
     const int64_t twoM = 2 * s.M;
     transform(s, s.G0, s.g0c, true);
-    if (s.p.method == 1) {
+    if (s.p.method == 1 && s.modal_blocked) {
+        HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
+        HIPCHK(hipMemsetAsync(s.levels, 0, size_t(s.Lr) * size_t(twoM) * sizeof(double), s.st));
+        HIPCHK(hipMemcpyAsync(s.levels, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+    } else if (s.p.method == 1) {
         HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
         HIPCHK(hipMemsetAsync(s.ring, 0, size_t(s.L) * size_t(twoM) * sizeof(double), s.st));
         HIPCHK(hipMemcpyAsync(s.ring, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
@@ -371,7 +378,16 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
         if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
         if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
         if (p->method == 1) {
-            if ((rc = dev_alloc(s, &s.ring, size_t(s.L) * size_t(twoM)))) return rc;
+            // many modes: stream the state in time blocks (thread per mode);
+            // few modes: keep each mode's state in the registers of one wave
+            s.modal_blocked = s.M >= kModalBlockedMin && s.L <= 32;
+            if (s.modal_blocked) {
+                s.Lr = s.L;
+                if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr) * size_t(twoM)))) return rc;
+                if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
+            } else {
+                if ((rc = dev_alloc(s, &s.ring, size_t(s.L) * size_t(twoM)))) return rc;
+            }
         } else {
             if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
         }
@@ -443,6 +459,55 @@ void launch_far_block(Solver& s) {
 
 // modal solver: advance by nsteps
 void modal_steps(Solver& s, int64_t nsteps) {
+    if (s.p.method == 1 && s.modal_blocked) {
+        while (nsteps > 0) {
+            const int64_t nblk = (s.n / s.Bt) * s.Bt + 1;  // block of the next step
+            if (s.n + 1 == nblk) {
+                HistBlockArgs hb{};
+                hb.n = nblk;
+                hb.L = s.L;
+                hb.Lr = s.Lr;
+                hb.M = s.M;
+                hb.np = s.np;
+                hb.chunk = s.chunk;
+                hb.BT = s.BTt;
+                hb.bt = int(std::min<int64_t>(s.Bt, s.N - nblk + 1));
+                hb.slot0 = ((nblk - s.L) % s.Lr + s.Lr) % s.Lr;
+                hb.levels = s.levels;
+                hb.H = s.H;
+                hb.ratio = s.d_ratio;
+                hb.coef = s.d_coef;
+                hb.Sf = s.Sf;
+                launch_hist_block(hb, s.nsplit, s.st);
+            }
+            const int bt = int(std::min<int64_t>(nblk + s.Bt - 1 - s.n, nsteps));
+            ModalWinArgs a{};
+            a.M = s.M;
+            a.nfirst = s.n + 1;
+            a.nblk = nblk;
+            a.bt = bt;
+            a.L = s.L;
+            a.Lr = s.Lr;
+            a.nsplit = s.nsplit;
+            a.BT = s.BTt;
+            a.scheme = s.p.scheme;
+            a.dstride = s.dstride;
+            a.inv_tau = 1.0 / s.tau;
+            a.c = s.c;
+            a.a = s.a;
+            a.d0[0] = s.dh[0][0];
+            a.d0[1] = s.dh[1][0];
+            a.lam = s.lam;
+            a.d = s.d_d;
+            a.g0 = s.g0c;
+            a.Sf = s.Sf;
+            a.levels = s.levels;
+            launch_modal_win(a, s.st);
+            s.n += bt;
+            nsteps -= bt;
+        }
+        return;
+    }
     if (s.p.method == 1) {
         while (nsteps > 0) {
             const int chunk = int(std::min<int64_t>(nsteps, 8192));
@@ -496,7 +561,7 @@ void modal_steps(Solver& s, int64_t nsteps) {
         a.g0 = s.g0c;
         a.F = s.F;
         a.levels = s.levels;
-        launch_modal_near(a, s.st);
+        launch_modal_near(a, s.B, s.st);
         s.n += bt;
         nsteps -= bt;
     }
@@ -628,7 +693,7 @@ std::vector<Seg> state_segments(const Solver& s, int64_t n) {
         v.push_back({s.levels, size_t(n + 1) * twoM});
     } else {
         const size_t hb = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
-        if (s.p.solver == 1) {
+        if (s.p.solver == 1 && !s.modal_blocked) {
             v.push_back({s.H, hb});
             v.push_back({s.ring, size_t(s.L) * twoM});
         } else {
@@ -869,7 +934,8 @@ int fp_current(void* handle, double* G_out, int64_t* n_out) {
     if (!handle || !G_out) return fail(CQ_EINVAL, "NULL argument");
     Solver& s = *static_cast<Solver*>(handle);
     if (s.p.solver == 1) {
-        const double* c = s.p.method == 1 ? s.ring : s.levels + s.n * 2 * s.M;
+        const double* c = s.p.method == 1 ? (s.modal_blocked ? s.levels + (s.n % s.Lr) * 2 * s.M : s.ring)
+                                           : s.levels + s.n * 2 * s.M;
         transform(s, c, G_out, false);
         HIPCHK(hipGetLastError());
         if (n_out) *n_out = s.n;

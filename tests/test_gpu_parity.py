@@ -63,6 +63,7 @@ SMALL = [
     (1, 1, 1, 0.5, 0.5, 0.2, 1.0, 7),
     (2, 31, 17, 0.2, 0.6, 0.55, 1.0, 100),      # ragged 2D tiles
     (2, 63, 63, 0.35, 0.65, 0.0, 1.0, 160),     # a = -1
+    (2, 97, 85, 0.3, 0.6, 0.6, 1.0, 100),       # >= 8192 modes: blocked modal fast form
 ]
 
 
