@@ -179,12 +179,41 @@ int fp_destroy(void* handle);
 int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double* GN,
              void* hip_stream);
 
+/* Batched fast solves (extension): `count` independent problems (own grid,
+ * orders, m, T, N, scheme; method must be 1, the fast form) solved by the
+ * modal solver in one captured HIP graph. Every problem's sine modes are
+ * work items of one persistent kernel per register class (problems grouped
+ * by nodes per lane), each mode running its problem's whole time loop, so
+ * problems of uneven size share the GPU without a barrier between them.
+ * G0[i], GN[i]: dev [2][M_i] (caller-owned, distinct). autotune != 0 times
+ * 64 and 32 lanes per mode for every class on a short run and keeps the
+ * faster (cached for the process); otherwise 64. The caller's stream is
+ * waited on before the solve and the call returns when every GN[i] is
+ * written. Temporary device buffers are allocated and freed inside.
+ * report (may be NULL) receives the classes and timings. */
+typedef struct {
+    int32_t problems;
+    int64_t modes;            /* sum of M_i                                   */
+    int32_t classes;          /* register classes launched (<= 8 reported)   */
+    int32_t class_npl64[8];   /* nodes per lane at 64 lanes of each class    */
+    int32_t class_lanes[8];   /* lanes per mode chosen for each class        */
+    int32_t class_problems[8];
+    double setup_s;           /* host set-up and forward transforms          */
+    double autotune_s;        /* tile timing (0 when cached or disabled)     */
+    double run_s;             /* the graph: time loops and inverse transforms */
+} cq_batch_report;
+
+int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_params* params,
+                     const double* const* G0, double* const* GN, void* hip_stream,
+                     int32_t autotune, cq_batch_report* report);
+
 /* Kernel timing (opt-in). While enabled, every kernel launch of the library
  * is bracketed by a pair of HIP events on the stream it runs on. The kernels
  * are grouped by kind: 0 fast history, 1 direct near field, 2 Toeplitz far
  * field (FP64 MFMA), 3 1D right-hand side + PCR solve, 4 2D right-hand side,
  * 5 DST GEMM (forward/inverse and per-mode solve), 6 standalone history
- * reduction, 7 modal fast steps, 8 modal direct near field + solve. cq_prof_read synchronises the recorded events and returns, for
+ * reduction, 7 modal fast steps, 8 modal direct near field + solve,
+ * 9 batched modal fast time loops. cq_prof_read synchronises the recorded events and returns, for
  * one kind, the launch count and the summed duration in milliseconds.
  * cq_prof_enable(1) also clears earlier records. Not thread safe. */
 int cq_prof_enable(int32_t on);

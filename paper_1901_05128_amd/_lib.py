@@ -22,8 +22,8 @@ STATUS_NAMES = {0: "CQ_OK", -1: "CQ_EINVAL", -2: "CQ_ESINGULAR", -3: "CQ_ENOMEM"
 
 # every entry point the header declares
 EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "fp_current", "fp_info",
-           "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "cq_prof_enable", "cq_prof_read",
-           "cq_last_error"]
+           "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "fp_solve_batched",
+           "cq_prof_enable", "cq_prof_read", "cq_last_error"]
 PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
               "reduce_row": 6, "modal_fast": 7, "modal_near": 8}
 
@@ -49,6 +49,12 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("N", C.c_int64), ("np_total", C.c_int32), ("lag", C.c_int32),
                 ("max_eps", C.c_double), ("theta", C.c_double * 2), ("block_B", C.c_int32),
                 ("ksplit", C.c_int32), ("device_bytes", C.c_size_t), ("state_bytes", C.c_size_t)]
+
+
+class BatchReport(C.Structure):
+    _fields_ = [("problems", C.c_int32), ("modes", C.c_int64), ("classes", C.c_int32),
+                ("class_npl64", C.c_int32 * 8), ("class_lanes", C.c_int32 * 8), ("class_problems", C.c_int32 * 8),
+                ("setup_s", C.c_double), ("autotune_s", C.c_double), ("run_s", C.c_double)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -81,6 +87,7 @@ def lib() -> C.CDLL:
     L.cq_prof_enable.argtypes = [I32]
     L.cq_prof_read.argtypes = [I32, P(I64), P(D)]
     L.fp_solve.argtypes = [P(Grid), P(Params), VP, VP, VP]
+    L.fp_solve_batched.argtypes = [I32, P(Grid), P(Params), P(VP), P(VP), VP, I32, P(BatchReport)]
     L.cq_last_error.argtypes = []
     L.cq_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -231,3 +238,21 @@ def fp_solve(grid: Grid, params: Params, G0, GN=None):
         GN = torch.empty((2, M), dtype=torch.float64, device=G0.device)
     _check(lib().fp_solve(C.byref(grid), C.byref(params), _dev(G0, "G0"), _dev(GN, "GN"), _stream()))
     return GN
+
+
+def fp_solve_batched(grids, params, G0s, GNs=None, autotune=True):
+    """Solve len(grids) independent fast problems in one batched launch.
+    Returns (list of GN tensors, BatchReport)."""
+    import torch
+    n = len(grids)
+    if not (len(params) == n == len(G0s)):
+        raise CQError(CQ_EINVAL, "grids, params and G0s must have the same length")
+    if GNs is None:
+        GNs = [torch.empty_like(g) for g in G0s]
+    ga = (Grid * n)(*grids)
+    pa = (Params * n)(*params)
+    g0 = (C.c_void_p * n)(*[_dev(g, "G0").value for g in G0s])
+    gn = (C.c_void_p * n)(*[_dev(g, "GN").value for g in GNs])
+    rep = BatchReport()
+    _check(lib().fp_solve_batched(n, ga, pa, g0, gn, _stream(), 1 if autotune else 0, C.byref(rep)))
+    return GNs, rep

@@ -1,0 +1,435 @@
+// Batched fast solves: many independent problems of uneven size in one
+// captured HIP graph (forward sine transforms, the batched modal fast
+// kernels, inverse transforms), with the lanes-per-mode tile of every
+// register class chosen by timing (autotuner, cached per process).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace cqfp;
+
+#define BHIP(expr)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(CQ_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+struct HostProblem {
+    int dim = 1, nx = 1, ny = 1;
+    int64_t M = 0, N = 0;
+    int np = 0, L = 0, scheme = 2;
+    double tau = 0, a = 0, c = 0;
+    double lx = 1, ly = 1;
+    std::vector<double> d[2];  // weights 0..N
+    FastRule rule[2];
+    int rc = CQ_OK;
+    std::string err;
+};
+
+double lam1d(int n, double len, int p) {
+    const double h = len / (n + 1);
+    const double s = std::sin(p * M_PI / (2.0 * (n + 1)));
+    return 4.0 / (h * h) * s * s;
+}
+
+std::vector<double> sine_tab(int n) {
+    std::vector<double> S(size_t(n) * size_t(n));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int64_t kk = (int64_t(i + 1) * (j + 1)) % (2 * int64_t(n + 1));
+            S[size_t(i) * size_t(n) + size_t(j)] = std::sin(M_PI * double(kk) / double(n + 1));
+        }
+    return S;
+}
+
+// host set-up of one problem: weights, fast rule (lag <= 64, <= 1024 nodes)
+void prepare(const cq_grid& g, const cq_params& p, HostProblem& h) {
+    h.dim = g.dim;
+    h.nx = g.nx;
+    h.ny = g.dim == 2 ? g.ny : 1;
+    h.lx = g.lx;
+    h.ly = g.ly;
+    h.M = int64_t(h.nx) * h.ny;
+    h.N = p.N;
+    h.scheme = p.scheme;
+    h.tau = p.T / double(p.N);
+    h.a = (1.0 - p.m) / (2.0 * p.m - 1.0);
+    h.c = (p.scheme == 1 ? 1.0 : 1.5) / h.tau;
+    const double beta[2] = {1.0 - p.alpha1, 1.0 - p.alpha2};
+    const int ns = p.ns ? p.ns : 30, np1 = p.np1 ? p.np1 : 16;
+    const int np_max = p.np_max ? p.np_max : 1024;
+    const double tol = p.fast_tol > 0 ? p.fast_tol : 1e-8;
+    for (int k = 0; k < 2; ++k) {
+        h.d[k].assign(size_t(h.N) + 1, 0.0);
+        weights(p.scheme, beta[k], h.tau, h.N, h.d[k].data());
+    }
+    int npk[2];
+    for (int k = 0; k < 2; ++k) {
+        if (p.np > 0) {
+            build_rule(p.scheme, beta[k], h.tau, p.np, np1, ns, h.rule[k]);
+        } else {
+            const int rc = choose_rule(p.scheme, beta[k], h.tau, h.N, tol, np_max, np1, ns, h.rule[k]);
+            if (rc != CQ_OK) {
+                h.rc = rc;
+                return;
+            }
+        }
+        npk[k] = int(h.rule[k].ratio.size());
+    }
+    if (npk[0] != npk[1]) {
+        const int k = npk[0] < npk[1] ? 0 : 1;
+        build_rule(p.scheme, beta[k], h.tau, std::max(npk[0], npk[1]) - (p.scheme == 2 ? np1 : 0), np1, ns,
+                   h.rule[k]);
+    }
+    if (p.scheme == 1) {  // exact window below 2np+2 (the rule is exact there)
+        const int Lw = std::min(32, 2 * int(h.rule[0].ratio.size()) + 2);
+        shift_lag(h.rule[0], Lw);
+        shift_lag(h.rule[1], Lw);
+    }
+    h.np = int(h.rule[0].ratio.size());
+    h.L = h.rule[0].lag;
+    if (h.L > 64 || h.np > 1024) h.rc = CQ_EINVAL;
+}
+
+struct DevBuf {
+    std::vector<void*> p;
+    ~DevBuf() {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <class T>
+    int alloc(T** out, size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CQ_ENOMEM, "batched solve: device allocation of %zu bytes failed", count * sizeof(T));
+        }
+        p.push_back(q);
+        *out = static_cast<T*>(q);
+        return CQ_OK;
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tune;  // (npl at 64 lanes, lag class) -> lanes per mode
+
+int npl_for(int np, int lpm) { return (np + lpm - 1) / lpm; }
+int npl_tmpl(int npl, int lpm) {
+    if (lpm == 64 && npl <= 1) return 1;
+    if (npl <= 2) return 2;
+    if (npl <= 4) return 4;
+    if (npl <= 8) return 8;
+    if (npl <= 12) return 12;
+    return 16;
+}
+
+}  // namespace
+
+extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_params* params,
+                                const double* const* G0, double* const* GN, void* hip_stream,
+                                int32_t autotune, cq_batch_report* report) {
+    clear_error();
+    if (count < 1 || !grids || !params || !G0 || !GN) return fail(CQ_EINVAL, "batched solve: bad arguments");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<HostProblem> hp(static_cast<size_t>(count));
+    for (int i = 0; i < count; ++i) {
+        const cq_grid& g = grids[i];
+        const cq_params& p = params[i];
+        if (!(g.dim == 1 || g.dim == 2) || g.nx < 1 || g.ny < 1 || (g.dim == 1 && g.ny != 1) || !(g.lx > 0) ||
+            (g.dim == 2 && !(g.ly > 0)))
+            return fail(CQ_EINVAL, "batched solve: problem %d has a bad grid", i);
+        if (!(p.alpha1 > 0 && p.alpha1 < 1 && p.alpha2 > 0 && p.alpha2 < 1) || !(p.m >= 0 && p.m <= 1) ||
+            p.m == 0.5 || !(p.T > 0) || p.N < 1 || (p.scheme != 1 && p.scheme != 2) || p.method != 1 ||
+            p.np < 0 || p.np > 1024 || (p.scheme == 2 && p.ns != 0 && (p.ns < 3 || p.ns > 64)))
+            return fail(CQ_EINVAL, "batched solve: problem %d has bad parameters (fast method only)", i);
+        if (!G0[i] || !GN[i]) return fail(CQ_EINVAL, "batched solve: NULL array for problem %d", i);
+    }
+    // host set-up in parallel
+    {
+        const int nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; ++t)
+            th.emplace_back([&, t] {
+                for (int i = t; i < count; i += nt) prepare(grids[i], params[i], hp[size_t(i)]);
+            });
+        for (auto& x : th) x.join();
+    }
+    for (int i = 0; i < count; ++i) {
+        const HostProblem& h = hp[size_t(i)];
+        if (h.rc == CQ_ETOL) return fail(CQ_ETOL, "batched solve: problem %d: fast rule cannot meet the tolerance", i);
+        if (h.rc != CQ_OK)
+            return fail(CQ_EINVAL, "batched solve: problem %d needs lag %d <= 64 and %d <= 1024 nodes", i, h.L, h.np);
+        // step operator check, as for a single solve
+        const double d10 = h.d[0][0], d20 = h.d[1][0];
+        const double K[2][2] = {{h.c / d10 + h.a, -h.a * d20 / d10}, {-h.a * d10 / d20, h.c / d20 + h.a}};
+        double th[2], V[2][2], Vi[2][2];
+        eig2(K, th, V, Vi);
+        double lmin = lam1d(h.nx, h.lx, 1) + (h.dim == 2 ? lam1d(h.ny, h.ly, 1) : 0.0);
+        if (!(th[0] + lmin > 0 && th[1] + lmin > 0))
+            return fail(CQ_ESINGULAR, "batched solve: problem %d: step operator not positive definite", i);
+    }
+    // concatenated tables
+    std::vector<BatchInst> inst(static_cast<size_t>(count));
+    std::vector<double> ratio, coef, dd, lam;
+    int64_t modes = 0;
+    for (int i = 0; i < count; ++i) {
+        HostProblem& h = hp[size_t(i)];
+        BatchInst& I = inst[size_t(i)];
+        I.mode_off = modes;
+        I.M = h.M;
+        I.N = h.N;
+        I.np = h.np;
+        I.L = h.L;
+        I.scheme = h.scheme;
+        I.rule_off = int64_t(ratio.size());
+        for (int k = 0; k < 2; ++k) {
+            ratio.insert(ratio.end(), h.rule[k].ratio.begin(), h.rule[k].ratio.end());
+            coef.insert(coef.end(), h.rule[k].coef.begin(), h.rule[k].coef.end());
+        }
+        I.d_off = int64_t(dd.size());
+        I.dstride = h.N + 1;
+        dd.insert(dd.end(), h.d[0].begin(), h.d[0].end());
+        dd.insert(dd.end(), h.d[1].begin(), h.d[1].end());
+        I.inv_tau = 1.0 / h.tau;
+        I.c = h.c;
+        I.a = h.a;
+        I.d00 = h.d[0][0];
+        I.d01 = h.d[1][0];
+        for (int j = 0; j < h.ny; ++j)
+            for (int q = 0; q < h.nx; ++q)
+                lam.push_back(lam1d(h.nx, h.lx, q + 1) + (h.dim == 2 ? lam1d(h.ny, h.ly, j + 1) : 0.0));
+        modes += h.M;
+    }
+    hipStream_t user = static_cast<hipStream_t>(hip_stream);
+    DevBuf buf;
+    BatchInst* d_inst;
+    double *d_ratio, *d_coef, *d_d, *d_lam, *d_g0, *d_gN, *d_tmp;
+    int rc;
+    int64_t maxM = 0;
+    for (auto& h : hp) maxM = std::max(maxM, h.M);
+    if ((rc = buf.alloc(&d_inst, inst.size())) || (rc = buf.alloc(&d_ratio, ratio.size())) ||
+        (rc = buf.alloc(&d_coef, coef.size())) || (rc = buf.alloc(&d_d, dd.size())) ||
+        (rc = buf.alloc(&d_lam, lam.size())) || (rc = buf.alloc(&d_g0, size_t(2 * modes))) ||
+        (rc = buf.alloc(&d_gN, size_t(2 * modes))) || (rc = buf.alloc(&d_tmp, size_t(2 * maxM))))
+        return rc;
+    BHIP(hipMemcpy(d_inst, inst.data(), inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(d_ratio, ratio.data(), ratio.size() * sizeof(double), hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(d_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(d_d, dd.data(), dd.size() * sizeof(double), hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+    // sine tables per distinct size
+    std::map<int, double*> sines;
+    for (auto& h : hp)
+        for (int n : {h.nx, h.dim == 2 ? h.ny : 0}) {
+            if (n <= 0 || sines.count(n)) continue;
+            double* q;
+            if ((rc = buf.alloc(&q, size_t(n) * size_t(n)))) return rc;
+            const std::vector<double> S = sine_tab(n);
+            BHIP(hipMemcpy(q, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+            sines[n] = q;
+        }
+    // register classes (nodes per lane at 64 lanes) and the problems in each
+    std::map<int, std::vector<int>> cls;
+    for (int i = 0; i < count; ++i) cls[npl_tmpl(npl_for(hp[size_t(i)].np, 64), 64)].push_back(i);
+    std::vector<int> lists;
+    std::vector<int64_t> cums;
+    struct Launch {
+        int npl64, lpm, count;
+        int64_t total;
+        size_t list_off, cum_off;
+        bool lag32;
+    };
+    std::vector<Launch> launches;
+    for (auto& kv : cls) {
+        Launch l{};
+        l.npl64 = kv.first;
+        l.count = int(kv.second.size());
+        l.list_off = lists.size();
+        l.cum_off = cums.size();
+        l.lag32 = true;
+        int64_t c = 0;
+        int maxnp = 0;
+        for (int i : kv.second) {
+            lists.push_back(i);
+            cums.push_back(c);
+            c += hp[size_t(i)].M;
+            l.lag32 = l.lag32 && hp[size_t(i)].L <= 32;
+            maxnp = std::max(maxnp, hp[size_t(i)].np);
+        }
+        cums.push_back(c);
+        l.total = c;
+        l.lpm = 64;
+        launches.push_back(l);
+    }
+    int* d_list;
+    int64_t* d_cum;
+    if ((rc = buf.alloc(&d_list, lists.size())) || (rc = buf.alloc(&d_cum, cums.size()))) return rc;
+    BHIP(hipMemcpy(d_list, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(d_cum, cums.data(), cums.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    hipStream_t st;
+    BHIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } sg{st};
+    // the caller's stream may still be producing G0
+    hipEvent_t ev_in;
+    BHIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    BHIP(hipEventRecord(ev_in, user));
+    BHIP(hipStreamWaitEvent(st, ev_in, 0));
+    (void)hipEventDestroy(ev_in);
+
+    auto make_args = [&](const Launch& l) {
+        BatchArgs a{};
+        a.inst = d_inst;
+        a.list = d_list + l.list_off;
+        a.cum = d_cum + l.cum_off;
+        a.count = l.count;
+        a.total = l.total;
+        a.ratio = d_ratio;
+        a.coef = d_coef;
+        a.d = d_d;
+        a.lam = d_lam;
+        a.g0 = d_g0;
+        a.gN = d_gN;
+        return a;
+    };
+    // forward transforms of every G0 into the concatenated coefficient array
+    auto transforms = [&](bool forward) {
+        for (int i = 0; i < count; ++i) {
+            const HostProblem& h = hp[size_t(i)];
+            const int64_t M = h.M;
+            const int64_t off = 2 * inst[size_t(i)].mode_off;
+            const double* in = forward ? G0[i] : d_gN + off;
+            double* out = forward ? d_g0 + off : GN[i];
+            if (h.dim == 1) {
+                GemmArgs ga{};
+                ga.R = 1; ga.C = h.nx; ga.K = h.nx; ga.lda = h.nx; ga.ldb = h.nx; ga.ldc = h.nx;
+                ga.A_shared = 0; ga.B_shared = 1;
+                ga.A0 = in; ga.A1 = in + M; ga.B0 = sines[h.nx]; ga.B1 = sines[h.nx]; ga.C0 = out; ga.C1 = out + M;
+                ga.scale = forward ? 2.0 / double(h.nx + 1) : 1.0;
+                launch_gemm(ga, 3, st);
+            } else {
+                GemmArgs ga{};
+                ga.R = h.ny; ga.C = h.nx; ga.K = h.nx; ga.lda = h.nx; ga.ldb = h.nx; ga.ldc = h.nx;
+                ga.A_shared = 0; ga.B_shared = 1;
+                ga.A0 = in; ga.A1 = in + M; ga.B0 = sines[h.nx]; ga.B1 = sines[h.nx];
+                ga.C0 = d_tmp; ga.C1 = d_tmp + M;
+                launch_gemm(ga, 0, st);
+                GemmArgs gb{};
+                gb.R = h.ny; gb.C = h.nx; gb.K = h.ny; gb.lda = h.ny; gb.ldb = h.nx; gb.ldc = h.nx;
+                gb.A_shared = 1; gb.B_shared = 0;
+                gb.A0 = sines[h.ny]; gb.A1 = sines[h.ny]; gb.B0 = d_tmp; gb.B1 = d_tmp + M;
+                gb.C0 = out; gb.C1 = out + M;
+                gb.scale = forward ? 4.0 / (double(h.nx + 1) * double(h.ny + 1)) : 1.0;
+                launch_gemm(gb, 3, st);
+            }
+        }
+    };
+    transforms(true);
+    BHIP(hipGetLastError());
+    const auto t1 = std::chrono::steady_clock::now();
+    // autotune: lanes per mode (64, or 32 when every lag fits) per class, by
+    // timing both on the class's problems truncated to a few steps
+    double tune_s = 0.0;
+    for (Launch& l : launches) {
+        const int npl32 = npl_for(l.npl64 * 64, 32);
+        const bool can32 = l.lag32 && npl32 <= 16;
+        const std::pair<int, int> key{l.npl64, l.lag32 ? 32 : 64};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                l.lpm = it->second;
+                continue;
+            }
+        }
+        if (!autotune || !can32) continue;
+        const auto ta = std::chrono::steady_clock::now();
+        // short copies of the class's problems (at most 64 steps)
+        std::vector<BatchInst> shortI(inst);
+        for (auto& I : shortI) I.N = std::min<int64_t>(I.N, 64);
+        BatchInst* d_short;
+        if ((rc = buf.alloc(&d_short, shortI.size()))) return rc;
+        BHIP(hipMemcpy(d_short, shortI.data(), shortI.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
+        BatchArgs a = make_args(l);
+        a.inst = d_short;
+        double* scratch;  // the timing runs write here, not into the results
+        if ((rc = buf.alloc(&scratch, size_t(2 * modes)))) return rc;
+        a.gN = scratch;
+        float best_ms = 1e30f;
+        int best = 64;
+        hipEvent_t e0, e1;
+        BHIP(hipEventCreate(&e0));
+        BHIP(hipEventCreate(&e1));
+        for (int lpm : {64, 32}) {
+            const int npl = npl_tmpl(npl_for(l.npl64 * 64, lpm), lpm);
+            launch_modal_batch(a, npl, lpm, st);  // warm
+            BHIP(hipEventRecord(e0, st));
+            launch_modal_batch(a, npl, lpm, st);
+            BHIP(hipEventRecord(e1, st));
+            BHIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BHIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = lpm;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        l.lpm = best;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = best;
+        }
+        tune_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ta).count();
+    }
+    // the batched run and the inverse transforms, captured as one graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (const Launch& l : launches) {
+        const int npl = npl_tmpl(npl_for(l.npl64 * 64, l.lpm), l.lpm);
+        launch_modal_batch(make_args(l), npl, l.lpm, st);
+    }
+    transforms(false);
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (ce != hipSuccess) return fail(CQ_EHIP, "graph capture: %s", hipGetErrorString(ce));
+    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(CQ_EHIP, "graph instantiate: %s", hipGetErrorString(ce));
+    }
+    const auto t2 = std::chrono::steady_clock::now();
+    ce = hipGraphLaunch(exec, st);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(st);
+    const auto t3 = std::chrono::steady_clock::now();
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (ce != hipSuccess) return fail(CQ_EHIP, "batched graph: %s", hipGetErrorString(ce));
+    if (report) {
+        report->problems = count;
+        report->modes = modes;
+        report->classes = int32_t(std::min<size_t>(launches.size(), 8));
+        for (int c = 0; c < report->classes; ++c) {
+            report->class_npl64[c] = launches[size_t(c)].npl64;
+            report->class_lanes[c] = launches[size_t(c)].lpm;
+            report->class_problems[c] = launches[size_t(c)].count;
+        }
+        report->setup_s = std::chrono::duration<double>(t1 - t0).count();
+        report->autotune_s = tune_s;
+        report->run_s = std::chrono::duration<double>(t3 - t2).count();
+    }
+    return CQ_OK;
+}

@@ -137,7 +137,29 @@ struct ModalWinArgs {
     double* levels;       // [Lr][2][M] coefficients, level l at slot l mod Lr
 };
 
+// one problem of a batch (device table entry)
+struct BatchInst {
+    int64_t mode_off;     // first mode of the problem in the concatenated arrays
+    int64_t M, N;         // modes, steps
+    int np, L, scheme, pad;
+    int64_t rule_off;     // ratio/coef [2][np] at rule_off
+    int64_t d_off;        // weights [2][dstride] at d_off
+    int64_t dstride;
+    double inv_tau, c, a, d00, d01;
+};
+
+struct BatchArgs {
+    const BatchInst* inst;
+    const int* list;      // problems of this launch
+    const int64_t* cum;   // cumulative mode counts over list (cum[0] = 0)
+    int count;            // problems in this launch
+    int64_t total;        // their modes
+    const double *ratio, *coef, *d, *lam, *g0;
+    double* gN;
+};
+
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
+void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
 void launch_modal_win(const ModalWinArgs& a, hipStream_t st);
 void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st);
 void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);

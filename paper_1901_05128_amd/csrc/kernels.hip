@@ -538,6 +538,111 @@ __global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
     }
 }
 
+// Batched fast form: many independent problems (grids, orders, m, N and
+// node counts differ) in one launch. Every group of LPM lanes owns one mode
+// of one problem and runs that problem's whole time loop, as k_modal_fast
+// does for a single problem (state in registers, window in lanes, reduction
+// over the group, 2x2 solve); the problem of a group is found by binary
+// search over the cumulative mode counts of the launch's problem list. All
+// problems of a launch share the register tile NPL (nodes per lane) and the
+// group width LPM (32 or 64 lanes; the lag must fit: L <= LPM). Starts from
+// zero state and G^0, writes the coefficients of G^N.
+template <int LPM>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = LPM / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NPL, int LPM>
+__global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
+    const int lane = threadIdx.x & (LPM - 1);
+    const int64_t group = (int64_t(blockIdx.x) * 256 + threadIdx.x) / LPM;
+    if (group >= p.total) return;  // uniform per group
+    // problem of this group
+    int lo = 0, hi = p.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.cum[mid] <= group) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst& I = p.inst[p.list[lo]];
+    const int64_t mode = group - p.cum[lo];
+    const int64_t M = I.M;
+    const int np = I.np, L = I.L;
+    const double* __restrict__ ratio = p.ratio + I.rule_off;
+    const double* __restrict__ coef = p.coef + I.rule_off;
+    const double* __restrict__ d0p = p.d + I.d_off;
+    const double* __restrict__ d1p = d0p + I.dstride;
+    double r[2][NPL], w[2][NPL], h[2][NPL];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) {
+            const int j = lane + LPM * q;
+            const bool ok = j < np;
+            r[k][q] = ok ? ratio[k * np + j] : 0.0;
+            w[k][q] = ok ? coef[k * np + j] : 0.0;
+            h[k][q] = 0.0;
+        }
+    const double dw0 = (lane < L - 1) ? d0p[lane + 1] : 0.0;
+    const double dw1 = (lane < L - 1) ? d1p[lane + 1] : 0.0;
+    const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
+    const double g00 = g0[mode], g01 = g0[M + mode];
+    // ring[i] = g^{n-1-i}; before step 1: g^0 and, for BDF2, g^{-1} := g^0
+    double ring0 = (lane <= 1) ? g00 : 0.0, ring1 = (lane <= 1) ? g01 : 0.0;
+    const double lam = p.lam[I.mode_off + mode];
+    const double L1 = I.a + lam;
+    const double m11 = I.c + I.d00 * L1, m22 = I.c + I.d01 * L1;
+    const double m12 = -I.a * I.d01, m21 = -I.a * I.d00;
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    const int base = threadIdx.x & ~(LPM - 1);  // first lane of this group in the wave
+    for (int64_t n = 1; n <= I.N; ++n) {
+        double p0 = 0.0, p1 = 0.0;
+        if (n >= L + 1) {
+            const double gin0 = __shfl(ring0, (base & 63) + L - 1, 64);
+            const double gin1 = __shfl(ring1, (base & 63) + L - 1, 64);
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) {
+                h[0][q] = fma(r[0][q], h[0][q], gin0);
+                h[1][q] = fma(r[1][q], h[1][q], gin1);
+                p0 = fma(w[0][q], h[0][q], p0);
+                p1 = fma(w[1][q], h[1][q], p1);
+            }
+        }
+        const int64_t wn = (n - 1 < L - 1) ? n - 1 : L - 1;
+        if (lane < wn) {
+            p0 = fma(dw0, ring0, p0);
+            p1 = fma(dw1, ring1, p1);
+        }
+        double S0 = group_sum<LPM>(p0);
+        double S1 = group_sum<LPM>(p1);
+        const double gm10 = __shfl(ring0, base & 63, 64), gm11 = __shfl(ring1, base & 63, 64);
+        double E0, E1;
+        if (I.scheme == 1) {
+            E0 = gm10 * I.inv_tau;
+            E1 = gm11 * I.inv_tau;
+        } else {
+            const double gm20 = __shfl(ring0, (base & 63) + 1, 64), gm21 = __shfl(ring1, (base & 63) + 1, 64);
+            E0 = (2.0 * gm10 - 0.5 * gm20) * I.inv_tau;
+            E1 = (2.0 * gm11 - 0.5 * gm21) * I.inv_tau;
+            S0 = fma(0.5 * d0p[n - 1], g00, S0);
+            S1 = fma(0.5 * d1p[n - 1], g01, S1);
+        }
+        const double r0 = E0 - (L1 * S0 - I.a * S1);
+        const double r1 = E1 - (L1 * S1 - I.a * S0);
+        const double gn0 = (m22 * r0 - m12 * r1) * idet;
+        const double gn1 = (m11 * r1 - m21 * r0) * idet;
+        const double up0 = __shfl_up(ring0, 1, LPM), up1 = __shfl_up(ring1, 1, LPM);
+        ring0 = (lane == 0) ? gn0 : up0;
+        ring1 = (lane == 0) ? gn1 : up1;
+    }
+    if (lane == 0) {
+        double* gN = p.gN + 2 * I.mode_off;
+        gN[mode] = ring0;
+        gN[M + mode] = ring1;
+    }
+}
+
 // Fast form for many modes: the compressed state streams through
 // k_hist_block (time-blocked, exactly as for the nodal solver, here on the
 // sine coefficients), and this kernel takes the steps of the block: thread
@@ -898,6 +1003,29 @@ void launch_modal_fast(const ModalFastArgs& a, hipStream_t st) {
     else
         hipLaunchKernelGGL(k_modal_fast<16>, grid, dim3(256), 0, st, a);
     prof_end(7, st);
+}
+
+void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st) {
+    const int64_t threads = a.total * lpm;
+    const dim3 grid(unsigned((threads + 255) / 256));
+#define CQ_BATCH(NP, LP) hipLaunchKernelGGL((k_modal_batch<NP, LP>), grid, dim3(256), 0, st, a)
+    prof_begin(9, st);
+    if (lpm == 32) {
+        if (npl <= 2) CQ_BATCH(2, 32);
+        else if (npl <= 4) CQ_BATCH(4, 32);
+        else if (npl <= 8) CQ_BATCH(8, 32);
+        else if (npl <= 12) CQ_BATCH(12, 32);
+        else CQ_BATCH(16, 32);
+    } else {
+        if (npl <= 1) CQ_BATCH(1, 64);
+        else if (npl <= 2) CQ_BATCH(2, 64);
+        else if (npl <= 4) CQ_BATCH(4, 64);
+        else if (npl <= 8) CQ_BATCH(8, 64);
+        else if (npl <= 12) CQ_BATCH(12, 64);
+        else CQ_BATCH(16, 64);
+    }
+    prof_end(9, st);
+#undef CQ_BATCH
 }
 
 void launch_modal_win(const ModalWinArgs& a, hipStream_t st) {

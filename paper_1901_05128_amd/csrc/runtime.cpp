@@ -715,7 +715,7 @@ size_t state_bytes(const Solver& s) {
 
 // ---- kernel timing ----
 namespace {
-constexpr int kProfKinds = 9;
+constexpr int kProfKinds = 10;
 struct ProfRec {
     hipEvent_t a, b;
 };
@@ -727,6 +727,8 @@ std::vector<ProfRec> g_prof_done[kProfKinds];
 namespace cqfp {
 void prof_begin(int kind, hipStream_t st) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     ProfRec r{};
     if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
     (void)hipEventRecord(r.a, st);
@@ -734,6 +736,8 @@ void prof_begin(int kind, hipStream_t st) {
 }
 void prof_end(int kind, hipStream_t st) {
     if (!g_prof_on || g_prof_open[kind].empty()) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     ProfRec r = g_prof_open[kind].back();
     g_prof_open[kind].pop_back();
     (void)hipEventRecord(r.b, st);

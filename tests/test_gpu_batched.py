@@ -1,0 +1,110 @@
+"""Batched fast solves (fp_solve_batched): uneven problems in one captured
+graph, checked against the per-mode oracle and against single solves."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1901_05128_amd as cq  # noqa: E402
+from oracle import modal  # noqa: E402
+from paper_1901_05128_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cq.lib()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _mixed(count, seed, nmax=300):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for b in range(count):
+        if rng.uniform() < 0.5:
+            dim, nx, ny = 1, int(rng.choice([7, 31, 100, 127, 255])), 1
+        else:
+            dim, nx, ny = 2, int(rng.choice([7, 15, 31])), int(rng.choice([9, 15, 33]))
+        N = int(rng.integers(40, nmax))
+        scheme = int(rng.integers(1, 3))
+        a1, a2 = (float(v) for v in rng.uniform(0.1, 0.9, size=2))
+        m = float(rng.uniform(0.55, 0.95))
+        np_ = max(8, int(math.ceil(3 * math.sqrt(N))))
+        probs.append((dim, nx, ny, a1, a2, m, 1.0, N, scheme, np_))
+    return probs
+
+
+def _run(probs, autotune=True, seed=0):
+    grids, params, g0s = [], [], []
+    for i, (dim, nx, ny, a1, a2, m, T, N, scheme, np_) in enumerate(probs):
+        grids.append(cq.make_grid(dim, nx, ny))
+        params.append(cq.make_params(a1, a2, m, T, N, scheme, 1, np_=np_))
+        g0s.append(torch.tensor(wl.g0_random(nx * ny, seed + i), device="cuda"))
+    outs, rep = cq.fp_solve_batched(grids, params, g0s, autotune=autotune)
+    return [o.cpu().numpy() for o in outs], [g.cpu().numpy() for g in g0s], rep
+
+
+def test_batched_matches_oracle_mixed():
+    probs = _mixed(14, 3)
+    outs, g0s, rep = _run(probs)
+    print(f"batch classes={rep.classes} lanes={list(rep.class_lanes)[:rep.classes]} "
+          f"run_s={rep.run_s:.3f}", flush=True)
+    assert rep.problems == len(probs)
+    assert rep.modes == sum(p[1] * p[2] for p in probs)
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, np_), out, g0 in zip(probs, outs, g0s):
+        ref_f = modal.reference(dim, nx, ny, a1, a2, m, T, N, g0, scheme, 1, np_=np_, np1=16, ns=30)
+        ref_d = modal.reference(dim, nx, ny, a1, a2, m, T, N, g0, scheme, 0)
+        ef, ed = rel(out, ref_f), rel(out, ref_d)
+        print(f"  {dim}d {nx}x{ny} N={N} scheme={scheme} np={np_}: vs fast {ef:.2e} vs direct {ed:.2e}",
+              flush=True)
+        assert ef <= 1e-11
+        assert ed <= 1e-8
+
+
+def test_batched_equals_single_solves_and_tiles_agree():
+    probs = _mixed(10, 8)
+    a, g0s, rep_a = _run(probs, autotune=True, seed=50)
+    b, _, rep_b = _run(probs, autotune=False, seed=50)
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, np_), oa, ob, g0 in zip(probs, a, b, g0s):
+        single = cq.fp_solve(cq.make_grid(dim, nx, ny),
+                             cq.make_params(a1, a2, m, T, N, scheme, 1, np_=np_, solver=cq.SOLVER_MODAL),
+                             torch.tensor(g0, device="cuda")).cpu().numpy()
+        assert rel(oa, single) <= 1e-13
+        assert rel(ob, single) <= 1e-13
+    assert all(x in (32, 64) for x in list(rep_a.class_lanes)[:rep_a.classes])
+    assert all(x == 64 for x in list(rep_b.class_lanes)[:rep_b.classes]) or rep_b.autotune_s == 0.0
+
+
+def test_batched_rejects_direct_method_and_bad_lag():
+    g = [cq.make_grid(1, 15)]
+    G0 = [torch.zeros((2, 15), dtype=torch.float64, device="cuda")]
+    with pytest.raises(cq.CQError):
+        cq.fp_solve_batched(g, [cq.make_params(0.3, 0.6, 0.7, 1.0, 10, 2, 0)], G0)
+    with pytest.raises(cq.CQError):
+        cq.fp_solve_batched(g, [cq.make_params(0.3, 0.6, 0.7, 1.0, 10, 2, 1, ns=80)], G0)
+
+
+def test_batched_reduced_c4_mix():
+    """The seeded 256-instance mix of the batched workload, 24 of them with N
+    scaled by 1/32 and grids capped, against single modal solves."""
+    inst = wl.batched_instances(24, seed=4, scale=1 / 32)
+    probs = []
+    for p in inst:
+        nx = min(p.nx, 511) if p.dim == 1 else min(p.nx, 63)
+        ny = 1 if p.dim == 1 else nx
+        np_ = max(8, int(math.ceil(3 * math.sqrt(p.N))))
+        probs.append((p.dim, nx, ny, p.alpha1, p.alpha2, p.m, p.T, p.N, 2, np_))
+    outs, g0s, rep = _run(probs, seed=200)
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, np_), out, g0 in zip(probs, outs, g0s):
+        single = cq.fp_solve(cq.make_grid(dim, nx, ny),
+                             cq.make_params(a1, a2, m, T, N, scheme, 1, np_=np_, solver=cq.SOLVER_MODAL),
+                             torch.tensor(g0, device="cuda")).cpu().numpy()
+        assert rel(out, single) <= 1e-13
