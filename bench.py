@@ -46,9 +46,9 @@ def kernel_work(kind, w, scheme, method, info, M):
     """Algorithmic (bytes, flops) summed over the launches of one solve."""
     N = w[8]
     twoM = 2 * M
-    if method == 1 and kind in ("hist_direct", "far_toeplitz"):
+    if method == 1 and kind in ("hist_direct", "far_toeplitz", "modal_near"):
         return 0, 0
-    if method == 0 and kind == "hist_fast":
+    if method == 0 and kind in ("hist_fast", "modal_fast"):
         return 0, 0
     if kind == "hist_fast":
         # one launch per block of bt steps: state read + write once, the bt
@@ -78,6 +78,21 @@ def kernel_work(kind, w, scheme, method, info, M):
     if kind == "dst_gemm":
         nx, ny = w[2], w[3]
         return 0, N * 2 * (2 * ny * nx * nx + 2 * ny * ny * nx) * 2
+    if kind == "modal_fast":
+        # wave-per-mode (few modes) or blocked (many modes: the window steps;
+        # the state pass is counted under hist_fast): 2 FMAs per node and
+        # component per step, plus the exact-weight window
+        L, npn = info.lag, info.np_total
+        if M >= 8192:
+            return N * twoM * 8 * 3, N * twoM * 2 * (L - 1)
+        return 0, N * twoM * (4 * npn + 2 * (L - 1))
+    if kind == "modal_near":
+        # in-block near field (b terms at block offset b) + far-field read + level write
+        B = info.block_B
+        f = 0
+        for n in range(1, N + 1):
+            f += twoM * 2 * ((n - 1) % B)
+        return N * twoM * 8 * 2, f
     if kind in ("solve_1d", "prep_2d"):
         # window of exact weights (fast) or the partial sums, G^{n-1}, G^{n-2}, G0, output
         win = (info.lag - 1) if method == 1 else 1
@@ -108,7 +123,9 @@ def cpu_baseline(w, seconds_target=20.0):
                           np_=(None if method == 0 else max(16, int(3 * N ** 0.5))), ns=30)
         dt = time.perf_counter() - t0
         done_dofsteps, spent = 4 * 2 * M * ns, dt
-        if dt * 2 > seconds_target or 2 * ns > N:
+        # the direct oracle's cost grows like ns^2: stop before the next
+        # doubling would pass the target
+        if dt * 4 > seconds_target or 2 * ns > N:
             break
         ns *= 2
     return {"value": done_dofsteps / spent, "unit": "DOF*steps/s", "cores": int(cores), "kind": "oracle",
@@ -133,17 +150,64 @@ def load_traffic(kernel_name):
         return None
 
 
+def bench_batched(args):
+    """One step = one batched solve of the 256 seeded fast-BDF2 problems
+    (1D 127..4095 nodes and 2D 63^2..255^2, N = 2^10..2^15, np = ceil(3 sqrt N))."""
+    import math
+
+    import torch
+
+    import paper_1901_05128_amd as cq
+    from paper_1901_05128_amd import workloads as wl
+    torch.cuda.set_device(0)
+    inst = wl.batched_instances(256, seed=4)
+    grids, params, g0s = [], [], []
+    for i, p in enumerate(inst):
+        grids.append(cq.make_grid(p.dim, p.nx, p.ny))
+        params.append(cq.make_params(p.alpha1, p.alpha2, p.m, p.T, p.N, 2, 1,
+                                     np_=int(math.ceil(3 * math.sqrt(p.N)))))
+        g0 = wl.g0_intervals(p.nx, 1000 + i) if p.dim == 1 else wl.g0_rectangle(p.nx, p.ny, 1000 + i)
+        g0s.append(torch.tensor(g0, dtype=torch.float64, device="cuda"))
+    outs = [torch.empty_like(g) for g in g0s]
+    for _ in range(args.warmup):
+        cq.fp_solve_batched(grids, params, g0s, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        reps.append(cq.fp_solve_batched(grids, params, g0s, outs)[1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dofsteps = args.steps * sum(2 * p.nx * p.ny * p.N for p in inst)
+    rep = reps[-1]
+    rec = {
+        "metric": "DOF*steps/s (batched fast BDF2 solves)", "value": dofsteps / (t1 - t0), "unit": "DOF*steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": (t1 - t0) / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded indicator initial data)",
+        "config": {"workload": "c4: 256 seeded fast-BDF2 problems, 1D 127-4095 nodes / 2D 63^2-255^2, "
+                               "N=2^10..2^15, np=ceil(3 sqrt N), one captured graph",
+                   "modes": rep.modes, "classes": rep.classes,
+                   "lanes_per_mode": list(rep.class_lanes)[:rep.classes]},
+        "breakdown": {"setup_s": rep.setup_s, "autotune_s": rep.autotune_s, "graph_run_s": rep.run_s},
+        "roofline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
     ap.add_argument("--variants", default="all", help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct")
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the variants one after another (default: one stream each, concurrently)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,6 +220,8 @@ def main():
 
     import paper_1901_05128_amd as cq
 
+    if args.workload == "c4":
+        return bench_batched(args)
     w = WORKLOADS[args.workload]
     desc, dim, nx, ny, a1, a2, m, T, N, seed = w
     M = nx * ny
@@ -164,21 +230,27 @@ def main():
     torch.cuda.set_device(0)
     G0 = torch.tensor(g0_for(w), dtype=torch.float64, device="cuda")
     grid = cq.make_grid(dim, nx, ny)
-    solvers = {}
+    solvers, streams = {}, {}
     for v in variants:
-        solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1], solver=SOLVERS[args.solver]), G0)
+        # each variant on its own stream (default priority) unless --serial
+        streams[v] = torch.cuda.current_stream() if args.serial else torch.cuda.Stream()
+        with torch.cuda.stream(streams[v]):
+            solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1],
+                                                        solver=SOLVERS[args.solver]), G0)
+    torch.cuda.synchronize()
     outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
 
     def one_step(events=None):
         for v in variants:
             s = solvers[v]
-            if events is not None:
-                events[v][0].record()
-            s.reset(G0)
-            s.step(N)
-            s.current(outs[v])
-            if events is not None:
-                events[v][1].record()
+            with torch.cuda.stream(streams[v]):
+                if events is not None:
+                    events[v][0].record()
+                s.reset(G0)
+                s.step(N)
+                s.current(outs[v])
+                if events is not None:
+                    events[v][1].record()
 
     for _ in range(args.warmup):
         one_step()
@@ -264,7 +336,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded indicator initial data)",
         "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
-                   "solver": args.solver,
+                   "solver": args.solver, "streams": "serial" if args.serial else "one per variant",
                    "variants": [VNAME[v] for v in variants], "dof": 2 * M, "N": N,
                    "fast_nodes": info_np},
         "breakdown": breakdown,

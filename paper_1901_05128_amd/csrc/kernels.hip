@@ -736,92 +736,82 @@ __global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
     }
 }
 
-// Direct form, part of one time block: thread per mode takes the steps
-// n = nfirst .. nfirst+bt-1 (inside the block n0+1 .. n0+B) in order.
-// S = F[b] (far field of the block, summed over the K-split by
-// k_reduce_far) + sum_{l=n0+1}^{n-1} d_{n-l} g^l. The levels of this block
-// stay in registers: ring[i] = g^{n-1-i}, i < BB, zero for levels before the
-// block; a step shifts them by one. BDF2's time part keeps g^{n-1}, g^{n-2}
-// apart (they may belong to the previous block). The weights d_1..d_{BB-1}
-// are wave-uniform. A block that starts mid-way (a run resumed inside a
-// block) first reloads its earlier in-block levels from memory.
+// Direct form, part of one time block: the steps n = nfirst .. nfirst+bt-1
+// (inside the block n0+1 .. n0+B) in order. A lane pair owns one mode, lane
+// k of the pair component k; the pair exchanges its history sums for the
+// 2x2 solve. S_k = F[b][k] (far field of the block, summed over the K-split
+// by k_reduce_far) + sum_{l=n0+1}^{n-1} d_{k,n-l} g_k^l. The levels of this
+// block stay in registers, ring[i] = g_k^{n-1-i} (zero for levels before the
+// block), shifted by one per step; BDF2's time part keeps g^{n-1}, g^{n-2}
+// apart (they may belong to the previous block). A run that resumes inside a
+// block first reloads the block's earlier levels.
 template <int BB>
 __global__ __launch_bounds__(256) void k_modal_near(ModalNearArgs p) {
-    const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (mode >= p.M) return;
+    // weights d_{k,1..BB-1}, staged once in LDS
+    __shared__ double wd[2][BB];
+    for (int e = threadIdx.x; e < 2 * BB; e += 256) {
+        const int kk = e / BB, i = e % BB;
+        wd[kk][i] = (i >= 1 && i < p.dstride) ? p.d[int64_t(kk) * p.dstride + i] : 0.0;
+    }
+    __syncthreads();
+    const int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t mode = gid >> 1;
+    const int k = int(gid & 1);
+    if (mode >= p.M) return;  // both lanes of a pair leave together
     const int64_t M = p.M, twoM = 2 * M;
     const double lam = p.lam[mode];
-    const double g00 = p.g0[mode], g01 = p.g0[M + mode];
+    const double g0k = p.g0[k * M + mode];
     const double L1 = p.a + lam;
     const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
     const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
     const double idet = 1.0 / (m11 * m22 - m12 * m21);
-    double* __restrict__ lv = p.levels + mode;
-    const double* __restrict__ d0p = p.d;
-    const double* __restrict__ d1p = p.d + p.dstride;
-    double ring0[BB], ring1[BB];
+    double* __restrict__ lv = p.levels + k * M + mode;
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    double ring[BB];
 #pragma unroll
     for (int i = 0; i < BB; ++i) {
         const int64_t l = p.nfirst - 1 - i;  // in-block levels already taken
-        const bool in = l >= p.n0 + 1;
-        ring0[i] = in ? lv[l * twoM] : 0.0;
-        ring1[i] = in ? lv[l * twoM + M] : 0.0;
+        ring[i] = (l >= p.n0 + 1) ? lv[l * twoM] : 0.0;
     }
-    double gm1_0 = lv[(p.nfirst - 1) * twoM], gm1_1 = lv[(p.nfirst - 1) * twoM + M];
-    const int64_t l2i = (p.nfirst >= 2) ? p.nfirst - 2 : 0;
-    double gm2_0 = lv[l2i * twoM], gm2_1 = lv[l2i * twoM + M];
-    // far-field values of the next step are loaded one step ahead
-    double f0 = 0.0, f1 = 0.0;
-    if (p.n0 >= 1 && p.bt > 0) {
-        const int64_t b = p.nfirst - p.n0 - 1;
-        f0 = p.F[(b * 2 + 0) * M + mode];
-        f1 = p.F[(b * 2 + 1) * M + mode];
-    }
+    double gm1 = lv[(p.nfirst - 1) * twoM];
+    double gm2 = lv[((p.nfirst >= 2) ? p.nfirst - 2 : 0) * twoM];
+    // far-field value of the next step is loaded one step ahead
+    double f = 0.0;
+    if (p.n0 >= 1 && p.bt > 0) f = p.F[((p.nfirst - p.n0 - 1) * 2 + k) * M + mode];
     for (int t = 0; t < p.bt; ++t) {
         const int64_t n = p.nfirst + t;
         const int64_t b = n - p.n0 - 1;
-        double S0 = f0, S1 = f1;
-        if (p.n0 >= 1 && t + 1 < p.bt) {
-            f0 = p.F[((b + 1) * 2 + 0) * M + mode];
-            f1 = p.F[((b + 1) * 2 + 1) * M + mode];
-        }
-        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+        double S = f;
+        if (p.n0 >= 1 && t + 1 < p.bt) f = p.F[((b + 1) * 2 + k) * M + mode];
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
         for (int i = 0; i + 1 < BB; i += 2) {
-            a0 = fma(d0p[i + 1], ring0[i], a0);
-            a1 = fma(d1p[i + 1], ring1[i], a1);
-            c0 = fma(d0p[i + 2], ring0[i + 1], c0);
-            c1 = fma(d1p[i + 2], ring1[i + 1], c1);
+            if (i < b) {
+                a0 = fma(wd[k][i + 1], ring[i], a0);
+                a1 = fma(wd[k][i + 2 < BB ? i + 2 : 0], ring[i + 1], a1);
+            }
         }
-        S0 += a0 + c0;
-        S1 += a1 + c1;
-        double E0, E1;
+        S += a0 + a1;
+        double E;
         if (p.scheme == 1) {
-            E0 = gm1_0 * p.inv_tau;
-            E1 = gm1_1 * p.inv_tau;
+            E = gm1 * p.inv_tau;
         } else {
-            E0 = (2.0 * gm1_0 - 0.5 * gm2_0) * p.inv_tau;
-            E1 = (2.0 * gm1_1 - 0.5 * gm2_1) * p.inv_tau;
-            S0 = fma(0.5 * d0p[n - 1], g00, S0);
-            S1 = fma(0.5 * d1p[n - 1], g01, S1);
+            E = (2.0 * gm1 - 0.5 * gm2) * p.inv_tau;
+            S = fma(0.5 * dk[n - 1], g0k, S);
         }
+        const double So = __shfl_xor(S, 1, 64);
+        const double Eo = __shfl_xor(E, 1, 64);
+        const double S0 = k ? So : S, S1 = k ? S : So;
+        const double E0 = k ? Eo : E, E1 = k ? E : Eo;
         const double r0 = E0 - (L1 * S0 - p.a * S1);
         const double r1 = E1 - (L1 * S1 - p.a * S0);
-        const double gn0 = (m22 * r0 - m12 * r1) * idet;
-        const double gn1 = (m11 * r1 - m21 * r0) * idet;
-        lv[n * twoM] = gn0;
-        lv[n * twoM + M] = gn1;
+        const double gn = k ? (m11 * r1 - m21 * r0) * idet : (m22 * r0 - m12 * r1) * idet;
+        lv[n * twoM] = gn;
 #pragma unroll
-        for (int i = BB - 1; i > 0; --i) {
-            ring0[i] = ring0[i - 1];
-            ring1[i] = ring1[i - 1];
-        }
-        ring0[0] = gn0;
-        ring1[0] = gn1;
-        gm2_0 = gm1_0;
-        gm2_1 = gm1_1;
-        gm1_0 = gn0;
-        gm1_1 = gn1;
+        for (int i = BB - 1; i > 0; --i) ring[i] = ring[i - 1];
+        ring[0] = gn;
+        gm2 = gm1;
+        gm1 = gn;
     }
 }
 
@@ -1035,7 +1025,7 @@ void launch_modal_win(const ModalWinArgs& a, hipStream_t st) {
 }
 
 void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st) {
-    const dim3 grid(unsigned((a.M + 255) / 256));
+    const dim3 grid(unsigned((2 * a.M + 255) / 256));
     prof_begin(8, st);
     if (B <= 64)
         hipLaunchKernelGGL(k_modal_near<64>, grid, dim3(256), 0, st, a);
