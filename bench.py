@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--no-prof", action="store_true", help="do not time kernels with events")
     ap.add_argument("--serial", action="store_true",
                     help="run the variants one after another (default: one stream each, concurrently)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-sized device buffer 4 times (a plain copy kernel of "
+                         "known size that scales the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -255,8 +258,6 @@ def main():
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    if not args.no_prof:
-        cq.prof_enable(True)
     ev = {v: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)] for v in variants}
     per_var_ms = {v: 0.0 for v in variants}
@@ -272,11 +273,23 @@ def main():
     dofsteps = args.steps * len(variants) * 2 * M * N
     value = dofsteps / elapsed
 
-    # kernel timing and roofline of the dominant kernel
+    # Kernel timing and the dominant kernel's roofline come from one more
+    # step outside the timed region, with the variants run one after another
+    # on one stream, so that each launch's duration is its own and not
+    # stretched by kernels of other variants sharing the GPU.
     kinds = ["hist_fast", "hist_direct", "far_toeplitz", "solve_1d", "prep_2d", "dst_gemm", "modal_fast",
              "modal_near"]
     ktime = {}
     if not args.no_prof:
+        torch.cuda.synchronize()
+        cq.prof_enable(True)
+        for v in variants:
+            s = solvers[v]
+            with torch.cuda.stream(streams[v]):
+                s.reset(G0)
+                s.step(N)
+                s.current(outs[v])
+            torch.cuda.synchronize()
         for kname in kinds:
             n_l, ms = cq.prof_read(kname)
             if n_l:
@@ -290,8 +303,8 @@ def main():
         for v in variants:
             info = solvers[v].info()
             b, f = kernel_work(dom, w, v[0], v[1], info, M)
-            tot_b += b * args.steps
-            tot_f += f * args.steps
+            tot_b += b
+            tot_f += f
         avg_s = ms / 1e3 / n_l
         f_frac = (tot_f / n_l / avg_s / 1e12) / FP64_PEAK_TFLOPS if tot_f else 0.0
         b_frac = (tot_b / n_l / avg_s / 1e9) / HBM_PEAK_GBS if tot_b else 0.0
@@ -307,6 +320,7 @@ def main():
         roofline["kernel"] = dom
         roofline["avg_launch_us"] = avg_s * 1e6
         roofline["launches"] = n_l
+        roofline["timed"] = "one extra serial step after the timed region, HIP events per launch"
         roofline["traffic"] = load_traffic(dom)
 
     # fast vs direct on the GPU (the metric's accuracy side)
@@ -344,6 +358,14 @@ def main():
         "kernels_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in ktime.items()},
         "roofline": roofline,
     }
+    if args.copy_probe:
+        nel = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes_each_way"] = nel * 8
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

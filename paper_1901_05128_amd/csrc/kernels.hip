@@ -736,28 +736,45 @@ __global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
     }
 }
 
+// Exchange of a double between the two lanes of a pair (lane ^ 1) with a
+// DPP quad permutation [1,0,3,2] on each 32-bit half.
+__device__ __forceinline__ double pair_swap(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(v & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(v >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // Direct form, part of one time block: the steps n = nfirst .. nfirst+bt-1
 // (inside the block n0+1 .. n0+B) in order. A lane pair owns one mode, lane
-// k of the pair component k; the pair exchanges its history sums for the
-// 2x2 solve. S_k = F[b][k] (far field of the block, summed over the K-split
-// by k_reduce_far) + sum_{l=n0+1}^{n-1} d_{k,n-l} g_k^l. The levels of this
-// block stay in registers, ring[i] = g_k^{n-1-i} (zero for levels before the
-// block), shifted by one per step; BDF2's time part keeps g^{n-1}, g^{n-2}
-// apart (they may belong to the previous block). A run that resumes inside a
-// block first reloads the block's earlier levels.
-template <int BB>
-__global__ __launch_bounds__(256) void k_modal_near(ModalNearArgs p) {
-    // weights d_{k,1..BB-1}, staged once in LDS
-    __shared__ double wd[2][BB];
-    for (int e = threadIdx.x; e < 2 * BB; e += 256) {
+// k of the pair component k. The history sum of step n0+1+b is
+//   S_k[b] = F[b][k] (far field of the block, summed over the K-split by
+//            k_reduce_far) + sum_{j<b} d_{k,b-j} g_k^{n0+1+j},
+// accumulated in push form: acc[b] starts as the far field (plus BDF2's
+// starting correction 1/2 d_{k,n-1} g_k^0) and each level is added into the
+// pending sums of all later steps of the block, so a step waits on one FMA
+// only and the loop makes no global loads. Steps are
+// unrolled so that acc[] stays in registers. The 2x2 solve is split by
+// lanes: g_k = P_k + Q_{k'}, where P_k = c_own E_k + u S_k is the lane's own
+// part and Q_k = x E_k + y S_k its part of the partner's value, so a step
+// exchanges one double. FULL is the whole-block case without per-step
+// guards; otherwise a run that resumes inside a block first pushes the
+// block's earlier levels from memory.
+template <int BB, bool FULL>
+__global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
+    // weights d_{k,0..BB-1} in LDS; the component rows are BB+1 apart so
+    // that the two components of a lane pair read different banks
+    __shared__ double wd[2 * (BB + 1)];
+    for (int e = threadIdx.x; e < 2 * BB; e += 64) {
         const int kk = e / BB, i = e % BB;
-        wd[kk][i] = (i >= 1 && i < p.dstride) ? p.d[int64_t(kk) * p.dstride + i] : 0.0;
+        wd[kk * (BB + 1) + i] = (i >= 1 && i < p.dstride) ? p.d[int64_t(kk) * p.dstride + i] : 0.0;
     }
     __syncthreads();
-    const int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t gid = int64_t(blockIdx.x) * 64 + threadIdx.x;
     const int64_t mode = gid >> 1;
     const int k = int(gid & 1);
     if (mode >= p.M) return;  // both lanes of a pair leave together
+    const double* __restrict__ w = wd + k * (BB + 1);
     const int64_t M = p.M, twoM = 2 * M;
     const double lam = p.lam[mode];
     const double g0k = p.g0[k * M + mode];
@@ -765,53 +782,73 @@ __global__ __launch_bounds__(256) void k_modal_near(ModalNearArgs p) {
     const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
     const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
     const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    // g = Minv r with r_k = E_k - L1 S_k + a S_k'; row k of Minv is (ck0, ck1)
+    const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
+    const double c_own = k ? i11 : i00;   // Minv[k][k]
+    const double c_part = k ? i01 : i10;  // Minv[k'][k]: weight of r_k in g_k'
+    const double u = p.a * (k ? i10 : i01) - L1 * c_own;  // S_k in g_k (through r_k and r_k')
+    const double x = c_part;
+    const double y = p.a * (k ? i00 : i11) - L1 * c_part;  // S_k in g_k'
+    const double et = p.inv_tau;
     double* __restrict__ lv = p.levels + k * M + mode;
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
-    double ring[BB];
+    const int b0 = int(p.nfirst - p.n0 - 1);  // first block offset taken here
+    const int bend = b0 + p.bt;               // one past the last
+    double acc[BB];
 #pragma unroll
-    for (int i = 0; i < BB; ++i) {
-        const int64_t l = p.nfirst - 1 - i;  // in-block levels already taken
-        ring[i] = (l >= p.n0 + 1) ? lv[l * twoM] : 0.0;
+    for (int b = 0; b < BB; ++b) {
+        double v = 0.0;
+        if (FULL || (b >= b0 && b < bend)) {
+            if (p.n0 >= 1) v = p.F[(int64_t(b) * 2 + k) * M + mode];
+            if (p.scheme == 2) v = fma(0.5 * dk[p.n0 + b], g0k, v);
+        }
+        acc[b] = v;
+    }
+    if (!FULL) {
+        for (int j = 0; j < b0; ++j) {
+            const double g = lv[(p.n0 + 1 + j) * twoM];
+#pragma unroll
+            for (int b = 1; b < BB; ++b)
+                if (b >= b0 && b > j) acc[b] = fma(w[b - j], g, acc[b]);
+        }
     }
     double gm1 = lv[(p.nfirst - 1) * twoM];
     double gm2 = lv[((p.nfirst >= 2) ? p.nfirst - 2 : 0) * twoM];
-    // far-field value of the next step is loaded one step ahead
-    double f = 0.0;
-    if (p.n0 >= 1 && p.bt > 0) f = p.F[((p.nfirst - p.n0 - 1) * 2 + k) * M + mode];
-    for (int t = 0; t < p.bt; ++t) {
-        const int64_t n = p.nfirst + t;
-        const int64_t b = n - p.n0 - 1;
-        double S = f;
-        if (p.n0 >= 1 && t + 1 < p.bt) f = p.F[((b + 1) * 2 + k) * M + mode];
-        double a0 = 0.0, a1 = 0.0;
+    const bool bdf2 = p.scheme == 2;
+    const double w1 = w[1];
+    // the most used weights stay in registers, the rest are read from LDS
+    constexpr int WR = 32;
+    double wr[WR];
 #pragma unroll
-        for (int i = 0; i + 1 < BB; i += 2) {
-            if (i < b) {
-                a0 = fma(wd[k][i + 1], ring[i], a0);
-                a1 = fma(wd[k][i + 2 < BB ? i + 2 : 0], ring[i + 1], a1);
+    for (int i = 0; i < WR; ++i) wr[i] = w[i + 2];
+    // Step b adds the previous level with one FMA (the critical path) and
+    // then pushes that level into the later sums; the barrier keeps each
+    // step's instructions together so that the pushes overlap the solve
+    // instead of being sunk into a serial chain before their use.
+    double gprev = 0.0;
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+        if (FULL || (b >= b0 && b < bend)) {
+            __builtin_amdgcn_sched_barrier(0);
+            const bool has_prev = FULL ? (b > 0) : (b > b0);
+            double S = acc[b];
+            if (has_prev) S = fma(w1, gprev, S);
+            const double E = bdf2 ? (2.0 * gm1 - 0.5 * gm2) * et : gm1 * et;
+            const double Q = fma(y, S, x * E);
+            const double P = fma(u, S, c_own * E);
+            const double gn = P + pair_swap(Q);
+            lv[(p.n0 + 1 + b) * twoM] = gn;
+            if (has_prev) {
+#pragma unroll
+                for (int bb = b + 1; bb < BB; ++bb) {
+                    const int i = bb - b + 1;
+                    acc[bb] = fma(i - 2 < WR ? wr[i - 2] : w[i], gprev, acc[bb]);
+                }
             }
+            gprev = gn;
+            gm2 = gm1;
+            gm1 = gn;
         }
-        S += a0 + a1;
-        double E;
-        if (p.scheme == 1) {
-            E = gm1 * p.inv_tau;
-        } else {
-            E = (2.0 * gm1 - 0.5 * gm2) * p.inv_tau;
-            S = fma(0.5 * dk[n - 1], g0k, S);
-        }
-        const double So = __shfl_xor(S, 1, 64);
-        const double Eo = __shfl_xor(E, 1, 64);
-        const double S0 = k ? So : S, S1 = k ? S : So;
-        const double E0 = k ? Eo : E, E1 = k ? E : Eo;
-        const double r0 = E0 - (L1 * S0 - p.a * S1);
-        const double r1 = E1 - (L1 * S1 - p.a * S0);
-        const double gn = k ? (m11 * r1 - m21 * r0) * idet : (m22 * r0 - m12 * r1) * idet;
-        lv[n * twoM] = gn;
-#pragma unroll
-        for (int i = BB - 1; i > 0; --i) ring[i] = ring[i - 1];
-        ring[0] = gn;
-        gm2 = gm1;
-        gm1 = gn;
     }
 }
 
@@ -1025,16 +1062,14 @@ void launch_modal_win(const ModalWinArgs& a, hipStream_t st) {
 }
 
 void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st) {
-    const dim3 grid(unsigned((2 * a.M + 255) / 256));
+    // the modal direct solver always uses blocks of 64 steps
+    (void)B;
+    const dim3 grid(unsigned((2 * a.M + 63) / 64));
     prof_begin(8, st);
-    if (B <= 64)
-        hipLaunchKernelGGL(k_modal_near<64>, grid, dim3(256), 0, st, a);
-    else if (B <= 128)
-        hipLaunchKernelGGL(k_modal_near<128>, grid, dim3(256), 0, st, a);
-    else if (B <= 192)
-        hipLaunchKernelGGL(k_modal_near<192>, grid, dim3(256), 0, st, a);
+    if (a.nfirst == a.n0 + 1 && a.bt == 64)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, true>), grid, dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL(k_modal_near<256>, grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, false>), grid, dim3(64), 0, st, a);
     prof_end(8, st);
 }
 
