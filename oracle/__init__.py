@@ -17,4 +17,7 @@ Modules
   modal        The same schemes for one Laplacian eigenmode (2x2 recurrences),
                used to check full-size GPU runs mode by mode.
   mittag_leffler  E_alpha(-x) from its spectral integral, for closed-form pins.
+  adjoint      Gradient of a loss of G^N with respect to G^0, alpha_1, alpha_2
+               and m: the discrete adjoint of the schemes above (an extension,
+               not in the paper).
 """
