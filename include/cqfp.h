@@ -179,6 +179,31 @@ int fp_destroy(void* handle);
 int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double* GN,
              void* hip_stream);
 
+/* Gradient of a loss of the final state (extension, not in the paper): the
+ * discrete adjoint of the scheme of (4.1)/(4.3) or (4.7)/(4.8) that fp_solve
+ * runs with the same grid and parameters (direct or fast; modal solver,
+ * solver = 1, required). Given gN = dl/dG^N (dev [2][M]) it writes
+ *   gG0  (dev [2][M])   dl/dG^0,
+ *   grad (host [3])     dl/dalpha_1, dl/dalpha_2, dl/dm,
+ *   GN   (dev [2][M])   G^N, or NULL.
+ * With mu^n the multipliers of the step equations c G^n - E^n + Dm X^n = 0
+ * (Dm = [[a+A, -a], [-a, a+A]], X^n the CQ sums of the scheme), they solve
+ * the transposed steps backwards in time: (cI + W_0 Dm) mu^n = [n=N] gN
+ * + (time-difference terms of mu^{n+1}, mu^{n+2}) - sum_{i>=1} W_i Dm
+ * mu^{n+i}, the same CQ recurrence with the same weights (fast or direct)
+ * run in reversed time on psi = Dm mu. Parameter gradients contract mu with
+ * d/dtheta of the step equations; for alpha_k the weights' beta-derivative
+ * is exact for the direct scheme; for the fast scheme beyond its lag the
+ * rule's factor tau^-beta is differentiated exactly and the rest by a
+ * fourth-order difference in beta of the rebuilt Gauss-Jacobi rule (below
+ * 1e-11 relative). The forward trajectory, its history sums and the adjoint
+ * (psi, mu) are kept in device memory: 4 (N+1) 2M doubles (CQ_ENOMEM
+ * beyond the free memory). Device work runs on hip_stream; the call
+ * synchronises it. Errors as fp_create, plus CQ_EINVAL for solver != 1 or
+ * a fast window (ns) above 32. */
+int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN,
+               double* gG0, double* grad, double* GN, void* hip_stream);
+
 /* Batched fast solves (extension): `count` independent problems (own grid,
  * orders, m, T, N, scheme; method must be 1, the fast form) solved by the
  * modal solver in one captured HIP graph. Every problem's sine modes are
@@ -213,7 +238,8 @@ int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_params* param
  * field (FP64 MFMA), 3 1D right-hand side + PCR solve, 4 2D right-hand side,
  * 5 DST GEMM (forward/inverse and per-mode solve), 6 standalone history
  * reduction, 7 modal fast steps, 8 modal direct near field + solve,
- * 9 batched modal fast time loops. cq_prof_read synchronises the recorded events and returns, for
+ * 9 batched modal fast time loops, 10 sum of the far field's K-split
+ * partials. cq_prof_read synchronises the recorded events and returns, for
  * one kind, the launch count and the summed duration in milliseconds.
  * cq_prof_enable(1) also clears earlier records. Not thread safe. */
 int cq_prof_enable(int32_t on);

@@ -44,9 +44,10 @@ Weight derivatives: for the exact weights, the recurrence of the weights
 module differentiated term by term (BE: g_i = g_{i-1}(1 - (1+beta)/i), so
 g'_i = g'_{i-1}(1 - (1+beta)/i) - g_{i-1}/i; BDF2: the product rule through
 the Cauchy product), times tau^-beta with its own derivative. For the
-Gauss-Jacobi sums, a five-point central difference in beta of the whole rule
-(nodes and weights recomputed), step h_rule; its error is of order
-h_rule^4 times the fifth derivative (about 1e-11 relative at the default).
+Gauss-Jacobi sums, the factor tau^-beta exactly and the rest by a five-point
+central difference in beta of the whole rule (nodes and weights recomputed),
+step h_rule; its error is of order h_rule^4 times the fifth derivative
+(below 1e-11 relative at the default).
 """
 from __future__ import annotations
 
@@ -88,8 +89,13 @@ def _rule_tail(scheme, beta, tau, N, np_, np1, lag):
     return approx_weights_fast(rules, lag, N)
 
 
-def scheme_weights(scheme, method, beta, tau, N, np_=None, np1=16, ns=30, h_rule=2e-3):
-    """(w, dw/dbeta) of the CQ sum as the scheme uses it, i = 0..N."""
+def scheme_weights(scheme, method, beta, tau, N, np_=None, np1=16, ns=30, h_rule=1e-3):
+    """(w, dw/dbeta) of the CQ sum as the scheme uses it, i = 0..N.
+
+    The Gauss-Jacobi sums carry the factor tau^-beta of (3.6)/(3.14); it is
+    differentiated exactly, w = tau^-beta q(beta) with q the sums at tau = 1,
+    and only q' comes from the five-point difference (its high derivatives
+    in beta stay small, where those of tau^-beta grow like ln(1/tau)^5)."""
     d = weights(scheme, beta, tau, N)
     dd = exact_weights_dbeta(scheme, beta, tau, N)
     if method == 0:
@@ -99,10 +105,12 @@ def scheme_weights(scheme, method, beta, tau, N, np_=None, np1=16, ns=30, h_rule
     lag = 2 if scheme == 1 else ns
     w, dw = d.copy(), dd.copy()
     if lag <= N:
-        w[lag:] = _rule_tail(scheme, beta, tau, N, np_, np1, lag)
-        f = lambda b: _rule_tail(scheme, b, tau, N, np_, np1, lag)
+        q = lambda b: _rule_tail(scheme, b, 1.0, N, np_, np1, lag)
         h = h_rule
-        dw[lag:] = (f(beta - 2 * h) - 8 * f(beta - h) + 8 * f(beta + h) - f(beta + 2 * h)) / (12 * h)
+        dq = (q(beta - 2 * h) - 8 * q(beta - h) + 8 * q(beta + h) - q(beta + 2 * h)) / (12 * h)
+        tb = tau ** (-beta)
+        w[lag:] = tb * q(beta)
+        dw[lag:] = tb * (dq - np.log(tau) * q(beta))
     return w, dw
 
 

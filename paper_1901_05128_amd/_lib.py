@@ -23,9 +23,9 @@ STATUS_NAMES = {0: "CQ_OK", -1: "CQ_EINVAL", -2: "CQ_ESINGULAR", -3: "CQ_ENOMEM"
 # every entry point the header declares
 EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "fp_current", "fp_info",
            "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "fp_solve_batched",
-           "cq_prof_enable", "cq_prof_read", "cq_last_error"]
+           "fp_adjoint", "cq_prof_enable", "cq_prof_read", "cq_last_error"]
 PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
-              "reduce_row": 6, "modal_fast": 7, "modal_near": 8}
+              "reduce_row": 6, "modal_fast": 7, "modal_near": 8, "batched": 9, "reduce_far": 10}
 
 
 class CQError(RuntimeError):
@@ -88,6 +88,7 @@ def lib() -> C.CDLL:
     L.cq_prof_read.argtypes = [I32, P(I64), P(D)]
     L.fp_solve.argtypes = [P(Grid), P(Params), VP, VP, VP]
     L.fp_solve_batched.argtypes = [I32, P(Grid), P(Params), P(VP), P(VP), VP, I32, P(BatchReport)]
+    L.fp_adjoint.argtypes = [P(Grid), P(Params), VP, VP, VP, P(D), VP, VP]
     L.cq_last_error.argtypes = []
     L.cq_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -238,6 +239,19 @@ def fp_solve(grid: Grid, params: Params, G0, GN=None):
         GN = torch.empty((2, M), dtype=torch.float64, device=G0.device)
     _check(lib().fp_solve(C.byref(grid), C.byref(params), _dev(G0, "G0"), _dev(GN, "GN"), _stream()))
     return GN
+
+
+def fp_adjoint(grid: Grid, params: Params, G0, gN, gG0=None, GN=None):
+    """Gradient of a loss of G^N (modal solver): given gN = dl/dG^N, returns
+    (dl/dG0 tensor, (dl/dalpha1, dl/dalpha2, dl/dm)); G^N is written to GN
+    when given."""
+    import torch
+    if gG0 is None:
+        gG0 = torch.empty_like(G0)
+    g = (C.c_double * 3)()
+    _check(lib().fp_adjoint(C.byref(grid), C.byref(params), _dev(G0, "G0"), _dev(gN, "gN"), _dev(gG0, "gG0"), g,
+                            _dev(GN, "GN") if GN is not None else None, _stream()))
+    return gG0, (g[0], g[1], g[2])
 
 
 def fp_solve_batched(grids, params, G0s, GNs=None, autotune=True):

@@ -18,6 +18,8 @@ void clear_error();
 // Weights d_i, i = 0..n, of ((1-z)/tau)^beta (scheme 1) or
 // (((1-z)+(1-z)^2/2)/tau)^beta (scheme 2), by first-order recurrences.
 void weights(int scheme, double beta, double tau, int64_t n, double* d);
+// d/dbeta of those weights, i = 0..n (the recurrences differentiated).
+void weights_dbeta(int scheme, double beta, double tau, int64_t n, double* dd);
 
 // Gauss-Jacobi nodes s_j (ascending) and weights lam_j for the weight
 // (1-s)^a (1+s)^b on [-1,1]: eigenvalues of the Jacobi matrix by Sturm
@@ -40,6 +42,11 @@ double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N);
 // Node-count scan; returns CQ_OK or CQ_ETOL.
 int choose_rule(int scheme, double beta, double tau, int64_t N, double tol, int np_max, int np1,
                 int ns, FastRule& out);
+
+// d/dbeta of the fast weights of an np-node rule (BDF2: np1 + np) started at
+// lag, for lag <= i <= N (five-point difference in beta, step h).
+void rule_weights_dbeta(int scheme, double beta, double tau, int np, int np1, int ns, int lag, int64_t N,
+                        double h, double* dw);
 
 // Eigen-decomposition of the 2x2 coupling K (real eigenvalues, since
 // K12*K21 >= 0): K = V diag(theta) V^{-1}.

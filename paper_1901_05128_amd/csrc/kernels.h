@@ -116,6 +116,14 @@ struct ModalNearArgs {
     const double* g0;
     const double* F;      // [B][2][M] reduced far field (n0 >= 1)
     double* levels;       // [N+1][2][M] coefficients
+    // forward: history sums S^n (with BDF2's starting correction) at
+    // Sout[n * sstride]; sstride = 0 points every step at one [2][M] scratch row
+    double* Sout;         // [N+1][2][M] (or [2][M] with sstride 0)
+    int64_t sstride;
+    // adjoint sweep (template ADJ): levels hold psi = Dm mu, mu^n goes to mu[n]
+    // (mu[0] = 0), and the cotangent gc enters the first step
+    double* mu;           // [N+1][2][M]
+    const double* gc;     // [2][M]
 };
 
 struct ModalWinArgs {
@@ -135,6 +143,41 @@ struct ModalWinArgs {
     const double* g0;
     const double* Sf;
     double* levels;       // [Lr][2][M] coefficients, level l at slot l mod Lr
+    double* Sout;         // as in ModalNearArgs
+    int64_t sstride;
+    double* mu;           // adjoint: [N+1][2][M]
+    const double* gc;     // adjoint: [2][M]
+};
+
+// Gradient passes of the adjoint (modal coefficients, time-major arrays
+// [N+1][2][M]; the adjoint's arrays are in reversed time, index N+1-n).
+struct AdjGradArgs {
+    int64_t M, N;
+    int scheme;
+    int64_t dstride;
+    double inv_tau;
+    double d0[2];          // d_{1,0}, d_{2,0}
+    const double* d;       // [2][dstride] exact weights
+    const double* traj;    // forward levels g^n
+    const double* Sx;      // forward history sums S^n
+    const double* mu;      // adjoint mu (reversed)
+    const double* psi;     // adjoint psi = Dm mu (reversed)
+    double* gG0c;          // [2][M] out: dl/dg^0
+    double* part;          // [blocks] out: partial sums of sum_n (mu_0 - mu_1).(X_0 - X_1)
+};
+
+// d/dbeta pass over one time block n0+1..n0+bt: for each component and mode
+//   acc += sum_b psi^n (F[b] + sum_{l=n0+1}^{n} dw_{n-l} g^l + [BDF2] 1/2 dd_{n-1} g^0)
+struct AdjBetaArgs {
+    int64_t M, N, n0;
+    int bt, scheme;
+    int64_t dstride;
+    const double* dw;      // [2][dstride] d/dbeta of the scheme's weights
+    const double* dd;      // [2][dstride] d/dbeta of the exact weights
+    const double* F;       // [B][2][M] reduced far field (n0 >= 1)
+    const double* traj;
+    const double* psi;
+    double* acc;           // [2][M]
 };
 
 // one problem of a batch (device table entry)
@@ -160,8 +203,14 @@ struct BatchArgs {
 
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
 void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
-void launch_modal_win(const ModalWinArgs& a, hipStream_t st);
-void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st);
+void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);
+void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st);
+void launch_adj_g0(const AdjGradArgs& a, hipStream_t st);
+// returns the number of partial sums written to a.part
+int launch_adj_da(const AdjGradArgs& a, hipStream_t st);
+void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st);
+// out[k] = sum_x acc[k][x] over blocks: partials [2][blocks]; returns blocks
+int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st);
 void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);

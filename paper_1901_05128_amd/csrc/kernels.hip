@@ -651,7 +651,12 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
 // (ring[i] = g^{n-1-i}, levels below 0 read as g^0 for BDF2's g^{-1}), then
 // the 2x2 solve; the new level goes to its slot of the level store (the
 // state pass of the next block reads it there).
-template <int LW>
+//
+// ADJ: one step of the adjoint sweep in reversed time. The same history of
+// the levels (here psi = Dm mu), then r = E(mu) - S (plus the cotangent at
+// the first step), mu = (c I + W_0 Dm)^-1 r = M^-T r and the new level
+// psi = Dm mu; mu^n goes to mu[n].
+template <int LW, bool ADJ>
 __global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
     const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (mode >= p.M) return;
@@ -674,6 +679,21 @@ __global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
         const int64_t sl = l % p.Lr;
         ring0[i] = ok ? lv[sl * twoM] : 0.0;
         ring1[i] = ok ? lv[sl * twoM + M] : 0.0;
+    }
+    // the variables of the time difference: the levels themselves (forward)
+    // or mu (adjoint; mu[0] = 0 and mu^{-1} = 0)
+    double e10, e11, e20, e21;
+    if (ADJ) {
+        const double* __restrict__ mv = p.mu + mode;
+        e10 = mv[(p.nfirst - 1) * twoM];
+        e11 = mv[(p.nfirst - 1) * twoM + M];
+        e20 = p.nfirst >= 2 ? mv[(p.nfirst - 2) * twoM] : 0.0;
+        e21 = p.nfirst >= 2 ? mv[(p.nfirst - 2) * twoM + M] : 0.0;
+    } else {
+        e10 = ring0[0];
+        e11 = ring1[0];
+        e20 = ring0[1];
+        e21 = ring1[1];
     }
     // partial sums of the next step are loaded one step ahead
     auto sf = [&](int64_t b, int k) {
@@ -711,28 +731,55 @@ __global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
         S1 += a1 + c1;
         double E0, E1;
         if (p.scheme == 1) {
-            E0 = ring0[0] * p.inv_tau;
-            E1 = ring1[0] * p.inv_tau;
+            E0 = e10 * p.inv_tau;
+            E1 = e11 * p.inv_tau;
         } else {
-            E0 = (2.0 * ring0[0] - 0.5 * ring0[1]) * p.inv_tau;
-            E1 = (2.0 * ring1[0] - 0.5 * ring1[1]) * p.inv_tau;
-            S0 = fma(0.5 * d0p[n - 1], g00, S0);
-            S1 = fma(0.5 * d1p[n - 1], g01, S1);
+            E0 = (2.0 * e10 - 0.5 * e20) * p.inv_tau;
+            E1 = (2.0 * e11 - 0.5 * e21) * p.inv_tau;
+            if (!ADJ) {
+                S0 = fma(0.5 * d0p[n - 1], g00, S0);
+                S1 = fma(0.5 * d1p[n - 1], g01, S1);
+            }
         }
-        const double r0 = E0 - (L1 * S0 - p.a * S1);
-        const double r1 = E1 - (L1 * S1 - p.a * S0);
-        const double gn0 = (m22 * r0 - m12 * r1) * idet;
-        const double gn1 = (m11 * r1 - m21 * r0) * idet;
+        double v0, v1;  // the new level
+        if (ADJ) {
+            if (n == 1) {
+                S0 -= p.gc[mode];
+                S1 -= p.gc[M + mode];
+            }
+            const double r0 = E0 - S0, r1 = E1 - S1;
+            const double u0 = (m22 * r0 - m21 * r1) * idet;
+            const double u1 = (m11 * r1 - m12 * r0) * idet;
+            v0 = L1 * u0 - p.a * u1;
+            v1 = L1 * u1 - p.a * u0;
+            p.mu[n * twoM + mode] = u0;
+            p.mu[n * twoM + M + mode] = u1;
+            e20 = e10;
+            e21 = e11;
+            e10 = u0;
+            e11 = u1;
+        } else {
+            p.Sout[n * p.sstride + mode] = S0;
+            p.Sout[n * p.sstride + M + mode] = S1;
+            const double r0 = E0 - (L1 * S0 - p.a * S1);
+            const double r1 = E1 - (L1 * S1 - p.a * S0);
+            v0 = (m22 * r0 - m12 * r1) * idet;
+            v1 = (m11 * r1 - m21 * r0) * idet;
+            e20 = e10;
+            e21 = e11;
+            e10 = v0;
+            e11 = v1;
+        }
         const int64_t so = n % p.Lr;
-        lv[so * twoM] = gn0;
-        lv[so * twoM + M] = gn1;
+        lv[so * twoM] = v0;
+        lv[so * twoM + M] = v1;
 #pragma unroll
         for (int i = LW - 1; i > 0; --i) {
             ring0[i] = ring0[i - 1];
             ring1[i] = ring1[i - 1];
         }
-        ring0[0] = gn0;
-        ring1[0] = gn1;
+        ring0[0] = v0;
+        ring1[0] = v1;
     }
 }
 
@@ -760,7 +807,7 @@ __device__ __forceinline__ double pair_swap(double x) {
 // exchanges one double. FULL is the whole-block case without per-step
 // guards; otherwise a run that resumes inside a block first pushes the
 // block's earlier levels from memory.
-template <int BB, bool FULL>
+template <int BB, bool FULL, bool ADJ>
 __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
     // weights d_{k,0..BB-1} in LDS; the component rows are BB+1 apart so
     // that the two components of a lane pair read different banks
@@ -782,13 +829,15 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
     const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
     const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
     const double idet = 1.0 / (m11 * m22 - m12 * m21);
-    // g = Minv r with r_k = E_k - L1 S_k + a S_k'; row k of Minv is (ck0, ck1)
     const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
-    const double c_own = k ? i11 : i00;   // Minv[k][k]
-    const double c_part = k ? i01 : i10;  // Minv[k'][k]: weight of r_k in g_k'
-    const double u = p.a * (k ? i10 : i01) - L1 * c_own;  // S_k in g_k (through r_k and r_k')
+    const double c_own = k ? i11 : i00;  // Minv[k][k]
+    // forward: g = Minv r with r_k = E_k - L1 S_k + a S_k'
+    const double c_part = k ? i01 : i10;                   // Minv[k'][k]: weight of r_k in g_k'
+    const double u = p.a * (k ? i10 : i01) - L1 * c_own;   // S_k in g_k (through r_k and r_k')
     const double x = c_part;
     const double y = p.a * (k ? i00 : i11) - L1 * c_part;  // S_k in g_k'
+    // adjoint: mu = Minv^T r with r_k = E_k - S_k; r_k enters mu_k' with Minv[k][k']
+    const double t_part = k ? i10 : i01;
     const double et = p.inv_tau;
     double* __restrict__ lv = p.levels + k * M + mode;
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
@@ -800,7 +849,8 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
         double v = 0.0;
         if (FULL || (b >= b0 && b < bend)) {
             if (p.n0 >= 1) v = p.F[(int64_t(b) * 2 + k) * M + mode];
-            if (p.scheme == 2) v = fma(0.5 * dk[p.n0 + b], g0k, v);
+            if (!ADJ && p.scheme == 2) v = fma(0.5 * dk[p.n0 + b], g0k, v);
+            if (ADJ && b == 0 && p.n0 == 0) v -= p.gc[k * M + mode];  // cotangent enters step 1
         }
         acc[b] = v;
     }
@@ -812,8 +862,11 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
                 if (b >= b0 && b > j) acc[b] = fma(w[b - j], g, acc[b]);
         }
     }
-    double gm1 = lv[(p.nfirst - 1) * twoM];
-    double gm2 = lv[((p.nfirst >= 2) ? p.nfirst - 2 : 0) * twoM];
+    // variables of the time difference: levels (forward) or mu (adjoint,
+    // mu[0] = 0 and mu^{-1} = 0)
+    const double* __restrict__ ev = ADJ ? p.mu + k * M + mode : lv;
+    double gm1 = ev[(p.nfirst - 1) * twoM];
+    double gm2 = (ADJ && p.nfirst < 2) ? 0.0 : ev[((p.nfirst >= 2) ? p.nfirst - 2 : 0) * twoM];
     const bool bdf2 = p.scheme == 2;
     const double w1 = w[1];
     // the most used weights stay in registers, the rest are read from LDS
@@ -834,10 +887,22 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
             double S = acc[b];
             if (has_prev) S = fma(w1, gprev, S);
             const double E = bdf2 ? (2.0 * gm1 - 0.5 * gm2) * et : gm1 * et;
-            const double Q = fma(y, S, x * E);
-            const double P = fma(u, S, c_own * E);
-            const double gn = P + pair_swap(Q);
-            lv[(p.n0 + 1 + b) * twoM] = gn;
+            double lev, e_new;
+            if (ADJ) {
+                const double r = E - S;
+                const double P = c_own * r, Q = t_part * r;
+                const double A = L1 * P - p.a * Q, Bv = L1 * Q - p.a * P;
+                e_new = P + pair_swap(Q);    // mu_k
+                lev = A + pair_swap(Bv);     // psi_k = L1 mu_k - a mu_k'
+                p.mu[(p.n0 + 1 + b) * twoM + k * M + mode] = e_new;
+            } else {
+                const double Q = fma(y, S, x * E);
+                const double P = fma(u, S, c_own * E);
+                lev = P + pair_swap(Q);
+                e_new = lev;
+                p.Sout[(p.n0 + 1 + b) * p.sstride + k * M + mode] = S;
+            }
+            lv[(p.n0 + 1 + b) * twoM] = lev;
             if (has_prev) {
 #pragma unroll
                 for (int bb = b + 1; bb < BB; ++bb) {
@@ -845,11 +910,130 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
                     acc[bb] = fma(i - 2 < WR ? wr[i - 2] : w[i], gprev, acc[bb]);
                 }
             }
-            gprev = gn;
+            gprev = lev;
             gm2 = gm1;
-            gm1 = gn;
+            gm1 = e_new;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient passes of the adjoint (modal coefficients). With the forward
+// levels g^n, history sums S^n (with BDF2's starting correction), and the
+// adjoint's mu^n, psi^n = Dm mu^n stored in reversed time (index N+1-n):
+//   dl/dg^0 = mu^1/tau (BE),
+//           = (3 mu^1 - mu^2)/(2 tau) - 1/2 sum_n d_{k,n-1} psi_k^n (BDF2),
+//   dl/da   = -sum_n (mu_1^n - mu_2^n)(X_1^n - X_2^n),  X^n = d_0 g^n + S^n,
+//   dl/dalpha_k = sum_n psi_k^n Y_k^n,
+//   Y_k^n = sum_{l=1}^{n} dw_{k,n-l} g_k^l + [BDF2] 1/2 dd_{k,n-1} g_k^0,
+// with dw, dd the beta-derivatives of the scheme's and the exact weights.
+
+// 256-thread block sum in a fixed order (deterministic)
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = 128; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// one thread per (component, mode)
+__global__ __launch_bounds__(256) void k_adj_g0(AdjGradArgs p) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= 2 * p.M) return;
+    const int64_t twoM = 2 * p.M, N = p.N;
+    const int k = int(e / p.M);
+    const double mu1 = p.mu[N * twoM + e];
+    if (p.scheme == 1) {
+        p.gG0c[e] = mu1 * p.inv_tau;
+        return;
+    }
+    const double mu2 = N >= 2 ? p.mu[(N - 1) * twoM + e] : 0.0;
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t n = 1;
+    for (; n + 1 <= N; n += 2) {
+        s0 = fma(dk[n - 1], p.psi[(N + 1 - n) * twoM + e], s0);
+        s1 = fma(dk[n], p.psi[(N - n) * twoM + e], s1);
+    }
+    if (n <= N) s0 = fma(dk[n - 1], p.psi[(N + 1 - n) * twoM + e], s0);
+    p.gG0c[e] = (3.0 * mu1 - mu2) * (0.5 * p.inv_tau) - 0.5 * (s0 + s1);
+}
+
+// one thread per mode; a partial sum per block
+__global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
+    __shared__ double red[256];
+    const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (mode < p.M) {
+        const int64_t M = p.M, twoM = 2 * M, N = p.N;
+        for (int64_t n = 1; n <= N; ++n) {
+            const int64_t t = n * twoM + mode, r = (N + 1 - n) * twoM + mode;
+            const double X0 = fma(p.d0[0], p.traj[t], p.Sx[t]);
+            const double X1 = fma(p.d0[1], p.traj[t + M], p.Sx[t + M]);
+            acc = fma(p.mu[r] - p.mu[r + M], X0 - X1, acc);
+        }
+    }
+    const double tot = block_sum256(acc, red);
+    if (threadIdx.x == 0) p.part[blockIdx.x] = tot;
+}
+
+// d/dbeta over one block of up to 64 steps: one thread per (component,
+// mode); the block's levels in registers, the weight derivatives dw_0..63 in
+// LDS (both components), the far part F from k_far_toeplitz on dw.
+__global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
+    constexpr int BB = 64;
+    __shared__ double wd[2][BB];
+    for (int e = threadIdx.x; e < 2 * BB; e += 256) {
+        const int kk = e / BB, i = e % BB;
+        wd[kk][i] = i < p.dstride ? p.dw[int64_t(kk) * p.dstride + i] : 0.0;
+    }
+    __syncthreads();
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= 2 * p.M) return;
+    const int64_t M = p.M, twoM = 2 * M, N = p.N;
+    const int k = int(e / M);
+    const int64_t mode = e - int64_t(k) * M;
+    const double* __restrict__ w = wd[k];
+    const double g0 = p.traj[e];
+    const double* __restrict__ ddk = p.dd + int64_t(k) * p.dstride;
+    double g[BB];
+#pragma unroll
+    for (int j = 0; j < BB; ++j) g[j] = j < p.bt ? p.traj[(p.n0 + 1 + j) * twoM + e] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+        if (b < p.bt) {
+            const int64_t n = p.n0 + 1 + b;
+            double Y0 = p.n0 >= 1 ? p.F[(int64_t(b) * 2 + k) * M + mode] : 0.0, Y1 = 0.0;
+#pragma unroll
+            for (int j = 0; j <= b; ++j) {
+                if (j & 1)
+                    Y1 = fma(w[b - j], g[j], Y1);
+                else
+                    Y0 = fma(w[b - j], g[j], Y0);
+            }
+            double Y = Y0 + Y1;
+            if (p.scheme == 2) Y = fma(0.5 * ddk[n - 1], g0, Y);
+            acc = fma(p.psi[(N + 1 - n) * twoM + e], Y, acc);
+        }
+    }
+    p.acc[e] += acc;
+}
+
+// per-component sums of acc[2][M]: partials part[k][block]
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ acc, int64_t M, int64_t per,
+                                                  double* __restrict__ part) {
+    __shared__ double red[256];
+    const int k = blockIdx.y;
+    const int64_t lo = int64_t(blockIdx.x) * per;
+    double v = 0.0;
+    for (int64_t x = lo + threadIdx.x; x < lo + per && x < M; x += 256) v += acc[int64_t(k) * M + x];
+    const double tot = block_sum256(v, red);
+    if (threadIdx.x == 0) part[int64_t(k) * gridDim.x + blockIdx.x] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -973,11 +1157,13 @@ void launch_far(const FarArgs& a, hipStream_t st) {
         case 3: hipLaunchKernelGGL(k_far_toeplitz<3>, grid, dim3(256), 0, st, a); break;
         default: hipLaunchKernelGGL(k_far_toeplitz<4>, grid, dim3(256), 0, st, a); break;
     }
+    prof_end(2, st);
     if (a.ks > 1 && a.reduce) {
         const int64_t per = int64_t(a.B) * a.ncomp * a.M;
+        prof_begin(10, st);
         hipLaunchKernelGGL(k_reduce_far, dim3(unsigned((per + 255) / 256)), dim3(256), 0, st, a.F, a.ks, per);
+        prof_end(10, st);
     }
-    prof_end(2, st);
 }
 
 void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st) {
@@ -1055,22 +1241,55 @@ void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st) {
 #undef CQ_BATCH
 }
 
-void launch_modal_win(const ModalWinArgs& a, hipStream_t st) {
+void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st) {
     prof_begin(7, st);
-    hipLaunchKernelGGL(k_modal_win<32>, dim3(unsigned((a.M + 255) / 256)), dim3(256), 0, st, a);
+    const dim3 grid(unsigned((a.M + 255) / 256));
+    if (adj)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, true>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, false>), grid, dim3(256), 0, st, a);
     prof_end(7, st);
 }
 
-void launch_modal_near(const ModalNearArgs& a, int B, hipStream_t st) {
+void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st) {
     // the modal direct solver always uses blocks of 64 steps
     (void)B;
     const dim3 grid(unsigned((2 * a.M + 63) / 64));
+    const bool full = a.nfirst == a.n0 + 1 && a.bt == 64;
     prof_begin(8, st);
-    if (a.nfirst == a.n0 + 1 && a.bt == 64)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, true>), grid, dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, false>), grid, dim3(64), 0, st, a);
+    if (adj) {
+        if (full)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, true, true>), grid, dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, false, true>), grid, dim3(64), 0, st, a);
+    } else {
+        if (full)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, true, false>), grid, dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_near<64, false, false>), grid, dim3(64), 0, st, a);
+    }
     prof_end(8, st);
+}
+
+void launch_adj_g0(const AdjGradArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_g0, dim3(unsigned((2 * a.M + 255) / 256)), dim3(256), 0, st, a);
+}
+
+int launch_adj_da(const AdjGradArgs& a, hipStream_t st) {
+    const int blocks = int((a.M + 255) / 256);
+    hipLaunchKernelGGL(k_adj_da, dim3(unsigned(blocks)), dim3(256), 0, st, a);
+    return blocks;
+}
+
+void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_beta, dim3(unsigned((2 * a.M + 255) / 256)), dim3(256), 0, st, a);
+}
+
+int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st) {
+    const int64_t per = 4096;
+    const int blocks = int((M + per - 1) / per);
+    hipLaunchKernelGGL(k_sum_rows, dim3(unsigned(blocks), 2), dim3(256), 0, st, acc, M, per, part);
+    return blocks;
 }
 
 const void* kernel_step_1d(int R) {

@@ -53,6 +53,11 @@ struct Solver {
            *g0c = nullptr, *ring = nullptr;
     int levels_pcr = 0;
     bool modal_blocked = false;  // modal fast form with the state streamed in time blocks
+    // gradient runs (modal): forward history sums, adjoint sweep
+    bool adj = false;
+    double *Sout = nullptr, *mu = nullptr;
+    const double* gc = nullptr;
+    double* Sscratch = nullptr;  // [2][M] row the modal kernels write S to when Sout is not kept
     size_t lds = 0;
     size_t dev_bytes = 0;
     std::vector<void*> allocs;
@@ -376,6 +381,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
     if (modal) {
         if ((rc = setup_tables(s))) return rc;
         if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.Sscratch, size_t(twoM)))) return rc;
         if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
         if (p->method == 1) {
             // many modes: stream the state in time blocks (thread per mode);
@@ -430,12 +436,12 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
     return CQ_OK;
 }
 
-int check_finite_g0(const double* G0dev, int64_t count, hipStream_t st) {
+int check_finite_g0(const double* G0dev, int64_t count, hipStream_t st, const char* what = "G0") {
     std::vector<double> h(static_cast<size_t>(count));
     HIPCHK(hipMemcpyAsync(h.data(), G0dev, size_t(count) * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (double v : h)
-        if (!std::isfinite(v)) return fail(CQ_ENONFINITE, "G0 holds a non-finite value");
+        if (!std::isfinite(v)) return fail(CQ_ENONFINITE, "%s holds a non-finite value", what);
     return CQ_OK;
 }
 
@@ -502,7 +508,11 @@ void modal_steps(Solver& s, int64_t nsteps) {
             a.g0 = s.g0c;
             a.Sf = s.Sf;
             a.levels = s.levels;
-            launch_modal_win(a, s.st);
+            a.Sout = s.Sout ? s.Sout : s.Sscratch;
+            a.sstride = s.Sout ? 2 * s.M : 0;
+            a.mu = s.mu;
+            a.gc = s.gc;
+            launch_modal_win(a, s.adj, s.st);
             s.n += bt;
             nsteps -= bt;
         }
@@ -561,7 +571,11 @@ void modal_steps(Solver& s, int64_t nsteps) {
         a.g0 = s.g0c;
         a.F = s.F;
         a.levels = s.levels;
-        launch_modal_near(a, s.B, s.st);
+        a.Sout = s.Sout ? s.Sout : s.Sscratch;
+        a.sstride = s.Sout ? 2 * s.M : 0;
+        a.mu = s.mu;
+        a.gc = s.gc;
+        launch_modal_near(a, s.B, s.adj, s.st);
         s.n += bt;
         nsteps -= bt;
     }
@@ -715,7 +729,7 @@ size_t state_bytes(const Solver& s) {
 
 // ---- kernel timing ----
 namespace {
-constexpr int kProfKinds = 10;
+constexpr int kProfKinds = 11;
 struct ProfRec {
     hipEvent_t a, b;
 };
@@ -1065,6 +1079,216 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
         if (e != hipSuccess) rc = fail(CQ_EHIP, "sync: %s", hipGetErrorString(e));
     }
     fp_destroy(h);
+    return rc;
+}
+
+// Gradient of a loss of G^N (forward solve with the trajectory kept in HBM,
+// adjoint sweep in reversed time with the same kernels, gradient passes).
+static int adjoint_run(Solver& s, const double* G0, const double* gN, double* gG0, double* grad, double* GN) {
+    int rc;
+    const cq_params* p = &s.p;
+    const int64_t M = s.M, N = s.N, twoM = 2 * M;
+    const size_t lev = size_t(N + 1) * size_t(twoM);
+    hipStream_t st = s.st;
+    if (p->method == 1 && s.L > 32)
+        return fail(CQ_EINVAL, "the adjoint's fast form needs a window of <= 32 levels (ns = %d)", s.L);
+    // the far field of the d/dbeta pass (and of the direct history): blocks of 64
+    s.B = 64;
+    {
+        const int64_t tiles = 2 * ((M + 63) / 64);
+        s.ks = int(std::min<int64_t>(64, std::max<int64_t>(1, (1024 + tiles - 1) / tiles)));
+    }
+    {
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        const size_t need = (4 * lev + size_t(s.ks) * 64 * size_t(twoM)) * sizeof(double);
+        if (need > fr)
+            return fail(CQ_ENOMEM, "the adjoint keeps 4 x (N+1) x 2M values (%zu bytes); %zu bytes free", need, fr);
+    }
+    double *traj, *Sx, *psi, *mu, *gc, *gG0c, *acc, *dw, *dd, *part, *part2;
+    if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
+    if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &s.Sscratch, size_t(twoM)))) return rc;
+    if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
+    if ((rc = setup_tables(s))) return rc;
+    if ((rc = dev_alloc(s, &traj, lev))) return rc;
+    if ((rc = dev_alloc(s, &Sx, lev))) return rc;
+    if ((rc = dev_alloc(s, &psi, lev))) return rc;
+    if ((rc = dev_alloc(s, &mu, lev))) return rc;
+    if ((rc = dev_alloc(s, &s.F, size_t(s.ks) * 64 * size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &gc, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &gG0c, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &acc, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &dw, size_t(2 * s.dstride)))) return rc;
+    if ((rc = dev_alloc(s, &dd, size_t(2 * s.dstride)))) return rc;
+    const int nblk_da = int((M + 255) / 256), nblk_rows = int((M + 4095) / 4096);
+    if ((rc = dev_alloc(s, &part, size_t(nblk_da)))) return rc;
+    if ((rc = dev_alloc(s, &part2, size_t(2 * nblk_rows)))) return rc;
+    HIPCHK(hipMemcpyAsync(s.d_d, s.dh[0].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
+                          st));
+    HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (p->method == 1) {
+        if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * M)))) return rc;
+        if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
+        if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
+        if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
+        std::vector<double> rr(size_t(2 * s.np)), cc(size_t(2 * s.np));
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < s.np; ++j) {
+                rr[size_t(k * s.np + j)] = s.rule[k].ratio[size_t(j)];
+                cc[size_t(k * s.np + j)] = s.rule[k].coef[size_t(j)];
+            }
+        if ((rc = upload(s.d_ratio, rr))) return rc;
+        if ((rc = upload(s.d_coef, cc))) return rc;
+        s.modal_blocked = true;  // thread per mode, level store of all N+1 levels
+    }
+    // weight derivatives: exact (recurrences differentiated); the fast
+    // scheme's beyond its lag from the rule
+    std::vector<double> hdw(size_t(2 * s.dstride)), hdd(size_t(2 * s.dstride));
+    for (int k = 0; k < 2; ++k) {
+        double* ddk = hdd.data() + size_t(k) * size_t(s.dstride);
+        double* dwk = hdw.data() + size_t(k) * size_t(s.dstride);
+        weights_dbeta(p->scheme, s.beta[k], s.tau, s.dstride - 1, ddk);
+        std::copy(ddk, ddk + s.dstride, dwk);
+        if (p->method == 1) {
+            const int np1 = p->scheme == 2 ? (p->np1 ? p->np1 : 16) : 0;
+            const int ns = p->ns ? p->ns : 30;
+            rule_weights_dbeta(p->scheme, s.beta[k], s.tau, s.np - np1, np1, ns, s.L, N, 1e-3, dwk);
+        }
+    }
+    if ((rc = upload(dw, hdw))) return rc;
+    if ((rc = upload(dd, hdd))) return rc;
+
+    // forward, keeping every level and history sum
+    s.levels = traj;
+    s.Lr = N + 1;
+    transform(s, s.G0, s.g0c, true);
+    HIPCHK(hipMemcpyAsync(traj, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(Sx, 0, size_t(twoM) * sizeof(double), st));
+    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(M) * sizeof(double), st));
+    s.adj = false;
+    s.Sout = Sx;
+    s.mu = nullptr;
+    s.gc = nullptr;
+    s.n = 0;
+    s.n0 = 0;
+    modal_steps(s, N);
+    if (GN) transform(s, traj + N * twoM, GN, false);
+
+    // adjoint sweep: levels psi, multipliers mu, both in reversed time
+    transform(s, gN, gc, false);  // dl/dg^N = S^T dl/dG^N, S symmetric
+    HIPCHK(hipMemsetAsync(psi, 0, size_t(twoM) * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(mu, 0, size_t(twoM) * sizeof(double), st));
+    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(M) * sizeof(double), st));
+    s.levels = psi;
+    s.adj = true;
+    s.Sout = nullptr;
+    s.mu = mu;
+    s.gc = gc;
+    s.n = 0;
+    s.n0 = 0;
+    modal_steps(s, N);
+
+    // gradients
+    AdjGradArgs ga{};
+    ga.M = M;
+    ga.N = N;
+    ga.scheme = p->scheme;
+    ga.dstride = s.dstride;
+    ga.inv_tau = 1.0 / s.tau;
+    ga.d0[0] = s.dh[0][0];
+    ga.d0[1] = s.dh[1][0];
+    ga.d = s.d_d;
+    ga.traj = traj;
+    ga.Sx = Sx;
+    ga.mu = mu;
+    ga.psi = psi;
+    ga.gG0c = gG0c;
+    ga.part = part;
+    launch_adj_g0(ga, st);
+    transform(s, gG0c, gG0, true);  // dl/dG0 = P^T dl/dg^0, P = scaled S, symmetric
+    launch_adj_da(ga, st);
+    HIPCHK(hipMemsetAsync(acc, 0, size_t(twoM) * sizeof(double), st));
+    for (int64_t n0 = 0; n0 < N; n0 += 64) {
+        const int bt = int(std::min<int64_t>(64, N - n0));
+        if (n0 >= 1) {
+            FarArgs fa{};
+            fa.n0 = n0;
+            fa.M = M;
+            fa.dstride = s.dstride;
+            fa.lstride = twoM;
+            fa.B = 64;
+            fa.ks = s.ks;
+            fa.ncomp = 2;
+            const int64_t mc = (n0 + s.ks - 1) / s.ks;
+            fa.mchunk = ((mc + 3) / 4) * 4;
+            fa.levels = traj;
+            fa.d = dw;
+            fa.F = s.F;
+            fa.reduce = 1;
+            launch_far(fa, st);
+        }
+        AdjBetaArgs ab{};
+        ab.M = M;
+        ab.N = N;
+        ab.n0 = n0;
+        ab.bt = bt;
+        ab.scheme = p->scheme;
+        ab.dstride = s.dstride;
+        ab.dw = dw;
+        ab.dd = dd;
+        ab.F = s.F;
+        ab.traj = traj;
+        ab.psi = psi;
+        ab.acc = acc;
+        launch_adj_beta(ab, st);
+    }
+    launch_sum_rows(acc, M, part2, st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hp(static_cast<size_t>(nblk_da)), hp2(static_cast<size_t>(2 * nblk_rows));
+    HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hp2.data(), part2, hp2.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double sa = 0.0, sb0 = 0.0, sb1 = 0.0;
+    for (double v : hp) sa += v;
+    for (int i = 0; i < nblk_rows; ++i) {
+        sb0 += hp2[size_t(i)];
+        sb1 += hp2[size_t(nblk_rows + i)];
+    }
+    const double da_dm = -1.0 / ((2.0 * p->m - 1.0) * (2.0 * p->m - 1.0));
+    grad[0] = sb0;            // dl/dalpha_1 = -dl/dbeta_1
+    grad[1] = sb1;
+    grad[2] = -sa * da_dm;    // dl/dm = dl/da da/dm, dl/da = -sum
+    return CQ_OK;
+}
+
+int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN, double* gG0,
+               double* grad, double* GN, void* hip_stream) {
+    clear_error();
+    int rc = validate(grid, prm);
+    if (rc) return rc;
+    if (!G0 || !gN || !gG0 || !grad) return fail(CQ_EINVAL, "G0, gN, gG0 and grad must not be NULL");
+    if (prm->solver != 1) return fail(CQ_EINVAL, "the adjoint runs on the modal solver (solver = 1)");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t M = int64_t(grid->nx) * (grid->dim == 2 ? grid->ny : 1);
+    Solver* s = new (std::nothrow) Solver();
+    if (!s) return fail(CQ_ENOMEM, "host allocation failed");
+    try {
+        rc = setup_host(*s, grid, prm, st);
+        if (!rc) rc = check_finite_g0(G0, 2 * M, st);
+        if (!rc) rc = check_finite_g0(gN, 2 * M, st, "gN");
+        if (!rc) rc = adjoint_run(*s, G0, gN, gG0, grad, GN);
+        if (!rc) {
+            hipError_t e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = fail(CQ_EHIP, "sync: %s", hipGetErrorString(e));
+        }
+    } catch (const std::bad_alloc&) {
+        rc = fail(CQ_ENOMEM, "host allocation failed");
+    }
+    if (rc) (void)hipStreamSynchronize(st);  // no kernel may still use the buffers freed below
+    delete s;
     return rc;
 }
 

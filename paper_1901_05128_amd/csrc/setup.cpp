@@ -59,6 +59,47 @@ void weights(int scheme, double beta, double tau, int64_t n, double* d) {
     }
 }
 
+// d/dbeta of the weights above, by differentiating the same recurrences:
+// with s = tau^-beta (s' = -ln(tau) s), BE g_i = g_{i-1} (1 - (1+beta)/i)
+// gives g'_i = g'_{i-1} (1 - (1+beta)/i) - g_{i-1}/i; the BDF2 recurrence
+// c_i = [(beta-(i-1)) p1 c_{i-1} + (2 beta-(i-2)) p2 c_{i-2}] / (p0 i) gives
+// c'_i = [p1 c_{i-1} + (beta-(i-1)) p1 c'_{i-1} + 2 p2 c_{i-2}
+//         + (2 beta-(i-2)) p2 c'_{i-2}] / (p0 i), c'_0 = ln(p0) c_0.
+void weights_dbeta(int scheme, double beta, double tau, int64_t n, double* dd) {
+    const double s = std::pow(tau, -beta), ds = -std::log(tau) * s;
+    if (scheme == 1) {
+        double g = 1.0, dg = 0.0;
+        dd[0] = ds;
+        for (int64_t i = 1; i <= n; ++i) {
+            const double f = 1.0 - (1.0 + beta) / double(i);
+            dg = dg * f - g / double(i);
+            g *= f;
+            dd[i] = ds * g + s * dg;
+        }
+        return;
+    }
+    const double p0 = 1.5, p1 = -2.0, p2 = 0.5;
+    double cm2 = 0.0, cm1 = std::pow(p0, beta);
+    double dm2 = 0.0, dm1 = std::log(p0) * cm1;
+    dd[0] = ds * cm1 + s * dm1;
+    for (int64_t i = 1; i <= n; ++i) {
+        const double di = double(i);
+        double c = (beta - (di - 1.0)) * p1 * cm1;
+        double dc = p1 * cm1 + (beta - (di - 1.0)) * p1 * dm1;
+        if (i >= 2) {
+            c += (2.0 * beta - (di - 2.0)) * p2 * cm2;
+            dc += 2.0 * p2 * cm2 + (2.0 * beta - (di - 2.0)) * p2 * dm2;
+        }
+        c /= p0 * di;
+        dc /= p0 * di;
+        dd[i] = ds * c + s * dc;
+        cm2 = cm1;
+        cm1 = c;
+        dm2 = dm1;
+        dm1 = dc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Gauss-Jacobi rule for (1-s)^a (1+s)^b.
 // Monic recurrence p_{k+1} = (s - al_k) p_k - be_k p_{k-1} with
@@ -230,6 +271,38 @@ double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N) {
     double m = 0.0;
     for (int64_t i = L; i <= N; ++i) m = std::max(m, std::fabs(d[size_t(i)] - acc[size_t(i - L)]));
     return m / std::fabs(d[0]);
+}
+
+// d/dbeta of the fast weights sum_j coef_j r_j^(i - lag), i = lag..N, for a
+// rule of np nodes (BDF2: np1 + np) started at `lag`. Every coefficient
+// carries tau^-beta (3.6)/(3.14): with q_i the sums at tau = 1, the weights
+// are tau^-beta q_i and their derivative tau^-beta (q'_i - ln(tau) q_i),
+// where q'_i is a five-point central difference in beta of the rule rebuilt
+// at beta +- h, +- 2h (nodes and weights move smoothly with beta).
+void rule_weights_dbeta(int scheme, double beta, double tau, int np, int np1, int ns, int lag, int64_t N,
+                        double h, double* dw) {
+    if (N < lag) return;
+    const double off[5] = {-2.0 * h, -h, h, 2.0 * h, 0.0};
+    const double cf[5] = {1.0 / (12.0 * h), -8.0 / (12.0 * h), 8.0 / (12.0 * h), -1.0 / (12.0 * h), 0.0};
+    const size_t len = size_t(N - lag + 1);
+    std::vector<double> dq(len, 0.0), q(len, 0.0);
+    for (int e = 0; e < 5; ++e) {
+        FastRule r;
+        build_rule(scheme, beta + off[e], 1.0, np, np1, ns, r);
+        shift_lag(r, lag);
+        std::vector<double>& acc = (e < 4) ? dq : q;
+        const double f = (e < 4) ? cf[e] : 1.0;
+        for (size_t j = 0; j < r.ratio.size(); ++j) {
+            double pw = r.coef[j] * f;
+            const double rr = r.ratio[j];
+            for (size_t i = 0; i < len; ++i) {
+                acc[i] += pw;
+                pw *= rr;
+            }
+        }
+    }
+    const double tb = std::pow(tau, -beta), lt = std::log(tau);
+    for (size_t i = 0; i < len; ++i) dw[int64_t(i) + lag] = tb * (dq[i] - lt * q[i]);
 }
 
 int choose_rule(int scheme, double beta, double tau, int64_t N, double tol, int np_max, int np1,

@@ -88,13 +88,17 @@ def g0_intervals(nx: int, seed: int) -> np.ndarray:
 
 def g0_rectangle(nx: int, ny: int, seed: int) -> np.ndarray:
     """G1 = G2 = indicator of one closed rectangle [u1,v1] x [u2,v2] drawn from
-    sorted U(0,1) pairs. Layout [2][ny][nx] flattened to [2][ny*nx] (x fastest)."""
+    sorted U(0,1) pairs; a rectangle that covers no grid node is drawn again
+    from the same stream. Layout [2][ny][nx] flattened to [2][ny*nx] (x fastest)."""
     rng = np.random.default_rng(seed)
-    ux, vx = np.sort(rng.uniform(0.0, 1.0, size=2))
-    uy, vy = np.sort(rng.uniform(0.0, 1.0, size=2))
     x = nodes_1d(nx)
     y = nodes_1d(ny)
-    ind = ((y[:, None] >= uy) & (y[:, None] <= vy) & (x[None, :] >= ux) & (x[None, :] <= vx))
+    while True:
+        ux, vx = np.sort(rng.uniform(0.0, 1.0, size=2))
+        uy, vy = np.sort(rng.uniform(0.0, 1.0, size=2))
+        ind = ((y[:, None] >= uy) & (y[:, None] <= vy) & (x[None, :] >= ux) & (x[None, :] <= vx))
+        if ind.any():
+            break
     f = ind.astype(np.float64).reshape(-1)
     return np.stack([f, f.copy()])
 
