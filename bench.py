@@ -195,12 +195,115 @@ def bench_batched(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_adjoint(args):
+    """One step = one gradient of l = 1/2 |G^N - target|^2 on the adjoint
+    workload (2D 127^2, BDF2 fast, N = 4096, np = 16 + 192, ns = 30): the
+    forward solve with the trajectory kept, the reversed-time adjoint sweep
+    and the gradient passes (dl/dG0 and the three scalars)."""
+    import numpy as np
+    import torch
+
+    import paper_1901_05128_amd as cq
+    from paper_1901_05128_amd import workloads as wl
+    torch.cuda.set_device(0)
+    nx = ny = 127
+    N = 4096
+    g = cq.make_grid(2, nx, ny)
+
+    def prm(a1, a2, m):
+        return cq.make_params(a1, a2, m, 1.0, N, 2, 1, np_=192, np1=16, ns=30, solver=cq.SOLVER_MODAL)
+
+    G0 = torch.tensor(wl.g0_rectangle(nx, ny, 5), dtype=torch.float64, device="cuda")
+    target = cq.fp_solve(g, prm(0.25, 0.55, 0.55), torch.tensor(wl.g0_rectangle(nx, ny, 6), dtype=torch.float64,
+                                                               device="cuda"))
+    p = prm(0.2, 0.6, 0.55)
+    GN = cq.fp_solve(g, p, G0)
+    gN = GN - target
+    gG0 = torch.empty_like(G0)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    h = cq.Adjoint(g, p)      # host set-up (weights, rules, derivatives) and device arrays, once
+    setup_s = time.perf_counter() - ts
+    for _ in range(args.warmup):
+        h.run(G0, gN, gG0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, grads = h.run(G0, gN, gG0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = (t1 - t0) / args.steps
+    ts = time.perf_counter()
+    cq.fp_adjoint(g, p, G0, gN, gG0)
+    oneshot_s = time.perf_counter() - ts
+    M = nx * ny
+    # kernel timing: one more gradient outside the timed region
+    kinds = ["hist_fast", "far_toeplitz", "reduce_far", "modal_fast", "dst_gemm"]
+    ktime = {}
+    roofline = None
+    if not args.no_prof:
+        cq.prof_enable(True)
+        h.run(G0, gN, gG0)
+        torch.cuda.synchronize()
+        for k in kinds:
+            n_l, ms = cq.prof_read(k)
+            if n_l:
+                ktime[k] = (n_l, ms)
+        cq.prof_enable(False)
+        twoM = 2 * M
+        npn, L, Bt = 16 + 192, 30, 30
+        work = {}
+        b_h, f_h = 0, 0
+        for n in range(1, N + 1, Bt):
+            bt = min(Bt, N - n + 1)
+            b_h += twoM * 8 * (2 * npn + 2 * bt)
+            f_h += twoM * 4 * npn * bt
+        work["hist_fast"] = (2 * b_h, 2 * f_h)          # forward and adjoint sweeps
+        f_far, b_far = 0, 0
+        for n0 in range(64, N, 64):
+            f_far += 2 * 64 * n0 * twoM
+            b_far += n0 * twoM * 8 + 64 * twoM * 8
+        work["far_toeplitz"] = (b_far, f_far)           # the d/dalpha pass
+        dom = max(ktime, key=lambda k: ktime[k][1])
+        if dom in work:
+            n_l, ms = ktime[dom]
+            avg = ms / 1e3 / n_l
+            b, f = work[dom]
+            ff = f / n_l / avg / 1e12 / FP64_PEAK_TFLOPS
+            bf = b / n_l / avg / 1e9 / HBM_PEAK_GBS
+            if ff >= bf:
+                roofline = {"bound": "mfma" if dom == "far_toeplitz" else "alu", "achieved": ff * FP64_PEAK_TFLOPS,
+                            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ff, "hbm_frac": bf}
+            else:
+                roofline = {"bound": "hbm", "achieved": bf * HBM_PEAK_GBS, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": bf, "fp64_frac": ff}
+            roofline.update({"kernel": dom, "avg_launch_us": avg * 1e6, "launches": n_l,
+                             "timed": "one extra gradient after the timed region, HIP events per launch",
+                             "traffic": load_traffic(dom)})
+    rec = {
+        "metric": "gradients/s (dl/dG0 and dl/dalpha_1, dl/dalpha_2, dl/dm)", "value": 1.0 / per,
+        "unit": "grads/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": per * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded rectangle indicators)",
+        "config": {"workload": "c5: adjoint, 2D 127x127 nodes, BDF2 fast (np 16+192, ns 30), N=4096, "
+                               "alpha=(0.2,0.6), m=0.55, target from alpha=(0.25,0.55)",
+                   "dof": 2 * M, "N": N},
+        "grads": list(grads),
+        "breakdown": {"handle_setup_s": setup_s, "one_shot_fp_adjoint_s": oneshot_s,
+                      "note": "value times fp_adjoint_run on a handle made once (fixed grid and parameters)"},
+        "kernels_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in ktime.items()},
+        "roofline": roofline,
+    }
+    h.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5"])
     ap.add_argument("--variants", default="all", help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct")
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
@@ -225,6 +328,8 @@ def main():
 
     if args.workload == "c4":
         return bench_batched(args)
+    if args.workload == "c5":
+        return bench_adjoint(args)
     w = WORKLOADS[args.workload]
     desc, dim, nx, ny, a1, a2, m, T, N, seed = w
     M = nx * ny
@@ -278,7 +383,7 @@ def main():
     # on one stream, so that each launch's duration is its own and not
     # stretched by kernels of other variants sharing the GPU.
     kinds = ["hist_fast", "hist_direct", "far_toeplitz", "solve_1d", "prep_2d", "dst_gemm", "modal_fast",
-             "modal_near"]
+             "modal_near", "reduce_far"]
     ktime = {}
     if not args.no_prof:
         torch.cuda.synchronize()

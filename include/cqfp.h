@@ -204,6 +204,17 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
 int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN,
                double* gG0, double* grad, double* GN, void* hip_stream);
 
+/* The same in two parts, for many gradients at one grid and parameter set:
+ * fp_adjoint_create does the host set-up (weights, rules and their
+ * beta-derivatives) and allocates the device arrays once; every
+ * fp_adjoint_run then only enqueues device work on the handle's stream (and
+ * synchronises it to return grad). Arguments and errors as fp_adjoint. The
+ * handle is released by fp_destroy; the stepping calls (fp_step, ...)
+ * reject it with CQ_EINVAL. */
+int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_stream, void** handle);
+int fp_adjoint_run(void* handle, const double* G0, const double* gN, double* gG0, double* grad,
+                   double* GN);
+
 /* Batched fast solves (extension): `count` independent problems (own grid,
  * orders, m, T, N, scheme; method must be 1, the fast form) solved by the
  * modal solver in one captured HIP graph. Every problem's sine modes are

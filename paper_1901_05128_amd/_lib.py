@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "CQ_OK", -1: "CQ_EINVAL", -2: "CQ_ESINGULAR", -3: "CQ_ENOMEM"
 # every entry point the header declares
 EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "fp_current", "fp_info",
            "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "fp_solve_batched",
-           "fp_adjoint", "cq_prof_enable", "cq_prof_read", "cq_last_error"]
+           "fp_adjoint", "fp_adjoint_create", "fp_adjoint_run", "cq_prof_enable", "cq_prof_read",
+           "cq_last_error"]
 PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
               "reduce_row": 6, "modal_fast": 7, "modal_near": 8, "batched": 9, "reduce_far": 10}
 
@@ -89,6 +90,8 @@ def lib() -> C.CDLL:
     L.fp_solve.argtypes = [P(Grid), P(Params), VP, VP, VP]
     L.fp_solve_batched.argtypes = [I32, P(Grid), P(Params), P(VP), P(VP), VP, I32, P(BatchReport)]
     L.fp_adjoint.argtypes = [P(Grid), P(Params), VP, VP, VP, P(D), VP, VP]
+    L.fp_adjoint_create.argtypes = [P(Grid), P(Params), VP, P(VP)]
+    L.fp_adjoint_run.argtypes = [VP, VP, VP, VP, P(D), VP]
     L.cq_last_error.argtypes = []
     L.cq_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -252,6 +255,42 @@ def fp_adjoint(grid: Grid, params: Params, G0, gN, gG0=None, GN=None):
     _check(lib().fp_adjoint(C.byref(grid), C.byref(params), _dev(G0, "G0"), _dev(gN, "gN"), _dev(gG0, "gG0"), g,
                             _dev(GN, "GN") if GN is not None else None, _stream()))
     return gG0, (g[0], g[1], g[2])
+
+
+class Adjoint:
+    """Gradient handle (fp_adjoint_create): set-up and device arrays once,
+    then run(G0, gN) per gradient."""
+
+    def __init__(self, grid: Grid, params: Params):
+        self._h = C.c_void_p()
+        self.M = grid.nx * (grid.ny if grid.dim == 2 else 1)
+        _check(lib().fp_adjoint_create(C.byref(grid), C.byref(params), _stream(), C.byref(self._h)))
+
+    def run(self, G0, gN, gG0=None, GN=None):
+        import torch
+        if gG0 is None:
+            gG0 = torch.empty_like(G0)
+        g = (C.c_double * 3)()
+        _check(lib().fp_adjoint_run(self._h, _dev(G0, "G0"), _dev(gN, "gN"), _dev(gG0, "gG0"), g,
+                                    _dev(GN, "GN") if GN is not None else None))
+        return gG0, (g[0], g[1], g[2])
+
+    def close(self):
+        if self._h:
+            _check(lib().fp_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fp_solve_batched(grids, params, G0s, GNs=None, autotune=True):

@@ -214,6 +214,8 @@ int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st);
 void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);
+// F[0][e] = sum_q F[q][e], e < per (q < ks slices, per apart)
+void launch_reduce_slices(double* F, int ks, int64_t per, hipStream_t st);
 // out[x] = sum_q F[q][0][0][x] (one history row of a single component)
 void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st);
 void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st);

@@ -59,23 +59,44 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
     const double* __restrict__ r = p.ratio + k * p.np;
     const double* __restrict__ w = p.coef + k * p.np;
     int j = j0;
-    // two nodes per iteration: independent recurrences interleave
+    // four nodes per group (independent recurrences interleave); the states
+    // of the next group are loaded before this group is advanced, so a load
+    // is in flight while the previous one is used
+    double hn0 = 0.0, hn1 = 0.0, hn2 = 0.0, hn3 = 0.0;
+    if (j + 4 <= j1) {
+        hn0 = __builtin_nontemporal_load(h + int64_t(j) * p.M);
+        hn1 = __builtin_nontemporal_load(h + int64_t(j + 1) * p.M);
+        hn2 = __builtin_nontemporal_load(h + int64_t(j + 2) * p.M);
+        hn3 = __builtin_nontemporal_load(h + int64_t(j + 3) * p.M);
+    }
 #pragma unroll 1
-    for (; j + 2 <= j1; j += 2) {
-        double h0 = __builtin_nontemporal_load(h + int64_t(j) * p.M);
-        double h1 = __builtin_nontemporal_load(h + int64_t(j + 1) * p.M);
-        const double r0 = r[j], r1 = r[j + 1], w0 = w[j], w1 = w[j + 1];
+    for (; j + 4 <= j1; j += 4) {
+        double h0 = hn0, h1 = hn1, h2 = hn2, h3 = hn3;
+        if (j + 8 <= j1) {
+            hn0 = __builtin_nontemporal_load(h + int64_t(j + 4) * p.M);
+            hn1 = __builtin_nontemporal_load(h + int64_t(j + 5) * p.M);
+            hn2 = __builtin_nontemporal_load(h + int64_t(j + 6) * p.M);
+            hn3 = __builtin_nontemporal_load(h + int64_t(j + 7) * p.M);
+        }
+        const double r0 = r[j], r1 = r[j + 1], r2 = r[j + 2], r3 = r[j + 3];
+        const double w0 = w[j], w1 = w[j + 1], w2 = w[j + 2], w3 = w[j + 3];
 #pragma unroll
         for (int b = 0; b < BT; ++b) {
             if (b < p.bt) {
                 h0 = fma(r0, h0, g[b]);
                 h1 = fma(r1, h1, g[b]);
+                h2 = fma(r2, h2, g[b]);
+                h3 = fma(r3, h3, g[b]);
                 acc[b] = fma(w0, h0, acc[b]);
                 acc[b] = fma(w1, h1, acc[b]);
+                acc[b] = fma(w2, h2, acc[b]);
+                acc[b] = fma(w3, h3, acc[b]);
             }
         }
         __builtin_nontemporal_store(h0, h + int64_t(j) * p.M);
         __builtin_nontemporal_store(h1, h + int64_t(j + 1) * p.M);
+        __builtin_nontemporal_store(h2, h + int64_t(j + 2) * p.M);
+        __builtin_nontemporal_store(h3, h + int64_t(j + 3) * p.M);
     }
     for (; j < j1; ++j) {
         double h0 = h[int64_t(j) * p.M];
@@ -645,9 +666,10 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
 
 // Fast form for many modes: the compressed state streams through
 // k_hist_block (time-blocked, exactly as for the nodal solver, here on the
-// sine coefficients), and this kernel takes the steps of the block: thread
-// per mode, S = sum of the block's partial sums Sf[.][b] + the exact-weight
-// window sum_{i<min(L-1,n-1)} d_{i+1} g^{n-1-i} from a register ring
+// sine coefficients; its node slices are then summed into slice 0), and this
+// kernel takes the steps of the block: thread per mode, S = the block's fast
+// partial sum Sf[0][b] + the exact-weight window
+// sum_{i<min(L-1,n-1)} d_{i+1} g^{n-1-i} from a register ring
 // (ring[i] = g^{n-1-i}, levels below 0 read as g^0 for BDF2's g^{-1}), then
 // the 2x2 solve; the new level goes to its slot of the level store (the
 // state pass of the next block reads it there).
@@ -657,10 +679,22 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
 // the first step), mu = (c I + W_0 Dm)^-1 r = M^-T r and the new level
 // psi = Dm mu; mu^n goes to mu[n].
 template <int LW, bool ADJ>
-__global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
-    const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
+__global__ __launch_bounds__(64) void k_modal_win(ModalWinArgs p) {
+    // the block's fast partial sums (slice 0, already summed over the node
+    // slices), staged per thread so that the time loop makes no global loads
+    __shared__ double fs[32][2][64];
+    const int tid = threadIdx.x;
+    const int64_t mode = int64_t(blockIdx.x) * 64 + tid;
     if (mode >= p.M) return;
     const int64_t M = p.M, twoM = 2 * M;
+    const int64_t b0 = p.nfirst - p.nblk;
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+        if (t < p.bt) {
+            fs[t][0][tid] = p.Sf[((b0 + t) * 2) * M + mode];
+            fs[t][1][tid] = p.Sf[((b0 + t) * 2 + 1) * M + mode];
+        }
+    }
     const double lam = p.lam[mode];
     const double g00 = p.g0[mode], g01 = p.g0[M + mode];
     const double L1 = p.a + lam;
@@ -695,25 +729,9 @@ __global__ __launch_bounds__(256) void k_modal_win(ModalWinArgs p) {
         e20 = ring0[1];
         e21 = ring1[1];
     }
-    // partial sums of the next step are loaded one step ahead
-    auto sf = [&](int64_t b, int k) {
-        double v = 0.0;
-        for (int c = 0; c < p.nsplit; ++c) v += p.Sf[((int64_t(c) * p.BT + b) * 2 + k) * M + mode];
-        return v;
-    };
-    double f0 = 0.0, f1 = 0.0;
-    if (p.bt > 0) {
-        f0 = sf(p.nfirst - p.nblk, 0);
-        f1 = sf(p.nfirst - p.nblk, 1);
-    }
     for (int t = 0; t < p.bt; ++t) {
         const int64_t n = p.nfirst + t;
-        const int64_t b = n - p.nblk;
-        double S0 = f0, S1 = f1;
-        if (t + 1 < p.bt) {
-            f0 = sf(b + 1, 0);
-            f1 = sf(b + 1, 1);
-        }
+        double S0 = fs[t][0][tid], S1 = fs[t][1][tid];
         const int64_t wn = (n - 1 < p.L - 1) ? n - 1 : p.L - 1;
         double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
 #pragma unroll
@@ -1166,6 +1184,12 @@ void launch_far(const FarArgs& a, hipStream_t st) {
     }
 }
 
+void launch_reduce_slices(double* F, int ks, int64_t per, hipStream_t st) {
+    prof_begin(10, st);
+    hipLaunchKernelGGL(k_reduce_far, dim3(unsigned((per + 255) / 256)), dim3(256), 0, st, F, ks, per);
+    prof_end(10, st);
+}
+
 void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st) {
     prof_begin(3, st);
     const int R = int((a.M + kNT1D - 1) / kNT1D);
@@ -1243,11 +1267,11 @@ void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st) {
 
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st) {
     prof_begin(7, st);
-    const dim3 grid(unsigned((a.M + 255) / 256));
+    const dim3 grid(unsigned((a.M + 63) / 64));
     if (adj)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, true>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, true>), grid, dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, false>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, false>), grid, dim3(64), 0, st, a);
     prof_end(7, st);
 }
 

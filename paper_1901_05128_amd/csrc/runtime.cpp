@@ -28,6 +28,13 @@ namespace {
 constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
 constexpr int64_t kModalBlockedMin = 8192;      // modes
 
+// device arrays of a gradient handle (trajectory, history sums, adjoint)
+struct AdjBufs {
+    double *traj = nullptr, *Sx = nullptr, *psi = nullptr, *mu = nullptr, *gc = nullptr, *gG0c = nullptr,
+           *acc = nullptr, *dw = nullptr, *dd = nullptr, *part = nullptr, *part2 = nullptr;
+    int nblk_da = 0, nblk_rows = 0;
+};
+
 struct Solver {
     cq_grid g{};
     cq_params p{};
@@ -58,6 +65,8 @@ struct Solver {
     double *Sout = nullptr, *mu = nullptr;
     const double* gc = nullptr;
     double* Sscratch = nullptr;  // [2][M] row the modal kernels write S to when Sout is not kept
+    int kind = 0;                // 0 stepping solver (fp_create), 1 gradient handle (fp_adjoint_create)
+    AdjBufs ab;
     size_t lds = 0;
     size_t dev_bytes = 0;
     std::vector<void*> allocs;
@@ -485,6 +494,8 @@ void modal_steps(Solver& s, int64_t nsteps) {
                 hb.coef = s.d_coef;
                 hb.Sf = s.Sf;
                 launch_hist_block(hb, s.nsplit, s.st);
+                // the window steps read the partial sums summed over the node slices
+                if (s.nsplit > 1) launch_reduce_slices(s.Sf, s.nsplit, int64_t(s.BTt) * 2 * s.M, s.st);
             }
             const int bt = int(std::min<int64_t>(nblk + s.Bt - 1 - s.n, nsteps));
             ModalWinArgs a{};
@@ -936,6 +947,7 @@ int fp_step(void* handle, int64_t nsteps) {
     clear_error();
     if (!handle) return fail(CQ_EINVAL, "handle is NULL");
     Solver& s = *static_cast<Solver*>(handle);
+    if (s.kind != 0) return fail(CQ_EINVAL, "not a stepping solver handle (use fp_adjoint_run)");
     if (nsteps < 0 || s.n + nsteps > s.N)
         return fail(CQ_EINVAL, "cannot take %lld steps from n = %lld (N = %lld)", (long long)nsteps, (long long)s.n,
                     (long long)s.N);
@@ -951,6 +963,7 @@ int fp_current(void* handle, double* G_out, int64_t* n_out) {
     clear_error();
     if (!handle || !G_out) return fail(CQ_EINVAL, "NULL argument");
     Solver& s = *static_cast<Solver*>(handle);
+    if (s.kind != 0) return fail(CQ_EINVAL, "not a stepping solver handle (use fp_adjoint_run)");
     if (s.p.solver == 1) {
         const double* c = s.p.method == 1 ? (s.modal_blocked ? s.levels + (s.n % s.Lr) * 2 * s.M : s.ring)
                                            : s.levels + s.n * 2 * s.M;
@@ -969,6 +982,7 @@ int fp_info(void* handle, cq_info* info) {
     clear_error();
     if (!handle || !info) return fail(CQ_EINVAL, "NULL argument");
     const Solver& s = *static_cast<const Solver*>(handle);
+    if (s.kind != 0) return fail(CQ_EINVAL, "not a stepping solver handle (use fp_adjoint_run)");
     info->n = s.n;
     info->N = s.N;
     info->np_total = s.np;
@@ -987,6 +1001,7 @@ int fp_get_state(void* handle, void* dst, size_t* bytes) {
     clear_error();
     if (!handle || !bytes) return fail(CQ_EINVAL, "NULL argument");
     Solver& s = *static_cast<Solver*>(handle);
+    if (s.kind != 0) return fail(CQ_EINVAL, "not a stepping solver handle (use fp_adjoint_run)");
     const size_t need = state_bytes(s);
     if (!dst) {
         *bytes = need;
@@ -1012,6 +1027,7 @@ int fp_set_state(void* handle, const void* src, size_t bytes) {
     clear_error();
     if (!handle || !src) return fail(CQ_EINVAL, "NULL argument");
     Solver& s = *static_cast<Solver*>(handle);
+    if (s.kind != 0) return fail(CQ_EINVAL, "not a stepping solver handle (use fp_adjoint_run)");
     if (bytes < 4 * sizeof(uint64_t)) return fail(CQ_EINVAL, "state too short");
     const uint64_t* hdr = static_cast<const uint64_t*>(src);
     if (hdr[0] != kStateMagic || hdr[2] != uint64_t(s.M) || hdr[3] != uint64_t(s.np))
@@ -1043,6 +1059,7 @@ int fp_reset(void* handle, const double* G0) {
     clear_error();
     if (!handle || !G0) return fail(CQ_EINVAL, "NULL argument");
     Solver& s = *static_cast<Solver*>(handle);
+    if (s.kind != 0) return fail(CQ_EINVAL, "not a stepping solver handle (use fp_adjoint_run)");
     const int64_t twoM = 2 * s.M;
     int rc = check_finite_g0(G0, twoM, s.st);
     if (rc) return rc;
@@ -1084,7 +1101,7 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
 
 // Gradient of a loss of G^N (forward solve with the trajectory kept in HBM,
 // adjoint sweep in reversed time with the same kernels, gradient passes).
-static int adjoint_run(Solver& s, const double* G0, const double* gN, double* gG0, double* grad, double* GN) {
+static int adjoint_setup(Solver& s) {
     int rc;
     const cq_params* p = &s.p;
     const int64_t M = s.M, N = s.N, twoM = 2 * M;
@@ -1105,30 +1122,30 @@ static int adjoint_run(Solver& s, const double* G0, const double* gN, double* gG
         if (need > fr)
             return fail(CQ_ENOMEM, "the adjoint keeps 4 x (N+1) x 2M values (%zu bytes); %zu bytes free", need, fr);
     }
-    double *traj, *Sx, *psi, *mu, *gc, *gG0c, *acc, *dw, *dd, *part, *part2;
+    AdjBufs& A = s.ab;
     if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
     if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.Sscratch, size_t(twoM)))) return rc;
     if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
     if ((rc = setup_tables(s))) return rc;
-    if ((rc = dev_alloc(s, &traj, lev))) return rc;
-    if ((rc = dev_alloc(s, &Sx, lev))) return rc;
-    if ((rc = dev_alloc(s, &psi, lev))) return rc;
-    if ((rc = dev_alloc(s, &mu, lev))) return rc;
+    if ((rc = dev_alloc(s, &A.traj, lev))) return rc;
+    if ((rc = dev_alloc(s, &A.Sx, lev))) return rc;
+    if ((rc = dev_alloc(s, &A.psi, lev))) return rc;
+    if ((rc = dev_alloc(s, &A.mu, lev))) return rc;
     if ((rc = dev_alloc(s, &s.F, size_t(s.ks) * 64 * size_t(twoM)))) return rc;
-    if ((rc = dev_alloc(s, &gc, size_t(twoM)))) return rc;
-    if ((rc = dev_alloc(s, &gG0c, size_t(twoM)))) return rc;
-    if ((rc = dev_alloc(s, &acc, size_t(twoM)))) return rc;
-    if ((rc = dev_alloc(s, &dw, size_t(2 * s.dstride)))) return rc;
-    if ((rc = dev_alloc(s, &dd, size_t(2 * s.dstride)))) return rc;
-    const int nblk_da = int((M + 255) / 256), nblk_rows = int((M + 4095) / 4096);
-    if ((rc = dev_alloc(s, &part, size_t(nblk_da)))) return rc;
-    if ((rc = dev_alloc(s, &part2, size_t(2 * nblk_rows)))) return rc;
+    if ((rc = dev_alloc(s, &A.gc, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &A.gG0c, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &A.acc, size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &A.dw, size_t(2 * s.dstride)))) return rc;
+    if ((rc = dev_alloc(s, &A.dd, size_t(2 * s.dstride)))) return rc;
+    A.nblk_da = int((M + 255) / 256);
+    A.nblk_rows = int((M + 4095) / 4096);
+    if ((rc = dev_alloc(s, &A.part, size_t(A.nblk_da)))) return rc;
+    if ((rc = dev_alloc(s, &A.part2, size_t(2 * A.nblk_rows)))) return rc;
     HIPCHK(hipMemcpyAsync(s.d_d, s.dh[0].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
                           st));
-    HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (p->method == 1) {
         if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * M)))) return rc;
         if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
@@ -1158,9 +1175,23 @@ static int adjoint_run(Solver& s, const double* G0, const double* gN, double* gG
             rule_weights_dbeta(p->scheme, s.beta[k], s.tau, s.np - np1, np1, ns, s.L, N, 1e-3, dwk);
         }
     }
-    if ((rc = upload(dw, hdw))) return rc;
-    if ((rc = upload(dd, hdd))) return rc;
+    if ((rc = upload(A.dw, hdw))) return rc;
+    if ((rc = upload(A.dd, hdd))) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    s.kind = 1;
+    return CQ_OK;
+}
 
+
+static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* gG0, double* grad, double* GN) {
+    const cq_params* p = &s.p;
+    AdjBufs& A = s.ab;
+    const int64_t M = s.M, N = s.N, twoM = 2 * M;
+    hipStream_t st = s.st;
+    double *traj = A.traj, *Sx = A.Sx, *psi = A.psi, *mu = A.mu, *gc = A.gc, *gG0c = A.gG0c, *acc = A.acc,
+           *dw = A.dw, *dd = A.dd, *part = A.part, *part2 = A.part2;
+    const int nblk_da = A.nblk_da, nblk_rows = A.nblk_rows;
+    HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
     // forward, keeping every level and history sum
     s.levels = traj;
     s.Lr = N + 1;
@@ -1264,31 +1295,51 @@ static int adjoint_run(Solver& s, const double* G0, const double* gN, double* gG
     return CQ_OK;
 }
 
-int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN, double* gG0,
-               double* grad, double* GN, void* hip_stream) {
+int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_stream, void** handle) {
     clear_error();
+    if (!handle) return fail(CQ_EINVAL, "handle is NULL");
+    *handle = nullptr;
     int rc = validate(grid, prm);
     if (rc) return rc;
-    if (!G0 || !gN || !gG0 || !grad) return fail(CQ_EINVAL, "G0, gN, gG0 and grad must not be NULL");
     if (prm->solver != 1) return fail(CQ_EINVAL, "the adjoint runs on the modal solver (solver = 1)");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const int64_t M = int64_t(grid->nx) * (grid->dim == 2 ? grid->ny : 1);
     Solver* s = new (std::nothrow) Solver();
     if (!s) return fail(CQ_ENOMEM, "host allocation failed");
     try {
         rc = setup_host(*s, grid, prm, st);
-        if (!rc) rc = check_finite_g0(G0, 2 * M, st);
-        if (!rc) rc = check_finite_g0(gN, 2 * M, st, "gN");
-        if (!rc) rc = adjoint_run(*s, G0, gN, gG0, grad, GN);
-        if (!rc) {
-            hipError_t e = hipStreamSynchronize(st);
-            if (e != hipSuccess) rc = fail(CQ_EHIP, "sync: %s", hipGetErrorString(e));
-        }
+        if (!rc) rc = adjoint_setup(*s);
     } catch (const std::bad_alloc&) {
         rc = fail(CQ_ENOMEM, "host allocation failed");
     }
-    if (rc) (void)hipStreamSynchronize(st);  // no kernel may still use the buffers freed below
-    delete s;
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        delete s;
+        return rc;
+    }
+    *handle = s;
+    return CQ_OK;
+}
+
+int fp_adjoint_run(void* handle, const double* G0, const double* gN, double* gG0, double* grad, double* GN) {
+    clear_error();
+    if (!handle) return fail(CQ_EINVAL, "handle is NULL");
+    Solver& s = *static_cast<Solver*>(handle);
+    if (s.kind != 1) return fail(CQ_EINVAL, "handle was not made by fp_adjoint_create");
+    if (!G0 || !gN || !gG0 || !grad) return fail(CQ_EINVAL, "G0, gN, gG0 and grad must not be NULL");
+    int rc = check_finite_g0(G0, 2 * s.M, s.st);
+    if (!rc) rc = check_finite_g0(gN, 2 * s.M, s.st, "gN");
+    if (!rc) rc = adjoint_exec(s, G0, gN, gG0, grad, GN);
+    if (rc) (void)hipStreamSynchronize(s.st);
+    return rc;
+}
+
+int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN, double* gG0,
+               double* grad, double* GN, void* hip_stream) {
+    void* h = nullptr;
+    int rc = fp_adjoint_create(grid, prm, hip_stream, &h);
+    if (rc) return rc;
+    rc = fp_adjoint_run(h, G0, gN, gG0, grad, GN);
+    fp_destroy(h);
     return rc;
 }
 

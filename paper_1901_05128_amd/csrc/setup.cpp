@@ -178,9 +178,12 @@ void gauss_jacobi(int n, double a, double b, std::vector<double>& s, std::vector
     s.assign(n, 0.0);
     lam.assign(n, 0.0);
     for (int j = 0; j < n; ++j) {
-        // the (j+1)-th smallest eigenvalue lies where the count passes j
-        double lo = -1.0, hi = 1.0;
-        for (int it = 0; it < 200; ++it) {
+        // the (j+1)-th smallest eigenvalue lies where the count passes j; it
+        // lies above the previous node. Bisection isolates it to a bracket
+        // far narrower than the node spacing (~(pi/n)^2 near the ends), and
+        // Newton, which converges quadratically from there, finishes it.
+        double lo = j > 0 ? s[j - 1] : -1.0, hi = 1.0;
+        for (int it = 0; it < 200 && hi - lo > 1e-10; ++it) {
             const double mid = 0.5 * (lo + hi);
             if (mid <= lo || mid >= hi) break;
             if (sturm_count(r, n, mid) > j)
@@ -189,7 +192,7 @@ void gauss_jacobi(int n, double a, double b, std::vector<double>& s, std::vector
                 lo = mid;
         }
         double x = 0.5 * (lo + hi);
-        for (int it = 0; it < 3; ++it) {
+        for (int it = 0; it < 4; ++it) {
             double qn, dqn, ss;
             ortho_eval(r, n, x, qn, dqn, ss);
             if (dqn == 0.0) break;

@@ -146,3 +146,23 @@ def test_full_size_parameter_gradients_match_finite_differences():
         print(f"  param {i}: adjoint {grads[i]:.10e}  fd {fd:.10e}  rel {abs(grads[i] - fd) / max(abs(fd), 1e-300):.2e}",
               flush=True)
         assert abs(grads[i] - fd) <= 1e-6 * abs(fd) + 1e-9 * L0
+
+
+def test_handle_matches_one_shot_and_is_reusable():
+    """fp_adjoint_create once, fp_adjoint_run twice (different cotangents):
+    each run equals the one-shot fp_adjoint bit for bit; the stepping calls
+    reject the handle."""
+    dim, nx, ny = 2, 21, 13
+    M = nx * ny
+    G0 = wl.g0_random(M, 41).reshape(2, M)
+    g = cq.make_grid(dim, nx, ny)
+    for method in (0, 1):
+        p = cq.make_params(0.35, 0.65, 0.7, 1.0, 130, 2, method, np_=24, solver=cq.SOLVER_MODAL)
+        with cq.Adjoint(g, p) as h:
+            for seed in (1, 2):
+                gN = np.random.default_rng(seed).standard_normal((2, M))
+                a0, ag = h.run(dev(G0), dev(gN))
+                b0, bg = cq.fp_adjoint(g, p, dev(G0), dev(gN))
+                assert torch.equal(a0, b0)
+                assert list(ag) == list(bg)
+            assert cq.lib().fp_step(h._h, 1) == -1  # CQ_EINVAL: not a stepping solver
