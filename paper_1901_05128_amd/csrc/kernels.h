@@ -133,7 +133,7 @@ struct ModalWinArgs {
     int bt;               // steps taken here (within that block)
     int L;                // lag (<= 32)
     int64_t Lr;           // slots of the level store (= L)
-    int nsplit, BT;       // Sf[nsplit][BT][2][M]
+    int nsplit, BT;       // Sf[nsplit][BT][2][M], read from slice 0 (summed over the slices)
     int scheme;
     int64_t dstride;
     double inv_tau, c, a;

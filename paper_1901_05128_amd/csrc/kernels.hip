@@ -183,23 +183,31 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
     bool xin[4];
 #pragma unroll
     for (int xb = 0; xb < 4; ++xb) xin[xb] = (x0 + xb * 16 + li) < p.M;
-    for (int64_t l0 = l_lo; l0 < l_hi; l0 += 4) {
-        const int64_t l = l0 + lk;
-        const bool lin = l < l_hi;
-        double bv[4];
+    // U K-steps of 4 levels per iteration: all their operand loads are
+    // issued before the first product, so one memory latency is spread over
+    // 4 U BB MFMAs instead of 4 BB
+    constexpr int U = 4;
+    for (int64_t l0 = l_lo; l0 < l_hi; l0 += 4 * U) {
+        double bv[U][4], av[U][BB];
 #pragma unroll
-        for (int xb = 0; xb < 4; ++xb)
-            bv[xb] = (lin && xin[xb]) ? G[l * ls + x0 + xb * 16 + li] : 0.0;
-        double av[BB];
+        for (int uu = 0; uu < U; ++uu) {
+            const int64_t l = l0 + 4 * uu + lk;
+            const bool lin = l < l_hi;
 #pragma unroll
-        for (int bb = 0; bb < BB; ++bb) {
-            const int b = brow0 + bb * 16 + li;
-            av[bb] = (lin && b < p.B) ? dk[p.n0 + 1 + b - l] : 0.0;
+            for (int xb = 0; xb < 4; ++xb)
+                bv[uu][xb] = (lin && xin[xb]) ? G[l * ls + x0 + xb * 16 + li] : 0.0;
+#pragma unroll
+            for (int bb = 0; bb < BB; ++bb) {
+                const int b = brow0 + bb * 16 + li;
+                av[uu][bb] = (lin && b < p.B) ? dk[p.n0 + 1 + b - l] : 0.0;
+            }
         }
 #pragma unroll
-        for (int bb = 0; bb < BB; ++bb)
+        for (int uu = 0; uu < U; ++uu)
 #pragma unroll
-            for (int xb = 0; xb < 4; ++xb) acc[bb][xb] = mfma16x16x4(av[bb], bv[xb], acc[bb][xb]);
+            for (int bb = 0; bb < BB; ++bb)
+#pragma unroll
+                for (int xb = 0; xb < 4; ++xb) acc[bb][xb] = mfma16x16x4(av[uu][bb], bv[uu][xb], acc[bb][xb]);
     }
 #pragma unroll
     for (int bb = 0; bb < BB; ++bb)
@@ -664,143 +672,6 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
     }
 }
 
-// Fast form for many modes: the compressed state streams through
-// k_hist_block (time-blocked, exactly as for the nodal solver, here on the
-// sine coefficients; its node slices are then summed into slice 0), and this
-// kernel takes the steps of the block: thread per mode, S = the block's fast
-// partial sum Sf[0][b] + the exact-weight window
-// sum_{i<min(L-1,n-1)} d_{i+1} g^{n-1-i} from a register ring
-// (ring[i] = g^{n-1-i}, levels below 0 read as g^0 for BDF2's g^{-1}), then
-// the 2x2 solve; the new level goes to its slot of the level store (the
-// state pass of the next block reads it there).
-//
-// ADJ: one step of the adjoint sweep in reversed time. The same history of
-// the levels (here psi = Dm mu), then r = E(mu) - S (plus the cotangent at
-// the first step), mu = (c I + W_0 Dm)^-1 r = M^-T r and the new level
-// psi = Dm mu; mu^n goes to mu[n].
-template <int LW, bool ADJ>
-__global__ __launch_bounds__(64) void k_modal_win(ModalWinArgs p) {
-    // the block's fast partial sums (slice 0, already summed over the node
-    // slices), staged per thread so that the time loop makes no global loads
-    __shared__ double fs[32][2][64];
-    const int tid = threadIdx.x;
-    const int64_t mode = int64_t(blockIdx.x) * 64 + tid;
-    if (mode >= p.M) return;
-    const int64_t M = p.M, twoM = 2 * M;
-    const int64_t b0 = p.nfirst - p.nblk;
-#pragma unroll
-    for (int t = 0; t < 32; ++t) {
-        if (t < p.bt) {
-            fs[t][0][tid] = p.Sf[((b0 + t) * 2) * M + mode];
-            fs[t][1][tid] = p.Sf[((b0 + t) * 2 + 1) * M + mode];
-        }
-    }
-    const double lam = p.lam[mode];
-    const double g00 = p.g0[mode], g01 = p.g0[M + mode];
-    const double L1 = p.a + lam;
-    const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
-    const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
-    const double idet = 1.0 / (m11 * m22 - m12 * m21);
-    const double* __restrict__ d0p = p.d;
-    const double* __restrict__ d1p = p.d + p.dstride;
-    double* __restrict__ lv = p.levels + mode;
-    double ring0[LW], ring1[LW];
-#pragma unroll
-    for (int i = 0; i < LW; ++i) {
-        int64_t l = p.nfirst - 1 - i;
-        if (l < 0) l = 0;
-        const bool ok = i < p.L && l >= p.nfirst - p.L;  // still in the store
-        const int64_t sl = l % p.Lr;
-        ring0[i] = ok ? lv[sl * twoM] : 0.0;
-        ring1[i] = ok ? lv[sl * twoM + M] : 0.0;
-    }
-    // the variables of the time difference: the levels themselves (forward)
-    // or mu (adjoint; mu[0] = 0 and mu^{-1} = 0)
-    double e10, e11, e20, e21;
-    if (ADJ) {
-        const double* __restrict__ mv = p.mu + mode;
-        e10 = mv[(p.nfirst - 1) * twoM];
-        e11 = mv[(p.nfirst - 1) * twoM + M];
-        e20 = p.nfirst >= 2 ? mv[(p.nfirst - 2) * twoM] : 0.0;
-        e21 = p.nfirst >= 2 ? mv[(p.nfirst - 2) * twoM + M] : 0.0;
-    } else {
-        e10 = ring0[0];
-        e11 = ring1[0];
-        e20 = ring0[1];
-        e21 = ring1[1];
-    }
-    for (int t = 0; t < p.bt; ++t) {
-        const int64_t n = p.nfirst + t;
-        double S0 = fs[t][0][tid], S1 = fs[t][1][tid];
-        const int64_t wn = (n - 1 < p.L - 1) ? n - 1 : p.L - 1;
-        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
-#pragma unroll
-        for (int i = 0; i + 1 < LW; i += 2) {
-            if (i < wn) {
-                a0 = fma(d0p[i + 1], ring0[i], a0);
-                a1 = fma(d1p[i + 1], ring1[i], a1);
-            }
-            if (i + 1 < wn) {
-                c0 = fma(d0p[i + 2], ring0[i + 1], c0);
-                c1 = fma(d1p[i + 2], ring1[i + 1], c1);
-            }
-        }
-        S0 += a0 + c0;
-        S1 += a1 + c1;
-        double E0, E1;
-        if (p.scheme == 1) {
-            E0 = e10 * p.inv_tau;
-            E1 = e11 * p.inv_tau;
-        } else {
-            E0 = (2.0 * e10 - 0.5 * e20) * p.inv_tau;
-            E1 = (2.0 * e11 - 0.5 * e21) * p.inv_tau;
-            if (!ADJ) {
-                S0 = fma(0.5 * d0p[n - 1], g00, S0);
-                S1 = fma(0.5 * d1p[n - 1], g01, S1);
-            }
-        }
-        double v0, v1;  // the new level
-        if (ADJ) {
-            if (n == 1) {
-                S0 -= p.gc[mode];
-                S1 -= p.gc[M + mode];
-            }
-            const double r0 = E0 - S0, r1 = E1 - S1;
-            const double u0 = (m22 * r0 - m21 * r1) * idet;
-            const double u1 = (m11 * r1 - m12 * r0) * idet;
-            v0 = L1 * u0 - p.a * u1;
-            v1 = L1 * u1 - p.a * u0;
-            p.mu[n * twoM + mode] = u0;
-            p.mu[n * twoM + M + mode] = u1;
-            e20 = e10;
-            e21 = e11;
-            e10 = u0;
-            e11 = u1;
-        } else {
-            p.Sout[n * p.sstride + mode] = S0;
-            p.Sout[n * p.sstride + M + mode] = S1;
-            const double r0 = E0 - (L1 * S0 - p.a * S1);
-            const double r1 = E1 - (L1 * S1 - p.a * S0);
-            v0 = (m22 * r0 - m12 * r1) * idet;
-            v1 = (m11 * r1 - m21 * r0) * idet;
-            e20 = e10;
-            e21 = e11;
-            e10 = v0;
-            e11 = v1;
-        }
-        const int64_t so = n % p.Lr;
-        lv[so * twoM] = v0;
-        lv[so * twoM + M] = v1;
-#pragma unroll
-        for (int i = LW - 1; i > 0; --i) {
-            ring0[i] = ring0[i - 1];
-            ring1[i] = ring1[i - 1];
-        }
-        ring0[0] = v0;
-        ring1[0] = v1;
-    }
-}
-
 // Exchange of a double between the two lanes of a pair (lane ^ 1) with a
 // DPP quad permutation [1,0,3,2] on each 32-bit half.
 __device__ __forceinline__ double pair_swap(double x) {
@@ -808,6 +679,132 @@ __device__ __forceinline__ double pair_swap(double x) {
     const int lo = __builtin_amdgcn_update_dpp(0, int(v & 0xffffffffll), 0xB1, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, int(v >> 32), 0xB1, 0xF, 0xF, false);
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Fast form for many modes: the compressed state streams through
+// k_hist_block (time-blocked, exactly as for the nodal solver, here on the
+// sine coefficients; its node slices are then summed into slice 0), and this
+// kernel takes the bt <= 32 steps of the block. A lane pair owns one mode,
+// lane k of the pair component k. The history sum of step n is
+//   S_k^n = Sf[0][n - nblk][k]                      (lags >= L, fast part)
+//         + sum_{i=1}^{min(L-1, n-1)} d_{k,i} g_k^{n-i}   (exact window),
+// accumulated in push form as in the direct near field: the window part of
+// the levels before this launch is added first (from the level store, slot
+// l mod Lr), and each new level is pushed into the later steps of the
+// launch, so a step waits on one FMA and the loop makes no global loads.
+// The 2x2 solve and the adjoint variant (ADJ) are those of k_modal_near.
+template <bool ADJ>
+__global__ __launch_bounds__(64) void k_modal_win(ModalWinArgs p) {
+    constexpr int BB = 32;
+    __shared__ double wd[2 * (BB + 1)];  // window weights d_{k,1..L-1}, zero beyond
+    for (int e = threadIdx.x; e < 2 * BB; e += 64) {
+        const int kk = e / BB, i = e % BB;
+        wd[kk * (BB + 1) + i] = (i >= 1 && i < p.L) ? p.d[int64_t(kk) * p.dstride + i] : 0.0;
+    }
+    __syncthreads();
+    const int64_t gid = int64_t(blockIdx.x) * 64 + threadIdx.x;
+    const int64_t mode = gid >> 1;
+    const int k = int(gid & 1);
+    if (mode >= p.M) return;  // both lanes of a pair leave together
+    const double* __restrict__ w = wd + k * (BB + 1);
+    const int64_t M = p.M, twoM = 2 * M;
+    const double lam = p.lam[mode];
+    const double g0k = p.g0[k * M + mode];
+    const double L1 = p.a + lam;
+    const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
+    const double m12 = -p.a * p.d0[1], m21 = -p.a * p.d0[0];
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
+    const double c_own = k ? i11 : i00;
+    const double c_part = k ? i01 : i10;
+    const double u = p.a * (k ? i10 : i01) - L1 * c_own;
+    const double x = c_part;
+    const double y = p.a * (k ? i00 : i11) - L1 * c_part;
+    const double t_part = k ? i10 : i01;
+    const double et = p.inv_tau;
+    double* __restrict__ lv = p.levels + k * M + mode;
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    const int64_t b0 = p.nfirst - p.nblk;
+    const int bt = p.bt;
+    double acc[BB];
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+        double v = 0.0;
+        if (b < bt) {
+            v = p.Sf[((b0 + b) * 2 + k) * M + mode];
+            if (!ADJ && p.scheme == 2) v = fma(0.5 * dk[p.nfirst + b - 1], g0k, v);
+            if (ADJ && p.nfirst + b == 1) v -= p.gc[k * M + mode];  // cotangent enters step 1
+        }
+        acc[b] = v;
+    }
+    // window part of the levels l = nfirst-j (j < L, l >= 1) already taken:
+    // all loads first, then the sums
+    {
+        double old[BB];
+        int64_t sl = (p.nfirst - 1) % p.Lr;  // slot of level nfirst-1
+#pragma unroll
+        for (int j = 1; j < BB; ++j) {
+            old[j] = (j < p.L && p.nfirst - j >= 1) ? lv[sl * twoM] : 0.0;
+            sl = (sl == 0) ? p.Lr - 1 : sl - 1;
+        }
+#pragma unroll
+        for (int j = 1; j < BB; ++j)
+#pragma unroll
+            for (int b = 0; b + j < BB; ++b)
+                if (b < bt) acc[b] = fma(w[b + j], old[j], acc[b]);
+    }
+    // variables of the time difference: levels (forward; level -1 reads as
+    // level 0) or mu (adjoint; mu[0] = 0 and mu^{-1} = 0)
+    double gm1, gm2;
+    if (ADJ) {
+        const double* __restrict__ mv = p.mu + k * M + mode;
+        gm1 = mv[(p.nfirst - 1) * twoM];
+        gm2 = p.nfirst >= 2 ? mv[(p.nfirst - 2) * twoM] : 0.0;
+    } else {
+        gm1 = lv[((p.nfirst - 1) % p.Lr) * twoM];
+        gm2 = lv[(((p.nfirst >= 2) ? p.nfirst - 2 : 0) % p.Lr) * twoM];
+    }
+    const bool bdf2 = p.scheme == 2;
+    const double w1 = w[1];
+    double wr[BB - 2];
+#pragma unroll
+    for (int i = 0; i < BB - 2; ++i) wr[i] = w[i + 2];
+    int64_t slot = p.nfirst % p.Lr;
+    double gprev = 0.0;
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+        if (b < bt) {
+            __builtin_amdgcn_sched_barrier(0);
+            const int64_t n = p.nfirst + b;
+            double S = acc[b];
+            if (b > 0) S = fma(w1, gprev, S);
+            const double E = bdf2 ? (2.0 * gm1 - 0.5 * gm2) * et : gm1 * et;
+            double lev, e_new;
+            if (ADJ) {
+                const double r = E - S;
+                const double P = c_own * r, Q = t_part * r;
+                const double A = L1 * P - p.a * Q, Bv = L1 * Q - p.a * P;
+                e_new = P + pair_swap(Q);
+                lev = A + pair_swap(Bv);
+                p.mu[n * twoM + k * M + mode] = e_new;
+            } else {
+                const double Q = fma(y, S, x * E);
+                const double P = fma(u, S, c_own * E);
+                lev = P + pair_swap(Q);
+                e_new = lev;
+                p.Sout[n * p.sstride + k * M + mode] = S;
+            }
+            lv[slot * twoM] = lev;
+            slot = (slot + 1 == p.Lr) ? 0 : slot + 1;
+            if (b > 0) {
+#pragma unroll
+                for (int bb = b + 1; bb < BB; ++bb) acc[bb] = fma(wr[bb - b - 1], gprev, acc[bb]);
+            }
+            gprev = lev;
+            gm2 = gm1;
+            gm1 = e_new;
+        }
+    }
 }
 
 // Direct form, part of one time block: the steps n = nfirst .. nfirst+bt-1
@@ -1267,11 +1264,11 @@ void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st) {
 
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st) {
     prof_begin(7, st);
-    const dim3 grid(unsigned((a.M + 63) / 64));
+    const dim3 grid(unsigned((2 * a.M + 63) / 64));
     if (adj)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, true>), grid, dim3(64), 0, st, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<true>), grid, dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<32, false>), grid, dim3(64), 0, st, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_modal_win<false>), grid, dim3(64), 0, st, a);
     prof_end(7, st);
 }
 
