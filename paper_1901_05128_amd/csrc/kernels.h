@@ -36,6 +36,8 @@ struct HistDirectArgs {
 
 struct FarArgs {
     int64_t n0, M, mchunk, dstride;
+    int64_t nl;            // levels 1..nl enter (nl = n0 for a history; up to n0 + B, with
+                           // d readable, and zero, down to index n0 + 1 - nl)
     int64_t lstride;       // elements between time levels (2M for a solver)
     int B, ks, ncomp;      // ncomp components (blockIdx.z), offset M apart
     int reduce;            // also sum the ks partials into slice 0
@@ -163,11 +165,14 @@ struct AdjGradArgs {
     const double* mu;      // adjoint mu (reversed)
     const double* psi;     // adjoint psi = Dm mu (reversed)
     double* gG0c;          // [2][M] out: dl/dg^0
-    double* part;          // [blocks] out: partial sums of sum_n (mu_0 - mu_1).(X_0 - X_1)
+    double* part;          // [nchunk][blocks] out: partial sums of sum_n (mu_0 - mu_1).(X_0 - X_1)
+    double* gpart;         // [nchunk][2][M] scratch: time-chunk partial sums for dl/dg^0
+    int nchunk;            // time chunks (<= N)
 };
 
 // d/dbeta pass over one time block n0+1..n0+bt: for each component and mode
-//   acc += sum_b psi^n (F[b] + sum_{l=n0+1}^{n} dw_{n-l} g^l + [BDF2] 1/2 dd_{n-1} g^0)
+//   acc += sum_b psi^n (F[b] + [BDF2] 1/2 dd_{n-1} g^0),
+// F[b] = sum_{l=1}^{n} dw_{n-l} g^l from k_far_toeplitz over levels 1..n0+bt
 struct AdjBetaArgs {
     int64_t M, N, n0;
     int bt, scheme;
@@ -206,7 +211,7 @@ void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);
 void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st);
 void launch_adj_g0(const AdjGradArgs& a, hipStream_t st);
-// returns the number of partial sums written to a.part
+// returns the number of partial sums written to a.part (blocks x chunks)
 int launch_adj_da(const AdjGradArgs& a, hipStream_t st);
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st);
 // out[k] = sum_x acc[k][x] over blocks: partials [2][blocks]; returns blocks

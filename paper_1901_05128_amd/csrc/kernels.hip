@@ -154,7 +154,9 @@ __global__ __launch_bounds__(256) void k_reduce_far(double* __restrict__ F, int 
 
 // ---------------------------------------------------------------------------
 // Direct history, far field of one time block (FP64 MFMA):
-//   F[q][b][k][x] = sum_{l in chunk q} d_k[n0+1+b-l] G_k^l[x],  b < B, 1 <= l <= n0.
+//   F[q][b][k][x] = sum_{l in chunk q} d_k[n0+1+b-l] G_k^l[x],  b < B, 1 <= l <= nl
+// (nl = n0 for the history; larger nl reaches into the block, where the
+// caller's weights read as zero at negative lags).
 // A lower-triangular Toeplitz block T[b][l] = d[n0+1+b-l] times the stored
 // levels. Workgroup: 4 waves share one 64-wide DOF tile; wave w owns rows
 // b in [16*BB*w, 16*BB*(w+1)). MFMA 16x16x4 f64 operands: A(16x4) lane L ->
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t l_lo = 1 + int64_t(q) * p.mchunk;
-    const int64_t l_hi = (l_lo + p.mchunk < p.n0 + 1) ? l_lo + p.mchunk : p.n0 + 1;
+    const int64_t l_hi = (l_lo + p.mchunk < p.nl + 1) ? l_lo + p.mchunk : p.nl + 1;
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
     const double* __restrict__ G = p.levels + int64_t(k) * p.M;
     const int64_t ls = p.lstride;
@@ -955,88 +957,92 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
     return red[0];
 }
 
-// one thread per (component, mode)
-__global__ __launch_bounds__(256) void k_adj_g0(AdjGradArgs p) {
+// dl/dg^0, BDF2 part: partial sums over time chunks, one thread per
+// (component, mode) and chunk: gpart[c][e] = sum_{n in chunk c} d_{k,n-1} psi_k^n
+__global__ __launch_bounds__(256) void k_adj_g0_part(AdjGradArgs p) {
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (e >= 2 * p.M) return;
     const int64_t twoM = 2 * p.M, N = p.N;
     const int k = int(e / p.M);
+    const int64_t per = (N + p.nchunk - 1) / p.nchunk;
+    const int64_t lo = 1 + int64_t(blockIdx.y) * per;
+    const int64_t hi = (lo + per - 1 < N) ? lo + per - 1 : N;
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t n = lo;
+    for (; n + 1 <= hi; n += 2) {
+        s0 = fma(dk[n - 1], p.psi[(N + 1 - n) * twoM + e], s0);
+        s1 = fma(dk[n], p.psi[(N - n) * twoM + e], s1);
+    }
+    if (n <= hi) s0 = fma(dk[n - 1], p.psi[(N + 1 - n) * twoM + e], s0);
+    p.gpart[int64_t(blockIdx.y) * twoM + e] = s0 + s1;
+}
+
+// dl/dg^0 = mu^1/tau (BE) or (3 mu^1 - mu^2)/(2 tau) - 1/2 sum_c gpart[c] (BDF2)
+__global__ __launch_bounds__(256) void k_adj_g0(AdjGradArgs p) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= 2 * p.M) return;
+    const int64_t twoM = 2 * p.M, N = p.N;
     const double mu1 = p.mu[N * twoM + e];
     if (p.scheme == 1) {
         p.gG0c[e] = mu1 * p.inv_tau;
         return;
     }
     const double mu2 = N >= 2 ? p.mu[(N - 1) * twoM + e] : 0.0;
-    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
-    double s0 = 0.0, s1 = 0.0;
-    int64_t n = 1;
-    for (; n + 1 <= N; n += 2) {
-        s0 = fma(dk[n - 1], p.psi[(N + 1 - n) * twoM + e], s0);
-        s1 = fma(dk[n], p.psi[(N - n) * twoM + e], s1);
-    }
-    if (n <= N) s0 = fma(dk[n - 1], p.psi[(N + 1 - n) * twoM + e], s0);
-    p.gG0c[e] = (3.0 * mu1 - mu2) * (0.5 * p.inv_tau) - 0.5 * (s0 + s1);
+    double sum = 0.0;
+    for (int c = 0; c < p.nchunk; ++c) sum += p.gpart[int64_t(c) * twoM + e];
+    p.gG0c[e] = (3.0 * mu1 - mu2) * (0.5 * p.inv_tau) - 0.5 * sum;
 }
 
-// one thread per mode; a partial sum per block
+// sum_n (mu_1^n - mu_2^n)(X_1^n - X_2^n) over a time chunk: one thread per
+// mode, a partial sum per block and chunk at part[chunk][block]
 __global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
     __shared__ double red[256];
     const int64_t mode = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
     if (mode < p.M) {
         const int64_t M = p.M, twoM = 2 * M, N = p.N;
-        for (int64_t n = 1; n <= N; ++n) {
+        const int64_t per = (N + p.nchunk - 1) / p.nchunk;
+        const int64_t lo = 1 + int64_t(blockIdx.y) * per;
+        const int64_t hi = (lo + per - 1 < N) ? lo + per - 1 : N;
+        for (int64_t n = lo; n <= hi; ++n) {
             const int64_t t = n * twoM + mode, r = (N + 1 - n) * twoM + mode;
             const double X0 = fma(p.d0[0], p.traj[t], p.Sx[t]);
             const double X1 = fma(p.d0[1], p.traj[t + M], p.Sx[t + M]);
-            acc = fma(p.mu[r] - p.mu[r + M], X0 - X1, acc);
+            if (n & 1)
+                acc1 = fma(p.mu[r] - p.mu[r + M], X0 - X1, acc1);
+            else
+                acc0 = fma(p.mu[r] - p.mu[r + M], X0 - X1, acc0);
         }
     }
-    const double tot = block_sum256(acc, red);
-    if (threadIdx.x == 0) p.part[blockIdx.x] = tot;
+    const double tot = block_sum256(acc0 + acc1, red);
+    if (threadIdx.x == 0) p.part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-// d/dbeta over one block of up to 64 steps: one thread per (component,
-// mode); the block's levels in registers, the weight derivatives dw_0..63 in
-// LDS (both components), the far part F from k_far_toeplitz on dw.
+// d/dbeta over one block of up to 64 steps, one thread per (component,
+// mode): F holds the whole CQ sum of the weight derivatives over levels
+// 1..n (k_far_toeplitz over levels up to the block's end); add BDF2's
+// starting correction and contract with psi.
 __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
-    constexpr int BB = 64;
-    __shared__ double wd[2][BB];
-    for (int e = threadIdx.x; e < 2 * BB; e += 256) {
-        const int kk = e / BB, i = e % BB;
-        wd[kk][i] = i < p.dstride ? p.dw[int64_t(kk) * p.dstride + i] : 0.0;
-    }
-    __syncthreads();
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (e >= 2 * p.M) return;
     const int64_t M = p.M, twoM = 2 * M, N = p.N;
     const int k = int(e / M);
     const int64_t mode = e - int64_t(k) * M;
-    const double* __restrict__ w = wd[k];
     const double g0 = p.traj[e];
     const double* __restrict__ ddk = p.dd + int64_t(k) * p.dstride;
-    double g[BB];
-#pragma unroll
-    for (int j = 0; j < BB; ++j) g[j] = j < p.bt ? p.traj[(p.n0 + 1 + j) * twoM + e] : 0.0;
-    double acc = 0.0;
-#pragma unroll
-    for (int b = 0; b < BB; ++b) {
-        if (b < p.bt) {
-            const int64_t n = p.n0 + 1 + b;
-            double Y0 = p.n0 >= 1 ? p.F[(int64_t(b) * 2 + k) * M + mode] : 0.0, Y1 = 0.0;
-#pragma unroll
-            for (int j = 0; j <= b; ++j) {
-                if (j & 1)
-                    Y1 = fma(w[b - j], g[j], Y1);
-                else
-                    Y0 = fma(w[b - j], g[j], Y0);
-            }
-            double Y = Y0 + Y1;
-            if (p.scheme == 2) Y = fma(0.5 * ddk[n - 1], g0, Y);
-            acc = fma(p.psi[(N + 1 - n) * twoM + e], Y, acc);
-        }
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < p.bt; ++b) {
+        const int64_t n = p.n0 + 1 + b;
+        double Y = p.F[(int64_t(b) * 2 + k) * M + mode];
+        if (p.scheme == 2) Y = fma(0.5 * ddk[n - 1], g0, Y);
+        if (b & 1)
+            acc1 = fma(p.psi[(N + 1 - n) * twoM + e], Y, acc1);
+        else
+            acc0 = fma(p.psi[(N + 1 - n) * twoM + e], Y, acc0);
     }
-    p.acc[e] += acc;
+    p.acc[e] += acc0 + acc1;
 }
 
 // per-component sums of acc[2][M]: partials part[k][block]
@@ -1293,13 +1299,15 @@ void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st) 
 }
 
 void launch_adj_g0(const AdjGradArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_g0, dim3(unsigned((2 * a.M + 255) / 256)), dim3(256), 0, st, a);
+    const unsigned bx = unsigned((2 * a.M + 255) / 256);
+    if (a.scheme == 2) hipLaunchKernelGGL(k_adj_g0_part, dim3(bx, unsigned(a.nchunk)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_g0, dim3(bx), dim3(256), 0, st, a);
 }
 
 int launch_adj_da(const AdjGradArgs& a, hipStream_t st) {
     const int blocks = int((a.M + 255) / 256);
-    hipLaunchKernelGGL(k_adj_da, dim3(unsigned(blocks)), dim3(256), 0, st, a);
-    return blocks;
+    hipLaunchKernelGGL(k_adj_da, dim3(unsigned(blocks), unsigned(a.nchunk)), dim3(256), 0, st, a);
+    return blocks * a.nchunk;
 }
 
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st) {

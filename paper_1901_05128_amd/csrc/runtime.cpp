@@ -27,12 +27,13 @@ namespace {
 
 constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
 constexpr int64_t kModalBlockedMin = 8192;      // modes
+constexpr int64_t kDwPad = 64;                  // zero lags in front of the d/dbeta weights
 
 // device arrays of a gradient handle (trajectory, history sums, adjoint)
 struct AdjBufs {
     double *traj = nullptr, *Sx = nullptr, *psi = nullptr, *mu = nullptr, *gc = nullptr, *gG0c = nullptr,
            *acc = nullptr, *dw = nullptr, *dd = nullptr, *part = nullptr, *part2 = nullptr;
-    int nblk_da = 0, nblk_rows = 0;
+    int nblk_da = 0, nblk_rows = 0, nchunk = 1;
 };
 
 struct Solver {
@@ -457,6 +458,7 @@ int check_finite_g0(const double* G0dev, int64_t count, hipStream_t st, const ch
 void launch_far_block(Solver& s) {
     FarArgs fa{};
     fa.n0 = s.n0;
+    fa.nl = s.n0;
     fa.M = s.M;
     fa.dstride = s.dstride;
     fa.lstride = 2 * s.M;
@@ -890,6 +892,7 @@ int cq_history(int32_t scheme, double beta, double tau, const double* G_hist, in
         } else {
             FarArgs fa{};
             fa.n0 = n - 1;
+            fa.nl = n - 1;
             fa.M = M;
             fa.dstride = dstride;
             fa.lstride = M;
@@ -1137,9 +1140,10 @@ static int adjoint_setup(Solver& s) {
     if ((rc = dev_alloc(s, &A.gc, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.gG0c, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.acc, size_t(twoM)))) return rc;
-    if ((rc = dev_alloc(s, &A.dw, size_t(2 * s.dstride)))) return rc;
+    if ((rc = dev_alloc(s, &A.dw, size_t(2 * (s.dstride + kDwPad))))) return rc;
     if ((rc = dev_alloc(s, &A.dd, size_t(2 * s.dstride)))) return rc;
-    A.nblk_da = int((M + 255) / 256);
+    A.nchunk = int(std::min<int64_t>(64, N));
+    A.nblk_da = int((M + 255) / 256) * A.nchunk;
     A.nblk_rows = int((M + 4095) / 4096);
     if ((rc = dev_alloc(s, &A.part, size_t(A.nblk_da)))) return rc;
     if ((rc = dev_alloc(s, &A.part2, size_t(2 * A.nblk_rows)))) return rc;
@@ -1163,10 +1167,11 @@ static int adjoint_setup(Solver& s) {
     }
     // weight derivatives: exact (recurrences differentiated); the fast
     // scheme's beyond its lag from the rule
-    std::vector<double> hdw(size_t(2 * s.dstride)), hdd(size_t(2 * s.dstride));
+    // dw rows: kDwPad zeros (negative lags), then the derivatives
+    std::vector<double> hdw(size_t(2 * (s.dstride + kDwPad)), 0.0), hdd(size_t(2 * s.dstride));
     for (int k = 0; k < 2; ++k) {
         double* ddk = hdd.data() + size_t(k) * size_t(s.dstride);
-        double* dwk = hdw.data() + size_t(k) * size_t(s.dstride);
+        double* dwk = hdw.data() + size_t(k) * size_t(s.dstride + kDwPad) + kDwPad;
         weights_dbeta(p->scheme, s.beta[k], s.tau, s.dstride - 1, ddk);
         std::copy(ddk, ddk + s.dstride, dwk);
         if (p->method == 1) {
@@ -1238,29 +1243,33 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     ga.psi = psi;
     ga.gG0c = gG0c;
     ga.part = part;
+    ga.gpart = s.F;  // free until the d/dbeta pass: ks*64 >= nchunk rows of 2M
+    ga.nchunk = A.nchunk;
     launch_adj_g0(ga, st);
     transform(s, gG0c, gG0, true);  // dl/dG0 = P^T dl/dg^0, P = scaled S, symmetric
     launch_adj_da(ga, st);
     HIPCHK(hipMemsetAsync(acc, 0, size_t(twoM) * sizeof(double), st));
     for (int64_t n0 = 0; n0 < N; n0 += 64) {
         const int bt = int(std::min<int64_t>(64, N - n0));
-        if (n0 >= 1) {
-            FarArgs fa{};
-            fa.n0 = n0;
-            fa.M = M;
-            fa.dstride = s.dstride;
-            fa.lstride = twoM;
-            fa.B = 64;
-            fa.ks = s.ks;
-            fa.ncomp = 2;
-            const int64_t mc = (n0 + s.ks - 1) / s.ks;
-            fa.mchunk = ((mc + 3) / 4) * 4;
-            fa.levels = traj;
-            fa.d = dw;
-            fa.F = s.F;
-            fa.reduce = 1;
-            launch_far(fa, st);
-        }
+        // CQ sums of the weight derivatives over levels 1..n for the block's
+        // steps: one Toeplitz product over levels 1..n0+bt (negative lags
+        // read the zero padding in front of each component's row)
+        FarArgs fa{};
+        fa.n0 = n0;
+        fa.nl = n0 + bt;
+        fa.M = M;
+        fa.dstride = s.dstride + kDwPad;
+        fa.lstride = twoM;
+        fa.B = 64;
+        fa.ks = s.ks;
+        fa.ncomp = 2;
+        const int64_t mc = (fa.nl + s.ks - 1) / s.ks;
+        fa.mchunk = ((mc + 3) / 4) * 4;
+        fa.levels = traj;
+        fa.d = dw + kDwPad;
+        fa.F = s.F;
+        fa.reduce = 1;
+        launch_far(fa, st);
         AdjBetaArgs ab{};
         ab.M = M;
         ab.N = N;
@@ -1268,7 +1277,7 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         ab.bt = bt;
         ab.scheme = p->scheme;
         ab.dstride = s.dstride;
-        ab.dw = dw;
+        ab.dw = dw + kDwPad;
         ab.dd = dd;
         ab.F = s.F;
         ab.traj = traj;
