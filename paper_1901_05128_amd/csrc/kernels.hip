@@ -156,72 +156,93 @@ __global__ __launch_bounds__(256) void k_reduce_far(double* __restrict__ F, int 
 // Direct history, far field of one time block (FP64 MFMA):
 //   F[q][b][k][x] = sum_{l in chunk q} d_k[n0+1+b-l] G_k^l[x],  b < B, 1 <= l <= nl
 // (nl = n0 for the history; larger nl reaches into the block, where the
-// caller's weights read as zero at negative lags).
-// A lower-triangular Toeplitz block T[b][l] = d[n0+1+b-l] times the stored
-// levels. Workgroup: 4 waves share one 64-wide DOF tile; wave w owns rows
-// b in [16*BB*w, 16*BB*(w+1)). MFMA 16x16x4 f64 operands: A(16x4) lane L ->
-// (row L%16, k L/16); B(4x16) lane L -> (k L/16, col L%16); C: item i of
-// lane L is row L/16 + 4i, col L%16 (checked on gfx950). The Toeplitz A fragment is read straight from
-// the weight vector (a 4 KB window, cache resident).
-template <int BB>
+// caller's weights read as zero at negative lags). A lower-triangular
+// Toeplitz block T[b][l] = d[n0+1+b-l] times the stored levels.
+//
+// Workgroup: 4 waves on one 64-wide DOF tile; wave w owns the 16 columns
+// x0+16w.. and all B rows (NR = B/16 row fragments), so one level operand
+// (B fragment, a single 8-byte load per lane) feeds NR MFMAs. The Toeplitz
+// A fragments come from LDS: per stage of up to TL levels the weights
+// d[n0+1+b-l] of the stage are staged once per workgroup (B + TL values),
+// which keeps the vector-memory address unit (the limit of a layout that
+// reloads both operands per product) for the levels alone.
+// MFMA 16x16x4 f64 operands: A(16x4) lane L -> (row L%16, k L/16);
+// B(4x16) lane L -> (k L/16, col L%16); C: item i of lane L is row
+// L/16 + 4i, col L%16 (checked on gfx950).
+template <int NR>
 __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
+    constexpr int TL = 1024;           // levels per weight stage
+    constexpr int B = NR * 16;
+    __shared__ double wt[B + TL + 1];  // [B + TL] weights of a stage, then one zero
     const int k = blockIdx.z;
     const int q = blockIdx.y;
-    const int64_t x0 = int64_t(blockIdx.x) * 64;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
+    const int64_t xcol = int64_t(blockIdx.x) * 64 + wave * 16 + li;
+    const bool xin = xcol < p.M;
+    const int64_t xc = xin ? xcol : 0;
     const int64_t l_lo = 1 + int64_t(q) * p.mchunk;
     const int64_t l_hi = (l_lo + p.mchunk < p.nl + 1) ? l_lo + p.mchunk : p.nl + 1;
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
-    const double* __restrict__ G = p.levels + int64_t(k) * p.M;
+    const double* __restrict__ G = p.levels + int64_t(k) * p.M + xc;
     const int64_t ls = p.lstride;
-    const int brow0 = wave * 16 * BB;
-    d4 acc[BB][4];
+    d4 acc[NR];
 #pragma unroll
-    for (int bb = 0; bb < BB; ++bb)
+    for (int r = 0; r < NR; ++r) acc[r] = d4{0.0, 0.0, 0.0, 0.0};
+    constexpr int U = 4;  // K-steps of 4 levels per batch
+    for (int64_t s0 = l_lo; s0 < l_hi; s0 += TL) {
+        const int64_t s1 = (s0 + TL < l_hi) ? s0 + TL : l_hi;
+        // stage: wt[j] = d[n0+1 - (s1-1) + j], j < B + (s1 - s0) - 1; zero after
+        const int64_t base = p.n0 + 1 - (s1 - 1);
+        const int len = int(B + (s1 - s0) - 1);
+        __syncthreads();
+        for (int j = threadIdx.x; j < B + TL + 1; j += 256) wt[j] = j < len ? dk[base + j] : 0.0;
+        __syncthreads();
+        // A fragment of row fragment r at level l: wt[(16r + li) + (s1 - 1 - l)],
+        // the zero entry for a level past the stage
+        const int zero = B + TL;
+        auto load = [&](int64_t l0, double (&b_)[U], double (&a_)[U][NR]) {
 #pragma unroll
-        for (int xb = 0; xb < 4; ++xb) acc[bb][xb] = d4{0.0, 0.0, 0.0, 0.0};
-    bool xin[4];
+            for (int uu = 0; uu < U; ++uu) {
+                const int64_t l = l0 + 4 * uu + lk;
+                const int lin = l < s1 ? 1 : 0;
+                b_[uu] = G[(lin ? l : s0) * ls];
+                // index arithmetic (not a select of addresses): past the stage
+                // every row reads the zero entry
+                const int base_i = lin * (li + int(s1 - 1 - l)) + (1 - lin) * zero;
 #pragma unroll
-    for (int xb = 0; xb < 4; ++xb) xin[xb] = (x0 + xb * 16 + li) < p.M;
-    // U K-steps of 4 levels per iteration: all their operand loads are
-    // issued before the first product, so one memory latency is spread over
-    // 4 U BB MFMAs instead of 4 BB
-    constexpr int U = 4;
-    for (int64_t l0 = l_lo; l0 < l_hi; l0 += 4 * U) {
-        double bv[U][4], av[U][BB];
-#pragma unroll
-        for (int uu = 0; uu < U; ++uu) {
-            const int64_t l = l0 + 4 * uu + lk;
-            const bool lin = l < l_hi;
-#pragma unroll
-            for (int xb = 0; xb < 4; ++xb)
-                bv[uu][xb] = (lin && xin[xb]) ? G[l * ls + x0 + xb * 16 + li] : 0.0;
-#pragma unroll
-            for (int bb = 0; bb < BB; ++bb) {
-                const int b = brow0 + bb * 16 + li;
-                av[uu][bb] = (lin && b < p.B) ? dk[p.n0 + 1 + b - l] : 0.0;
+                for (int r = 0; r < NR; ++r) a_[uu][r] = wt[base_i + lin * 16 * r];
             }
+        };
+        auto mma = [&](const double (&b_)[U], const double (&a_)[U][NR]) {
+#pragma unroll
+            for (int uu = 0; uu < U; ++uu)
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r] = mfma16x16x4(a_[uu][r], b_[uu], acc[r]);
+        };
+        // two buffers in turn: the level loads of one batch are in flight
+        // while the other's products run
+        double bv[U], av[U][NR], bw[U], aw[U][NR];
+        load(s0, bv, av);
+        for (int64_t l0 = s0; l0 < s1; l0 += 8 * U) {
+            load(l0 + 4 * U, bw, aw);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(bv, av);
+            __builtin_amdgcn_sched_barrier(0);
+            load(l0 + 8 * U, bv, av);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(bw, aw);
+            __builtin_amdgcn_sched_barrier(0);
         }
-#pragma unroll
-        for (int uu = 0; uu < U; ++uu)
-#pragma unroll
-            for (int bb = 0; bb < BB; ++bb)
-#pragma unroll
-                for (int xb = 0; xb < 4; ++xb) acc[bb][xb] = mfma16x16x4(av[uu][bb], bv[uu][xb], acc[bb][xb]);
     }
+    if (!xin) return;
 #pragma unroll
-    for (int bb = 0; bb < BB; ++bb)
+    for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int xb = 0; xb < 4; ++xb) {
-            const int64_t xx = x0 + xb * 16 + li;
-            if (xx >= p.M) continue;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int b = brow0 + bb * 16 + lk + 4 * i;
-                if (b < p.B) p.F[((int64_t(q) * p.B + b) * p.ncomp + k) * p.M + xx] = acc[bb][xb][i];
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int b = 16 * r + lk + 4 * i;
+            if (b < p.B) p.F[((int64_t(q) * p.B + b) * p.ncomp + k) * p.M + xcol] = acc[r][i];
         }
 }
 
@@ -1172,11 +1193,11 @@ void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, h
 void launch_far(const FarArgs& a, hipStream_t st) {
     dim3 grid(unsigned((a.M + 63) / 64), unsigned(a.ks), unsigned(a.ncomp));
     prof_begin(2, st);
-    switch (a.B / 64) {
-        case 1: hipLaunchKernelGGL(k_far_toeplitz<1>, grid, dim3(256), 0, st, a); break;
-        case 2: hipLaunchKernelGGL(k_far_toeplitz<2>, grid, dim3(256), 0, st, a); break;
-        case 3: hipLaunchKernelGGL(k_far_toeplitz<3>, grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_far_toeplitz<4>, grid, dim3(256), 0, st, a); break;
+    switch ((a.B + 63) / 64) {
+        case 1: hipLaunchKernelGGL(k_far_toeplitz<4>, grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_far_toeplitz<8>, grid, dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL(k_far_toeplitz<12>, grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_far_toeplitz<16>, grid, dim3(256), 0, st, a); break;
     }
     prof_end(2, st);
     if (a.ks > 1 && a.reduce) {

@@ -77,6 +77,17 @@ struct Solver {
     }
 };
 
+// K-split of the far field: about 3072 workgroups (four rounds of the
+// 256 CUs x 3 resident 4-wave groups), at most 32 slices (their sum is
+// read back once per block).
+int far_ksplit(int64_t M) {
+    const int64_t tiles = 2 * ((M + 63) / 64);
+    return int(std::min<int64_t>(32, std::max<int64_t>(1, (3072 + tiles - 1) / tiles)));
+}
+
+// slices for one launch: at least 64 levels per slice
+int far_ks_for(int ks, int64_t nl) { return int(std::max<int64_t>(1, std::min<int64_t>(ks, (nl + 63) / 64))); }
+
 int dev_alloc(Solver& s, double** ptr, size_t count) {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(double);
@@ -192,8 +203,7 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     if (p->method == 0) {
         s.B = p->block_B ? p->block_B : (s.dim == 1 ? 64 : 128);
         if (p->solver == 1) s.B = 64;  // the modal near field keeps a 64-level ring in registers
-        const int64_t tiles = 2 * ((s.M + 63) / 64);
-        s.ks = int(std::min<int64_t>(64, std::max<int64_t>(1, (1024 + tiles - 1) / tiles)));
+        s.ks = far_ksplit(s.M);
     }
     s.dstride = s.N + 257 + 1;
     for (int k = 0; k < 2; ++k) {
@@ -463,9 +473,9 @@ void launch_far_block(Solver& s) {
     fa.dstride = s.dstride;
     fa.lstride = 2 * s.M;
     fa.B = s.B;
-    fa.ks = s.ks;
+    fa.ks = far_ks_for(s.ks, s.n0);
     fa.ncomp = 2;
-    int64_t mc = (s.n0 + s.ks - 1) / s.ks;
+    int64_t mc = (s.n0 + fa.ks - 1) / fa.ks;
     fa.mchunk = ((mc + 3) / 4) * 4;
     fa.levels = s.levels;
     fa.d = s.d_d;
@@ -1114,10 +1124,7 @@ static int adjoint_setup(Solver& s) {
         return fail(CQ_EINVAL, "the adjoint's fast form needs a window of <= 32 levels (ns = %d)", s.L);
     // the far field of the d/dbeta pass (and of the direct history): blocks of 64
     s.B = 64;
-    {
-        const int64_t tiles = 2 * ((M + 63) / 64);
-        s.ks = int(std::min<int64_t>(64, std::max<int64_t>(1, (1024 + tiles - 1) / tiles)));
-    }
+    s.ks = far_ksplit(M);
     {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
@@ -1261,9 +1268,9 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         fa.dstride = s.dstride + kDwPad;
         fa.lstride = twoM;
         fa.B = 64;
-        fa.ks = s.ks;
+        fa.ks = far_ks_for(s.ks, fa.nl);
         fa.ncomp = 2;
-        const int64_t mc = (fa.nl + s.ks - 1) / s.ks;
+        const int64_t mc = (fa.nl + fa.ks - 1) / fa.ks;
         fa.mchunk = ((mc + 3) / 4) * 4;
         fa.levels = traj;
         fa.d = dw + kDwPad;
