@@ -490,10 +490,42 @@ __global__ __launch_bounds__(256) void k_prep_2d(StepArgs p) {
 // With no coupling between modes there is no per-step global dependency:
 // the transform runs once at the start and once per read-out.
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane sums with DPP (no LDS round trip): a double moved by a DPP
+// pattern on each 32-bit half; lanes a pattern does not write (rows outside
+// row_mask) read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// sum over each group of G lanes (G = 2, 4, 8, 16), in every lane of the group
+template <int G>
+__device__ __forceinline__ double row_group_sum(double v) {
+    if (G >= 2) v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    if (G >= 4) v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    if (G >= 8) v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+    if (G >= 16) v += dpp_move<0x140, 0xF>(v); // row_mirror
     return v;
+}
+
+// sum over the 64 lanes, in every lane: rows of 16, then row_bcast15 (row r
+// += lane 15 of row r-1, rows 1 and 3) and row_bcast31 (rows 2 and 3 += lane
+// 31), which leaves the total in lane 63
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_group_sum<16>(v);
+    v += dpp_move<0x142, 0xA>(v);
+    v += dpp_move<0x143, 0xC>(v);
+    return lane_value(v, 63);
 }
 
 // Fast form, persistent: one wave per mode runs `nsteps` steps. Lane l holds
@@ -539,7 +571,7 @@ __global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
         if (n >= p.L + 1) {
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const double gin = __shfl(ring[k], p.L - 1, 64);
+                const double gin = lane_value(ring[k], p.L - 1);
                 double pa = 0.0, pb = 0.0;
 #pragma unroll
                 for (int q = 0; q < NPL; ++q) {
@@ -559,13 +591,13 @@ __global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
         }
         double S0 = wave_sum(part[0]);
         double S1 = wave_sum(part[1]);
-        const double gm10 = __shfl(ring[0], 0, 64), gm11 = __shfl(ring[1], 0, 64);
+        const double gm10 = lane_value(ring[0], 0), gm11 = lane_value(ring[1], 0);
         double E0, E1;
         if (p.scheme == 1) {
             E0 = gm10 * p.inv_tau;
             E1 = gm11 * p.inv_tau;
         } else {
-            const double gm20 = __shfl(ring[0], 1, 64), gm21 = __shfl(ring[1], 1, 64);
+            const double gm20 = lane_value(ring[0], 1), gm21 = lane_value(ring[1], 1);
             E0 = (2.0 * gm10 - 0.5 * gm20) * p.inv_tau;
             E1 = (2.0 * gm11 - 0.5 * gm21) * p.inv_tau;
             S0 = fma(0.5 * p.d[n - 1], g00, S0);
@@ -575,7 +607,8 @@ __global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
         const double r1 = E1 - (L1 * S1 - p.a * S0);
         const double gn0 = (m22 * r0 - m12 * r1) * idet;
         const double gn1 = (m11 * r1 - m21 * r0) * idet;
-        const double up0 = __shfl_up(ring[0], 1, 64), up1 = __shfl_up(ring[1], 1, 64);
+        // levels move up one lane (DPP wave_shr:1)
+        const double up0 = dpp_move<0x138, 0xF>(ring[0]), up1 = dpp_move<0x138, 0xF>(ring[1]);
         ring[0] = (lane == 0) ? gn0 : up0;
         ring[1] = (lane == 0) ? gn1 : up1;
     }
@@ -601,9 +634,14 @@ __global__ __launch_bounds__(256) void k_modal_fast(ModalFastArgs p) {
 // zero state and G^0, writes the coefficients of G^N.
 template <int LPM>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = LPM / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    if (LPM == 64) return wave_sum(v);
+    if (LPM == 32) {  // rows 0+1 and 2+3: totals in lanes 31 and 63
+        v = row_group_sum<16>(v);
+        v += dpp_move<0x142, 0xA>(v);
+        const double s0 = lane_value(v, 31), s1 = lane_value(v, 63);
+        return (threadIdx.x & 32) ? s1 : s0;
+    }
+    return row_group_sum<LPM>(v);
 }
 
 template <int NPL, int LPM>
