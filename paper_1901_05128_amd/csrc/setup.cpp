@@ -110,7 +110,9 @@ void weights_dbeta(int scheme, double beta, double tau, int64_t n, double* dd) {
 // (diagonal al_k, off-diagonal sqrt(be_k)); each is isolated by bisection on
 // the Sturm count and refined by Newton on the orthonormal polynomial. The
 // weights are the Christoffel numbers 1 / sum_{k<n} q_k(s_j)^2 with q_k the
-// orthonormal polynomials (q_0 = 1/sqrt(mu_0)).
+// orthonormal polynomials (q_0 = 1/sqrt(mu_0)). From the third node on,
+// Newton starts from an angle extrapolated from the previous two nodes and
+// the result is kept when the Sturm counts confirm it; otherwise bisection.
 namespace {
 
 struct JacobiRec {
@@ -178,27 +180,61 @@ void gauss_jacobi(int n, double a, double b, std::vector<double>& s, std::vector
     s.assign(n, 0.0);
     lam.assign(n, 0.0);
     for (int j = 0; j < n; ++j) {
-        // the (j+1)-th smallest eigenvalue lies where the count passes j; it
-        // lies above the previous node. Bisection isolates it to a bracket
-        // far narrower than the node spacing (~(pi/n)^2 near the ends), and
-        // Newton, which converges quadratically from there, finishes it.
-        double lo = j > 0 ? s[j - 1] : -1.0, hi = 1.0;
-        for (int it = 0; it < 200 && hi - lo > 1e-10; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi) break;
-            if (sturm_count(r, n, mid) > j)
-                hi = mid;
-            else
-                lo = mid;
+        const double lo0 = j > 0 ? s[j - 1] : -1.0;
+        double x = 0.0;
+        bool ok = false;
+        if (j >= 2) {
+            // the nodes are nearly evenly spaced in theta (s = -cos theta):
+            // Newton from the extrapolated angle, accepted only if the Sturm
+            // counts just below and above it show the (j+1)-th eigenvalue
+            const double t1 = std::acos(-s[j - 1]), t2 = std::acos(-s[j - 2]);
+            const double t = 2.0 * t1 - t2;
+            if (t > t1 && t < M_PI) {
+                x = -std::cos(t);
+                const double spacing = x - lo0;
+                bool conv = false;
+                for (int it = 0; it < 16 && x > lo0 && x < 1.0; ++it) {
+                    double qn, dqn, ss;
+                    ortho_eval(r, n, x, qn, dqn, ss);
+                    if (dqn == 0.0) break;
+                    const double dx = qn / dqn;
+                    x -= dx;
+                    if (std::fabs(dx) <= 1e-13 * spacing) {  // one more step after this one
+                        ortho_eval(r, n, x, qn, dqn, ss);
+                        if (dqn != 0.0) x -= qn / dqn;
+                        conv = true;
+                        break;
+                    }
+                }
+                if (conv && x > lo0 && x < 1.0) {
+                    const double e = 1e-9 * (x - lo0);
+                    ok = sturm_count(r, n, x - e) == j && sturm_count(r, n, x + e) == j + 1;
+                }
+            }
         }
-        double x = 0.5 * (lo + hi);
-        for (int it = 0; it < 4; ++it) {
-            double qn, dqn, ss;
-            ortho_eval(r, n, x, qn, dqn, ss);
-            if (dqn == 0.0) break;
-            const double xn = x - qn / dqn;
-            if (!(xn > lo - 1e-12 && xn < hi + 1e-12)) break;  // keep the bracketed root
-            x = xn;
+        if (!ok) {
+            // the (j+1)-th smallest eigenvalue lies where the count passes j,
+            // above the previous node. Bisection isolates it to a bracket far
+            // narrower than the node spacing (~(pi/n)^2 near the ends), and
+            // Newton, which converges quadratically from there, finishes it.
+            double lo = lo0, hi = 1.0;
+            for (int it = 0; it < 200 && hi - lo > 1e-10; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (sturm_count(r, n, mid) > j)
+                    hi = mid;
+                else
+                    lo = mid;
+            }
+            x = 0.5 * (lo + hi);
+            for (int it = 0; it < 4; ++it) {
+                double qn, dqn, ss;
+                ortho_eval(r, n, x, qn, dqn, ss);
+                if (dqn == 0.0) break;
+                const double xn = x - qn / dqn;
+                if (!(xn > lo - 1e-12 && xn < hi + 1e-12)) break;  // keep the bracketed root
+                x = xn;
+            }
         }
         double qn, dqn, ss;
         ortho_eval(r, n, x, qn, dqn, ss);
