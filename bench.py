@@ -180,6 +180,15 @@ def bench_batched(args):
     t1 = time.perf_counter()
     dofsteps = args.steps * sum(2 * p.nx * p.ny * p.N for p in inst)
     rep = reps[-1]
+    # the time loops' work: per mode, component and step, the state update and
+    # its weighting (4 flops per node, 16 + ceil(3 sqrt N) nodes) and the
+    # exact-weight window (2 flops per lag below N_s = 30); FP64 vector bound
+    flops = sum(2 * p.nx * p.ny * p.N * (4 * (16 + int(math.ceil(3 * math.sqrt(p.N)))) + 2 * 29) for p in inst)
+    ach = flops / rep.run_s / 1e12
+    roofline = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_PEAK_TFLOPS, "kernel": "k_modal_batch (all classes)",
+                "timed": "graph run time of the last step (the kernels run inside one captured graph)",
+                "traffic": None}
     rec = {
         "metric": "DOF*steps/s (batched fast BDF2 solves)", "value": dofsteps / (t1 - t0), "unit": "DOF*steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": (t1 - t0) / args.steps * 1e3,
@@ -190,7 +199,7 @@ def bench_batched(args):
                    "modes": rep.modes, "classes": rep.classes,
                    "lanes_per_mode": list(rep.class_lanes)[:rep.classes]},
         "breakdown": {"setup_s": rep.setup_s, "autotune_s": rep.autotune_s, "graph_run_s": rep.run_s},
-        "roofline": None,
+        "roofline": roofline,
     }
     print(json.dumps(rec), flush=True)
 

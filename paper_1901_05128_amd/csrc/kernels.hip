@@ -722,7 +722,8 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
         const double r1 = E1 - (L1 * S1 - I.a * S0);
         const double gn0 = (m22 * r0 - m12 * r1) * idet;
         const double gn1 = (m11 * r1 - m21 * r0) * idet;
-        const double up0 = __shfl_up(ring0, 1, LPM), up1 = __shfl_up(ring1, 1, LPM);
+        // levels move up one lane (DPP wave_shr:1; a group's lane 0 takes the new level)
+        const double up0 = dpp_move<0x138, 0xF>(ring0), up1 = dpp_move<0x138, 0xF>(ring1);
         ring0 = (lane == 0) ? gn0 : up0;
         ring1 = (lane == 0) ? gn1 : up1;
     }
