@@ -139,3 +139,34 @@ def test_fast_create_reports_etol_before_device():
     prm = cq.make_params(0.3, 0.7, 0.3, 1.0, 65536, 1, 1, fast_tol=1e-8, np_max=16)
     rc, _ = _create(cq.make_grid(1, 31), prm)
     assert rc == _lib.CQ_ETOL
+
+
+def _adjoint_create(grid, prm):
+    h = C.c_void_p()
+    rc = cq.lib().fp_adjoint_create(C.byref(grid), C.byref(prm), None, C.byref(h))
+    return rc, h
+
+
+def test_adjoint_create_host_checks():
+    """The gradient handle's argument checks come before any device call:
+    the nodal solver, bad parameters and a fast window above 32 levels are
+    rejected with CQ_EINVAL; a singular step operator with CQ_ESINGULAR."""
+    g = cq.make_grid(1, 31)
+    rc, h = _adjoint_create(g, cq.make_params(0.3, 0.7, 0.3, 1.0, 10, 1, 0, solver=cq.SOLVER_NODAL))
+    assert rc == _lib.CQ_EINVAL and not h.value
+    assert "modal" in cq.lib().cq_last_error().decode()
+    rc, h = _adjoint_create(g, cq.make_params(0.0, 0.7, 0.3, 1.0, 10, 1, 0, solver=cq.SOLVER_MODAL))
+    assert rc == _lib.CQ_EINVAL
+    rc, h = _adjoint_create(g, cq.make_params(0.3, 0.7, 0.3, 1.0, 100, 2, 1, np_=16, ns=40,
+                                              solver=cq.SOLVER_MODAL))
+    assert rc == _lib.CQ_EINVAL and "32" in cq.lib().cq_last_error().decode()
+    rc, h = _adjoint_create(cq.make_grid(1, 127), cq.make_params(0.1, 0.1, 0.45, 1.0, 1, 1, 0,
+                                                                 solver=cq.SOLVER_MODAL))
+    assert rc == _lib.CQ_ESINGULAR
+
+
+def test_handle_calls_reject_null():
+    L = cq.lib()
+    assert L.fp_step(None, 1) == _lib.CQ_EINVAL
+    assert L.fp_adjoint_run(None, None, None, None, None, None) == _lib.CQ_EINVAL
+    assert L.fp_destroy(None) == _lib.CQ_OK
