@@ -166,3 +166,23 @@ def test_handle_matches_one_shot_and_is_reusable():
                 assert torch.equal(a0, b0)
                 assert list(ag) == list(bg)
             assert cq.lib().fp_step(h._h, 1) == -1  # CQ_EINVAL: not a stepping solver
+
+
+def test_autograd_wrapper_matches_adjoint():
+    """loss.backward() through paper_1901_05128_amd.autograd.solve gives the
+    gradients fp_adjoint gives for the same cotangent."""
+    from paper_1901_05128_amd import autograd as ag
+    nx = 31
+    G0n = wl.g0_random(nx, 51).reshape(2, nx)
+    tgt = torch.tensor(np.random.default_rng(52).standard_normal((2, nx)), device="cuda")
+    G0 = dev(G0n).requires_grad_()
+    a1 = torch.tensor(0.3, dtype=torch.float64, device="cuda", requires_grad=True)
+    a2 = torch.tensor(0.7, dtype=torch.float64, device="cuda", requires_grad=True)
+    m = torch.tensor(0.35, dtype=torch.float64, device="cuda", requires_grad=True)
+    GN = ag.solve(G0, a1, a2, m, 1, nx, 1, T=1.0, N=80, scheme=2, method=1, np_=12, np1=8, ns=10)
+    loss = 0.5 * ((GN - tgt) ** 2).sum()
+    loss.backward()
+    p = cq.make_params(0.3, 0.7, 0.35, 1.0, 80, 2, 1, np_=12, np1=8, ns=10, solver=cq.SOLVER_MODAL)
+    gG0, grads = cq.fp_adjoint(cq.make_grid(1, nx), p, dev(G0n), (GN - tgt).detach().contiguous())
+    assert torch.equal(G0.grad, gG0)
+    assert [a1.grad.item(), a2.grad.item(), m.grad.item()] == list(grads)
