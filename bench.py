@@ -273,6 +273,9 @@ def bench_adjoint(args):
             f_far += 2 * 64 * n0 * twoM
             b_far += n0 * twoM * 8 + 64 * twoM * 8
         work["far_toeplitz"] = (b_far, f_far)           # the d/dalpha pass
+        # window steps, both sweeps: 2 flops per lag below L, Sf read, level and
+        # S (forward) or mu (adjoint) written
+        work["modal_fast"] = (2 * N * twoM * 8 * 3, 2 * N * twoM * 2 * (L - 1))
         dom = max(ktime, key=lambda k: ktime[k][1])
         if dom in work:
             n_l, ms = ktime[dom]
