@@ -788,43 +788,48 @@ __global__ __launch_bounds__(64) void k_modal_win(ModalWinArgs p) {
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
     const int64_t b0 = p.nfirst - p.nblk;
     const int bt = p.bt;
+    // Prologue loads are unconditional (clamped, valid addresses; at most one
+    // uniform branch around a group) so that they are all in flight at once.
     double acc[BB];
 #pragma unroll
     for (int b = 0; b < BB; ++b) {
-        double v = 0.0;
-        if (b < bt) {
-            v = p.Sf[((b0 + b) * 2 + k) * M + mode];
-            if (!ADJ && p.scheme == 2) v = fma(0.5 * dk[p.nfirst + b - 1], g0k, v);
-            if (ADJ && p.nfirst + b == 1) v -= p.gc[k * M + mode];  // cotangent enters step 1
-        }
-        acc[b] = v;
+        const int64_t r = (b0 + b < p.BT) ? b0 + b : p.BT - 1;  // rows past the block are not used
+        acc[b] = p.Sf[(r * 2 + k) * M + mode];
     }
+    if (!ADJ && p.scheme == 2) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] = fma(0.5 * dk[p.nfirst + b - 1], g0k, acc[b]);
+    }
+    if (ADJ && p.nfirst == 1) acc[0] -= p.gc[k * M + mode];  // cotangent enters step 1
     // window part of the levels l = nfirst-j (j < L, l >= 1) already taken:
-    // all loads first, then the sums
+    // all loads first (an absent level reads level 0, which is finite, times 0),
+    // then the sums
     {
         double old[BB];
         int64_t sl = (p.nfirst - 1) % p.Lr;  // slot of level nfirst-1
 #pragma unroll
         for (int j = 1; j < BB; ++j) {
-            old[j] = (j < p.L && p.nfirst - j >= 1) ? lv[sl * twoM] : 0.0;
+            const bool ok = j < p.L && p.nfirst - j >= 1;
+            old[j] = lv[(ok ? sl : 0) * twoM] * (ok ? 1.0 : 0.0);
             sl = (sl == 0) ? p.Lr - 1 : sl - 1;
         }
 #pragma unroll
         for (int j = 1; j < BB; ++j)
 #pragma unroll
-            for (int b = 0; b + j < BB; ++b)
-                if (b < bt) acc[b] = fma(w[b + j], old[j], acc[b]);
+            for (int b = 0; b + j < BB; ++b) acc[b] = fma(w[b + j], old[j], acc[b]);  // b >= bt unused
     }
     // variables of the time difference: levels (forward; level -1 reads as
-    // level 0) or mu (adjoint; mu[0] = 0 and mu^{-1} = 0)
+    // level 0) or mu (adjoint; row 0 of mu is zero and stands for mu^0 and
+    // mu^{-1}); unconditional loads, like those above
     double gm1, gm2;
+    const int64_t nm2 = (p.nfirst >= 2) ? p.nfirst - 2 : 0;
     if (ADJ) {
         const double* __restrict__ mv = p.mu + k * M + mode;
         gm1 = mv[(p.nfirst - 1) * twoM];
-        gm2 = p.nfirst >= 2 ? mv[(p.nfirst - 2) * twoM] : 0.0;
+        gm2 = mv[nm2 * twoM];
     } else {
         gm1 = lv[((p.nfirst - 1) % p.Lr) * twoM];
-        gm2 = lv[(((p.nfirst >= 2) ? p.nfirst - 2 : 0) % p.Lr) * twoM];
+        gm2 = lv[(nm2 % p.Lr) * twoM];
     }
     const bool bdf2 = p.scheme == 2;
     const double w1 = w[1];
@@ -920,17 +925,21 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
     const int b0 = int(p.nfirst - p.n0 - 1);  // first block offset taken here
     const int bend = b0 + p.bt;               // one past the last
+    // Prologue loads are unconditional within one uniform branch per group
+    // (all B rows of F exist; the weights reach index n0+B-1 < dstride), so
+    // they are all in flight at once; rows outside the launch are not used.
     double acc[BB];
 #pragma unroll
-    for (int b = 0; b < BB; ++b) {
-        double v = 0.0;
-        if (FULL || (b >= b0 && b < bend)) {
-            if (p.n0 >= 1) v = p.F[(int64_t(b) * 2 + k) * M + mode];
-            if (!ADJ && p.scheme == 2) v = fma(0.5 * dk[p.n0 + b], g0k, v);
-            if (ADJ && b == 0 && p.n0 == 0) v -= p.gc[k * M + mode];  // cotangent enters step 1
-        }
-        acc[b] = v;
+    for (int b = 0; b < BB; ++b) acc[b] = 0.0;
+    if (p.n0 >= 1) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] = p.F[(int64_t(b) * 2 + k) * M + mode];
     }
+    if (!ADJ && p.scheme == 2) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] = fma(0.5 * dk[p.n0 + b], g0k, acc[b]);
+    }
+    if (ADJ && p.n0 == 0 && b0 == 0) acc[0] -= p.gc[k * M + mode];  // cotangent enters step 1
     if (!FULL) {
         for (int j = 0; j < b0; ++j) {
             const double g = lv[(p.n0 + 1 + j) * twoM];
@@ -939,11 +948,12 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
                 if (b >= b0 && b > j) acc[b] = fma(w[b - j], g, acc[b]);
         }
     }
-    // variables of the time difference: levels (forward) or mu (adjoint,
-    // mu[0] = 0 and mu^{-1} = 0)
+    // variables of the time difference: levels (forward; level -1 reads as
+    // level 0) or mu (adjoint; row 0 of mu is zero and stands for mu^0 and
+    // mu^{-1})
     const double* __restrict__ ev = ADJ ? p.mu + k * M + mode : lv;
     double gm1 = ev[(p.nfirst - 1) * twoM];
-    double gm2 = (ADJ && p.nfirst < 2) ? 0.0 : ev[((p.nfirst >= 2) ? p.nfirst - 2 : 0) * twoM];
+    double gm2 = ev[((p.nfirst >= 2) ? p.nfirst - 2 : 0) * twoM];
     const bool bdf2 = p.scheme == 2;
     const double w1 = w[1];
     // the most used weights stay in registers, the rest are read from LDS
