@@ -36,8 +36,9 @@ struct HistDirectArgs {
 
 struct FarArgs {
     int64_t n0, M, mchunk, dstride;
-    int64_t nl;            // levels 1..nl enter (nl = n0 for a history; up to n0 + B, with
+    int64_t nl;            // levels l0..nl enter (nl = n0 for a history; up to n0 + B, with
                            // d readable, and zero, down to index n0 + 1 - nl)
+    int64_t l0 = 1;        // first level (slice q covers l0 + q*mchunk ..)
     int64_t lstride;       // elements between time levels (2M for a solver)
     int B, ks, ncomp;      // ncomp components (blockIdx.z), offset M apart
     int reduce;            // also sum the ks partials into slice 0
@@ -116,7 +117,11 @@ struct ModalNearArgs {
     const double* lam;
     const double* d;
     const double* g0;
-    const double* F;      // [B][2][M] reduced far field (n0 >= 1)
+    // far field of the block, the sum of two parts (either may be NULL =
+    // zero): F, rows of a reduced pass over levels 1..n0' (n0' <= n0), and
+    // F2, the levels n0'+1..n0 that pass did not see
+    const double* F;      // [64][2][M] (row stride 2M)
+    const double* F2;     // [64][2][M]
     double* levels;       // [N+1][2][M] coefficients
     // forward: history sums S^n (with BDF2's starting correction) at
     // Sout[n * sstride]; sstride = 0 points every step at one [2][M] scratch row

@@ -154,9 +154,9 @@ __global__ __launch_bounds__(256) void k_reduce_far(double* __restrict__ F, int 
 
 // ---------------------------------------------------------------------------
 // Direct history, far field of one time block (FP64 MFMA):
-//   F[q][b][k][x] = sum_{l in chunk q} d_k[n0+1+b-l] G_k^l[x],  b < B, 1 <= l <= nl
-// (nl = n0 for the history; larger nl reaches into the block, where the
-// caller's weights read as zero at negative lags). A lower-triangular
+//   F[q][b][k][x] = sum_{l in chunk q} d_k[n0+1+b-l] G_k^l[x],  b < B, l0 <= l <= nl
+// (l0 = 1 and nl = n0 for the history; larger nl reaches into the block,
+// where the caller's weights read as zero at negative lags). A lower-triangular
 // Toeplitz block T[b][l] = d[n0+1+b-l] times the stored levels.
 //
 // Workgroup: 4 waves on one 64-wide DOF tile; wave w owns the 16 columns
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
     const int64_t xcol = int64_t(blockIdx.x) * 64 + wave * 16 + li;
     const bool xin = xcol < p.M;
     const int64_t xc = xin ? xcol : 0;
-    const int64_t l_lo = 1 + int64_t(q) * p.mchunk;
+    const int64_t l_lo = p.l0 + int64_t(q) * p.mchunk;
     const int64_t l_hi = (l_lo + p.mchunk < p.nl + 1) ? l_lo + p.mchunk : p.nl + 1;
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
     const double* __restrict__ G = p.levels + int64_t(k) * p.M + xc;
@@ -926,14 +926,19 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
     const int b0 = int(p.nfirst - p.n0 - 1);  // first block offset taken here
     const int bend = b0 + p.bt;               // one past the last
     // Prologue loads are unconditional within one uniform branch per group
-    // (all B rows of F exist; the weights reach index n0+B-1 < dstride), so
-    // they are all in flight at once; rows outside the launch are not used.
+    // (all BB rows of F and F2 exist; the weights reach index n0+B-1 <
+    // dstride), so they are all in flight at once; rows outside the launch
+    // are not used.
     double acc[BB];
 #pragma unroll
     for (int b = 0; b < BB; ++b) acc[b] = 0.0;
-    if (p.n0 >= 1) {
+    if (p.F) {
 #pragma unroll
         for (int b = 0; b < BB; ++b) acc[b] = p.F[(int64_t(b) * 2 + k) * M + mode];
+    }
+    if (p.F2) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] += p.F2[(int64_t(b) * 2 + k) * M + mode];
     }
     if (!ADJ && p.scheme == 2) {
 #pragma unroll

@@ -28,6 +28,7 @@ namespace {
 constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
 constexpr int64_t kModalBlockedMin = 8192;      // modes
 constexpr int64_t kDwPad = 64;                  // zero lags in front of the d/dbeta weights
+constexpr int kModalFarPass = 128;              // modal direct: rows of one far-field pass
 
 // device arrays of a gradient handle (trajectory, history sums, adjoint)
 struct AdjBufs {
@@ -49,6 +50,15 @@ struct Solver {
     // direct
     int B = 0, ks = 1;
     int64_t n0 = 0;
+    // modal direct: one pass over the history serves Bf/B blocks. The pass
+    // of the block n0 starts at far_base = (n0/Bf)*Bf and covers the levels
+    // 1..far_base for the rows far_base+1 .. far_base+Bf (in F); F2 holds the
+    // levels far_base+1..n0 for the block mid_n0. Both depend on n0 alone,
+    // so a resumed run repeats the arithmetic of an uninterrupted one.
+    // -1: not computed.
+    int Bf = 64;
+    int64_t far_base = -1, mid_n0 = -1;
+    double* F2 = nullptr;
     int64_t Lr = 0;
     int64_t dstride = 0;
     std::vector<double> dh[2];
@@ -77,12 +87,18 @@ struct Solver {
     }
 };
 
-// K-split of the far field: about 3072 workgroups (four rounds of the
-// 256 CUs x 3 resident 4-wave groups), at most 32 slices (their sum is
-// read back once per block).
+// K-split of the far field: about 512 workgroups, one round of the 256 CUs
+// with two resident 4-wave groups each (the 128-row pass holds ~236
+// registers per lane), at most 32 slices. More slices add partial sums that
+// are written and read back once per pass; measured, 512 beat 768..3072 on the
+// 1D workload (24.1 against 25.9 ms a solve) and tied on the 2D one.
+#ifndef CQFP_FAR_WORKGROUPS
+#define CQFP_FAR_WORKGROUPS 512
+#endif
 int far_ksplit(int64_t M) {
     const int64_t tiles = 2 * ((M + 63) / 64);
-    return int(std::min<int64_t>(32, std::max<int64_t>(1, (3072 + tiles - 1) / tiles)));
+    const int64_t wg = CQFP_FAR_WORKGROUPS;
+    return int(std::min<int64_t>(32, std::max<int64_t>(1, (wg + tiles - 1) / tiles)));
 }
 
 // slices for one launch: at least 64 levels per slice
@@ -202,7 +218,10 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     // direct block length and K-split (enough workgroups to fill 256 CUs)
     if (p->method == 0) {
         s.B = p->block_B ? p->block_B : (s.dim == 1 ? 64 : 128);
-        if (p->solver == 1) s.B = 64;  // the modal near field keeps a 64-level ring in registers
+        if (p->solver == 1) {  // the modal near field keeps a 64-step block in registers
+            s.B = 64;
+            s.Bf = p->block_B ? p->block_B : kModalFarPass;
+        }
         s.ks = far_ksplit(s.M);
     }
     s.dstride = s.N + 257 + 1;
@@ -396,7 +415,8 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
         if ((rc = upload(s.d_coef, cc))) return rc;
     }
     if (p->method == 0) {
-        if ((rc = dev_alloc(s, &s.F, size_t(int64_t(s.ks) * s.B * twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.F, size_t(int64_t(s.ks) * std::max(s.B, s.Bf) * twoM)))) return rc;
+        if (modal && (rc = dev_alloc(s, &s.F2, size_t(64 * twoM)))) return rc;
     }
     if (modal) {
         if ((rc = setup_tables(s))) return rc;
@@ -465,14 +485,14 @@ int check_finite_g0(const double* G0dev, int64_t count, hipStream_t st, const ch
     return CQ_OK;
 }
 
-void launch_far_block(Solver& s) {
+void launch_far_block(Solver& s, int rows) {
     FarArgs fa{};
     fa.n0 = s.n0;
     fa.nl = s.n0;
     fa.M = s.M;
     fa.dstride = s.dstride;
     fa.lstride = 2 * s.M;
-    fa.B = s.B;
+    fa.B = rows;
     fa.ks = far_ks_for(s.ks, s.n0);
     fa.ncomp = 2;
     int64_t mc = (s.n0 + fa.ks - 1) / fa.ks;
@@ -570,11 +590,35 @@ void modal_steps(Solver& s, int64_t nsteps) {
         }
         return;
     }
+    const int64_t twoM = 2 * s.M;
     while (nsteps > 0) {
         const int64_t n0 = (s.n / s.B) * s.B;  // block of the next step
-        if (s.n == n0) {
-            s.n0 = n0;
-            if (n0 >= 1) launch_far_block(s);
+        const int64_t base = (n0 / s.Bf) * s.Bf;
+        if (s.far_base != base) {
+            // a pass over levels 1..base for the rows base+1 .. base+Bf
+            s.far_base = base;
+            s.n0 = base;
+            if (base >= 1) launch_far_block(s, s.Bf);
+        }
+        if (n0 > base && s.mid_n0 != n0) {
+            // the levels since the pass, base+1 .. n0, for this block
+            s.mid_n0 = n0;
+            FarArgs fa{};
+            fa.n0 = n0;
+            fa.l0 = s.far_base + 1;
+            fa.nl = n0;
+            fa.M = s.M;
+            fa.dstride = s.dstride;
+            fa.lstride = twoM;
+            fa.B = s.B;
+            fa.ks = 1;
+            fa.ncomp = 2;
+            fa.mchunk = ((n0 - s.far_base + 3) / 4) * 4;
+            fa.levels = s.levels;
+            fa.d = s.d_d;
+            fa.F = s.F2;
+            fa.reduce = 0;
+            launch_far(fa, s.st);
         }
         const int bt = int(std::min<int64_t>(n0 + s.B - s.n, nsteps));
         ModalNearArgs a{};
@@ -592,7 +636,8 @@ void modal_steps(Solver& s, int64_t nsteps) {
         a.lam = s.lam;
         a.d = s.d_d;
         a.g0 = s.g0c;
-        a.F = s.F;
+        a.F = s.far_base >= 1 ? s.F + (n0 - s.far_base) * twoM : nullptr;
+        a.F2 = n0 > s.far_base ? s.F2 : nullptr;
         a.levels = s.levels;
         a.Sout = s.Sout ? s.Sout : s.Sscratch;
         a.sstride = s.Sout ? 2 * s.M : 0;
@@ -629,7 +674,7 @@ void step_once(Solver& s) {
     if (s.p.method == 0) {
         if ((n - 1) % s.B == 0) {
             s.n0 = n - 1;
-            if (s.n0 >= 1) launch_far_block(s);
+            if (s.n0 >= 1) launch_far_block(s, s.B);
         }
         HistDirectArgs ha{};
         ha.n = n;
@@ -1003,7 +1048,7 @@ int fp_info(void* handle, cq_info* info) {
     info->max_eps = s.max_eps;
     info->theta[0] = s.theta[0];
     info->theta[1] = s.theta[1];
-    info->block_B = s.p.method == 1 ? s.Bt : s.B;
+    info->block_B = s.p.method == 1 ? s.Bt : (s.p.solver == 1 ? s.Bf : s.B);
     info->ksplit = s.ks;
     info->device_bytes = s.dev_bytes;
     info->state_bytes = state_bytes(s);
@@ -1062,7 +1107,9 @@ int fp_set_state(void* handle, const void* src, size_t bytes) {
     }
     if (s.p.method == 0) {  // far field of the block that contains step n+1
         s.n0 = (n / s.B) * s.B;
-        if (n % s.B != 0 && s.n0 >= 1) launch_far_block(s);
+        s.far_base = -1;  // modal: the next step recomputes its block's far field
+        s.mid_n0 = -1;
+        if (s.p.solver == 0 && n % s.B != 0 && s.n0 >= 1) launch_far_block(s, s.B);
     }
     HIPCHK(hipGetLastError());
     return CQ_OK;
@@ -1078,6 +1125,8 @@ int fp_reset(void* handle, const double* G0) {
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
     s.n = 0;
+    s.far_base = -1;
+    s.mid_n0 = -1;
     s.n0 = 0;
     if (s.p.solver == 1) return modal_start(s);
     HIPCHK(hipMemcpyAsync(s.levels, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
@@ -1122,13 +1171,16 @@ static int adjoint_setup(Solver& s) {
     hipStream_t st = s.st;
     if (p->method == 1 && s.L > 32)
         return fail(CQ_EINVAL, "the adjoint's fast form needs a window of <= 32 levels (ns = %d)", s.L);
-    // the far field of the d/dbeta pass (and of the direct history): blocks of 64
+    // the far field of the d/dbeta pass (and of the direct history): blocks of
+    // 64, direct history passes of Bf rows
     s.B = 64;
+    s.Bf = p->block_B ? p->block_B : kModalFarPass;
     s.ks = far_ksplit(M);
+    const size_t frows = size_t(s.ks) * size_t(std::max(s.B, s.Bf)) * size_t(twoM);
     {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
-        const size_t need = (4 * lev + size_t(s.ks) * 64 * size_t(twoM)) * sizeof(double);
+        const size_t need = (4 * lev + frows + 64 * size_t(twoM)) * sizeof(double);
         if (need > fr)
             return fail(CQ_ENOMEM, "the adjoint keeps 4 x (N+1) x 2M values (%zu bytes); %zu bytes free", need, fr);
     }
@@ -1143,7 +1195,8 @@ static int adjoint_setup(Solver& s) {
     if ((rc = dev_alloc(s, &A.Sx, lev))) return rc;
     if ((rc = dev_alloc(s, &A.psi, lev))) return rc;
     if ((rc = dev_alloc(s, &A.mu, lev))) return rc;
-    if ((rc = dev_alloc(s, &s.F, size_t(s.ks) * 64 * size_t(twoM)))) return rc;
+    if ((rc = dev_alloc(s, &s.F, frows))) return rc;
+    if ((rc = dev_alloc(s, &s.F2, size_t(64) * size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.gc, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.gG0c, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.acc, size_t(twoM)))) return rc;
@@ -1216,6 +1269,8 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     s.mu = nullptr;
     s.gc = nullptr;
     s.n = 0;
+    s.far_base = -1;
+    s.mid_n0 = -1;
     s.n0 = 0;
     modal_steps(s, N);
     if (GN) transform(s, traj + N * twoM, GN, false);
@@ -1231,6 +1286,8 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     s.mu = mu;
     s.gc = gc;
     s.n = 0;
+    s.far_base = -1;
+    s.mid_n0 = -1;
     s.n0 = 0;
     modal_steps(s, N);
 

@@ -125,14 +125,34 @@ def test_direct_block_sizes(block_B):
     assert rel(out, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("block_B", [64, 256], ids=["B64", "B256"])
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_modal_direct_far_passes(block_B, scheme):
+    """Modal direct form with one far-field pass per block_B/64 near blocks
+    (the later blocks of a pass add the levels since the pass separately),
+    over several passes and a ragged last block, against the oracle."""
+    nx, N = 45, 700
+    G0 = wl.g0_random(nx, 31)
+    p = cq.make_params(0.35, 0.65, 0.7, 1.0, N, scheme, 0, block_B=block_B, solver=1)
+    out = cq.fp_solve(cq.make_grid(1, nx), p, dev(G0)).cpu().numpy()
+    ref = modal.reference(1, nx, 1, 0.35, 0.65, 0.7, 1.0, N, G0, scheme, 0)
+    assert rel(out, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("dim", [1, 2])
-@pytest.mark.parametrize("solver", [0, 1], ids=["nodal", "modal"])
-def test_state_roundtrip_is_bitwise(method, dim, solver):
+@pytest.mark.parametrize("solver,block_B,k", [(0, 64, 77), (1, 64, 77), (1, 0, 77), (1, 0, 128), (1, 192, 200)],
+                         ids=["nodal", "modal", "modal-pass128-k77", "modal-pass128-k128", "modal-pass192-k200"])
+def test_state_roundtrip_is_bitwise(method, dim, solver, block_B, k):
+    """Stop after k steps, move the state to a new handle, finish: the levels
+    equal those of one uninterrupted run bit for bit (for the modal direct
+    form also when k falls inside a far-field pass or inside a block)."""
+    if method == 1 and block_B != 64:
+        pytest.skip("block_B only changes the direct form")
     nx, ny = (50, 1) if dim == 1 else (12, 10)
-    N, k = 140, 77
+    N = 260
     G0 = wl.g0_random(nx * ny, 12)
-    g, p = cq.make_grid(dim, nx, ny), cq.make_params(0.3, 0.7, 0.6, 1.0, N, 2, method, block_B=64,
+    g, p = cq.make_grid(dim, nx, ny), cq.make_params(0.3, 0.7, 0.6, 1.0, N, 2, method, block_B=block_B,
                                                      solver=solver)
     with cq.Solver(g, p, dev(G0)) as s:
         s.step(N)
