@@ -42,7 +42,7 @@ def g0_for(w):
     return wl.g0_intervals(nx, seed) if dim == 1 else wl.g0_rectangle(nx, ny, seed)
 
 
-def kernel_work(kind, w, scheme, method, info, M):
+def kernel_work(kind, w, scheme, method, info, M, solver=1):
     """Algorithmic (bytes, flops) summed over the launches of one solve."""
     N = w[8]
     twoM = 2 * M
@@ -62,11 +62,23 @@ def kernel_work(kind, w, scheme, method, info, M):
             f += twoM * 4 * npn * bt
         return b, f
     if kind == "far_toeplitz":
-        B = info.block_B
+        # nodal: one pass per block of B steps over the levels before it.
+        # modal: one pass of Bf rows per Bf steps, and for each later 64-step
+        # block of the pass the levels since the pass. Rows past N are not
+        # counted; bytes = levels read once + rows written once.
+        Bf = info.block_B
+        Bn = 64 if solver == 1 else Bf
         fl, by = 0, 0
-        for n0 in range(B, N, B):
-            fl += 2 * B * n0 * twoM
-            by += n0 * twoM * 8 + B * twoM * 8
+        for n0 in range(Bn, N, Bn):
+            base = (n0 // Bf) * Bf
+            rows_pass = min(Bf, N - n0)
+            if base == n0:
+                fl += 2 * rows_pass * n0 * twoM
+                by += (n0 + rows_pass) * twoM * 8
+            else:
+                rows, lv = min(Bn, N - n0), n0 - base
+                fl += 2 * rows * lv * twoM
+                by += (lv + rows) * twoM * 8
         return by, fl
     if kind == "hist_direct":
         B = info.block_B
@@ -88,7 +100,7 @@ def kernel_work(kind, w, scheme, method, info, M):
         return 0, N * twoM * (4 * npn + 2 * (L - 1))
     if kind == "modal_near":
         # in-block near field (b terms at block offset b) + far-field read + level write
-        B = info.block_B
+        B = 64
         f = 0
         for n in range(1, N + 1):
             f += twoM * 2 * ((n - 1) % B)
@@ -419,7 +431,7 @@ def main():
         tot_b, tot_f = 0, 0
         for v in variants:
             info = solvers[v].info()
-            b, f = kernel_work(dom, w, v[0], v[1], info, M)
+            b, f = kernel_work(dom, w, v[0], v[1], info, M, SOLVERS[args.solver])
             tot_b += b
             tot_f += f
         avg_s = ms / 1e3 / n_l

@@ -55,6 +55,7 @@ class Info(C.Structure):
 class BatchReport(C.Structure):
     _fields_ = [("problems", C.c_int32), ("modes", C.c_int64), ("classes", C.c_int32),
                 ("class_npl64", C.c_int32 * 8), ("class_lanes", C.c_int32 * 8), ("class_problems", C.c_int32 * 8),
+                ("class_blocked", C.c_int32 * 8),
                 ("setup_s", C.c_double), ("autotune_s", C.c_double), ("run_s", C.c_double)]
 
 

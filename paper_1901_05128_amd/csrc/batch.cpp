@@ -70,9 +70,12 @@ void prepare(const cq_grid& g, const cq_params& p, HostProblem& h) {
     const int ns = p.ns ? p.ns : 30, np1 = p.np1 ? p.np1 : 16;
     const int np_max = p.np_max ? p.np_max : 1024;
     const double tol = p.fast_tol > 0 ? p.fast_tol : 1e-8;
+    // weights d_0..d_max(N,64): the kernels read the exact-weight window
+    // (lags < L <= 64) whatever N is
+    const int64_t nd = std::max<int64_t>(h.N, 64);
     for (int k = 0; k < 2; ++k) {
-        h.d[k].assign(size_t(h.N) + 1, 0.0);
-        weights(p.scheme, beta[k], h.tau, h.N, h.d[k].data());
+        h.d[k].assign(size_t(nd) + 1, 0.0);
+        weights(p.scheme, beta[k], h.tau, nd, h.d[k].data());
     }
     int npk[2];
     for (int k = 0; k < 2; ++k) {
@@ -197,7 +200,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
             coef.insert(coef.end(), h.rule[k].coef.begin(), h.rule[k].coef.end());
         }
         I.d_off = int64_t(dd.size());
-        I.dstride = h.N + 1;
+        I.dstride = int64_t(h.d[0].size());
         dd.insert(dd.end(), h.d[0].begin(), h.d[0].end());
         dd.insert(dd.end(), h.d[1].begin(), h.d[1].end());
         I.inv_tau = 1.0 / h.tau;
@@ -243,8 +246,10 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     for (int i = 0; i < count; ++i) cls[npl_tmpl(npl_for(hp[size_t(i)].np, 64), 64)].push_back(i);
     std::vector<int> lists;
     std::vector<int64_t> cums;
+    // lpm: lanes per mode of the per-step kernel (64 or 32), or 0 for the
+    // time-blocked kernel (one wave per mode, needs lags <= 32 and <= 768 nodes)
     struct Launch {
-        int npl64, lpm, count;
+        int npl64, lpm, count, maxnp, minlag;
         int64_t total;
         size_t list_off, cum_off;
         bool lag32;
@@ -258,17 +263,21 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         l.cum_off = cums.size();
         l.lag32 = true;
         int64_t c = 0;
-        int maxnp = 0;
+        int maxnp = 0, minlag = 64;
         for (int i : kv.second) {
             lists.push_back(i);
             cums.push_back(c);
             c += hp[size_t(i)].M;
             l.lag32 = l.lag32 && hp[size_t(i)].L <= 32;
             maxnp = std::max(maxnp, hp[size_t(i)].np);
+            minlag = std::min(minlag, hp[size_t(i)].L);
         }
         cums.push_back(c);
         l.total = c;
-        l.lpm = 64;
+        l.maxnp = maxnp;
+        l.minlag = minlag;
+        // without timing: time-blocked where every lag allows blocks of >= 8 steps
+        l.lpm = (l.lag32 && minlag >= 8 && npl_for(maxnp, 32) <= 24) ? 0 : 64;
         launches.push_back(l);
     }
     int* d_list;
@@ -339,13 +348,19 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     transforms(true);
     BHIP(hipGetLastError());
     const auto t1 = std::chrono::steady_clock::now();
-    // autotune: lanes per mode (64, or 32 when every lag fits) per class, by
-    // timing both on the class's problems truncated to a few steps
+    // nodes per lane of a class's kernel
+    auto npl_of = [](const Launch& l, int lpm) {
+        return lpm == 0 ? npl_for(l.maxnp, 32) : npl_tmpl(npl_for(l.npl64 * 64, lpm), lpm);
+    };
+    // autotune per class: the time-blocked kernel, 64 and 32 lanes per mode
+    // (each where it applies), timed on the class's problems truncated to a
+    // few steps
     double tune_s = 0.0;
     for (Launch& l : launches) {
         const int npl32 = npl_for(l.npl64 * 64, 32);
         const bool can32 = l.lag32 && npl32 <= 16;
-        const std::pair<int, int> key{l.npl64, l.lag32 ? 32 : 64};
+        const bool cantb = l.lag32 && npl_for(l.maxnp, 32) <= 24;
+        const std::pair<int, int> key{l.npl64 * 2048 + l.maxnp, l.lag32 ? l.minlag : 64};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(key);
@@ -354,7 +369,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
                 continue;
             }
         }
-        if (!autotune || !can32) continue;
+        if (!autotune || (!can32 && !cantb)) continue;
         const auto ta = std::chrono::steady_clock::now();
         // short copies of the class's problems (at most 64 steps)
         std::vector<BatchInst> shortI(inst);
@@ -368,12 +383,13 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         if ((rc = buf.alloc(&scratch, size_t(2 * modes)))) return rc;
         a.gN = scratch;
         float best_ms = 1e30f;
-        int best = 64;
+        int best = l.lpm;
         hipEvent_t e0, e1;
         BHIP(hipEventCreate(&e0));
         BHIP(hipEventCreate(&e1));
-        for (int lpm : {64, 32}) {
-            const int npl = npl_tmpl(npl_for(l.npl64 * 64, lpm), lpm);
+        for (int lpm : {0, 64, 32}) {
+            if ((lpm == 0 && !cantb) || (lpm == 32 && !can32)) continue;
+            const int npl = npl_of(l, lpm);
             launch_modal_batch(a, npl, lpm, st);  // warm
             BHIP(hipEventRecord(e0, st));
             launch_modal_batch(a, npl, lpm, st);
@@ -399,10 +415,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     BHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (const Launch& l : launches) {
-        const int npl = npl_tmpl(npl_for(l.npl64 * 64, l.lpm), l.lpm);
-        launch_modal_batch(make_args(l), npl, l.lpm, st);
-    }
+    for (const Launch& l : launches) launch_modal_batch(make_args(l), npl_of(l, l.lpm), l.lpm, st);
     transforms(false);
     hipError_t ce = hipStreamEndCapture(st, &graph);
     if (ce != hipSuccess) return fail(CQ_EHIP, "graph capture: %s", hipGetErrorString(ce));
@@ -424,7 +437,8 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         report->classes = int32_t(std::min<size_t>(launches.size(), 8));
         for (int c = 0; c < report->classes; ++c) {
             report->class_npl64[c] = launches[size_t(c)].npl64;
-            report->class_lanes[c] = launches[size_t(c)].lpm;
+            report->class_lanes[c] = launches[size_t(c)].lpm ? launches[size_t(c)].lpm : 64;
+            report->class_blocked[c] = launches[size_t(c)].lpm == 0 ? 1 : 0;
             report->class_problems[c] = launches[size_t(c)].count;
         }
         report->setup_s = std::chrono::duration<double>(t1 - t0).count();

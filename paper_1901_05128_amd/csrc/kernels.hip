@@ -501,6 +501,15 @@ __device__ __forceinline__ double dpp_move(double v) {
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// DPP move with out-of-range source lanes reading zero (bound_ctrl)
+template <int CTRL>
+__device__ __forceinline__ double dpp_zero(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(int(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 __device__ __forceinline__ double lane_value(double v, int lane) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
@@ -678,59 +687,250 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
     const double dw1 = (lane < L - 1) ? d1p[lane + 1] : 0.0;
     const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
     const double g00 = g0[mode], g01 = g0[M + mode];
-    // ring[i] = g^{n-1-i}; before step 1: g^0 and, for BDF2, g^{-1} := g^0
-    double ring0 = (lane <= 1) ? g00 : 0.0, ring1 = (lane <= 1) ? g01 : 0.0;
+    // the problem's constants in registers (the loop reads no table entry)
+    const int64_t N = I.N;
+    const bool bdf2 = I.scheme == 2;
+    const double inv_tau = I.inv_tau, ca = I.a;
+    // ring[i] = g^{n-1-i} (lane i of the group) at the start of step n
+    double ring0 = (lane == 0) ? g00 : 0.0, ring1 = (lane == 0) ? g01 : 0.0;
+    // g^{n-1} and g^{n-2} (g^{-1} := g^0), the same in every lane of a group
+    double gm10 = g00, gm11 = g01, gm20 = g00, gm21 = g01;
     const double lam = p.lam[I.mode_off + mode];
-    const double L1 = I.a + lam;
+    const double L1 = ca + lam;
     const double m11 = I.c + I.d00 * L1, m22 = I.c + I.d01 * L1;
-    const double m12 = -I.a * I.d01, m21 = -I.a * I.d00;
+    const double m12 = -ca * I.d01, m21 = -ca * I.d00;
     const double idet = 1.0 / (m11 * m22 - m12 * m21);
-    const int base = threadIdx.x & ~(LPM - 1);  // first lane of this group in the wave
-    for (int64_t n = 1; n <= I.N; ++n) {
+    const int src_in = (threadIdx.x & ~(LPM - 1) & 63) + L - 2;  // lane of g^{n+1-L} at step n (L >= 2)
+    // BDF2 starting correction of step n, 1/2 d_{k,n-1} g_k^0; the weight of
+    // the next step is loaded one step ahead
+    double cr0 = bdf2 ? 0.5 * d0p[0] * g00 : 0.0, cr1 = bdf2 ? 0.5 * d1p[0] * g01 : 0.0;
+    double gin0 = 0.0, gin1 = 0.0;  // g^{n-L} (zero while n < L + 1)
+    for (int64_t n = 1; n <= N; ++n) {
+        const int64_t nx = n < N ? n : N;
+        const double dn0 = d0p[nx], dn1 = d1p[nx];
+        // the level entering the state at step n+1 (taken before the shift)
+        const double gnext0 = __shfl(ring0, src_in, 64), gnext1 = __shfl(ring1, src_in, 64);
         double p0 = 0.0, p1 = 0.0;
-        if (n >= L + 1) {
-            const double gin0 = __shfl(ring0, (base & 63) + L - 1, 64);
-            const double gin1 = __shfl(ring1, (base & 63) + L - 1, 64);
 #pragma unroll
-            for (int q = 0; q < NPL; ++q) {
-                h[0][q] = fma(r[0][q], h[0][q], gin0);
-                h[1][q] = fma(r[1][q], h[1][q], gin1);
-                p0 = fma(w[0][q], h[0][q], p0);
-                p1 = fma(w[1][q], h[1][q], p1);
-            }
+        for (int q = 0; q < NPL; ++q) {
+            h[0][q] = fma(r[0][q], h[0][q], gin0);
+            h[1][q] = fma(r[1][q], h[1][q], gin1);
+            p0 = fma(w[0][q], h[0][q], p0);
+            p1 = fma(w[1][q], h[1][q], p1);
         }
-        const int64_t wn = (n - 1 < L - 1) ? n - 1 : L - 1;
-        if (lane < wn) {
-            p0 = fma(dw0, ring0, p0);
-            p1 = fma(dw1, ring1, p1);
-        }
-        double S0 = group_sum<LPM>(p0);
-        double S1 = group_sum<LPM>(p1);
-        const double gm10 = __shfl(ring0, base & 63, 64), gm11 = __shfl(ring1, base & 63, 64);
-        double E0, E1;
-        if (I.scheme == 1) {
-            E0 = gm10 * I.inv_tau;
-            E1 = gm11 * I.inv_tau;
-        } else {
-            const double gm20 = __shfl(ring0, (base & 63) + 1, 64), gm21 = __shfl(ring1, (base & 63) + 1, 64);
-            E0 = (2.0 * gm10 - 0.5 * gm20) * I.inv_tau;
-            E1 = (2.0 * gm11 - 0.5 * gm21) * I.inv_tau;
-            S0 = fma(0.5 * d0p[n - 1], g00, S0);
-            S1 = fma(0.5 * d1p[n - 1], g01, S1);
-        }
-        const double r0 = E0 - (L1 * S0 - I.a * S1);
-        const double r1 = E1 - (L1 * S1 - I.a * S0);
+        // exact-weight window: lags 1..min(L-1, n-1)
+        const bool win = lane < ((n - 1 < L - 1) ? n - 1 : L - 1);
+        p0 = fma(win ? dw0 : 0.0, ring0, p0);
+        p1 = fma(win ? dw1 : 0.0, ring1, p1);
+        const double S0 = group_sum<LPM>(p0) + cr0;
+        const double S1 = group_sum<LPM>(p1) + cr1;
+        const double E0 = (bdf2 ? 2.0 * gm10 - 0.5 * gm20 : gm10) * inv_tau;
+        const double E1 = (bdf2 ? 2.0 * gm11 - 0.5 * gm21 : gm11) * inv_tau;
+        const double r0 = E0 - (L1 * S0 - ca * S1);
+        const double r1 = E1 - (L1 * S1 - ca * S0);
         const double gn0 = (m22 * r0 - m12 * r1) * idet;
         const double gn1 = (m11 * r1 - m21 * r0) * idet;
         // levels move up one lane (DPP wave_shr:1; a group's lane 0 takes the new level)
         const double up0 = dpp_move<0x138, 0xF>(ring0), up1 = dpp_move<0x138, 0xF>(ring1);
         ring0 = (lane == 0) ? gn0 : up0;
         ring1 = (lane == 0) ? gn1 : up1;
+        gm20 = gm10;
+        gm21 = gm11;
+        gm10 = gn0;
+        gm11 = gn1;
+        const bool enter = n + 1 >= L + 1;
+        gin0 = enter ? gnext0 : 0.0;
+        gin1 = enter ? gnext1 : 0.0;
+        cr0 = bdf2 ? 0.5 * dn0 * g00 : 0.0;
+        cr1 = bdf2 ? 0.5 * dn1 * g01 : 0.0;
     }
     if (lane == 0) {
         double* gN = p.gN + 2 * I.mode_off;
         gN[mode] = ring0;
         gN[M + mode] = ring1;
+    }
+}
+
+// Batched fast solve, time-blocked: one wave per mode, lanes 0..31 hold
+// component 0 and lanes 32..63 component 1 (lane l: component k = l/32,
+// position t = l%32). The steps go in blocks of bt <= L (the lag): the
+// levels entering the compressed state at steps n0+1..n0+bt are
+// g^{n0+1-L}..g^{n0+bt-L}, all known when the block starts, so
+//  (A) the state advances over the whole block first: each lane owns the
+//      nodes t + 32q of its component (NP nodes), and per step it adds its
+//      part of sum_j w_j h_j into a[] (no cross-lane work per step);
+//  (B) the partial sums of 8 steps are summed over the 32 lanes of a
+//      component by recursive halving (pairs by DPP row_half_mirror and
+//      quad_perm; each stage keeps half of the values and adds the
+//      partner's copy of that half; then the lanes t^8 and t^16, which hold
+//      the same step, are added in), which leaves step t's fast part in
+//      lane t of its component;
+//  (C) the window (exact weights, lags 1..L-1) and the 2x2 solve then run
+//      step by step in push form with lane t owning step n0+1+t: the levels
+//      before the block are pushed first, and each new level is pushed into
+//      the later steps' sums, so a step reads its sum (readlane), solves, and
+//      adds one FMA per lane.
+// lv: lane 32k+t holds g_k^{n0-t} (zero for levels < 1); wc: lane 32k+t holds
+// d_{k,t-b} at step b (zero outside lags 1..L-1); lvnew: lane 32k+b holds
+// the block's level of step b. Needs 2 <= L <= 32 and np <= 32*NP.
+template <int NP>
+__global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t group = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (group >= p.total) return;  // uniform per wave
+    int lo = 0, hi = p.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.cum[mid] <= group) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst& I = p.inst[p.list[lo]];
+    const int64_t mode = group - p.cum[lo];
+    const int64_t M = I.M, N = I.N;
+    const int np = I.np, L = I.L;
+    const int k = lane >> 5, t = lane & 31;
+    const bool hi_half = k != 0;
+    const double* __restrict__ ratio = p.ratio + I.rule_off + k * np;
+    const double* __restrict__ coef = p.coef + I.rule_off + k * np;
+    const double* __restrict__ dk = p.d + I.d_off + k * I.dstride;
+    double r[NP], w[NP], h[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int j = t + 32 * q;
+        const bool ok = j < np;
+        r[q] = ok ? ratio[j] : 0.0;
+        w[q] = ok ? coef[j] : 0.0;
+        h[q] = 0.0;
+    }
+    // window weights of this lane: d_{k,t} for 1 <= t < L (lag t of step t from the block's first level)
+    const double dwin = (t >= 1 && t < L) ? dk[t] : 0.0;
+    const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
+    const double g00 = g0[mode], g01 = g0[M + mode];
+    const double g0k = hi_half ? g01 : g00;
+    const bool bdf2 = I.scheme == 2;
+    const double inv_tau = I.inv_tau, ca = I.a;
+    const double lam = p.lam[I.mode_off + mode];
+    const double L1 = ca + lam;
+    const double m11 = I.c + I.d00 * L1, m22 = I.c + I.d01 * L1;
+    const double m12 = -ca * I.d01, m21 = -ca * I.d00;
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
+    // g = Minv (E - D S), D = [[L1, -a], [-a, L1]]: coefficients of S
+    const double s00 = ca * i01 - L1 * i00, s01 = ca * i00 - L1 * i01;
+    const double s10 = ca * i11 - L1 * i10, s11 = ca * i10 - L1 * i11;
+    // E = e1 g^{n-1} + e2 g^{n-2} (BE: g^{n-1}/tau; BDF2: (2 g^{n-1} - g^{n-2}/2)/tau)
+    const double e1 = (bdf2 ? 2.0 : 1.0) * inv_tau, e2 = (bdf2 ? -0.5 : 0.0) * inv_tau;
+    double P0 = fma(i01, g01, i00 * g00), P1 = fma(i11, g01, i10 * g00);  // Minv g^{n-1}
+    double R0 = P0, R1 = P1;                                              // Minv g^{n-2}, g^{-1} := g^0
+    double gl0 = g00, gl1 = g01;                                          // newest level
+    double lv = 0.0;                                   // no level >= 1 yet
+    const int src0 = (lane & 32) + L - 1;              // lane of g_k^{n0+1-L} in lv
+    for (int64_t n0 = 0; n0 < N; n0 += L) {
+        const int bt = int((N - n0 < L) ? N - n0 : L);
+        double acc = 0.0;
+        // (A) + (B): the fast part, 8 steps at a time
+#pragma unroll 1
+        for (int b0 = 0; b0 < bt; b0 += 8) {
+            // a[pos(j)]: pos swaps bits 0 and 1 of j (the halving below
+            // leaves value pos(t%8) in lane t)
+            double a[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int b = b0 + j;
+                const int pj = (j & 4) | ((j & 1) << 1) | ((j >> 1) & 1);
+                const double gin = __shfl(lv, b < L ? src0 - b : 0, 64);
+                double s = 0.0;
+                if (b < bt) {  // uniform
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) {
+                        h[q] = fma(r[q], h[q], gin);
+                        s = fma(w[q], h[q], s);
+                    }
+                }
+                a[pj] = s;
+            }
+            // halving: row_half_mirror (side bit 2), quad_perm [1,0,3,2]
+            // (bit 0), quad_perm [2,3,0,1] (bit 1); then lanes t^8 and t^16
+            // hold the same value and are added in
+            {
+                const bool sd = (lane >> 2) & 1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double keep = sd ? a[4 + i] : a[i], send = sd ? a[i] : a[4 + i];
+                    a[i] = keep + dpp_move<0x141, 0xF>(send);
+                }
+            }
+            {
+                const bool sd = lane & 1;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const double keep = sd ? a[2 + i] : a[i], send = sd ? a[i] : a[2 + i];
+                    a[i] = keep + dpp_move<0xB1, 0xF>(send);
+                }
+            }
+            double v;
+            {
+                const bool sd = (lane >> 1) & 1;
+                const double keep = sd ? a[1] : a[0], send = sd ? a[0] : a[1];
+                v = keep + dpp_move<0x4E, 0xF>(send);
+            }
+            v += __shfl_xor(v, 8, 64);
+            v += __shfl_xor(v, 16, 64);
+            if ((t >> 3) == (b0 >> 3)) acc = v;
+        }
+        // BDF2 starting correction 1/2 d_{k,n-1} g_k^0 of step n = n0+1+t
+        if (bdf2) {
+            const int64_t ix = (n0 + t <= N) ? n0 + t : N;
+            acc = fma(0.5 * dk[ix], g0k, acc);
+        }
+        // (C) window part of the levels before the block: level n0-u reaches
+        // step n0+1+t at lag t+1+u (groups of 8 levels; the weights of lags
+        // >= L are zero, so the last group may run past L-1)
+        {
+            double wl = dpp_zero<0x130>(dwin);  // wave_shl:1, lane t: d_{k,t+1}
+            wl = (t == 31) ? 0.0 : wl;
+            for (int u0 = 0; u0 + 1 < L; u0 += 8) {
+#pragma unroll
+                for (int u = u0; u < u0 + 8; ++u) {
+                    const double g = __shfl(lv, (lane & 32) + (u & 31), 64);
+                    acc = fma(wl, g, acc);
+                    const double nx = dpp_zero<0x130>(wl);
+                    wl = (t == 31) ? 0.0 : nx;
+                }
+            }
+        }
+        // (C) the steps of the block. With Minv the inverse of the step
+        // matrix, g^n = Minv (E - D S): the E part is e1 P + e2 R with P =
+        // Minv g^{n-1} and R = Minv g^{n-2}, the S part s.S, so a step
+        // waits on its sum and two FMAs.
+        double wc = dwin, lvnew = 0.0;
+        for (int b = 0; b < bt; ++b) {
+            const double S0 = lane_value(acc, b), S1 = lane_value(acc, 32 + b);
+            const double E0 = fma(e1, P0, e2 * R0), E1 = fma(e1, P1, e2 * R1);
+            const double gn0 = fma(s01, S1, fma(s00, S0, E0));
+            const double gn1 = fma(s11, S1, fma(s10, S0, E1));
+            const double gk = hi_half ? gn1 : gn0;
+            acc = fma(wc, gk, acc);
+            const double wsh = dpp_zero<0x138>(wc);  // wave_shr:1
+            wc = (t == 0) ? 0.0 : wsh;
+            lvnew = (t == b) ? gk : lvnew;
+            R0 = P0;
+            R1 = P1;
+            P0 = fma(i01, gn1, i00 * gn0);
+            P1 = fma(i11, gn1, i10 * gn0);
+            gl0 = gn0;
+            gl1 = gn1;
+        }
+        // level store for the next block: lane 32k+t <- g_k^{n0+bt-t}
+        {
+            const double fresh = __shfl(lvnew, (lane & 32) + ((bt - 1 - t) & 31), 64);
+            const double older = __shfl(lv, (lane & 32) + ((t - bt) & 31), 64);
+            lv = (t < bt) ? fresh : older;
+        }
+    }
+    if (lane == 0) {
+        double* gN = p.gN + 2 * I.mode_off;
+        gN[mode] = gl0;
+        gN[M + mode] = gl1;
     }
 }
 
@@ -1321,6 +1521,20 @@ void launch_modal_fast(const ModalFastArgs& a, hipStream_t st) {
 }
 
 void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st) {
+    if (lpm == 0) {  // time-blocked, one wave per mode; npl = nodes per lane over 32 lanes
+        const dim3 grid(unsigned((a.total + 3) / 4));
+#define CQ_BATCH_TB(NP) hipLaunchKernelGGL((k_modal_batch_tb<NP>), grid, dim3(256), 0, st, a)
+        prof_begin(9, st);
+        if (npl <= 4) CQ_BATCH_TB(4);
+        else if (npl <= 8) CQ_BATCH_TB(8);
+        else if (npl <= 12) CQ_BATCH_TB(12);
+        else if (npl <= 16) CQ_BATCH_TB(16);
+        else if (npl <= 20) CQ_BATCH_TB(20);
+        else CQ_BATCH_TB(24);
+        prof_end(9, st);
+#undef CQ_BATCH_TB
+        return;
+    }
     const int64_t threads = a.total * lpm;
     const dim3 grid(unsigned((threads + 255) / 256));
 #define CQ_BATCH(NP, LP) hipLaunchKernelGGL((k_modal_batch<NP, LP>), grid, dim3(256), 0, st, a)

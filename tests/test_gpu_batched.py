@@ -83,6 +83,33 @@ def test_batched_equals_single_solves_and_tiles_agree():
     assert all(x == 64 for x in list(rep_b.class_lanes)[:rep_b.classes]) or rep_b.autotune_s == 0.0
 
 
+@pytest.mark.parametrize("np_", [None, 200, 380, 500, 700])
+def test_time_blocked_kernel(np_):
+    """BDF2 problems (lag 30) without autotuning take the time-blocked kernel:
+    blocks of 30 steps, a ragged last block, runs shorter than one block or
+    one half-block, and node counts up to 768 (every register class of the
+    kernel), against the oracle and against single modal solves."""
+    rng = np.random.default_rng(17)
+    probs = []
+    for N in (7, 16, 29, 31, 45, 61, 90, 151):
+        dim, nx, ny = (1, int(rng.choice([31, 63])), 1) if N % 2 else (2, 9, 11)
+        a1, a2 = (float(v) for v in rng.uniform(0.1, 0.9, size=2))
+        m = float(rng.uniform(0.55, 0.95))
+        probs.append((dim, nx, ny, a1, a2, m, 1.0, N, 2, np_ or max(8, int(math.ceil(3 * math.sqrt(N))))))
+    outs, g0s, rep = _run(probs, autotune=False, seed=300)
+    print(f"batch classes={rep.classes} blocked={list(rep.class_blocked)[:rep.classes]}", flush=True)
+    assert all(x == 1 for x in list(rep.class_blocked)[:rep.classes])
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, npn), out, g0 in zip(probs, outs, g0s):
+        single = cq.fp_solve(cq.make_grid(dim, nx, ny),
+                             cq.make_params(a1, a2, m, T, N, scheme, 1, np_=npn, solver=cq.SOLVER_MODAL),
+                             torch.tensor(g0, device="cuda")).cpu().numpy()
+        ref = modal.reference(dim, nx, ny, a1, a2, m, T, N, g0, scheme, 1, np_=npn, np1=16, ns=30)
+        e1, e2 = rel(out, single), rel(out, ref)
+        print(f"  {dim}d {nx}x{ny} N={N} np={npn}: vs single {e1:.2e} vs oracle {e2:.2e}", flush=True)
+        assert e1 <= 1e-13
+        assert e2 <= 1e-11
+
+
 def test_batched_rejects_direct_method_and_bad_lag():
     g = [cq.make_grid(1, 15)]
     G0 = [torch.zeros((2, 15), dtype=torch.float64, device="cuda")]
