@@ -371,9 +371,10 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         }
         if (!autotune || (!can32 && !cantb)) continue;
         const auto ta = std::chrono::steady_clock::now();
-        // short copies of the class's problems (at most 64 steps)
+        // short copies of the class's problems (at most 256 steps: long enough
+        // for the time-blocked kernel to pass its first blocks)
         std::vector<BatchInst> shortI(inst);
-        for (auto& I : shortI) I.N = std::min<int64_t>(I.N, 64);
+        for (auto& I : shortI) I.N = std::min<int64_t>(I.N, 256);
         BatchInst* d_short;
         if ((rc = buf.alloc(&d_short, shortI.size()))) return rc;
         BHIP(hipMemcpy(d_short, shortI.data(), shortI.size() * sizeof(BatchInst), hipMemcpyHostToDevice));

@@ -12,6 +12,8 @@
 // fast form).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cstdint>
 
 #include "kernels.h"
@@ -827,22 +829,27 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
     for (int64_t n0 = 0; n0 < N; n0 += L) {
         const int bt = int((N - n0 < L) ? N - n0 : L);
         double acc = 0.0;
-        // (A) + (B): the fast part, 8 steps at a time
-#pragma unroll 1
-        for (int b0 = 0; b0 < bt; b0 += 8) {
+        // (A) + (B): the fast part, 8 steps at a time; a full pass has no
+        // per-step branch, so its eight level loads are all in flight first
+        auto pass = [&](auto full_t, int b0) {
+            constexpr bool FULLP = decltype(full_t)::value;
+            double gin[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int b = b0 + j;
+                gin[j] = __shfl(lv, b < L ? src0 - b : 0, 64);
+            }
             // a[pos(j)]: pos swaps bits 0 and 1 of j (the halving below
             // leaves value pos(t%8) in lane t)
             double a[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const int b = b0 + j;
                 const int pj = (j & 4) | ((j & 1) << 1) | ((j >> 1) & 1);
-                const double gin = __shfl(lv, b < L ? src0 - b : 0, 64);
                 double s = 0.0;
-                if (b < bt) {  // uniform
+                if (FULLP || b0 + j < bt) {  // uniform
 #pragma unroll
                     for (int q = 0; q < NP; ++q) {
-                        h[q] = fma(r[q], h[q], gin);
+                        h[q] = fma(r[q], h[q], gin[j]);
                         s = fma(w[q], h[q], s);
                     }
                 }
@@ -876,6 +883,13 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
             v += __shfl_xor(v, 8, 64);
             v += __shfl_xor(v, 16, 64);
             if ((t >> 3) == (b0 >> 3)) acc = v;
+        };
+#pragma unroll 1
+        for (int b0 = 0; b0 < bt; b0 += 8) {
+            if (b0 + 8 <= bt)
+                pass(std::true_type{}, b0);
+            else
+                pass(std::false_type{}, b0);
         }
         // BDF2 starting correction 1/2 d_{k,n-1} g_k^0 of step n = n0+1+t
         if (bdf2) {
@@ -889,10 +903,12 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
             double wl = dpp_zero<0x130>(dwin);  // wave_shl:1, lane t: d_{k,t+1}
             wl = (t == 31) ? 0.0 : wl;
             for (int u0 = 0; u0 + 1 < L; u0 += 8) {
+                double g[8];
 #pragma unroll
-                for (int u = u0; u < u0 + 8; ++u) {
-                    const double g = __shfl(lv, (lane & 32) + (u & 31), 64);
-                    acc = fma(wl, g, acc);
+                for (int u = 0; u < 8; ++u) g[u] = __shfl(lv, (lane & 32) + ((u0 + u) & 31), 64);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    acc = fma(wl, g[u], acc);
                     const double nx = dpp_zero<0x130>(wl);
                     wl = (t == 31) ? 0.0 : nx;
                 }
