@@ -280,11 +280,15 @@ def bench_adjoint(args):
             b_h += twoM * 8 * (2 * npn + 2 * bt)
             f_h += twoM * 4 * npn * bt
         work["hist_fast"] = (2 * b_h, 2 * f_h)          # forward and adjoint sweeps
-        f_far, b_far = 0, 0
-        for n0 in range(64, N, 64):
-            f_far += 2 * 64 * n0 * twoM
-            b_far += n0 * twoM * 8 + 64 * twoM * 8
-        work["far_toeplitz"] = (b_far, f_far)           # the d/dalpha pass
+        # the d/dalpha pass: Y^n = sum_{l=1}^{n} dw_{n-l} g^l for every step
+        # (2n flops per mode and component), in passes of 128 steps that read
+        # the levels 1..n0+bt once and write bt rows
+        f_far = sum(2 * n * twoM for n in range(1, N + 1))
+        b_far = 0
+        for n0 in range(0, N, 128):
+            bt = min(128, N - n0)
+            b_far += (n0 + bt) * twoM * 8 + bt * twoM * 8
+        work["far_toeplitz"] = (b_far, f_far)
         # window steps, both sweeps: 2 flops per lag below L, Sf read, level and
         # S (forward) or mu (adjoint) written
         work["modal_fast"] = (2 * N * twoM * 8 * 3, 2 * N * twoM * 2 * (L - 1))

@@ -27,7 +27,7 @@ namespace {
 
 constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
 constexpr int64_t kModalBlockedMin = 8192;      // modes
-constexpr int64_t kDwPad = 64;                  // zero lags in front of the d/dbeta weights
+constexpr int64_t kDwPad = 256;                 // zero lags in front of the d/dbeta weights (>= pass rows)
 constexpr int kModalFarPass = 128;              // modal direct: rows of one far-field pass
 
 // device arrays of a gradient handle (trajectory, history sums, adjoint)
@@ -1313,18 +1313,19 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     transform(s, gG0c, gG0, true);  // dl/dG0 = P^T dl/dg^0, P = scaled S, symmetric
     launch_adj_da(ga, st);
     HIPCHK(hipMemsetAsync(acc, 0, size_t(twoM) * sizeof(double), st));
-    for (int64_t n0 = 0; n0 < N; n0 += 64) {
-        const int bt = int(std::min<int64_t>(64, N - n0));
+    for (int64_t n0 = 0; n0 < N; n0 += s.Bf) {
+        const int bt = int(std::min<int64_t>(s.Bf, N - n0));
         // CQ sums of the weight derivatives over levels 1..n for the block's
-        // steps: one Toeplitz product over levels 1..n0+bt (negative lags
-        // read the zero padding in front of each component's row)
+        // steps (blocks of Bf <= kDwPad): one Toeplitz product over levels
+        // 1..n0+bt (negative lags read the zero padding in front of each
+        // component's row)
         FarArgs fa{};
         fa.n0 = n0;
         fa.nl = n0 + bt;
         fa.M = M;
         fa.dstride = s.dstride + kDwPad;
         fa.lstride = twoM;
-        fa.B = 64;
+        fa.B = s.Bf;
         fa.ks = far_ks_for(s.ks, fa.nl);
         fa.ncomp = 2;
         const int64_t mc = (fa.nl + fa.ks - 1) / fa.ks;
