@@ -13,15 +13,16 @@ struct HistBlockArgs {
     int64_t Lr;           // slots in the level store (>= L)
     int64_t M;            // nodes per component
     int np;               // fast nodes per component
-    int chunk;            // nodes per blockIdx.y slice
+    int chunk;            // nodes per lane of a DOF's lane group
     int BT;               // template block length (>= bt)
     int bt;               // steps in this block (<= L)
     int64_t slot0;        // slot of level n - L: (n - L) mod Lr, in [0, Lr)
     const double* levels; // [Lr][2][M]
-    double* H;            // [2][np][M]
+    double* H;            // [2][np][hstride]
+    int64_t hstride;      // >= M rounded up to 256 (every lane of the pass has a slot)
     const double* ratio;  // [2][np]
     const double* coef;   // [2][np]
-    double* Sf;           // [nsplit][BT][2][M]
+    double* Sf;           // [BT][2][M]
 };
 
 struct HistDirectArgs {
@@ -52,10 +53,9 @@ struct StepArgs {
     int64_t n, M, Lr;
     int64_t slot1, slot2, slot_out;  // slots of levels n-1, max(n-2,0) and n
     int scheme;
-    // history: S' = sum_c Sp[c*pstride + boff + k*M + x] + sum_{i<=win} d_i G^{n-i} + corr_k G0
+    // history: S' = Sp[boff + k*M + x] + sum_{i<=win} d_i G^{n-i} + corr_k G0
     const double* Sp;
-    int nsplit;
-    int64_t pstride, boff;
+    int64_t boff;
     int win;
     const double* d;      // [2][dstride]
     int64_t dstride;
@@ -103,7 +103,8 @@ struct ModalFastArgs {
     const double* coef;   // [2][np]
     const double* d;      // [2][dstride]
     const double* g0;     // [2][M] sine coefficients of G^0
-    double* H;            // [2][np][M]
+    double* H;            // [2][np][hstride]
+    int64_t hstride;      // >= M rounded up to 256 (every lane of the pass has a slot)
     double* ring;         // [L][2][M], ring[i] = g^{n-1-i}
 };
 
@@ -140,7 +141,7 @@ struct ModalWinArgs {
     int bt;               // steps taken here (within that block)
     int L;                // lag (<= 32)
     int64_t Lr;           // slots of the level store (= L)
-    int nsplit, BT;       // Sf[nsplit][BT][2][M], read from slice 0 (summed over the slices)
+    int BT;               // Sf[BT][2][M]
     int scheme;
     int64_t dstride;
     double inv_tau, c, a;
@@ -221,11 +222,10 @@ int launch_adj_da(const AdjGradArgs& a, hipStream_t st);
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st);
 // out[k] = sum_x acc[k][x] over blocks: partials [2][blocks]; returns blocks
 int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st);
-void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st);
+void launch_hist_block(const HistBlockArgs& a, int lanes, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);
 // F[0][e] = sum_q F[q][e], e < per (q < ks slices, per apart)
-void launch_reduce_slices(double* F, int ks, int64_t per, hipStream_t st);
 // out[x] = sum_q F[q][0][0][x] (one history row of a single component)
 void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st);
 void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st);

@@ -26,6 +26,33 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Cross-lane sums with DPP (no LDS round trip): a double moved by a DPP
+// pattern on each 32-bit half; lanes a pattern does not write (rows outside
+// row_mask) read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// DPP move with out-of-range source lanes reading zero (bound_ctrl)
+template <int CTRL>
+__device__ __forceinline__ double dpp_zero(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(int(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // ---------------------------------------------------------------------------
 // Fast history (3.10)/(3.18), time-blocked. For lag L the state
 //   H_j(m) = sum_{l=1}^{m-L} r_j^(m-L-l) G^l,   H_j(m) = r_j H_j(m-1) + G^{m-L},
@@ -34,30 +61,38 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 // (BT <= L) every level it needs is known before step n is solved. One pass
 // over the state therefore advances it by BT steps and emits S_f for all of
 // them: the state (the bulk of the bytes) is read and written once per BT
-// steps instead of once per step. blockIdx.z = component, blockIdx.y = slice
-// of the nodes (partial sums), one DOF per thread; H is [2][np][M] so a wave
-// streams 64 consecutive DOFs of one node; r_j and coef_j are wave-uniform.
-// Output Sf[slice][b][k][x].
-template <int BT>
+// steps instead of once per step. blockIdx.z = component. When the DOFs
+// alone cannot fill the GPU, S waves of a workgroup share one 64-DOF tile,
+// wave s taking the node slice [s*chunk, (s+1)*chunk); their partial sums
+// meet in LDS and the slice-0 wave adds them in slice order and stores.
+// One DOF per lane; H is [2][np][M], so a wave streams 64 consecutive DOFs
+// of one node, and r_j and coef_j are wave-uniform. Output Sf[b][k][x].
+template <int BT, int S>
 __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
+    constexpr int TILES = 4 / S;  // 64-DOF tiles per workgroup
+    __shared__ double red[S > 1 ? (S - 1) * TILES * BT * 64 : 1];
     const int k = blockIdx.z;
-    const int c = blockIdx.y;
-    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (x >= p.M) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = wave % S, tile = wave / S;
+    const int64_t x = (int64_t(blockIdx.x) * TILES + tile) * 64 + lane;
+    const bool xin = x < p.M;
+    const int64_t xc = xin ? x : p.M - 1;  // levels of a valid DOF for the padding lanes
     const int64_t twoM = 2 * p.M;
-    const double* __restrict__ lv = p.levels + int64_t(k) * p.M + x;
+    const double* __restrict__ lv = p.levels + int64_t(k) * p.M + xc;
     double g[BT], acc[BT];
 #pragma unroll
     for (int b = 0; b < BT; ++b) {
         const int64_t l = p.n + b - p.L;  // level entering the state at step n+b
-        int64_t sl = p.slot0 + b;         // its slot: (n - L + b) mod Lr
-        if (sl >= p.Lr) sl -= p.Lr;
-        g[b] = (b < p.bt && l >= 1) ? lv[sl * twoM] : 0.0;
+        int64_t slot = p.slot0 + b;       // its slot: (n - L + b) mod Lr
+        if (slot >= p.Lr) slot -= p.Lr;
+        g[b] = (b < p.bt && l >= 1) ? lv[slot * twoM] : 0.0;
         acc[b] = 0.0;
     }
-    const int j0 = c * p.chunk;
+    const int j0 = __builtin_amdgcn_readfirstlane(sl * p.chunk);  // wave-uniform
     const int j1 = (j0 + p.chunk < p.np) ? j0 + p.chunk : p.np;
-    double* __restrict__ h = p.H + (int64_t(k) * p.np) * p.M + x;
+    // state rows are hstride (a multiple of 256) long: every lane owns a slot
+    const int64_t hs = p.hstride;
+    double* __restrict__ h = p.H + (int64_t(k) * p.np) * hs + x;
     const double* __restrict__ r = p.ratio + k * p.np;
     const double* __restrict__ w = p.coef + k * p.np;
     int j = j0;
@@ -66,19 +101,19 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
     // is in flight while the previous one is used
     double hn0 = 0.0, hn1 = 0.0, hn2 = 0.0, hn3 = 0.0;
     if (j + 4 <= j1) {
-        hn0 = __builtin_nontemporal_load(h + int64_t(j) * p.M);
-        hn1 = __builtin_nontemporal_load(h + int64_t(j + 1) * p.M);
-        hn2 = __builtin_nontemporal_load(h + int64_t(j + 2) * p.M);
-        hn3 = __builtin_nontemporal_load(h + int64_t(j + 3) * p.M);
+        hn0 = __builtin_nontemporal_load(h + int64_t(j) * hs);
+        hn1 = __builtin_nontemporal_load(h + int64_t(j + 1) * hs);
+        hn2 = __builtin_nontemporal_load(h + int64_t(j + 2) * hs);
+        hn3 = __builtin_nontemporal_load(h + int64_t(j + 3) * hs);
     }
 #pragma unroll 1
     for (; j + 4 <= j1; j += 4) {
         double h0 = hn0, h1 = hn1, h2 = hn2, h3 = hn3;
         if (j + 8 <= j1) {
-            hn0 = __builtin_nontemporal_load(h + int64_t(j + 4) * p.M);
-            hn1 = __builtin_nontemporal_load(h + int64_t(j + 5) * p.M);
-            hn2 = __builtin_nontemporal_load(h + int64_t(j + 6) * p.M);
-            hn3 = __builtin_nontemporal_load(h + int64_t(j + 7) * p.M);
+            hn0 = __builtin_nontemporal_load(h + int64_t(j + 4) * hs);
+            hn1 = __builtin_nontemporal_load(h + int64_t(j + 5) * hs);
+            hn2 = __builtin_nontemporal_load(h + int64_t(j + 6) * hs);
+            hn3 = __builtin_nontemporal_load(h + int64_t(j + 7) * hs);
         }
         const double r0 = r[j], r1 = r[j + 1], r2 = r[j + 2], r3 = r[j + 3];
         const double w0 = w[j], w1 = w[j + 1], w2 = w[j + 2], w3 = w[j + 3];
@@ -95,13 +130,13 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
                 acc[b] = fma(w3, h3, acc[b]);
             }
         }
-        __builtin_nontemporal_store(h0, h + int64_t(j) * p.M);
-        __builtin_nontemporal_store(h1, h + int64_t(j + 1) * p.M);
-        __builtin_nontemporal_store(h2, h + int64_t(j + 2) * p.M);
-        __builtin_nontemporal_store(h3, h + int64_t(j + 3) * p.M);
+        __builtin_nontemporal_store(h0, h + int64_t(j) * hs);
+        __builtin_nontemporal_store(h1, h + int64_t(j + 1) * hs);
+        __builtin_nontemporal_store(h2, h + int64_t(j + 2) * hs);
+        __builtin_nontemporal_store(h3, h + int64_t(j + 3) * hs);
     }
     for (; j < j1; ++j) {
-        double h0 = h[int64_t(j) * p.M];
+        double h0 = h[int64_t(j) * hs];
         const double r0 = r[j], w0 = w[j];
 #pragma unroll
         for (int b = 0; b < BT; ++b) {
@@ -110,11 +145,25 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
                 acc[b] = fma(w0, h0, acc[b]);
             }
         }
-        h[int64_t(j) * p.M] = h0;
+        h[int64_t(j) * hs] = h0;
     }
+    if (S > 1) {
+        double* __restrict__ mine = red + int64_t(tile * (S - 1)) * BT * 64 + lane;
+        if (sl > 0) {
+#pragma unroll
+            for (int b = 0; b < BT; ++b) mine[((sl - 1) * BT + b) * 64] = acc[b];
+        }
+        __syncthreads();
+        if (sl > 0) return;
+#pragma unroll 1
+        for (int q = 0; q < S - 1; ++q)
+#pragma unroll
+            for (int b = 0; b < BT; ++b) acc[b] += mine[(q * BT + b) * 64];
+    }
+    if (!xin) return;
 #pragma unroll
     for (int b = 0; b < BT; ++b)
-        if (b < p.bt) p.Sf[((int64_t(c) * BT + b) * 2 + k) * p.M + x] = acc[b];
+        if (b < p.bt) p.Sf[(int64_t(b) * 2 + k) * p.M + x] = acc[b];
 }
 
 // ---------------------------------------------------------------------------
@@ -268,15 +317,14 @@ __device__ __forceinline__ void dd_add(double& hi, double& lo, double x) {
     lo += e;
 }
 
-// History sum of step n at node x of component k, from the partial sums
+// History sum of step n at node x of component k, from the partial sum
 // (fast: Sf of this step's block; direct: the near/far kernel's output) plus
 // the exact-weight window sum_{i=1}^{win} d_i G^{n-i} (win <= 31; the loads
 // are issued before the sum) plus the BDF2 correction d_{n-1}/2 G^0.
 // Returns S'. Level n-i sits at slot s1 - (i-1) (mod Lr).
 __device__ __forceinline__ double history_at(const StepArgs& p, int k, int64_t x) {
     const int64_t M = p.M;
-    double s = 0.0;
-    for (int c = 0; c < p.nsplit; ++c) s += p.Sp[int64_t(c) * p.pstride + p.boff + k * M + x];
+    double s = p.Sp[p.boff + k * M + x];
     if (p.win > 0) {
         const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
         const double* __restrict__ lv = p.levels + int64_t(k) * M + x;
@@ -491,33 +539,6 @@ __global__ __launch_bounds__(256) void k_prep_2d(StepArgs p) {
 //       = E - [(a+l) S'_1 - a S'_2 ; (a+l) S'_2 - a S'_1].
 // With no coupling between modes there is no per-step global dependency:
 // the transform runs once at the start and once per read-out.
-
-// Cross-lane sums with DPP (no LDS round trip): a double moved by a DPP
-// pattern on each 32-bit half; lanes a pattern does not write (rows outside
-// row_mask) read 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROWS, 0xF, false);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-// DPP move with out-of-range source lanes reading zero (bound_ctrl)
-template <int CTRL>
-__device__ __forceinline__ double dpp_zero(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp(int(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), lane);
-    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
 
 // sum over each group of G lanes (G = 2, 4, 8, 16), in every lane of the group
 template <int G>
@@ -1426,16 +1447,30 @@ __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
 
 // ---------------------------------------------------------------------------
 // launchers (optionally bracketed by timing events, see prof_begin/prof_end)
-void launch_hist_block(const HistBlockArgs& a, int nsplit, hipStream_t st) {
-    dim3 grid(unsigned((a.M + 255) / 256), unsigned(nsplit), 2);
+void launch_hist_block(const HistBlockArgs& a, int lanes, hipStream_t st) {
+    dim3 grid(unsigned((a.M * lanes + 255) / 256), 1, 2);
+#define CQ_HB(BT, S) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hist_block<BT, S>), grid, dim3(256), 0, st, a)
+#define CQ_HB_S(BT)               \
+    switch (lanes) {              \
+        case 1: CQ_HB(BT, 1); break; \
+        case 2: CQ_HB(BT, 2); break; \
+        default: CQ_HB(BT, 4); break; \
+    }
     prof_begin(0, st);
-    if (a.BT <= 8)
-        hipLaunchKernelGGL(k_hist_block<8>, grid, dim3(256), 0, st, a);
-    else if (a.BT <= 16)
-        hipLaunchKernelGGL(k_hist_block<16>, grid, dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_hist_block<32>, grid, dim3(256), 0, st, a);
+    if (a.BT <= 8) {
+        CQ_HB_S(8)
+    } else if (a.BT <= 16) {
+        CQ_HB_S(16)
+    } else if (a.BT <= 24) {
+        CQ_HB_S(24)
+    } else if (a.BT <= 30) {  // the BDF2 lag 30: two fewer rows of registers than 32
+        CQ_HB_S(30)
+    } else {
+        CQ_HB_S(32)
+    }
     prof_end(0, st);
+#undef CQ_HB_S
+#undef CQ_HB
 }
 
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st) {
@@ -1478,11 +1513,6 @@ void launch_far(const FarArgs& a, hipStream_t st) {
     }
 }
 
-void launch_reduce_slices(double* F, int ks, int64_t per, hipStream_t st) {
-    prof_begin(10, st);
-    hipLaunchKernelGGL(k_reduce_far, dim3(unsigned((per + 255) / 256)), dim3(256), 0, st, F, ks, per);
-    prof_end(10, st);
-}
 
 void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st) {
     prof_begin(3, st);

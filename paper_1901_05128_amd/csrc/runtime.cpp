@@ -45,7 +45,8 @@ struct Solver {
     double tau = 0, a = 0, beta[2] = {0, 0}, c = 0, hx = 0, hy = 0;
     hipStream_t st = nullptr;
     // fast
-    int L = 2, np = 0, nsplit = 1, chunk = 0, Bt = 1, BTt = 8;
+    int L = 2, np = 0, hlanes = 1, chunk = 0, Bt = 1, BTt = 8;
+    int64_t hstride = 0;  // DOFs between nodes of the state H[2][np][hstride]
     double max_eps = 0;
     // direct
     int B = 0, ks = 1;
@@ -103,6 +104,9 @@ int far_ksplit(int64_t M) {
 
 // slices for one launch: at least 64 levels per slice
 int far_ks_for(int ks, int64_t nl) { return int(std::max<int64_t>(1, std::min<int64_t>(ks, (nl + 63) / 64))); }
+
+// values of the fast-history state H
+size_t hcount(const Solver& s) { return size_t(2) * size_t(s.np) * size_t(s.hstride); }
 
 int dev_alloc(Solver& s, double** ptr, size_t count) {
     void* q = nullptr;
@@ -276,17 +280,22 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
         }
         s.np = int(rule[0].ratio.size());
         s.L = rule[0].lag;
-        if (p->solver == 1 && (s.L > 64 || s.np > 1024))
-            return fail(CQ_EINVAL, "modal fast solver needs lag <= 64 and <= 1024 nodes (lag %d, nodes %d)", s.L,
-                        s.np);
+        if (s.np > 1024)
+            return fail(CQ_EINVAL, "the fast form keeps at most 1024 nodes per component (got %d)", s.np);
+        if (p->solver == 1 && s.L > 64)
+            return fail(CQ_EINVAL, "modal fast solver needs lag <= 64 (lag %d)", s.L);
         s.Bt = std::min(s.L, 32);
-        s.BTt = s.Bt <= 8 ? 8 : (s.Bt <= 16 ? 16 : 32);
+        s.BTt = s.Bt <= 8 ? 8 : (s.Bt <= 16 ? 16 : (s.Bt <= 24 ? 24 : (s.Bt <= 30 ? 30 : 32)));
         s.max_eps = std::max(rule[0].max_eps, rule[1].max_eps);
-        const int64_t tiles = 2 * ((s.M + 255) / 256);
-        int want = int(std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
-        want = std::min(want, s.dim == 1 ? 16 : 4);
-        s.nsplit = std::max(1, std::min(want, s.np / 8 > 0 ? s.np / 8 : 1));
-        s.chunk = (s.np + s.nsplit - 1) / s.nsplit;
+        // waves per 64-DOF tile in the state pass (node slices): enough for
+        // ~1536 waves (1.5 per SIMD; the pass holds ~165 registers per lane,
+        // three waves per SIMD), at least 8 nodes per slice, 1, 2 or 4
+        const int64_t waves = (2 * s.M + 63) / 64;
+        int want = int(std::max<int64_t>(1, (1536 + waves - 1) / waves));
+        want = std::min(want, std::max(1, s.np / 8));
+        s.hlanes = 1;
+        while (s.hlanes < want && s.hlanes < 4) s.hlanes *= 2;
+        s.chunk = (s.np + s.hlanes - 1) / s.hlanes;
         s.Lr = s.L;
     } else {
         s.Lr = s.N + 1;
@@ -374,11 +383,11 @@ int modal_start(Solver& s) {
     const int64_t twoM = 2 * s.M;
     transform(s, s.G0, s.g0c, true);
     if (s.p.method == 1 && s.modal_blocked) {
-        HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
+        HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), s.st));
         HIPCHK(hipMemsetAsync(s.levels, 0, size_t(s.Lr) * size_t(twoM) * sizeof(double), s.st));
         HIPCHK(hipMemcpyAsync(s.levels, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
     } else if (s.p.method == 1) {
-        HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
+        HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), s.st));
         HIPCHK(hipMemsetAsync(s.ring, 0, size_t(s.L) * size_t(twoM) * sizeof(double), s.st));
         HIPCHK(hipMemcpyAsync(s.ring, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
         HIPCHK(hipMemcpyAsync(s.ring + twoM, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
@@ -401,10 +410,15 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
                           st));
     HIPCHK(hipMemcpyAsync(s.G0, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (p->method == 1) {
-        if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * s.M)))) return rc;
+        // the state pass (k_hist_block) runs whole 256-DOF workgroups: its
+        // node rows are padded to a multiple of 256; the wave-per-mode
+        // kernel (modal, few modes) keeps them at M
+        const bool wave_per_mode = modal && !(s.M >= kModalBlockedMin && s.L <= 32);
+        s.hstride = wave_per_mode ? s.M : ((s.M + 255) / 256) * 256;
+        if ((rc = dev_alloc(s, &s.H, hcount(s)))) return rc;
         if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
         if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
-        HIPCHK(hipMemsetAsync(s.H, 0, size_t(2 * int64_t(s.np) * s.M) * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), st));
         std::vector<double> rr(size_t(2 * s.np)), cc(size_t(2 * s.np));
         for (int k = 0; k < 2; ++k)
             for (int j = 0; j < s.np; ++j) {
@@ -430,7 +444,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
             if (s.modal_blocked) {
                 s.Lr = s.L;
                 if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr) * size_t(twoM)))) return rc;
-                if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
+                if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.BTt) * twoM)))) return rc;
             } else {
                 if ((rc = dev_alloc(s, &s.ring, size_t(s.L) * size_t(twoM)))) return rc;
             }
@@ -445,7 +459,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
     if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
     HIPCHK(hipMemcpyAsync(s.levels, G0dev, twoM * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (p->method == 0 && (rc = dev_alloc(s, &s.Spart, size_t(twoM)))) return rc;
-    if (p->method == 1 && (rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
+    if (p->method == 1 && (rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.BTt) * twoM)))) return rc;
     if (s.dim == 1) {
         s.levels_pcr = 0;
         while ((int64_t(1) << s.levels_pcr) < s.M) ++s.levels_pcr;
@@ -522,12 +536,11 @@ void modal_steps(Solver& s, int64_t nsteps) {
                 hb.slot0 = ((nblk - s.L) % s.Lr + s.Lr) % s.Lr;
                 hb.levels = s.levels;
                 hb.H = s.H;
+                hb.hstride = s.hstride;
                 hb.ratio = s.d_ratio;
                 hb.coef = s.d_coef;
                 hb.Sf = s.Sf;
-                launch_hist_block(hb, s.nsplit, s.st);
-                // the window steps read the partial sums summed over the node slices
-                if (s.nsplit > 1) launch_reduce_slices(s.Sf, s.nsplit, int64_t(s.BTt) * 2 * s.M, s.st);
+                launch_hist_block(hb, s.hlanes, s.st);
             }
             const int bt = int(std::min<int64_t>(nblk + s.Bt - 1 - s.n, nsteps));
             ModalWinArgs a{};
@@ -537,7 +550,6 @@ void modal_steps(Solver& s, int64_t nsteps) {
             a.bt = bt;
             a.L = s.L;
             a.Lr = s.Lr;
-            a.nsplit = s.nsplit;
             a.BT = s.BTt;
             a.scheme = s.p.scheme;
             a.dstride = s.dstride;
@@ -689,8 +701,6 @@ void step_once(Solver& s) {
         ha.Spart = s.Spart;
         launch_hist_direct(ha, s.st);
         sa.Sp = s.Spart;
-        sa.nsplit = 1;
-        sa.pstride = 0;
         sa.boff = 0;
         sa.win = 0;
     } else {
@@ -707,14 +717,13 @@ void step_once(Solver& s) {
             hb.slot0 = ((n - s.L) % s.Lr + s.Lr) % s.Lr;
             hb.levels = s.levels;
             hb.H = s.H;
+            hb.hstride = s.hstride;
             hb.ratio = s.d_ratio;
             hb.coef = s.d_coef;
             hb.Sf = s.Sf;
-            launch_hist_block(hb, s.nsplit, s.st);
+            launch_hist_block(hb, s.hlanes, s.st);
         }
         sa.Sp = s.Sf;
-        sa.nsplit = s.nsplit;
-        sa.pstride = int64_t(s.BTt) * twoM;
         sa.boff = ((n - 1) % s.Bt) * twoM;
         sa.win = int(std::min<int64_t>(s.L - 1, n - 1));
     }
@@ -774,14 +783,14 @@ std::vector<Seg> state_segments(const Solver& s, int64_t n) {
     if (s.p.method == 0) {
         v.push_back({s.levels, size_t(n + 1) * twoM});
     } else {
-        const size_t hb = size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double);
+        const size_t hb = hcount(s) * sizeof(double);
         if (s.p.solver == 1 && !s.modal_blocked) {
             v.push_back({s.H, hb});
             v.push_back({s.ring, size_t(s.L) * twoM});
         } else {
             v.push_back({s.levels, size_t(s.Lr) * twoM});
             v.push_back({s.H, hb});
-            v.push_back({s.Sf, size_t(s.nsplit) * size_t(s.BTt) * twoM});
+            v.push_back({s.Sf, size_t(s.BTt) * twoM});
         }
     }
     return v;
@@ -1130,7 +1139,7 @@ int fp_reset(void* handle, const double* G0) {
     s.n0 = 0;
     if (s.p.solver == 1) return modal_start(s);
     HIPCHK(hipMemcpyAsync(s.levels, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
-    if (s.H) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(s.M) * sizeof(double), s.st));
+    if (s.H) HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), s.st));
     return CQ_OK;
 }
 
@@ -1211,10 +1220,11 @@ static int adjoint_setup(Solver& s) {
     HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
                           st));
     if (p->method == 1) {
-        if ((rc = dev_alloc(s, &s.H, size_t(2 * int64_t(s.np) * M)))) return rc;
+        s.hstride = ((M + 255) / 256) * 256;  // the state pass runs whole 256-DOF workgroups
+        if ((rc = dev_alloc(s, &s.H, hcount(s)))) return rc;
         if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
         if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
-        if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.nsplit) * s.BTt * twoM)))) return rc;
+        if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.BTt) * twoM)))) return rc;
         std::vector<double> rr(size_t(2 * s.np)), cc(size_t(2 * s.np));
         for (int k = 0; k < 2; ++k)
             for (int j = 0; j < s.np; ++j) {
@@ -1263,7 +1273,7 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     transform(s, s.G0, s.g0c, true);
     HIPCHK(hipMemcpyAsync(traj, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(Sx, 0, size_t(twoM) * sizeof(double), st));
-    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(M) * sizeof(double), st));
+    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), st));
     s.adj = false;
     s.Sout = Sx;
     s.mu = nullptr;
@@ -1279,7 +1289,7 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     transform(s, gN, gc, false);  // dl/dg^N = S^T dl/dG^N, S symmetric
     HIPCHK(hipMemsetAsync(psi, 0, size_t(twoM) * sizeof(double), st));
     HIPCHK(hipMemsetAsync(mu, 0, size_t(twoM) * sizeof(double), st));
-    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, size_t(2) * size_t(s.np) * size_t(M) * sizeof(double), st));
+    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), st));
     s.levels = psi;
     s.adj = true;
     s.Sout = nullptr;
