@@ -65,7 +65,9 @@ typedef struct {
  *    errors eps_i of (3.8)/(3.16) unless np > 0 is given.
  *  np: Gauss-Jacobi nodes (BE) or N_{p,2} (BDF2); 0 = choose by the scan.
  *  np1: N_{p,1} for BDF2 (0 selects 16). ns: N_s for BDF2 (0 selects 30;
- *    must be >= 3). np_max: scan limit (0 selects 1024).
+ *    must be >= 3). np_max: scan limit (0 selects 1024). A solver keeps
+ *    at most 1024 fast nodes per component (np, or np1 + np for BDF2);
+ *    more is CQ_EINVAL.
  *  block_B: direct method, time-block length of the Toeplitz far-field
  *    update (0 = automatic; otherwise 64, 128, 192 or 256). The modal solver
  *    steps in blocks of 64 and takes block_B as the rows of one far-field
