@@ -250,40 +250,44 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
         __syncthreads();
         for (int j = threadIdx.x; j < B + TL + 1; j += 256) wt[j] = j < len ? dk[base + j] : 0.0;
         __syncthreads();
-        // A fragment of row fragment r at level l: wt[(16r + li) + (s1 - 1 - l)],
-        // the zero entry for a level past the stage
         const int zero = B + TL;
-        auto load = [&](int64_t l0, double (&b_)[U], double (&a_)[U][NR]) {
+        // level operands (the B fragments): one 8-byte load per lane and K-step
+        auto loadb = [&](int64_t l0, double (&b_)[U]) {
+#pragma unroll
+            for (int uu = 0; uu < U; ++uu) {
+                const int64_t l = l0 + 4 * uu + lk;
+                b_[uu] = G[(l < s1 ? l : s0) * ls];
+            }
+        };
+        // A fragment of row fragment r at level l: wt[(16r + li) + (s1 - 1 - l)],
+        // the zero entry for a level past the stage (index arithmetic, not a
+        // select of addresses); read from LDS just before its products, so
+        // no register buffer holds them (four waves fit on a SIMD)
+        auto mma = [&](int64_t l0, const double (&b_)[U]) {
 #pragma unroll
             for (int uu = 0; uu < U; ++uu) {
                 const int64_t l = l0 + 4 * uu + lk;
                 const int lin = l < s1 ? 1 : 0;
-                b_[uu] = G[(lin ? l : s0) * ls];
-                // index arithmetic (not a select of addresses): past the stage
-                // every row reads the zero entry
                 const int base_i = lin * (li + int(s1 - 1 - l)) + (1 - lin) * zero;
+                double a_[NR];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) a_[uu][r] = wt[base_i + lin * 16 * r];
+                for (int r = 0; r < NR; ++r) a_[r] = wt[base_i + lin * 16 * r];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r] = mfma16x16x4(a_[r], b_[uu], acc[r]);
             }
         };
-        auto mma = [&](const double (&b_)[U], const double (&a_)[U][NR]) {
-#pragma unroll
-            for (int uu = 0; uu < U; ++uu)
-#pragma unroll
-                for (int r = 0; r < NR; ++r) acc[r] = mfma16x16x4(a_[uu][r], b_[uu], acc[r]);
-        };
-        // two buffers in turn: the level loads of one batch are in flight
+        // two level buffers in turn: the loads of one batch are in flight
         // while the other's products run
-        double bv[U], av[U][NR], bw[U], aw[U][NR];
-        load(s0, bv, av);
+        double bv[U], bw[U];
+        loadb(s0, bv);
         for (int64_t l0 = s0; l0 < s1; l0 += 8 * U) {
-            load(l0 + 4 * U, bw, aw);
+            loadb(l0 + 4 * U, bw);
             __builtin_amdgcn_sched_barrier(0);
-            mma(bv, av);
+            mma(l0, bv);
             __builtin_amdgcn_sched_barrier(0);
-            load(l0 + 8 * U, bv, av);
+            loadb(l0 + 8 * U, bv);
             __builtin_amdgcn_sched_barrier(0);
-            mma(bw, aw);
+            mma(l0 + 4 * U, bw);
             __builtin_amdgcn_sched_barrier(0);
         }
     }

@@ -88,11 +88,10 @@ struct Solver {
     }
 };
 
-// K-split of the far field: about 512 workgroups, one round of the 256 CUs
-// with two resident 4-wave groups each (the 128-row pass holds ~236
-// registers per lane), at most 32 slices. More slices add partial sums that
-// are written and read back once per pass; measured, 512 beat 768..3072 on the
-// 1D workload (24.1 against 25.9 ms a solve) and tied on the 2D one.
+// K-split of the far field: about 512 workgroups, at most 32 slices. More
+// slices add partial sums that are written and read back once per pass;
+// measured, 512 beat 768..3072 (and tied 256) on the 1D workload and
+// tied on the 2D one.
 #ifndef CQFP_FAR_WORKGROUPS
 #define CQFP_FAR_WORKGROUPS 512
 #endif
