@@ -95,58 +95,66 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
     double* __restrict__ h = p.H + (int64_t(k) * p.np) * hs + x;
     const double* __restrict__ r = p.ratio + k * p.np;
     const double* __restrict__ w = p.coef + k * p.np;
-    int j = j0;
     // four nodes per group (independent recurrences interleave); the states
     // of the next group are loaded before this group is advanced, so a load
-    // is in flight while the previous one is used
-    double hn0 = 0.0, hn1 = 0.0, hn2 = 0.0, hn3 = 0.0;
-    if (j + 4 <= j1) {
-        hn0 = __builtin_nontemporal_load(h + int64_t(j) * hs);
-        hn1 = __builtin_nontemporal_load(h + int64_t(j + 1) * hs);
-        hn2 = __builtin_nontemporal_load(h + int64_t(j + 2) * hs);
-        hn3 = __builtin_nontemporal_load(h + int64_t(j + 3) * hs);
-    }
+    // is in flight while the previous one is used. A full block (bt == BT)
+    // runs without per-step guards.
+    auto nodes = [&](auto full_t) {
+        constexpr bool FULLB = decltype(full_t)::value;
+        int j = j0;
+        double hn0 = 0.0, hn1 = 0.0, hn2 = 0.0, hn3 = 0.0;
+        if (j + 4 <= j1) {
+            hn0 = __builtin_nontemporal_load(h + int64_t(j) * hs);
+            hn1 = __builtin_nontemporal_load(h + int64_t(j + 1) * hs);
+            hn2 = __builtin_nontemporal_load(h + int64_t(j + 2) * hs);
+            hn3 = __builtin_nontemporal_load(h + int64_t(j + 3) * hs);
+        }
 #pragma unroll 1
-    for (; j + 4 <= j1; j += 4) {
-        double h0 = hn0, h1 = hn1, h2 = hn2, h3 = hn3;
-        if (j + 8 <= j1) {
-            hn0 = __builtin_nontemporal_load(h + int64_t(j + 4) * hs);
-            hn1 = __builtin_nontemporal_load(h + int64_t(j + 5) * hs);
-            hn2 = __builtin_nontemporal_load(h + int64_t(j + 6) * hs);
-            hn3 = __builtin_nontemporal_load(h + int64_t(j + 7) * hs);
-        }
-        const double r0 = r[j], r1 = r[j + 1], r2 = r[j + 2], r3 = r[j + 3];
-        const double w0 = w[j], w1 = w[j + 1], w2 = w[j + 2], w3 = w[j + 3];
-#pragma unroll
-        for (int b = 0; b < BT; ++b) {
-            if (b < p.bt) {
-                h0 = fma(r0, h0, g[b]);
-                h1 = fma(r1, h1, g[b]);
-                h2 = fma(r2, h2, g[b]);
-                h3 = fma(r3, h3, g[b]);
-                acc[b] = fma(w0, h0, acc[b]);
-                acc[b] = fma(w1, h1, acc[b]);
-                acc[b] = fma(w2, h2, acc[b]);
-                acc[b] = fma(w3, h3, acc[b]);
+        for (; j + 4 <= j1; j += 4) {
+            double h0 = hn0, h1 = hn1, h2 = hn2, h3 = hn3;
+            if (j + 8 <= j1) {
+                hn0 = __builtin_nontemporal_load(h + int64_t(j + 4) * hs);
+                hn1 = __builtin_nontemporal_load(h + int64_t(j + 5) * hs);
+                hn2 = __builtin_nontemporal_load(h + int64_t(j + 6) * hs);
+                hn3 = __builtin_nontemporal_load(h + int64_t(j + 7) * hs);
             }
-        }
-        __builtin_nontemporal_store(h0, h + int64_t(j) * hs);
-        __builtin_nontemporal_store(h1, h + int64_t(j + 1) * hs);
-        __builtin_nontemporal_store(h2, h + int64_t(j + 2) * hs);
-        __builtin_nontemporal_store(h3, h + int64_t(j + 3) * hs);
-    }
-    for (; j < j1; ++j) {
-        double h0 = h[int64_t(j) * hs];
-        const double r0 = r[j], w0 = w[j];
+            const double r0 = r[j], r1 = r[j + 1], r2 = r[j + 2], r3 = r[j + 3];
+            const double w0 = w[j], w1 = w[j + 1], w2 = w[j + 2], w3 = w[j + 3];
 #pragma unroll
-        for (int b = 0; b < BT; ++b) {
-            if (b < p.bt) {
-                h0 = fma(r0, h0, g[b]);
-                acc[b] = fma(w0, h0, acc[b]);
+            for (int b = 0; b < BT; ++b) {
+                if (FULLB || b < p.bt) {
+                    h0 = fma(r0, h0, g[b]);
+                    h1 = fma(r1, h1, g[b]);
+                    h2 = fma(r2, h2, g[b]);
+                    h3 = fma(r3, h3, g[b]);
+                    acc[b] = fma(w0, h0, acc[b]);
+                    acc[b] = fma(w1, h1, acc[b]);
+                    acc[b] = fma(w2, h2, acc[b]);
+                    acc[b] = fma(w3, h3, acc[b]);
+                }
             }
+            __builtin_nontemporal_store(h0, h + int64_t(j) * hs);
+            __builtin_nontemporal_store(h1, h + int64_t(j + 1) * hs);
+            __builtin_nontemporal_store(h2, h + int64_t(j + 2) * hs);
+            __builtin_nontemporal_store(h3, h + int64_t(j + 3) * hs);
         }
-        h[int64_t(j) * hs] = h0;
-    }
+        for (; j < j1; ++j) {
+            double h0 = h[int64_t(j) * hs];
+            const double r0 = r[j], w0 = w[j];
+#pragma unroll
+            for (int b = 0; b < BT; ++b) {
+                if (FULLB || b < p.bt) {
+                    h0 = fma(r0, h0, g[b]);
+                    acc[b] = fma(w0, h0, acc[b]);
+                }
+            }
+            h[int64_t(j) * hs] = h0;
+        }
+    };
+    if (BT <= 30 && p.bt == BT)  // (at BT = 32 the unguarded copy costs a wave per SIMD in registers)
+        nodes(std::true_type{});
+    else
+        nodes(std::false_type{});
     if (S > 1) {
         double* __restrict__ mine = red + int64_t(tile * (S - 1)) * BT * 64 + lane;
         if (sl > 0) {
