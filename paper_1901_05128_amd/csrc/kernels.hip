@@ -1087,6 +1087,10 @@ __global__ __launch_bounds__(64) void k_modal_win(ModalWinArgs p) {
     for (int i = 0; i < BB - 2; ++i) wr[i] = w[i + 2];
     int64_t slot = p.nfirst % p.Lr;
     double gprev = 0.0;
+    // every prologue load has landed: the steps below are separate blocks
+    // (b < bt), and without this wait the compiler waits for all memory
+    // operations, the previous step's stores included, at each step
+    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int b = 0; b < BB; ++b) {
         if (b < bt) {
@@ -1220,6 +1224,7 @@ __global__ __launch_bounds__(64) void k_modal_near(ModalNearArgs p) {
     // step's instructions together so that the pushes overlap the solve
     // instead of being sunk into a serial chain before their use.
     double gprev = 0.0;
+    __builtin_amdgcn_s_waitcnt(0);  // prologue loads landed (see k_modal_win)
 #pragma unroll
     for (int b = 0; b < BB; ++b) {
         if (FULL || (b >= b0 && b < bend)) {
