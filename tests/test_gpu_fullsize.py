@@ -80,3 +80,33 @@ def test_configuration3_full_size_sampled_modes(scheme, method):
     modes = [(1, 1), (3, 2), (40, 17)] if method == 1 else [(1, 1), (7, 128)]
     got, ref, cmax = _run(2, nx, ny, 0.2, 0.6, 0.55, N, G0, scheme, method, modes)
     _check(got, ref, cmax, _tol(N, method))
+
+
+def test_configuration4_full_size_sampled_modes():
+    """Three problems of the seeded 256-problem batch at full size (the
+    largest 2D one, 255^2 with N = 2^15; the largest 1D one, 4095 nodes with
+    N = 2^15; and the first problem), solved together by fp_solve_batched
+    without autotuning, which takes the time-blocked kernel for these BDF2
+    problems; sampled sine modes against the oracle's per-mode recurrence
+    with the same node counts (np = ceil(3 sqrt N), 16 + np in all, N_s = 30)."""
+    import math
+    inst = wl.batched_instances(256, seed=4)
+    pick = [23, 44, 0]
+    grids, params, g0s, probs = [], [], [], []
+    for i in pick:
+        p = inst[i]
+        npn = int(math.ceil(3 * math.sqrt(p.N)))
+        grids.append(cq.make_grid(p.dim, p.nx, p.ny))
+        params.append(cq.make_params(p.alpha1, p.alpha2, p.m, p.T, p.N, 2, 1, np_=npn))
+        G0 = wl.g0_intervals(p.nx, 1000 + i) if p.dim == 1 else wl.g0_rectangle(p.nx, p.ny, 1000 + i)
+        g0s.append(torch.tensor(G0, dtype=torch.float64, device="cuda"))
+        probs.append((p, npn, G0))
+    outs, rep = cq.fp_solve_batched(grids, params, g0s, autotune=False)
+    assert all(x == 1 for x in list(rep.class_blocked)[:rep.classes])
+    for (p, npn, G0), out in zip(probs, outs):
+        print(f"c4 full size: {p.name} {p.dim}d {p.nx}x{p.ny} N={p.N} np={npn}", flush=True)
+        coef = modal.to_modes(out.cpu().numpy(), p.dim, p.nx, p.ny)
+        modes = [(1, 1), (3, 2), (40, 17)] if p.dim == 2 else [(1, 1), (2, 1), (300, 1), (4095, 1)]
+        idx = [(q - 1) * p.nx + (pp - 1) for (pp, q) in modes]
+        ref = modal.run_modes(p.dim, p.nx, p.ny, modes, p.alpha1, p.alpha2, p.m, p.T, p.N, G0, 2, 1, np_=npn, ns=30)
+        _check(coef[:, idx], ref, np.max(np.abs(coef)), _tol(p.N, 1))
