@@ -200,3 +200,20 @@ def test_step_past_end_rejected():
         s.step(3)
         with pytest.raises(cq.CQError):
             s.step(2)
+
+
+@pytest.mark.parametrize("dim,nx,ny", [(1, 1, 1), (2, 1, 1), (2, 1, 7), (2, 7, 1), (1, 2, 1)])
+@pytest.mark.parametrize("m", [1.0, 0.0, 0.7])
+@pytest.mark.parametrize("solver", [0, 1], ids=["nodal", "modal"])
+def test_degenerate_grids_and_coupling(dim, nx, ny, m, solver):
+    """One-node and one-row grids, the decoupled case m = 1 (a = 0) and
+    m = 0 (a = -1), orders near the ends of (0,1), every scheme and method,
+    against the oracle."""
+    N = 70
+    G0 = wl.g0_random(nx * ny, 3)
+    for scheme in (1, 2):
+        ref = modal.reference(dim, nx, ny, 0.05, 0.95, m, 1.0, N, G0, scheme, 0)
+        for method in (0, 1):
+            p = cq.make_params(0.05, 0.95, m, 1.0, N, scheme, method, solver=solver)
+            out = cq.fp_solve(cq.make_grid(dim, nx, ny), p, dev(G0)).cpu().numpy()
+            assert rel(out, ref) <= (1e-12 if method == 0 else 1e-8), (scheme, method, rel(out, ref))
