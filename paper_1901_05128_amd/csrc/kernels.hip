@@ -859,70 +859,102 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
     double gl0 = g00, gl1 = g01;                                          // newest level
     double lv = 0.0;                                   // no level >= 1 yet
     const int src0 = (lane & 32) + L - 1;              // lane of g_k^{n0+1-L} in lv
+    // (B) sum of 8 steps' partial sums over a component's 32 lanes:
+    // a[pos(j)] holds step b0+j (pos swaps bits 0 and 1 of j); halving by
+    // row_half_mirror (side bit 2), quad_perm [1,0,3,2] (bit 0) and
+    // quad_perm [2,3,0,1] (bit 1) leaves step b0 + t%8 in lane t, and the
+    // lanes t^8 and t^16, which hold the same step, are added in; lanes of
+    // those eight steps take the total.
+    auto reduce8 = [&](double (&a)[8], int b0, double& dst) {
+        {
+            const bool sd = (lane >> 2) & 1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double keep = sd ? a[4 + i] : a[i], send = sd ? a[i] : a[4 + i];
+                a[i] = keep + dpp_move<0x141, 0xF>(send);
+            }
+        }
+        {
+            const bool sd = lane & 1;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const double keep = sd ? a[2 + i] : a[i], send = sd ? a[i] : a[2 + i];
+                a[i] = keep + dpp_move<0xB1, 0xF>(send);
+            }
+        }
+        double v;
+        {
+            const bool sd = (lane >> 1) & 1;
+            const double keep = sd ? a[1] : a[0], send = sd ? a[0] : a[1];
+            v = keep + dpp_move<0x4E, 0xF>(send);
+        }
+        v += __shfl_xor(v, 8, 64);
+        v += __shfl_xor(v, 16, 64);
+        if ((t >> 3) == (b0 >> 3)) dst = v;
+    };
+    constexpr int POS[8] = {0, 2, 1, 3, 4, 6, 5, 7};
+    // (C) one step of the block (lane t holds the pending sum of step
+    // n0+1+t): with Minv the inverse of the step matrix, g^n = Minv (E - D S):
+    // the E part is e1 P + e2 R with P = Minv g^{n-1} and R = Minv g^{n-2},
+    // the S part s.S, so a step waits on its sum and two FMAs. Returns this
+    // lane's component of the new level.
+    double acc = 0.0, wc = 0.0, lvnew = 0.0;
+    auto cstep = [&](int b) {
+        const double S0 = lane_value(acc, b), S1 = lane_value(acc, 32 + b);
+        const double E0 = fma(e1, P0, e2 * R0), E1 = fma(e1, P1, e2 * R1);
+        const double gn0 = fma(s01, S1, fma(s00, S0, E0));
+        const double gn1 = fma(s11, S1, fma(s10, S0, E1));
+        const double gk = hi_half ? gn1 : gn0;
+        acc = fma(wc, gk, acc);
+        const double wsh = dpp_zero<0x138>(wc);  // wave_shr:1
+        wc = (t == 0) ? 0.0 : wsh;
+        lvnew = (t == b) ? gk : lvnew;
+        R0 = P0;
+        R1 = P1;
+        P0 = fma(i01, gn1, i00 * gn0);
+        P1 = fma(i11, gn1, i10 * gn0);
+        gl0 = gn0;
+        gl1 = gn1;
+        return gk;
+    };
+    // (A) the state advanced by one step with input gin, this lane's part of
+    // sum_j w_j h_j
+    auto astep = [&](double gin) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            h[q] = fma(r[q], h[q], gin);
+            s = fma(w[q], h[q], s);
+        }
+        return s;
+    };
+    bool have_fast = false;  // acc holds the block's fast part already
     for (int64_t n0 = 0; n0 < N; n0 += L) {
         const int bt = int((N - n0 < L) ? N - n0 : L);
-        double acc = 0.0;
-        // (A) + (B): the fast part, 8 steps at a time; a full pass has no
-        // per-step branch, so its eight level loads are all in flight first
-        auto pass = [&](auto full_t, int b0) {
-            constexpr bool FULLP = decltype(full_t)::value;
-            double gin[8];
+        if (!have_fast) {
+            // (A) + (B) from the level store, 8 steps at a time; a full pass
+            // has no per-step branch, so its eight level loads are all in
+            // flight first
+            acc = 0.0;
+            auto pass = [&](auto full_t, int b0) {
+                constexpr bool FULLP = decltype(full_t)::value;
+                double gin[8], a[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int b = b0 + j;
-                gin[j] = __shfl(lv, b < L ? src0 - b : 0, 64);
-            }
-            // a[pos(j)]: pos swaps bits 0 and 1 of j (the halving below
-            // leaves value pos(t%8) in lane t)
-            double a[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int pj = (j & 4) | ((j & 1) << 1) | ((j >> 1) & 1);
-                double s = 0.0;
-                if (FULLP || b0 + j < bt) {  // uniform
-#pragma unroll
-                    for (int q = 0; q < NP; ++q) {
-                        h[q] = fma(r[q], h[q], gin[j]);
-                        s = fma(w[q], h[q], s);
-                    }
+                for (int j = 0; j < 8; ++j) {
+                    const int b = b0 + j;
+                    gin[j] = __shfl(lv, b < L ? src0 - b : 0, 64);
                 }
-                a[pj] = s;
-            }
-            // halving: row_half_mirror (side bit 2), quad_perm [1,0,3,2]
-            // (bit 0), quad_perm [2,3,0,1] (bit 1); then lanes t^8 and t^16
-            // hold the same value and are added in
-            {
-                const bool sd = (lane >> 2) & 1;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const double keep = sd ? a[4 + i] : a[i], send = sd ? a[i] : a[4 + i];
-                    a[i] = keep + dpp_move<0x141, 0xF>(send);
-                }
-            }
-            {
-                const bool sd = lane & 1;
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const double keep = sd ? a[2 + i] : a[i], send = sd ? a[i] : a[2 + i];
-                    a[i] = keep + dpp_move<0xB1, 0xF>(send);
-                }
-            }
-            double v;
-            {
-                const bool sd = (lane >> 1) & 1;
-                const double keep = sd ? a[1] : a[0], send = sd ? a[0] : a[1];
-                v = keep + dpp_move<0x4E, 0xF>(send);
-            }
-            v += __shfl_xor(v, 8, 64);
-            v += __shfl_xor(v, 16, 64);
-            if ((t >> 3) == (b0 >> 3)) acc = v;
-        };
+                for (int j = 0; j < 8; ++j) a[POS[j]] = (FULLP || b0 + j < bt) ? astep(gin[j]) : 0.0;
+                reduce8(a, b0, acc);
+            };
 #pragma unroll 1
-        for (int b0 = 0; b0 < bt; b0 += 8) {
-            if (b0 + 8 <= bt)
-                pass(std::true_type{}, b0);
-            else
-                pass(std::false_type{}, b0);
+            for (int b0 = 0; b0 < bt; b0 += 8) {
+                if (b0 + 8 <= bt)
+                    pass(std::true_type{}, b0);
+                else
+                    pass(std::false_type{}, b0);
+            }
         }
         // BDF2 starting correction 1/2 d_{k,n-1} g_k^0 of step n = n0+1+t
         if (bdf2) {
@@ -947,28 +979,41 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
                 }
             }
         }
-        // (C) the steps of the block. With Minv the inverse of the step
-        // matrix, g^n = Minv (E - D S): the E part is e1 P + e2 R with P =
-        // Minv g^{n-1} and R = Minv g^{n-2}, the S part s.S, so a step
-        // waits on its sum and two FMAs.
-        double wc = dwin, lvnew = 0.0;
-        for (int b = 0; b < bt; ++b) {
-            const double S0 = lane_value(acc, b), S1 = lane_value(acc, 32 + b);
-            const double E0 = fma(e1, P0, e2 * R0), E1 = fma(e1, P1, e2 * R1);
-            const double gn0 = fma(s01, S1, fma(s00, S0, E0));
-            const double gn1 = fma(s11, S1, fma(s10, S0, E1));
-            const double gk = hi_half ? gn1 : gn0;
-            acc = fma(wc, gk, acc);
-            const double wsh = dpp_zero<0x138>(wc);  // wave_shr:1
-            wc = (t == 0) ? 0.0 : wsh;
-            lvnew = (t == b) ? gk : lvnew;
-            R0 = P0;
-            R1 = P1;
-            P0 = fma(i01, gn1, i00 * gn0);
-            P1 = fma(i11, gn1, i10 * gn0);
-            gl0 = gn0;
-            gl1 = gn1;
+        // (C) the steps. When this block and the next are full, the next
+        // block's state pass rides along: its step b takes the level just
+        // solved at step b (lag L), so its FMAs fill the solve's dependency
+        // chain, 8 steps per group (the group count fixed at compile time,
+        // a remainder group of 1..7 steps).
+        wc = dwin;
+        lvnew = 0.0;
+        const bool pipe = bt == L && N - (n0 + L) >= L;
+        if (pipe) {
+            double accn = 0.0;
+            auto group = [&](auto rc, int c0) {
+                constexpr int RC = decltype(rc)::value;
+                double a[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[POS[j]] = (j < RC) ? astep(cstep(c0 + j)) : 0.0;
+                reduce8(a, c0, accn);
+            };
+            int c0 = 0;
+#pragma unroll 1
+            for (; c0 + 8 <= bt; c0 += 8) group(std::integral_constant<int, 8>{}, c0);
+            switch (bt - c0) {
+                case 1: group(std::integral_constant<int, 1>{}, c0); break;
+                case 2: group(std::integral_constant<int, 2>{}, c0); break;
+                case 3: group(std::integral_constant<int, 3>{}, c0); break;
+                case 4: group(std::integral_constant<int, 4>{}, c0); break;
+                case 5: group(std::integral_constant<int, 5>{}, c0); break;
+                case 6: group(std::integral_constant<int, 6>{}, c0); break;
+                case 7: group(std::integral_constant<int, 7>{}, c0); break;
+                default: break;
+            }
+            acc = accn;
+        } else {
+            for (int b = 0; b < bt; ++b) cstep(b);
         }
+        have_fast = pipe;
         // level store for the next block: lane 32k+t <- g_k^{n0+bt-t}
         {
             const double fresh = __shfl(lvnew, (lane & 32) + ((bt - 1 - t) & 31), 64);
