@@ -92,6 +92,7 @@ struct GemmArgs {
 struct ModalFastArgs {
     int64_t M;            // modes (nodes per component)
     int64_t n0;           // steps already taken
+    int64_t N;            // steps of the whole run (time-blocked kernel: block lengths)
     int nsteps;
     int np, L;            // nodes per component (<= 1024), lag (<= 64)
     int scheme;
@@ -104,8 +105,12 @@ struct ModalFastArgs {
     const double* d;      // [2][dstride]
     const double* g0;     // [2][M] sine coefficients of G^0
     double* H;            // [2][np][hstride]
-    int64_t hstride;      // >= M rounded up to 256 (every lane of the pass has a slot)
-    double* ring;         // [L][2][M], ring[i] = g^{n-1-i}
+    int64_t hstride;      // DOFs between nodes of H (M here)
+    // per-step kernel: [L][2][M], ring[i] = g^{n-1-i} before step n (g^{-1} := g^0);
+    // time-blocked kernel (modal_fast_blocked): [2L][2][M], ring[i] = g^{n-i}
+    // after n steps (g^0 included, zero below), and H is the state at the
+    // start of the L-block that holds step n+1
+    double* ring;
 };
 
 struct ModalNearArgs {
@@ -214,6 +219,7 @@ struct BatchArgs {
 
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
 void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
+bool modal_fast_blocked(int L, int np);  // launch_modal_fast takes the time-blocked kernel
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);
 void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st);
 void launch_adj_g0(const AdjGradArgs& a, hipStream_t st);

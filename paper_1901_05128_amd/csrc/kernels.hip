@@ -808,57 +808,58 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
 // lv: lane 32k+t holds g_k^{n0-t} (zero for levels < 1); wc: lane 32k+t holds
 // d_{k,t-b} at step b (zero outside lags 1..L-1); lvnew: lane 32k+b holds
 // the block's level of step b. Needs 2 <= L <= 32 and np <= 32*NP.
+// The time-blocked steps nbeg+1..nend of one mode (one wave; lanes 0..31
+// component 0, 32..63 component 1, lane l: component k = l/32, position
+// t = l%32). The steps go in blocks of bt <= L (the lag): the levels
+// entering the compressed state at steps n0+1..n0+bt are g^{n0+1-L}..
+// g^{n0+bt-L}, all known when the block starts, so
+//  (A) the state advances over the whole block first: each lane owns the
+//      nodes t + 32q of its component (NP nodes), and per step it adds its
+//      part of sum_j w_j h_j into a[] (no cross-lane work per step);
+//  (B) the partial sums of 8 steps are summed over the 32 lanes of a
+//      component by recursive halving, which leaves step t's fast part in
+//      lane t of its component;
+//  (C) the window (exact weights, lags 1..L-1) and the 2x2 solve then run
+//      step by step in push form with lane t owning step n0+1+t: the levels
+//      before the block are pushed first, and each new level is pushed into
+//      the later steps' sums, so a step reads its sum (readlane), solves, and
+//      adds one FMA per lane. When the next block is full too, its (A) runs
+//      inside these steps.
+// Blocks start at nbeg + jL and take min(L, ntot - start) steps; a call may
+// end inside a block (nend), after whose steps the rest of the block is not
+// taken. The fast part of a block is always formed for its whole length, so
+// the arithmetic of every step depends on the block alone, not on where the
+// calls end. State in and out: h (this lane's nodes, at the start of the
+// block that holds step nend+1: when nend falls inside a block, h as it was
+// before that block's state pass is written to hsave (row stride hrow, nodes
+// j < np) and e_end receives the steps taken of it, else e_end = 0); lv
+// (lane 32k+t: g_k^{s-t}, zero for levels < 1, s the start of that block);
+// lvnew_out (lane 32k+j: the block's level of step j < e_end); P = Minv g^n,
+// R = Minv g^{n-1}, gl = g^n. dk: this component's exact weights, readable up
+// to dlast; dwin: d_{k,t} for 1 <= t < L, else 0. Needs 2 <= L <= 32,
+// np <= 32*NP.
 template <int NP>
-__global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
-    const int lane = threadIdx.x & 63;
-    const int64_t group = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (group >= p.total) return;  // uniform per wave
-    int lo = 0, hi = p.count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (p.cum[mid] <= group) lo = mid; else hi = mid - 1;
-    }
-    const BatchInst& I = p.inst[p.list[lo]];
-    const int64_t mode = group - p.cum[lo];
-    const int64_t M = I.M, N = I.N;
-    const int np = I.np, L = I.L;
-    const int k = lane >> 5, t = lane & 31;
-    const bool hi_half = k != 0;
-    const double* __restrict__ ratio = p.ratio + I.rule_off + k * np;
-    const double* __restrict__ coef = p.coef + I.rule_off + k * np;
-    const double* __restrict__ dk = p.d + I.d_off + k * I.dstride;
+__device__ __forceinline__ void tb_steps(const int lane, const int L, const bool bdf2, const int64_t nbeg,
+                                         const int64_t nend, const int64_t ntot, double* __restrict__ hsave,
+                                         const int64_t hrow, const int np, int& e_end, double& lvnew_out,
+                                         const double (&r_)[NP], const double (&w_)[NP],
+                                         double (&h_)[NP], const double* __restrict__ dk, const int64_t dlast,
+                                         const double dwin, const double g0k, const double e1, const double e2,
+                                         const double s00, const double s01, const double s10, const double s11,
+                                         const double i00, const double i01, const double i10, const double i11,
+                                         double& P0_, double& P1_, double& R0_, double& R1_, double& gl0_,
+                                         double& gl1_, double& lv_) {
+    double P0 = P0_, P1 = P1_, R0 = R0_, R1 = R1_, gl0 = gl0_, gl1 = gl1_, lv = lv_;
     double r[NP], w[NP], h[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-        const int j = t + 32 * q;
-        const bool ok = j < np;
-        r[q] = ok ? ratio[j] : 0.0;
-        w[q] = ok ? coef[j] : 0.0;
-        h[q] = 0.0;
+        r[q] = r_[q];
+        w[q] = w_[q];
+        h[q] = h_[q];
     }
-    // window weights of this lane: d_{k,t} for 1 <= t < L (lag t of step t from the block's first level)
-    const double dwin = (t >= 1 && t < L) ? dk[t] : 0.0;
-    const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
-    const double g00 = g0[mode], g01 = g0[M + mode];
-    const double g0k = hi_half ? g01 : g00;
-    const bool bdf2 = I.scheme == 2;
-    const double inv_tau = I.inv_tau, ca = I.a;
-    const double lam = p.lam[I.mode_off + mode];
-    const double L1 = ca + lam;
-    const double m11 = I.c + I.d00 * L1, m22 = I.c + I.d01 * L1;
-    const double m12 = -ca * I.d01, m21 = -ca * I.d00;
-    const double idet = 1.0 / (m11 * m22 - m12 * m21);
-    const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
-    // g = Minv (E - D S), D = [[L1, -a], [-a, L1]]: coefficients of S
-    const double s00 = ca * i01 - L1 * i00, s01 = ca * i00 - L1 * i01;
-    const double s10 = ca * i11 - L1 * i10, s11 = ca * i10 - L1 * i11;
-    // E = e1 g^{n-1} + e2 g^{n-2} (BE: g^{n-1}/tau; BDF2: (2 g^{n-1} - g^{n-2}/2)/tau)
-    const double e1 = (bdf2 ? 2.0 : 1.0) * inv_tau, e2 = (bdf2 ? -0.5 : 0.0) * inv_tau;
-    double P0 = fma(i01, g01, i00 * g00), P1 = fma(i11, g01, i10 * g00);  // Minv g^{n-1}
-    double R0 = P0, R1 = P1;                                              // Minv g^{n-2}, g^{-1} := g^0
-    double gl0 = g00, gl1 = g01;                                          // newest level
-    double lv = 0.0;                                   // no level >= 1 yet
-    const int src0 = (lane & 32) + L - 1;              // lane of g_k^{n0+1-L} in lv
+    const int t = lane & 31;
+    const bool hi_half = (lane & 32) != 0;
+    const int src0 = (lane & 32) + L - 1;  // lane of g_k^{n0+1-L} in lv
     // (B) sum of 8 steps' partial sums over a component's 32 lanes:
     // a[pos(j)] holds step b0+j (pos swaps bits 0 and 1 of j); halving by
     // row_half_mirror (side bit 2), quad_perm [1,0,3,2] (bit 0) and
@@ -929,8 +930,16 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
         return s;
     };
     bool have_fast = false;  // acc holds the block's fast part already
-    for (int64_t n0 = 0; n0 < N; n0 += L) {
-        const int bt = int((N - n0 < L) ? N - n0 : L);
+    e_end = 0;
+    for (int64_t n0 = nbeg; n0 < nend; n0 += L) {
+        const int bt = int((ntot - n0 < L) ? ntot - n0 : L);     // the block's length
+        const int bc = int((nend - n0 < bt) ? nend - n0 : bt);   // its steps taken here
+        if (bc < bt && hsave) {
+            // the call ends inside this block: keep the state of its start
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                if ((lane & 31) + 32 * q < np) hsave[int64_t((lane & 31) + 32 * q) * hrow] = h[q];
+        }
         if (!have_fast) {
             // (A) + (B) from the level store, 8 steps at a time; a full pass
             // has no per-step branch, so its eight level loads are all in
@@ -958,7 +967,7 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
         }
         // BDF2 starting correction 1/2 d_{k,n-1} g_k^0 of step n = n0+1+t
         if (bdf2) {
-            const int64_t ix = (n0 + t <= N) ? n0 + t : N;
+            const int64_t ix = (n0 + t <= dlast) ? n0 + t : dlast;
             acc = fma(0.5 * dk[ix], g0k, acc);
         }
         // (C) window part of the levels before the block: level n0-u reaches
@@ -986,7 +995,7 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
         // a remainder group of 1..7 steps).
         wc = dwin;
         lvnew = 0.0;
-        const bool pipe = bt == L && N - (n0 + L) >= L;
+        const bool pipe = bc == L && ntot - (n0 + L) >= L && nend - (n0 + L) >= L;
         if (pipe) {
             double accn = 0.0;
             auto group = [&](auto rc, int c0) {
@@ -1011,9 +1020,14 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
             }
             acc = accn;
         } else {
-            for (int b = 0; b < bt; ++b) cstep(b);
+            for (int b = 0; b < bc; ++b) cstep(b);
         }
         have_fast = pipe;
+        if (bc < bt) {  // the call ends inside this block (the last of the loop)
+            e_end = bc;
+            lvnew_out = lvnew;
+            break;
+        }
         // level store for the next block: lane 32k+t <- g_k^{n0+bt-t}
         {
             const double fresh = __shfl(lvnew, (lane & 32) + ((bt - 1 - t) & 31), 64);
@@ -1021,10 +1035,153 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
             lv = (t < bt) ? fresh : older;
         }
     }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) h_[q] = h[q];
+    P0_ = P0;
+    P1_ = P1;
+    R0_ = R0;
+    R1_ = R1;
+    gl0_ = gl0;
+    gl1_ = gl1;
+    lv_ = lv;
+}
+
+// Batched fast solve, time-blocked (tb_steps): one wave per mode, from the
+// zero state over all N steps of the mode's problem.
+template <int NP>
+__global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t group = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (group >= p.total) return;  // uniform per wave
+    int lo = 0, hi = p.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.cum[mid] <= group) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst& I = p.inst[p.list[lo]];
+    const int64_t mode = group - p.cum[lo];
+    const int64_t M = I.M, N = I.N;
+    const int np = I.np, L = I.L;
+    const int k = lane >> 5, t = lane & 31;
+    const bool hi_half = k != 0;
+    const double* __restrict__ ratio = p.ratio + I.rule_off + k * np;
+    const double* __restrict__ coef = p.coef + I.rule_off + k * np;
+    const double* __restrict__ dk = p.d + I.d_off + k * I.dstride;
+    double r[NP], w[NP], h[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int j = t + 32 * q;
+        const bool ok = j < np;
+        r[q] = ok ? ratio[j] : 0.0;
+        w[q] = ok ? coef[j] : 0.0;
+        h[q] = 0.0;
+    }
+    // window weights of this lane: d_{k,t} for 1 <= t < L (lag t of step t from the block's first level)
+    const double dwin = (t >= 1 && t < L) ? dk[t] : 0.0;
+    const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
+    const double g00 = g0[mode], g01 = g0[M + mode];
+    const double g0k = hi_half ? g01 : g00;
+    const bool bdf2 = I.scheme == 2;
+    const double inv_tau = I.inv_tau, ca = I.a;
+    const double lam = p.lam[I.mode_off + mode];
+    const double L1 = ca + lam;
+    const double m11 = I.c + I.d00 * L1, m22 = I.c + I.d01 * L1;
+    const double m12 = -ca * I.d01, m21 = -ca * I.d00;
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
+    // g = Minv (E - D S), D = [[L1, -a], [-a, L1]]: coefficients of S
+    const double s00 = ca * i01 - L1 * i00, s01 = ca * i00 - L1 * i01;
+    const double s10 = ca * i11 - L1 * i10, s11 = ca * i10 - L1 * i11;
+    // E = e1 g^{n-1} + e2 g^{n-2} (BE: g^{n-1}/tau; BDF2: (2 g^{n-1} - g^{n-2}/2)/tau)
+    const double e1 = (bdf2 ? 2.0 : 1.0) * inv_tau, e2 = (bdf2 ? -0.5 : 0.0) * inv_tau;
+    double P0 = fma(i01, g01, i00 * g00), P1 = fma(i11, g01, i10 * g00);  // Minv g^{n-1}
+    double R0 = P0, R1 = P1;                                              // Minv g^{n-2}, g^{-1} := g^0
+    double gl0 = g00, gl1 = g01;                                          // newest level
+    double lv = 0.0;                                                      // no level >= 1 yet
+    int e_end;
+    double lvnew;
+    tb_steps<NP>(lane, L, bdf2, 0, N, N, nullptr, 0, np, e_end, lvnew, r, w, h, dk, N, dwin, g0k, e1, e2, s00, s01,
+                 s10, s11, i00, i01, i10, i11, P0, P1, R0, R1, gl0, gl1, lv);
     if (lane == 0) {
         double* gN = p.gN + 2 * I.mode_off;
         gN[mode] = gl0;
         gN[M + mode] = gl1;
+    }
+}
+
+// Fast form for few modes, time-blocked (tb_steps): one wave per mode runs
+// the steps n0+1..n0+nsteps. Its blocks are [jL, jL+L) of the whole run, so
+// a call that starts inside a block takes that block again from its start
+// (the same arithmetic, so the same levels) and the results do not depend
+// on how the run is cut into calls. State between calls: H = the state at
+// the start of the block that holds step n+1; ring2[i] = g^{n-i} for
+// n-i >= 0 (g^0 included), i < 2L.
+template <int NP>
+__global__ __launch_bounds__(256) void k_modal_fast_tb(ModalFastArgs p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t mode = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (mode >= p.M) return;  // uniform per wave
+    const int64_t M = p.M, twoM = 2 * M;
+    const int np = p.np, L = p.L;
+    const int k = lane >> 5, t = lane & 31;
+    const double* __restrict__ ratio = p.ratio + k * np;
+    const double* __restrict__ coef = p.coef + k * np;
+    const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
+    double* __restrict__ H = p.H + int64_t(k) * np * p.hstride + mode;
+    double r[NP], w[NP], h[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int j = t + 32 * q;
+        const bool ok = j < np;
+        r[q] = ok ? ratio[j] : 0.0;
+        w[q] = ok ? coef[j] : 0.0;
+        h[q] = ok ? H[int64_t(j) * p.hstride] : 0.0;
+    }
+    const double dwin = (t >= 1 && t < L) ? dk[t] : 0.0;
+    const double g00 = p.g0[mode], g01 = p.g0[M + mode];
+    const double g0k = k ? g01 : g00;
+    const bool bdf2 = p.scheme == 2;
+    const double ca = p.a, lam = p.lam[mode];
+    const double L1 = ca + lam;
+    const double m11 = p.c + p.d0[0] * L1, m22 = p.c + p.d0[1] * L1;
+    const double m12 = -ca * p.d0[1], m21 = -ca * p.d0[0];
+    const double idet = 1.0 / (m11 * m22 - m12 * m21);
+    const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
+    const double s00 = ca * i01 - L1 * i00, s01 = ca * i00 - L1 * i01;
+    const double s10 = ca * i11 - L1 * i10, s11 = ca * i10 - L1 * i11;
+    const double e1 = (bdf2 ? 2.0 : 1.0) * p.inv_tau, e2 = (bdf2 ? -0.5 : 0.0) * p.inv_tau;
+    // the start of the block that holds step n+1, its levels before it
+    const int64_t n = p.n0, ks = (n / L) * L, b = n - ks;
+    double* __restrict__ ring = p.ring + mode;
+    double lv = (t < L && ks - t >= 1) ? ring[(b + t) * twoM + k * M] : 0.0;
+    const double gm10 = ring[b * twoM], gm11 = ring[b * twoM + M];  // g^{ks} (g^0 at ks = 0)
+    const double gm20 = ks >= 1 ? ring[(b + 1) * twoM] : g00, gm21 = ks >= 1 ? ring[(b + 1) * twoM + M] : g01;
+    double P0 = fma(i01, gm11, i00 * gm10), P1 = fma(i11, gm11, i10 * gm10);
+    double R0 = fma(i01, gm21, i00 * gm20), R1 = fma(i11, gm21, i10 * gm20);
+    double gl0 = gm10, gl1 = gm11;
+    const int64_t nend = n + p.nsteps;
+    int e_end;
+    double lvnew = 0.0;
+    tb_steps<NP>(lane, L, bdf2, ks, nend, p.N, H, p.hstride, np, e_end, lvnew, r, w, h, dk, p.dstride - 1, dwin,
+                 g0k, e1, e2, s00, s01, s10, s11, i00, i01, i10, i11, P0, P1, R0, R1, gl0, gl1, lv);
+    if (e_end == 0) {  // ended on a block boundary: h is the next block's starting state
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int j = t + 32 * q;
+            if (j < np) H[int64_t(j) * p.hstride] = h[q];
+        }
+    }
+    // ring2[i] = g^{nend-i}: the block's levels taken so far (lvnew, newest
+    // first), then the levels before the block (lv); g^0 itself at level 0
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int i = t + 32 * half;
+        const int inew = e_end - 1 - i, iold = i - e_end;
+        const double vnew = __shfl(lvnew, (lane & 32) + (inew & 31), 64);
+        const double vold = __shfl(lv, (lane & 32) + (iold & 31), 64);
+        const int64_t l = nend - i;
+        const double v = l == 0 ? g0k : (l < 0 ? 0.0 : (inew >= 0 ? vnew : (iold < 32 ? vold : 0.0)));
+        if (i < 2 * L) ring[int64_t(i) * twoM + k * M] = v;
     }
 }
 
@@ -1609,10 +1766,31 @@ void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
     prof_end(5, st);
 }
 
+// time-blocked where the lag allows blocks of 8..32 steps and the nodes fit
+// 24 per lane over 32 lanes; otherwise a reduction per step
+bool modal_fast_blocked(int L, int np) { return L >= 8 && L <= 32 && (np + 31) / 32 <= 24; }
+
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st) {
     dim3 grid(unsigned((a.M + 3) / 4));
-    const int npl = (a.np + 63) / 64;
     prof_begin(7, st);
+    const int np32 = (a.np + 31) / 32;
+    if (modal_fast_blocked(a.L, a.np)) {
+        if (np32 <= 4)
+            hipLaunchKernelGGL(k_modal_fast_tb<4>, grid, dim3(256), 0, st, a);
+        else if (np32 <= 8)
+            hipLaunchKernelGGL(k_modal_fast_tb<8>, grid, dim3(256), 0, st, a);
+        else if (np32 <= 12)
+            hipLaunchKernelGGL(k_modal_fast_tb<12>, grid, dim3(256), 0, st, a);
+        else if (np32 <= 16)
+            hipLaunchKernelGGL(k_modal_fast_tb<16>, grid, dim3(256), 0, st, a);
+        else if (np32 <= 20)
+            hipLaunchKernelGGL(k_modal_fast_tb<20>, grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_modal_fast_tb<24>, grid, dim3(256), 0, st, a);
+        prof_end(7, st);
+        return;
+    }
+    const int npl = (a.np + 63) / 64;
     if (npl <= 1)
         hipLaunchKernelGGL(k_modal_fast<1>, grid, dim3(256), 0, st, a);
     else if (npl <= 2)

@@ -107,6 +107,9 @@ int far_ks_for(int ks, int64_t nl) { return int(std::max<int64_t>(1, std::min<in
 // values of the fast-history state H
 size_t hcount(const Solver& s) { return size_t(2) * size_t(s.np) * size_t(s.hstride); }
 
+// slots of the modal few-mode level ring (the time-blocked kernel keeps 2L)
+int ring_slots(const Solver& s) { return modal_fast_blocked(s.L, s.np) ? 2 * s.L : s.L; }
+
 int dev_alloc(Solver& s, double** ptr, size_t count) {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(double);
@@ -387,9 +390,11 @@ int modal_start(Solver& s) {
         HIPCHK(hipMemcpyAsync(s.levels, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
     } else if (s.p.method == 1) {
         HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), s.st));
-        HIPCHK(hipMemsetAsync(s.ring, 0, size_t(s.L) * size_t(twoM) * sizeof(double), s.st));
+        HIPCHK(hipMemsetAsync(s.ring, 0, size_t(ring_slots(s)) * size_t(twoM) * sizeof(double), s.st));
         HIPCHK(hipMemcpyAsync(s.ring, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
-        HIPCHK(hipMemcpyAsync(s.ring + twoM, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
+        if (!modal_fast_blocked(s.L, s.np))  // per-step ring: level -1 := level 0
+            HIPCHK(hipMemcpyAsync(s.ring + twoM, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice,
+                                  s.st));
     } else {
         HIPCHK(hipMemcpyAsync(s.levels, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, s.st));
     }
@@ -445,7 +450,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
                 if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr) * size_t(twoM)))) return rc;
                 if ((rc = dev_alloc(s, &s.Sf, size_t(int64_t(s.BTt) * twoM)))) return rc;
             } else {
-                if ((rc = dev_alloc(s, &s.ring, size_t(s.L) * size_t(twoM)))) return rc;
+                if ((rc = dev_alloc(s, &s.ring, size_t(ring_slots(s)) * size_t(twoM)))) return rc;
             }
         } else {
             if ((rc = dev_alloc(s, &s.levels, size_t(s.Lr * twoM)))) return rc;
@@ -578,6 +583,7 @@ void modal_steps(Solver& s, int64_t nsteps) {
             ModalFastArgs a{};
             a.M = s.M;
             a.n0 = s.n;
+            a.N = s.N;
             a.nsteps = chunk;
             a.np = s.np;
             a.L = s.L;
@@ -594,6 +600,7 @@ void modal_steps(Solver& s, int64_t nsteps) {
             a.d = s.d_d;
             a.g0 = s.g0c;
             a.H = s.H;
+            a.hstride = s.hstride;
             a.ring = s.ring;
             launch_modal_fast(a, s.st);
             s.n += chunk;
@@ -785,7 +792,7 @@ std::vector<Seg> state_segments(const Solver& s, int64_t n) {
         const size_t hb = hcount(s) * sizeof(double);
         if (s.p.solver == 1 && !s.modal_blocked) {
             v.push_back({s.H, hb});
-            v.push_back({s.ring, size_t(s.L) * twoM});
+            v.push_back({s.ring, size_t(ring_slots(s)) * twoM});
         } else {
             v.push_back({s.levels, size_t(s.Lr) * twoM});
             v.push_back({s.H, hb});
