@@ -217,3 +217,25 @@ def test_degenerate_grids_and_coupling(dim, nx, ny, m, solver):
             p = cq.make_params(0.05, 0.95, m, 1.0, N, scheme, method, solver=solver)
             out = cq.fp_solve(cq.make_grid(dim, nx, ny), p, dev(G0)).cpu().numpy()
             assert rel(out, ref) <= (1e-12 if method == 0 else 1e-8), (scheme, method, rel(out, ref))
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_modal_steps_in_uneven_chunks_bitwise(method, scheme, dim):
+    """fp_step in chunks that start and end inside the time blocks (direct:
+    64-step blocks and 128-step far passes; fast: L-step blocks) gives the
+    same levels, bit for bit, as one call."""
+    nx, ny = (40, 1) if dim == 1 else (9, 7)
+    N = 190
+    G0 = wl.g0_random(nx * ny, 41)
+    g = cq.make_grid(dim, nx, ny)
+    p = cq.make_params(0.35, 0.7, 0.6, 1.0, N, scheme, method, solver=cq.SOLVER_MODAL)
+    with cq.Solver(g, p, dev(G0)) as s:
+        s.step(N)
+        one = s.current()[0].cpu().numpy()
+    with cq.Solver(g, p, dev(G0)) as s:
+        for c in (1, 2, 29, 30, 31, 7, 64, 26):
+            s.step(c)
+        many = s.current()[0].cpu().numpy()
+    assert np.array_equal(one, many)
