@@ -1196,10 +1196,10 @@ __device__ __forceinline__ double pair_swap(double x) {
 
 // Fast form for many modes: the compressed state streams through
 // k_hist_block (time-blocked, exactly as for the nodal solver, here on the
-// sine coefficients; its node slices are then summed into slice 0), and this
-// kernel takes the bt <= 32 steps of the block. A lane pair owns one mode,
-// lane k of the pair component k. The history sum of step n is
-//   S_k^n = Sf[0][n - nblk][k]                      (lags >= L, fast part)
+// sine coefficients), and this kernel takes the bt <= 32 steps of the block.
+// A lane pair owns one mode, lane k of the pair component k. The history
+// sum of step n is
+//   S_k^n = Sf[n - nblk][k]                         (lags >= L, fast part)
 //         + sum_{i=1}^{min(L-1, n-1)} d_{k,i} g_k^{n-i}   (exact window),
 // accumulated in push form as in the direct near field: the window part of
 // the levels before this launch is added first (from the level store, slot
