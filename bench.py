@@ -281,12 +281,13 @@ def bench_adjoint(args):
             f_h += twoM * 4 * npn * bt
         work["hist_fast"] = (2 * b_h, 2 * f_h)          # forward and adjoint sweeps
         # the d/dalpha pass: Y^n = sum_{l=1}^{n} dw_{n-l} g^l for every step
-        # (2n flops per mode and component), in passes of 128 steps that read
-        # the levels 1..n0+bt once and write bt rows
+        # (2n flops per mode and component), in passes of 256 steps (128 below
+        # 8192 modes) that read the levels 1..n0+bt once and write bt rows
         f_far = sum(2 * n * twoM for n in range(1, N + 1))
         b_far = 0
-        for n0 in range(0, N, 128):
-            bt = min(128, N - n0)
+        pass_rows = 256 if M >= 8192 else 128
+        for n0 in range(0, N, pass_rows):
+            bt = min(pass_rows, N - n0)
             b_far += (n0 + bt) * twoM * 8 + bt * twoM * 8
         work["far_toeplitz"] = (b_far, f_far)
         # window steps, both sweeps: 2 flops per lag below L, Sf read, level and
