@@ -1550,30 +1550,40 @@ __global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
     if (threadIdx.x == 0) p.part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-// d/dbeta over one block of up to 64 steps, one thread per (component,
-// mode): F holds the whole CQ sum of the weight derivatives over levels
-// 1..n (k_far_toeplitz over levels up to the block's end); add BDF2's
-// starting correction and contract with psi.
+// d/dbeta over one time block: F holds the whole CQ sum of the weight
+// derivatives over levels 1..n (k_far_toeplitz over levels up to the
+// block's end); add BDF2's starting correction and contract with psi. A
+// workgroup covers 64 (component, mode) pairs; its 4 waves take a quarter
+// of the block's steps each (a column of F and psi per wave and step, read
+// coalesced), and the partial sums meet in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
-    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= 2 * p.M) return;
+    __shared__ double red[3][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t M = p.M, twoM = 2 * M, N = p.N;
-    const int k = int(e / M);
-    const int64_t mode = e - int64_t(k) * M;
-    const double g0 = p.traj[e];
+    const int64_t e = int64_t(blockIdx.x) * 64 + lane;
+    const bool ein = e < twoM;
+    const int64_t ec = ein ? e : twoM - 1;  // idle lanes read a valid column
+    const int k = int(ec / M);
+    const int64_t mode = ec - int64_t(k) * M;
+    const double g0 = p.traj[ec];
     const double* __restrict__ ddk = p.dd + int64_t(k) * p.dstride;
+    const int per = (p.bt + 3) >> 2;
+    const int b0 = w * per, b1 = min(p.bt, b0 + per);
     double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll 8
-    for (int b = 0; b < p.bt; ++b) {
+#pragma unroll 4
+    for (int b = b0; b < b1; ++b) {
         const int64_t n = p.n0 + 1 + b;
         double Y = p.F[(int64_t(b) * 2 + k) * M + mode];
         if (p.scheme == 2) Y = fma(0.5 * ddk[n - 1], g0, Y);
         if (b & 1)
-            acc1 = fma(p.psi[(N + 1 - n) * twoM + e], Y, acc1);
+            acc1 = fma(p.psi[(N + 1 - n) * twoM + ec], Y, acc1);
         else
-            acc0 = fma(p.psi[(N + 1 - n) * twoM + e], Y, acc0);
+            acc0 = fma(p.psi[(N + 1 - n) * twoM + ec], Y, acc0);
     }
-    p.acc[e] += acc0 + acc1;
+    const double v = acc0 + acc1;
+    if (w) red[w - 1][lane] = v;
+    __syncthreads();
+    if (w == 0 && ein) p.acc[e] += ((v + red[0][lane]) + red[1][lane]) + red[2][lane];
 }
 
 // per-component sums of acc[2][M]: partials part[k][block]
@@ -1886,7 +1896,7 @@ int launch_adj_da(const AdjGradArgs& a, hipStream_t st) {
 }
 
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_beta, dim3(unsigned((2 * a.M + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_beta, dim3(unsigned((2 * a.M + 63) / 64)), dim3(256), 0, st, a);
 }
 
 int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st) {
