@@ -21,6 +21,8 @@
 namespace cqfp {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+// read-only data that a wave reads at uniform addresses (scalar loads)
+typedef __attribute__((address_space(4))) const double cdouble;
 
 __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -93,8 +95,12 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
     // state rows are hstride (a multiple of 256) long: every lane owns a slot
     const int64_t hs = p.hstride;
     double* __restrict__ h = p.H + (int64_t(k) * p.np) * hs + x;
-    const double* __restrict__ r = p.ratio + k * p.np;
-    const double* __restrict__ w = p.coef + k * p.np;
+    // ratios and coefficients are wave-uniform: read through the constant
+    // address space they become scalar loads, which the wait for a group's
+    // state (vector memory counter) does not include, so the next group's
+    // state loads stay in flight while this group is advanced
+    const cdouble* r = (const cdouble*)(p.ratio + k * p.np);
+    const cdouble* w = (const cdouble*)(p.coef + k * p.np);
     // four nodes per group (independent recurrences interleave); the states
     // of the next group are loaded before this group is advanced, so a load
     // is in flight while the previous one is used. A full block (bt == BT)
