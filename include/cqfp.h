@@ -201,9 +201,14 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
  * is exact for the direct scheme; for the fast scheme beyond its lag the
  * rule's factor tau^-beta is differentiated exactly and the rest by a
  * fourth-order difference in beta of the rebuilt Gauss-Jacobi rule (below
- * 1e-11 relative). The forward trajectory, its history sums and the adjoint
- * (psi, mu) are kept in device memory: 4 (N+1) 2M doubles (CQ_ENOMEM
- * beyond the free memory). Device work runs on hip_stream; the call
+ * 1e-11 relative). The alpha contraction sum_n psi^n . sum_l dw_{n-l} g^l
+ * runs in the frequency domain for N <= 4096 (steps in blocks of up to 256,
+ * one 512-point FFT per block, mode and component, and the block pairs
+ * contracted with the spectra of the weight windows between them), else as
+ * Toeplitz products; setting the environment variable CQFP_BETA_TOEPLITZ
+ * (not "0") when the handle is made selects the Toeplitz form at any N. The forward trajectory, its history
+ * sums and the adjoint (psi, mu) are kept in device memory: 4 (N+1) 2M
+ * doubles (CQ_ENOMEM beyond the free memory). Device work runs on hip_stream; the call
  * synchronises it. Errors as fp_create, plus CQ_EINVAL for solver != 1 or
  * a fast window (ns) above 32. */
 int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN,
@@ -262,8 +267,10 @@ int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_params* param
  * 5 DST GEMM (forward/inverse and per-mode solve), 6 standalone history
  * reduction, 7 modal fast steps, 8 modal direct near field + solve,
  * 9 batched modal fast time loops, 10 sum of the far field's K-split
- * partials. cq_prof_read synchronises the recorded events and returns, for
- * one kind, the launch count and the summed duration in milliseconds.
+ * partials, 11 time-series transposes of the adjoint, 12 the adjoint's
+ * spectral d/dbeta contraction (FFT per column and dot). cq_prof_read
+ * synchronises the recorded events and returns, for one kind, the launch
+ * count and the summed duration in milliseconds.
  * cq_prof_enable(1) also clears earlier records. Not thread safe. */
 int cq_prof_enable(int32_t on);
 int cq_prof_read(int32_t kind, int64_t* launches, double* total_ms);

@@ -26,7 +26,8 @@ EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "
            "fp_adjoint", "fp_adjoint_create", "fp_adjoint_run", "cq_prof_enable", "cq_prof_read",
            "cq_last_error"]
 PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
-              "reduce_row": 6, "modal_fast": 7, "modal_near": 8, "batched": 9, "reduce_far": 10}
+              "reduce_row": 6, "modal_fast": 7, "modal_near": 8, "batched": 9, "reduce_far": 10,
+              "transpose": 11, "beta_spec": 12}
 
 
 class CQError(RuntimeError):

@@ -196,6 +196,27 @@ struct AdjBetaArgs {
     double* acc;           // [2][M]
 };
 
+// d/dbeta through block DFTs, block pairs d >= 2: per column e of [2][M]
+// (component k = e / M), a_t = psi^{t+1}, b_t = g^{t+1} for t < N, in nb > 2
+// blocks of Bk = P/2 steps
+constexpr int kSpecMaxLds = 8192;  // nb * P complex doubles (128 KB of LDS)
+struct BetaSpecArgs {
+    int64_t N, M;
+    int nb, P, logP;      // P = 2^logP = 2 Bk, nb = ceil(N / Bk), nb P <= kSpecMaxLds
+    int cols;             // modes per workgroup (blockIdx.x), component blockIdx.y
+    const double* psiT;   // [2M][N] columns a
+    const double* gT;     // [2M][N] columns b
+    const double* tw;     // [P/2][2] exp(-2 pi i j / P)
+    double* spec;         // [2][nwg][(nb-2)(Bk+1)][2] partial block spectra X_{d,f}, d >= 2
+};
+
+struct BetaDotArgs {
+    int nb, P, nwg;
+    const double* spec;   // as in BetaSpecArgs
+    const double* W;      // [2][nb (Bk+1)][2] window spectra, every d
+    double* part;         // [2][blocks]
+};
+
 // one problem of a batch (device table entry)
 struct BatchInst {
     int64_t mode_off;     // first mode of the problem in the concatenated arrays
@@ -228,6 +249,12 @@ int launch_adj_da(const AdjGradArgs& a, hipStream_t st);
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st);
 // out[k] = sum_x acc[k][x] over blocks: partials [2][blocks]; returns blocks
 int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st);
+void launch_cols_transpose(const double* src, int64_t row0, int dir, int64_t ncols, int64_t nt, double* dst,
+                           hipStream_t st);
+void launch_beta_spec(const BetaSpecArgs& a, int nwg, hipStream_t st);
+void launch_fft_w(const double* dw, int64_t dwstride, int64_t N, int nb, int P, int logP, const double* tw,
+                  double* W, hipStream_t st);
+int launch_beta_dot(const BetaDotArgs& a, hipStream_t st);  // returns blocks per component
 void launch_hist_block(const HistBlockArgs& a, int lanes, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);

@@ -1592,6 +1592,187 @@ __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
     if (w == 0 && ein) p.acc[e] += ((v + red[0][lane]) + red[1][lane]) + red[2][lane];
 }
 
+// ---------------------------------------------------------------------------
+// d/dbeta in the frequency domain, block by block. With a_t = psi^{t+1},
+// b_t = g^{t+1} and c = dw * b (c_t = Y^{t+1} without BDF2's g^0 term), cut
+// the steps into nb blocks of Bk; block i of a and block j of b (i >= j)
+// meet only through the lags (i-j) Bk + r, |r| < Bk, i.e. through the window
+// w_d[r] = dw_{d Bk + r}, d = i - j. Zero-padded to P = 2 Bk points the
+// circular correlation of the pair is the linear one, and Parseval gives
+//   sum_t a_t c_t = (1/P) sum_d sum_f W_{d,f} sum_j conj(A^(j+d)_f) B^(j)_f,
+// with A^(i), B^(j) the P-point DFTs of the blocks and W_d that of the
+// window. Rounding of a block pair scales with |a| |b| over the pair times
+// the weights of its window, not with the products that occur (for a fast-
+// decaying mode a is large where b is negligible), so the pairs d = 0, 1,
+// whose windows hold the largest weights, are summed exactly (Toeplitz
+// products over the levels of the previous and the current block) and only
+// d >= 2 (lags above Bk) here: (1/P) sum_{d>=2,f} W_{d,f} X_{d,f}, X summed
+// over the modes, nb FFTs and (nb-2)(nb-1)/2 block products of Bk+1
+// frequencies per mode. Both real blocks share one complex FFT, z = a + i b:
+//   A_f = (Z_f + conj Z_{P-f}) / 2,   B_f = (Z_f - conj Z_{P-f}) / (2i).
+
+// dst[c][t] = src[(row0 + dir * t) * ncols + c] for c < ncols, t < nt: time
+// series of the time-major [rows][ncols] arrays as contiguous columns
+// (64 x 64 tiles through LDS, both sides coalesced)
+__global__ __launch_bounds__(256) void k_cols_transpose(const double* __restrict__ src, int64_t row0, int dir,
+                                                        int64_t ncols, int64_t nt, double* __restrict__ dst) {
+    __shared__ double tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t c0 = int64_t(blockIdx.x) * 64, t0 = int64_t(blockIdx.y) * 64;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t t = t0 + r, c = c0 + tx;
+        if (t < nt && c < ncols) tile[r][tx] = src[(row0 + dir * t) * ncols + c];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t c = c0 + r, t = t0 + tx;
+        if (t < nt && c < ncols) dst[c * nt + t] = tile[tx][r];
+    }
+}
+
+// nb in-place radix-2 FFTs (decimation in time) of P = 2^logP complex values
+// each, side by side in LDS (block i at z + i P): input in bit-reversed
+// order, output X_f = sum_t x_t exp(-2 pi i f t / P) in natural order;
+// tw[j] = exp(-2 pi i j / P), j < P/2. Ends synchronised.
+__device__ void lds_fft_batch(double2* z, int nb, int P, int logP, const double2* __restrict__ tw) {
+    const int hP = P >> 1;
+    for (int s = 0; s < logP; ++s) {
+        const int half = 1 << s;
+        for (int t = threadIdx.x; t < nb * hP; t += blockDim.x) {
+            const int blk = t >> (logP - 1), tt = t & (hP - 1);
+            const int pos = tt & (half - 1);
+            const int i = blk * P + (((tt >> s) << (s + 1)) | pos);
+            const int j = i + half;
+            const double2 w = tw[pos << (logP - 1 - s)];
+            const double2 u = z[i], v = z[j];
+            const double vr = v.x * w.x - v.y * w.y;
+            const double vi = v.x * w.y + v.y * w.x;
+            z[i] = make_double2(u.x + vr, u.y + vi);
+            z[j] = make_double2(u.x - vr, u.y - vi);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int bit_reverse(int t, int logP) {
+    return logP ? int(__builtin_bitreverse32(unsigned(t)) >> (32 - logP)) : 0;
+}
+
+// X_{d,f} over the modes [blockIdx.x * cols, +cols) of component blockIdx.y:
+// per mode, load the nb blocks (a, b) into LDS in bit-reversed order, FFT
+// them, and add sum_j conj(A^(j+d)_f) B^(j)_f for the (d, f), d >= 2,
+// f <= Bk, that the thread owns (q = (d-2)(Bk+1) + f = tid + 1024 r) into
+// registers. Partial spectra per workgroup, summed in k_beta_dot in a fixed
+// order.
+__global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
+    __shared__ double2 z[kSpecMaxLds];
+    constexpr int QR = kSpecMaxLds / 2 / 1024 + 1;
+    const int k = blockIdx.y, tid = threadIdx.x;
+    const int P = p.P, logP = p.logP, Bk = P >> 1, nb = p.nb, Q = (nb - 2) * (Bk + 1);
+    const double2* __restrict__ tw = reinterpret_cast<const double2*>(p.tw);
+    double xr[QR], xi[QR];
+#pragma unroll
+    for (int r = 0; r < QR; ++r) xr[r] = xi[r] = 0.0;
+    const int64_t m0 = int64_t(blockIdx.x) * p.cols;
+    const int64_t m1 = (m0 + p.cols < p.M) ? m0 + p.cols : p.M;
+    for (int64_t mode = m0; mode < m1; ++mode) {
+        const int64_t e = int64_t(k) * p.M + mode;
+        const double* __restrict__ a = p.psiT + e * p.N;
+        const double* __restrict__ b = p.gT + e * p.N;
+        for (int t = tid; t < nb * P; t += 1024) {
+            const int blk = t >> logP, u = t & (P - 1);
+            const int64_t tg = int64_t(blk) * Bk + u;
+            double av = 0.0, bv = 0.0;
+            if (u < Bk && tg < p.N) {
+                av = a[tg];
+                bv = b[tg];
+            }
+            z[blk * P + bit_reverse(u, logP)] = make_double2(av, bv);
+        }
+        __syncthreads();
+        lds_fft_batch(z, nb, P, logP, tw);
+#pragma unroll
+        for (int r = 0; r < QR; ++r) {
+            const int q = tid + 1024 * r;
+            if (q < Q) {
+                const int d = 2 + q / (Bk + 1), f = q % (Bk + 1), fc = (P - f) & (P - 1);
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j + d < nb; ++j) {
+                    const double2 zif = z[(j + d) * P + f], zic = z[(j + d) * P + fc];
+                    const double2 zjf = z[j * P + f], zjc = z[j * P + fc];
+                    const double ar = 0.5 * (zif.x + zic.x), ai = 0.5 * (zif.y - zic.y);
+                    const double br = 0.5 * (zjf.y + zjc.y), bi = -0.5 * (zjf.x - zjc.x);
+                    sr += ar * br + ai * bi;  // conj(A) B
+                    si += ar * bi - ai * br;
+                }
+                xr[r] += sr;
+                xi[r] += si;
+            }
+        }
+        __syncthreads();  // z is reloaded by the next mode
+    }
+    double* __restrict__ out = p.spec + (int64_t(k) * gridDim.x + blockIdx.x) * int64_t(Q) * 2;
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+        const int q = tid + 1024 * r;
+        if (q < Q) {
+            out[2 * q] = xr[r];
+            out[2 * q + 1] = xi[r];
+        }
+    }
+}
+
+// W_{d,f}^(k): P-point DFTs of the windows w_d[r] = dw_{k, d Bk + r} (r in
+// (-Bk, Bk) at index r mod P; lags below 0 or from N on are 0), both
+// components from one complex FFT (z = w^(0) + i w^(1)): W[k][d][f][re, im],
+// f <= Bk. One workgroup.
+__global__ __launch_bounds__(1024) void k_fft_w(const double* __restrict__ dw, int64_t dwstride, int64_t N,
+                                                int nb, int P, int logP, const double* __restrict__ twp,
+                                                double* __restrict__ W) {
+    __shared__ double2 z[kSpecMaxLds];
+    const int Bk = P >> 1, Q = nb * (Bk + 1);
+    for (int t = threadIdx.x; t < nb * P; t += 1024) {
+        const int d = t >> logP, r = t & (P - 1);
+        const int64_t lag = int64_t(d) * Bk + (r < Bk ? r : r - P);
+        const bool ok = r != Bk && lag >= 0 && lag < N;
+        z[d * P + bit_reverse(r, logP)] = ok ? make_double2(dw[lag], dw[dwstride + lag]) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    lds_fft_batch(z, nb, P, logP, reinterpret_cast<const double2*>(twp));
+    for (int q = threadIdx.x; q < Q; q += 1024) {
+        const int d = q / (Bk + 1), f = q - d * (Bk + 1);
+        const double2 zf = z[d * P + f], zc = z[d * P + ((P - f) & (P - 1))];
+        W[2 * q] = 0.5 * (zf.x + zc.x);
+        W[2 * q + 1] = 0.5 * (zf.y - zc.y);
+        W[2 * (Q + q)] = 0.5 * (zf.y + zc.y);
+        W[2 * (Q + q) + 1] = -0.5 * (zf.x - zc.x);
+    }
+}
+
+// part[k][block] = (1/P) sum over the block's q = (d-2)(Bk+1) + f, d >= 2,
+// of w_f Re(W_{d,f} X_q), X_q the sum of the nwg partial spectra (in order),
+// w_f = 1 at f = 0 and Bk, else 2 (the conjugate half). grid (blocks, 2),
+// 64 threads.
+__global__ __launch_bounds__(64) void k_beta_dot(BetaDotArgs p) {
+    const int Bk = p.P >> 1, Q = (p.nb - 2) * (Bk + 1), QW = p.nb * (Bk + 1), k = blockIdx.y;
+    const int q = blockIdx.x * 64 + threadIdx.x;
+    double v = 0.0;
+    if (q < Q) {
+        const int f = q % (Bk + 1);
+        double xr = 0.0, xi = 0.0;
+        const double* __restrict__ sp = p.spec + (int64_t(k) * p.nwg * Q + q) * 2;
+        for (int g = 0; g < p.nwg; ++g) {
+            xr += sp[int64_t(g) * Q * 2];
+            xi += sp[int64_t(g) * Q * 2 + 1];
+        }
+        const double* __restrict__ w = p.W + (int64_t(k) * QW + 2 * (Bk + 1) + q) * 2;
+        v = ((f == 0 || f == Bk) ? 1.0 : 2.0) * (w[0] * xr - w[1] * xi);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (threadIdx.x == 0) p.part[int64_t(k) * gridDim.x + blockIdx.x] = v / double(p.P);
+}
+
 // per-component sums of acc[2][M]: partials part[k][block]
 __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ acc, int64_t M, int64_t per,
                                                   double* __restrict__ part) {
@@ -1903,6 +2084,33 @@ int launch_adj_da(const AdjGradArgs& a, hipStream_t st) {
 
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_beta, dim3(unsigned((2 * a.M + 63) / 64)), dim3(256), 0, st, a);
+}
+
+void launch_cols_transpose(const double* src, int64_t row0, int dir, int64_t ncols, int64_t nt, double* dst,
+                           hipStream_t st) {
+    prof_begin(11, st);
+    hipLaunchKernelGGL(k_cols_transpose, dim3(unsigned((ncols + 63) / 64), unsigned((nt + 63) / 64)), dim3(256), 0,
+                       st, src, row0, dir, ncols, nt, dst);
+    prof_end(11, st);
+}
+
+void launch_beta_spec(const BetaSpecArgs& a, int nwg, hipStream_t st) {
+    prof_begin(12, st);
+    hipLaunchKernelGGL(k_beta_spec, dim3(unsigned(nwg), 2), dim3(1024), 0, st, a);
+    prof_end(12, st);
+}
+
+void launch_fft_w(const double* dw, int64_t dwstride, int64_t N, int nb, int P, int logP, const double* tw,
+                  double* W, hipStream_t st) {
+    hipLaunchKernelGGL(k_fft_w, dim3(1), dim3(1024), 0, st, dw, dwstride, N, nb, P, logP, tw, W);
+}
+
+int launch_beta_dot(const BetaDotArgs& a, hipStream_t st) {
+    const int blocks = ((a.nb - 2) * ((a.P >> 1) + 1) + 63) / 64;
+    prof_begin(12, st);
+    hipLaunchKernelGGL(k_beta_dot, dim3(unsigned(blocks), 2), dim3(64), 0, st, a);
+    prof_end(12, st);
+    return blocks;
 }
 
 int launch_sum_rows(const double* acc, int64_t M, double* part, hipStream_t st) {

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -37,6 +38,13 @@ struct AdjBufs {
     double *traj = nullptr, *Sx = nullptr, *psi = nullptr, *mu = nullptr, *gc = nullptr, *gG0c = nullptr,
            *acc = nullptr, *dw = nullptr, *dd = nullptr, *part = nullptr, *part2 = nullptr;
     int nblk_da = 0, nblk_rows = 0, nchunk = 1;
+    // d/dbeta in blocks of spec_bk steps (0: Toeplitz passes over all
+    // levels): exact near field over the previous and the current block, and
+    // for nb > 2 blocks the farther block pairs through block DFTs of P =
+    // 2 spec_bk points (twiddles, window spectra of dw, partial spectra per
+    // workgroup, per-block dot products)
+    double *tw = nullptr, *W = nullptr, *spec = nullptr, *bpart = nullptr;
+    int spec_bk = 0, specP = 0, specLog = 0, spec_nb = 0, spec_nwg = 0, spec_cols = 0, nblk_dot = 0;
 };
 
 struct Solver {
@@ -814,7 +822,7 @@ size_t state_bytes(const Solver& s) {
 
 // ---- kernel timing ----
 namespace {
-constexpr int kProfKinds = 11;
+constexpr int kProfKinds = 13;
 struct ProfRec {
     hipEvent_t a, b;
 };
@@ -1193,7 +1201,24 @@ static int adjoint_setup(Solver& s) {
     s.B = 64;
     s.Bf = p->block_B ? p->block_B : modal_far_pass(M);
     s.ks = far_ksplit(M);
-    const size_t frows = size_t(s.ks) * size_t(std::max(s.B, s.Bf)) * size_t(twoM);
+    AdjBufs& A = s.ab;
+    // d/dbeta: blocks of about N/8 steps (a power of two, at most 256) while
+    // their P-point transforms fit in LDS (N <= 4096), unless
+    // CQFP_BETA_TOEPLITZ is set; else Toeplitz passes over all levels
+    const char* force_toeplitz = std::getenv("CQFP_BETA_TOEPLITZ");
+    {
+        int lb = 0;
+        while ((int64_t(8) << lb) < N && lb < 8) ++lb;
+        const int Bk = 1 << lb;
+        const int64_t nb = (N + Bk - 1) / Bk;
+        if (nb * 2 * Bk <= kSpecMaxLds && !(force_toeplitz && force_toeplitz[0] && force_toeplitz[0] != '0')) {
+            A.spec_bk = Bk;
+            A.specP = 2 * Bk;
+            A.specLog = lb + 1;
+            A.spec_nb = int(nb);
+        }
+    }
+    const size_t frows = size_t(s.ks) * size_t(std::max({s.B, s.Bf, A.spec_bk})) * size_t(twoM);
     {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
@@ -1201,7 +1226,6 @@ static int adjoint_setup(Solver& s) {
         if (need > fr)
             return fail(CQ_ENOMEM, "the adjoint keeps 4 x (N+1) x 2M values (%zu bytes); %zu bytes free", need, fr);
     }
-    AdjBufs& A = s.ab;
     if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
     if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
@@ -1260,6 +1284,27 @@ static int adjoint_setup(Solver& s) {
     }
     if ((rc = upload(A.dw, hdw))) return rc;
     if ((rc = upload(A.dd, hdd))) return rc;
+    if (A.spec_nb > 2) {
+        const int Bk = A.spec_bk, P = A.specP, nb = A.spec_nb;
+        const int Q = (nb - 2) * (Bk + 1);
+        const int64_t nwg = std::min<int64_t>(128, M);  // 2 x 128 workgroups: one per CU
+        A.spec_cols = int((M + nwg - 1) / nwg);
+        A.spec_nwg = int((M + A.spec_cols - 1) / A.spec_cols);
+        A.nblk_dot = (Q + 63) / 64;
+        std::vector<double> htw(static_cast<size_t>(P));
+        for (int j = 0; j < Bk; ++j) {
+            const double ang = 2.0 * std::acos(-1.0) * double(j) / double(P);
+            htw[size_t(2 * j)] = std::cos(ang);
+            htw[size_t(2 * j + 1)] = -std::sin(ang);
+        }
+        if ((rc = dev_alloc(s, &A.tw, size_t(P)))) return rc;
+        if ((rc = upload(A.tw, htw))) return rc;
+        if ((rc = dev_alloc(s, &A.W, size_t(4) * size_t(nb) * size_t(Bk + 1)))) return rc;
+        if ((rc = dev_alloc(s, &A.spec, size_t(4) * size_t(A.spec_nwg) * size_t(Q)))) return rc;
+        if ((rc = dev_alloc(s, &A.bpart, size_t(2 * A.nblk_dot)))) return rc;
+        launch_fft_w(A.dw + kDwPad, s.dstride + kDwPad, N, nb, P, A.specLog, A.tw, A.W, st);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipStreamSynchronize(st));
     s.kind = 1;
     return CQ_OK;
@@ -1330,23 +1375,30 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     launch_adj_g0(ga, st);
     transform(s, gG0c, gG0, true);  // dl/dG0 = P^T dl/dg^0, P = scaled S, symmetric
     launch_adj_da(ga, st);
+    // d/dbeta: Toeplitz products of the weight derivatives, over all levels
+    // in passes of Bf steps, or in blocks of spec_bk steps over the levels of
+    // the previous and the current block only (the farther block pairs
+    // follow through block DFTs); BDF2's g^0 term enters with the contraction
     HIPCHK(hipMemsetAsync(acc, 0, size_t(twoM) * sizeof(double), st));
-    for (int64_t n0 = 0; n0 < N; n0 += s.Bf) {
-        const int bt = int(std::min<int64_t>(s.Bf, N - n0));
-        // CQ sums of the weight derivatives over levels 1..n for the block's
-        // steps (blocks of Bf <= kDwPad): one Toeplitz product over levels
-        // 1..n0+bt (negative lags read the zero padding in front of each
+    const int rows = A.spec_bk ? A.spec_bk : s.Bf;
+    for (int64_t n0 = 0; n0 < N; n0 += rows) {
+        const int bt = int(std::min<int64_t>(rows, N - n0));
+        // CQ sums of the weight derivatives over levels l0..n for the block's
+        // steps (blocks of <= kDwPad steps): one Toeplitz product over levels
+        // l0..n0+bt (negative lags read the zero padding in front of each
         // component's row)
         FarArgs fa{};
         fa.n0 = n0;
+        fa.l0 = A.spec_bk ? std::max<int64_t>(1, n0 - rows + 1) : 1;
         fa.nl = n0 + bt;
         fa.M = M;
         fa.dstride = s.dstride + kDwPad;
         fa.lstride = twoM;
-        fa.B = s.Bf;
-        fa.ks = far_ks_for(s.ks, fa.nl);
+        fa.B = rows;
+        const int64_t nlev = fa.nl - fa.l0 + 1;
+        fa.ks = far_ks_for(s.ks, nlev);
         fa.ncomp = 2;
-        const int64_t mc = (fa.nl + fa.ks - 1) / fa.ks;
+        const int64_t mc = (nlev + fa.ks - 1) / fa.ks;
         fa.mchunk = ((mc + 3) / 4) * 4;
         fa.levels = traj;
         fa.d = dw + kDwPad;
@@ -1370,15 +1422,49 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     }
     launch_sum_rows(acc, M, part2, st);
     HIPCHK(hipGetLastError());
-    std::vector<double> hp(static_cast<size_t>(nblk_da)), hp2(static_cast<size_t>(2 * nblk_rows));
+    if (A.spec_nb > 2) {
+        // columns a_t = psi^{t+1} (stored in reversed time, row N - t) and
+        // b_t = g^{t+1} into mu and Sx, which the passes above were the last to read
+        launch_cols_transpose(psi, N, -1, twoM, N, mu, st);
+        launch_cols_transpose(traj, 1, 1, twoM, N, Sx, st);
+        BetaSpecArgs bs{};
+        bs.N = N;
+        bs.M = M;
+        bs.nb = A.spec_nb;
+        bs.P = A.specP;
+        bs.logP = A.specLog;
+        bs.cols = A.spec_cols;
+        bs.psiT = mu;
+        bs.gT = Sx;
+        bs.tw = A.tw;
+        bs.spec = A.spec;
+        launch_beta_spec(bs, A.spec_nwg, st);
+        BetaDotArgs bd{};
+        bd.nb = A.spec_nb;
+        bd.P = A.specP;
+        bd.nwg = A.spec_nwg;
+        bd.spec = A.spec;
+        bd.W = A.W;
+        bd.part = A.bpart;
+        launch_beta_dot(bd, st);
+        HIPCHK(hipGetLastError());
+    }
+    std::vector<double> hp(static_cast<size_t>(nblk_da)), hp2(static_cast<size_t>(2 * nblk_rows)),
+        hb(static_cast<size_t>(2 * A.nblk_dot));
     HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(hp2.data(), part2, hp2.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (A.spec_nb > 2)
+        HIPCHK(hipMemcpyAsync(hb.data(), A.bpart, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     double sa = 0.0, sb0 = 0.0, sb1 = 0.0;
     for (double v : hp) sa += v;
     for (int i = 0; i < nblk_rows; ++i) {
         sb0 += hp2[size_t(i)];
         sb1 += hp2[size_t(nblk_rows + i)];
+    }
+    for (int i = 0; i < A.nblk_dot; ++i) {
+        sb0 += hb[size_t(i)];
+        sb1 += hb[size_t(A.nblk_dot + i)];
     }
     const double da_dm = -1.0 / ((2.0 * p->m - 1.0) * (2.0 * p->m - 1.0));
     grad[0] = sb0;            // dl/dalpha_1 = -dl/dbeta_1
