@@ -259,7 +259,7 @@ def bench_adjoint(args):
     oneshot_s = time.perf_counter() - ts
     M = nx * ny
     # kernel timing: one more gradient outside the timed region
-    kinds = ["hist_fast", "far_toeplitz", "reduce_far", "modal_fast", "dst_gemm"]
+    kinds = ["hist_fast", "far_toeplitz", "reduce_far", "modal_fast", "dst_gemm", "transpose", "beta_spec"]
     ktime = {}
     roofline = None
     if not args.no_prof:
@@ -280,16 +280,24 @@ def bench_adjoint(args):
             b_h += twoM * 8 * (2 * npn + 2 * bt)
             f_h += twoM * 4 * npn * bt
         work["hist_fast"] = (2 * b_h, 2 * f_h)          # forward and adjoint sweeps
-        # the d/dalpha pass: Y^n = sum_{l=1}^{n} dw_{n-l} g^l for every step
-        # (2n flops per mode and component), in passes of 256 steps (128 below
-        # 8192 modes) that read the levels 1..n0+bt once and write bt rows
-        f_far = sum(2 * n * twoM for n in range(1, N + 1))
-        b_far = 0
-        pass_rows = 256 if M >= 8192 else 128
-        for n0 in range(0, N, pass_rows):
-            bt = min(pass_rows, N - n0)
-            b_far += (n0 + bt) * twoM * 8 + bt * twoM * 8
+        # the d/dalpha contraction's near field: blocks of Bk = 256 steps, each
+        # step n of block i summing dw_{n-l} g^l over the levels l of blocks
+        # i-1 and i up to n (2 flops per product, mode and component); a
+        # block reads those levels once and writes its rows
+        Bk = 256
+        f_far, b_far = 0, 0
+        for n0 in range(0, N, Bk):
+            bt = min(Bk, N - n0)
+            l0 = max(1, n0 - Bk + 1)
+            f_far += sum(2 * (n - l0 + 1) * twoM for n in range(n0 + 1, n0 + bt + 1))
+            b_far += (n0 + bt - l0 + 1) * twoM * 8 + bt * twoM * 8
         work["far_toeplitz"] = (b_far, f_far)
+        # its farther block pairs: per mode and component 16 FFTs of 512 points
+        # (5 P log2 P flops each) and 105 block products of 257 frequencies
+        # (8 flops each), reading psi and g (N doubles each)
+        nb, P = N // Bk, 2 * Bk
+        work["beta_spec"] = (twoM * 2 * N * 8, twoM * (nb * 5 * P * 9 + (nb - 2) * (nb - 1) // 2 * (Bk + 1) * 8))
+        work["transpose"] = (2 * 2 * N * twoM * 8, 0)
         # window steps, both sweeps: 2 flops per lag below L, Sf read, level and
         # S (forward) or mu (adjoint) written
         work["modal_fast"] = (2 * N * twoM * 8 * 3, 2 * N * twoM * 2 * (L - 1))
