@@ -200,6 +200,7 @@ struct AdjBetaArgs {
 // (component k = e / M), a_t = psi^{t+1}, b_t = g^{t+1} for t < N, in nb > 2
 // blocks of Bk = P/2 steps
 constexpr int kSpecMaxLds = 8192;  // nb * P complex doubles (128 KB of LDS)
+constexpr int kSpecMaxP = 512;     // blocks of at most 256 steps
 struct BetaSpecArgs {
     int64_t N, M;
     int nb, P, logP;      // P = 2^logP = 2 Bk, nb = ceil(N / Bk), nb P <= kSpecMaxLds

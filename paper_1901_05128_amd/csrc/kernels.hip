@@ -1630,25 +1630,55 @@ __global__ __launch_bounds__(256) void k_cols_transpose(const double* __restrict
     }
 }
 
-// nb in-place radix-2 FFTs (decimation in time) of P = 2^logP complex values
-// each, side by side in LDS (block i at z + i P): input in bit-reversed
-// order, output X_f = sum_t x_t exp(-2 pi i f t / P) in natural order;
-// tw[j] = exp(-2 pi i j / P), j < P/2. Ends synchronised.
-__device__ void lds_fft_batch(double2* z, int nb, int P, int logP, const double2* __restrict__ tw) {
-    const int hP = P >> 1;
-    for (int s = 0; s < logP; ++s) {
-        const int half = 1 << s;
+// nb in-place FFTs (decimation in time) of P = 2^logP complex values each,
+// side by side in LDS (block i at z + i P): input in bit-reversed order,
+// output X_f = sum_t x_t exp(-2 pi i f t / P) in natural order; tw[j] =
+// exp(-2 pi i j / P), j < P/2 (in LDS). The radix-2 stages go in pairs: a
+// thread takes four values i, i+h, i+2h, i+3h (h = 2^s) through stage s
+// (pairs (i, i+h), (i+2h, i+3h), twiddle W_2h^pos) and stage s+1 (pairs
+// (i, i+2h) with W_4h^pos, (i+h, i+3h) with W_4h^(pos+h)) in registers, so
+// the values cross LDS once per two stages; an odd last stage is radix 2.
+// Ends synchronised.
+__device__ __forceinline__ double2 cmul(double2 a, double2 w) {
+    return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+
+__device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int logP, const double2* tw) {
+    int s = 0;
+    for (; s + 1 < logP; s += 2) {
+        const int h = 1 << s, qP = P >> 2;
+        for (int t = threadIdx.x; t < nb * qP; t += blockDim.x) {
+            const int blk = t >> (logP - 2), tt = t & (qP - 1);
+            const int pos = tt & (h - 1);
+            const int i = blk * P + ((tt >> s) << (s + 2)) + pos;
+            double2 a = z[i], b = z[i + h], c = z[i + 2 * h], d = z[i + 3 * h];
+            const double2 w1 = tw[pos << (logP - 1 - s)];
+            const double2 w2 = tw[pos << (logP - 2 - s)];
+            const double2 w3 = tw[(pos + h) << (logP - 2 - s)];
+            double2 u = cmul(b, w1);
+            b = make_double2(a.x - u.x, a.y - u.y);
+            a = make_double2(a.x + u.x, a.y + u.y);
+            u = cmul(d, w1);
+            d = make_double2(c.x - u.x, c.y - u.y);
+            c = make_double2(c.x + u.x, c.y + u.y);
+            u = cmul(c, w2);
+            z[i + 2 * h] = make_double2(a.x - u.x, a.y - u.y);
+            z[i] = make_double2(a.x + u.x, a.y + u.y);
+            u = cmul(d, w3);
+            z[i + 3 * h] = make_double2(b.x - u.x, b.y - u.y);
+            z[i + h] = make_double2(b.x + u.x, b.y + u.y);
+        }
+        __syncthreads();
+    }
+    if (s < logP) {  // last stage, radix 2 (s = logP - 1)
+        const int h = 1 << s, hP = P >> 1;
         for (int t = threadIdx.x; t < nb * hP; t += blockDim.x) {
-            const int blk = t >> (logP - 1), tt = t & (hP - 1);
-            const int pos = tt & (half - 1);
-            const int i = blk * P + (((tt >> s) << (s + 1)) | pos);
-            const int j = i + half;
-            const double2 w = tw[pos << (logP - 1 - s)];
-            const double2 u = z[i], v = z[j];
-            const double vr = v.x * w.x - v.y * w.y;
-            const double vi = v.x * w.y + v.y * w.x;
-            z[i] = make_double2(u.x + vr, u.y + vi);
-            z[j] = make_double2(u.x - vr, u.y - vi);
+            const int blk = t >> (logP - 1), pos = t & (hP - 1);
+            const int i = blk * P + pos;
+            const double2 u = cmul(z[i + h], tw[pos]);
+            const double2 a = z[i];
+            z[i] = make_double2(a.x + u.x, a.y + u.y);
+            z[i + h] = make_double2(a.x - u.x, a.y - u.y);
         }
         __syncthreads();
     }
@@ -1660,50 +1690,86 @@ __device__ __forceinline__ int bit_reverse(int t, int logP) {
 
 // X_{d,f} over the modes [blockIdx.x * cols, +cols) of component blockIdx.y:
 // per mode, load the nb blocks (a, b) into LDS in bit-reversed order, FFT
-// them, and add sum_j conj(A^(j+d)_f) B^(j)_f for the (d, f), d >= 2,
+// them, split each block's spectrum in place (A_f into slot f, B_f into slot
+// P-f for 0 < f < Bk; at f = 0 and Bk both are real and share the slot as
+// (A, B)), and add sum_j conj(A^(j+d)_f) B^(j)_f for the (d, f), d >= 2,
 // f <= Bk, that the thread owns (q = (d-2)(Bk+1) + f = tid + 1024 r) into
 // registers. Partial spectra per workgroup, summed in k_beta_dot in a fixed
 // order.
 __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
     __shared__ double2 z[kSpecMaxLds];
+    __shared__ double2 tws[kSpecMaxP / 2];
     constexpr int QR = kSpecMaxLds / 2 / 1024 + 1;
     const int k = blockIdx.y, tid = threadIdx.x;
-    const int P = p.P, logP = p.logP, Bk = P >> 1, nb = p.nb, Q = (nb - 2) * (Bk + 1);
-    const double2* __restrict__ tw = reinterpret_cast<const double2*>(p.tw);
+    const int P = p.P, logP = p.logP, Bk = P >> 1, nb = p.nb, F1 = Bk + 1;
+    const int Q = (nb - 2) * F1, NI = nb * F1;
+    for (int j = tid; j < Bk; j += 1024) tws[j] = reinterpret_cast<const double2*>(p.tw)[j];
     double xr[QR], xi[QR];
 #pragma unroll
     for (int r = 0; r < QR; ++r) xr[r] = xi[r] = 0.0;
     const int64_t m0 = int64_t(blockIdx.x) * p.cols;
     const int64_t m1 = (m0 + p.cols < p.M) ? m0 + p.cols : p.M;
-    for (int64_t mode = m0; mode < m1; ++mode) {
+    // a mode's steps t = blk Bk + u < nb Bk <= kSpecMaxLds / 2, LV per thread;
+    // the next mode's are loaded into registers while this one is transformed
+    constexpr int LV = kSpecMaxLds / 2 / 1024;
+    double pa[LV], pb[LV];
+    auto fetch = [&](int64_t mode) {
         const int64_t e = int64_t(k) * p.M + mode;
         const double* __restrict__ a = p.psiT + e * p.N;
         const double* __restrict__ b = p.gT + e * p.N;
-        for (int t = tid; t < nb * P; t += 1024) {
-            const int blk = t >> logP, u = t & (P - 1);
-            const int64_t tg = int64_t(blk) * Bk + u;
-            double av = 0.0, bv = 0.0;
-            if (u < Bk && tg < p.N) {
-                av = a[tg];
-                bv = b[tg];
+#pragma unroll
+        for (int v = 0; v < LV; ++v) {
+            const int t = tid + 1024 * v;
+            pa[v] = (t < p.N) ? a[t] : 0.0;
+            pb[v] = (t < p.N) ? b[t] : 0.0;
+        }
+    };
+    if (m0 < m1) fetch(m0);
+    for (int64_t mode = m0; mode < m1; ++mode) {
+        // block blk, step u to slot bit_reverse(u), its zero padding u + Bk to
+        // bit_reverse(u + Bk): every slot of the nb blocks is written
+#pragma unroll
+        for (int v = 0; v < LV; ++v) {
+            const int t = tid + 1024 * v;
+            if (t < nb * Bk) {
+                const int blk = t >> (logP - 1), u = t & (Bk - 1);
+                z[blk * P + bit_reverse(u, logP)] = make_double2(pa[v], pb[v]);
+                z[blk * P + bit_reverse(u + Bk, logP)] = make_double2(0.0, 0.0);
             }
-            z[blk * P + bit_reverse(u, logP)] = make_double2(av, bv);
         }
         __syncthreads();
-        lds_fft_batch(z, nb, P, logP, tw);
+        if (mode + 1 < m1) fetch(mode + 1);
+        lds_fft_batch(z, nb, P, logP, tws);
+        // A_f = (Z_f + conj Z_{P-f}) / 2, B_f = (Z_f - conj Z_{P-f}) / (2i); the
+        // slot pair (f, P-f) belongs to one thread
+        for (int it = tid; it < NI; it += 1024) {
+            const int blk = it / F1, f = it - blk * F1;
+            const int i0 = blk * P + f, i1 = blk * P + ((P - f) & (P - 1));
+            const double2 zf = z[i0], zc = z[i1];
+            const double2 A = make_double2(0.5 * (zf.x + zc.x), 0.5 * (zf.y - zc.y));
+            const double2 B = make_double2(0.5 * (zf.y + zc.y), -0.5 * (zf.x - zc.x));
+            if (f == 0 || f == Bk) {
+                z[i0] = make_double2(A.x, B.x);
+            } else {
+                z[i0] = A;
+                z[i1] = B;
+            }
+        }
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
             const int q = tid + 1024 * r;
             if (q < Q) {
-                const int d = 2 + q / (Bk + 1), f = q % (Bk + 1), fc = (P - f) & (P - 1);
+                const int d = 2 + q / F1, f = q % F1;
+                const bool edge = f == 0 || f == Bk;
+                const int fb = edge ? f : P - f;
                 double sr = 0.0, si = 0.0;
                 for (int j = 0; j + d < nb; ++j) {
-                    const double2 zif = z[(j + d) * P + f], zic = z[(j + d) * P + fc];
-                    const double2 zjf = z[j * P + f], zjc = z[j * P + fc];
-                    const double ar = 0.5 * (zif.x + zic.x), ai = 0.5 * (zif.y - zic.y);
-                    const double br = 0.5 * (zjf.y + zjc.y), bi = -0.5 * (zjf.x - zjc.x);
-                    sr += ar * br + ai * bi;  // conj(A) B
-                    si += ar * bi - ai * br;
+                    const double2 za = z[(j + d) * P + f], zb = z[j * P + fb];
+                    const double2 A = edge ? make_double2(za.x, 0.0) : za;
+                    const double2 B = edge ? make_double2(zb.y, 0.0) : zb;
+                    sr += A.x * B.x + A.y * B.y;  // conj(A) B
+                    si += A.x * B.y - A.y * B.x;
                 }
                 xr[r] += sr;
                 xi[r] += si;
@@ -1730,7 +1796,9 @@ __global__ __launch_bounds__(1024) void k_fft_w(const double* __restrict__ dw, i
                                                 int nb, int P, int logP, const double* __restrict__ twp,
                                                 double* __restrict__ W) {
     __shared__ double2 z[kSpecMaxLds];
+    __shared__ double2 tws[kSpecMaxP / 2];
     const int Bk = P >> 1, Q = nb * (Bk + 1);
+    for (int j = threadIdx.x; j < Bk; j += 1024) tws[j] = reinterpret_cast<const double2*>(twp)[j];
     for (int t = threadIdx.x; t < nb * P; t += 1024) {
         const int d = t >> logP, r = t & (P - 1);
         const int64_t lag = int64_t(d) * Bk + (r < Bk ? r : r - P);
@@ -1738,7 +1806,7 @@ __global__ __launch_bounds__(1024) void k_fft_w(const double* __restrict__ dw, i
         z[d * P + bit_reverse(r, logP)] = ok ? make_double2(dw[lag], dw[dwstride + lag]) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    lds_fft_batch(z, nb, P, logP, reinterpret_cast<const double2*>(twp));
+    lds_fft_batch(z, nb, P, logP, tws);
     for (int q = threadIdx.x; q < Q; q += 1024) {
         const int d = q / (Bk + 1), f = q - d * (Bk + 1);
         const double2 zf = z[d * P + f], zc = z[d * P + ((P - f) & (P - 1))];
