@@ -183,14 +183,15 @@ struct AdjGradArgs {
 
 // d/dbeta pass over one time block n0+1..n0+bt: for each component and mode
 //   acc += sum_b psi^n (F[b] + [BDF2] 1/2 dd_{n-1} g^0),
-// F[b] = sum_{l=1}^{n} dw_{n-l} g^l from k_far_toeplitz over levels 1..n0+bt
+// F[b] = sum_{l=l0}^{n} dw_{n-l} g^l from k_far_toeplitz over levels
+// l0..n0+bt (l0 = 1, or the first level of the previous block when the
+// farther levels go through block DFTs)
 struct AdjBetaArgs {
     int64_t M, N, n0;
     int bt, scheme;
     int64_t dstride;
-    const double* dw;      // [2][dstride] d/dbeta of the scheme's weights
     const double* dd;      // [2][dstride] d/dbeta of the exact weights
-    const double* F;       // [B][2][M] reduced far field (n0 >= 1)
+    const double* F;       // [B][2][M] reduced far field of the block
     const double* traj;
     const double* psi;
     double* acc;           // [2][M]

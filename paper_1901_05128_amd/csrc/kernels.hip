@@ -1556,9 +1556,10 @@ __global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
     if (threadIdx.x == 0) p.part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
-// d/dbeta over one time block: F holds the whole CQ sum of the weight
-// derivatives over levels 1..n (k_far_toeplitz over levels up to the
-// block's end); add BDF2's starting correction and contract with psi. A
+// d/dbeta over one time block: F holds the CQ sum of the weight derivatives
+// over the levels l0..n of k_far_toeplitz (all levels, or those of the
+// previous and the current block); add BDF2's starting correction and
+// contract with psi. A
 // workgroup covers 64 (component, mode) pairs; its 4 waves take a quarter
 // of the block's steps each (a column of F and psi per wave and step, read
 // coalesced), and the partial sums meet in LDS in a fixed order.

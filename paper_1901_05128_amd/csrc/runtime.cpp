@@ -1412,7 +1412,6 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         ab.bt = bt;
         ab.scheme = p->scheme;
         ab.dstride = s.dstride;
-        ab.dw = dw + kDwPad;
         ab.dd = dd;
         ab.F = s.F;
         ab.traj = traj;
