@@ -108,7 +108,7 @@ struct Solver {
 int far_ksplit(int64_t M) {
     const int64_t tiles = 2 * ((M + 63) / 64);
     const int64_t wg = CQFP_FAR_WORKGROUPS;
-    return int(std::min<int64_t>(32, std::max<int64_t>(1, (wg + tiles - 1) / tiles)));
+    return int(std::min<int64_t>(32, std::max<int64_t>(1, (wg + tiles / 2) / tiles)));  // nearest
 }
 
 // slices for one launch: at least 64 levels per slice
