@@ -338,8 +338,9 @@ def bench_adjoint(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 5; 1 for the long workloads c3 and c4)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2; 1 for c3 and c4)")
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5"])
     ap.add_argument("--variants", default="all", help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct")
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
@@ -352,6 +353,11 @@ def main():
                     help="after the run, copy a MIB-sized device buffer 4 times (a plain copy kernel of "
                          "known size that scales the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    long_run = args.workload in ("c3", "c4")
+    if args.steps is None:
+        args.steps = 1 if long_run else 5
+    if args.warmup is None:
+        args.warmup = 1 if long_run else 2
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path "
