@@ -1,14 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the CQ Fokker-Planck solver on one MI355X.
 
-One bench step = one full solve (all N time steps, inputs resident in HBM) of
-every variant of the workload: BE and BDF2, each with the fast history and
-with the direct (blocked Toeplitz) history. The value is whole-job
-DOF*steps/s (DOF = 2 components x grid nodes) over all variants; per-variant
-rates, the fast-vs-direct difference, the dominant kernel's roofline and the
-CPU oracle's rate on a bounded sample are reported beside it.
+One bench step = full solves (all N time steps, inputs resident in HBM) of
+the workload's timed variants, run concurrently, one stream each. For the
+2D 255^2, N = 2^16 workload (the default) that is the BDF2 scheme with the
+fast history and with the direct (blocked Toeplitz) history; for the 1D
+workloads it is BE and BDF2, each fast and direct. The value is whole-job
+DOF*steps/s (DOF = 2 components x grid nodes) over the timed variants. Every
+variant (BE included) then runs once more, serially and outside the timed
+region, with HIP events around every kernel launch: that pass gives the
+per-variant times, the fast-vs-direct difference of both schemes and the
+dominant kernel's roofline. The CPU oracle's rate is reported beside it
+(timed on a prefix of the same workload, extrapolated to N steps).
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload c2|c3|c1]
+Usage: python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|t5]
 """
 import argparse
 import hashlib
@@ -28,8 +33,22 @@ WORKLOADS = {
     "c1": ("1D 127 nodes, N=1000", 1, 127, 1, 0.3, 0.7, 0.3, 1.0, 1000, 1),
     "c2": ("1D 1023 nodes, N=2^14", 1, 1023, 1, 0.4, 0.8, 0.45, 1.0, 2 ** 14, 2),
     "c3": ("2D 255x255 nodes, N=2^16", 2, 255, 255, 0.2, 0.6, 0.55, 1.0, 2 ** 16, 3),
+    # the paper's Table 5 problem (Section 5): h = 1/1024, T = 10, tau = 1/2000,
+    # a = -1 (m = 0), BDF2 (SBD) direct and fast, smooth data (a)
+    "t5": ("1D 1023 nodes, T=10, tau=1/2000 (N=20000), data (a), the paper's Table 5", 1, 1023, 1, 0.3, 0.8, 0.0,
+           10.0, 20000, None),
 }
 VARIANTS = [(1, 1), (1, 0), (2, 1), (2, 0)]  # (scheme, method)
+# variants inside the timed step (the rest run in the serial pass only)
+TIMED = {"c3": [(2, 1), (2, 0)], "t5": [(2, 1), (2, 0)]}
+# variants of the serial pass (default: all four)
+SERIAL = {"t5": [(2, 1), (2, 0)]}
+# Table 5's CPU times (seconds, BDF2 direct / fast, order pairs (0.3,0.8),
+# (0.4,0.7), (0.5,0.6); the paper names no machine) and its L2 errors
+# E_1, E_2 against a tau/2 run
+T5_PAPER = {"direct_s": [870.13, 883.70, 882.48], "fast_s": [209.44, 210.83, 211.36],
+            "direct_E": [[2.628e-10, 7.571e-09], [4.019e-10, 3.471e-09], [7.399e-10, 1.561e-09]],
+            "fast_E": [[3.543e-10, 1.321e-08], [4.862e-10, 5.697e-09], [1.008e-09, 2.375e-09]]}
 VNAME = {(1, 1): "be_fast", (1, 0): "be_direct", (2, 1): "bdf2_fast", (2, 0): "bdf2_direct"}
 SOLVERS = {"nodal": 0, "modal": 1}
 
@@ -37,6 +56,8 @@ SOLVERS = {"nodal": 0, "modal": 1}
 def g0_for(w):
     from paper_1901_05128_amd import workloads as wl
     _, dim, nx, ny, *_rest, seed = w
+    if seed is None:
+        return wl.g0_smooth(nx, ny)
     if nx == 127 and dim == 1:
         return wl.g0_c1(nx, seed)
     return wl.g0_intervals(nx, seed) if dim == 1 else wl.g0_rectangle(nx, ny, seed)
@@ -112,38 +133,91 @@ def kernel_work(kind, w, scheme, method, info, M, solver=1):
     return 0, 0
 
 
-def cpu_baseline(w, seconds_target=20.0):
-    """The oracle (nodal direct and fast steppers) on the first steps of the
-    same workload: same grid, tau and data, N_sample < N steps."""
+def cpu_baseline(w, variants):
+    """The oracle (oracle.stepper: nodal direct and fast steppers) timed on
+    prefixes of the same workload (same grid, tau and G0) and extrapolated
+    to all N steps. The direct stepper's step n costs c1 + c2 (n - 1): c2
+    (one history level of both components) is the oracle's own history sum
+    over a block of stored levels, timed with all BLAS threads and with one;
+    c1 comes from two prefix runs (their difference cancels the set-up, the
+    history share of the extra steps taken out). The fast stepper's step
+    costs a constant once its state is live (steps beyond the lag): the
+    difference of two prefix runs past the lag. Elementwise numpy and the
+    sparse LU solves run on one thread, so only c2 depends on the core
+    count."""
     import numpy as np
     from oracle import stepper
+    from oracle.weights import weights
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count() or 1
     desc, dim, nx, ny, a1, a2, m, T, N, seed = w
     G0 = g0_for(w)
     tau = T / N
     M = nx * ny
-    ns = 64
-    done_dofsteps, spent = 0, 0.0
-    while True:
+    t_start = time.perf_counter()
+
+    def run(scheme, method, n):
         t0 = time.perf_counter()
-        for scheme, method in VARIANTS:
-            stepper.solve(dim, nx, ny, a1, a2, m, ns * tau, ns, G0, scheme, method,
-                          np_=(None if method == 0 else max(16, int(3 * N ** 0.5))), ns=30)
-        dt = time.perf_counter() - t0
-        done_dofsteps, spent = 4 * 2 * M * ns, dt
-        # the direct oracle's cost grows like ns^2: stop before the next
-        # doubling would pass the target
-        if dt * 4 > seconds_target or 2 * ns > N:
-            break
-        ns *= 2
-    return {"value": done_dofsteps / spent, "unit": "DOF*steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {ns} of the {N} steps of {desc} (same tau and G0), BE+BDF2 x direct+fast, "
-                      f"numpy/scipy fp64, {spent:.1f} s; the direct form's per-step cost grows with n, so "
-                      f"this overstates the oracle's full-run rate"}
+        stepper.solve(dim, nx, ny, a1, a2, m, n * tau, n, G0, scheme, method,
+                      np_=(None if method == 0 else max(16, int(np.ceil(3 * N ** 0.5)))), ns=30)
+        return time.perf_counter() - t0
+
+    # c2: the history sum over nh stored levels of [2][M] (about 256 MB)
+    nh = int(max(16, min(N, 256e6 // (16 * M))))
+    rng = np.random.default_rng(0)
+    Gh = rng.standard_normal((nh, 2 * M))
+    d = weights(2, 1.0 - a1, tau, nh)
+
+    def t_hist():
+        best = 1e30
+        for _ in range(3):
+            t0 = time.perf_counter()
+            stepper.cq_history(d, Gh)
+            best = min(best, time.perf_counter() - t0)
+        return best / (nh - 1)
+
+    c2_all = t_hist()
+    c2_one = c2_all
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            c2_one = t_hist()
+    del Gh
+    na, nb = (64, 256) if dim == 1 else (8, 24)
+    full = {"all": 0.0, "one": 0.0}
+    parts = []
+    for scheme, method in variants:
+        if method == 0:
+            ta, tb = run(scheme, 0, na), run(scheme, 0, nb)
+            hist_steps = sum(k - 1 for k in range(na + 1, nb + 1))
+            c1 = max(0.0, (tb - ta - c2_all * hist_steps) / (nb - na))
+            tot = N * (N - 1) / 2
+            full["all"] += c1 * N + c2_all * tot
+            full["one"] += c1 * N + c2_one * tot
+            parts.append(f"{VNAME[(scheme, 0)]}: prefixes {na}/{nb} steps {ta:.3f}/{tb:.3f} s, "
+                         f"c1 {c1 * 1e3:.2f} ms/step")
+        else:
+            lag = 3 if scheme == 1 else 31
+            fa, fb = (max(na, lag), max(na, lag) + (nb - na)) if dim == 1 else (lag, lag + 4)
+            ta, tb = run(scheme, 1, fa), run(scheme, 1, fb)
+            per = (tb - ta) / (fb - fa)
+            full["all"] += per * N
+            full["one"] += per * N
+            parts.append(f"{VNAME[(scheme, 1)]}: prefixes {fa}/{fb} steps {ta:.3f}/{tb:.3f} s, "
+                         f"{per * 1e3:.3f} ms/step")
+    work = len(variants) * 2 * M * N
+    spent = time.perf_counter() - t_start
+    return {"value": work / full["all"], "unit": "DOF*steps/s", "cores": int(cores), "kind": "oracle",
+            "extrapolated": True, "value_1core": work / full["one"],
+            "est_full_run_s": full["all"], "est_full_run_s_1core": full["one"],
+            "sample": f"{desc}, the timed variants ({', '.join(VNAME[v] for v in variants)}) of the oracle "
+                      f"(numpy/scipy fp64 nodal steppers) on prefixes of the workload, extrapolated to N = {N}: "
+                      + "; ".join(parts)
+                      + f"; history sum c2 {c2_all * 1e3:.3f} ms per level ({cores} threads), "
+                        f"{c2_one * 1e3:.3f} ms (1 thread), timed over {nh} levels; {spent:.1f} s of CPU work"}
 
 
 def load_traffic(kernel_name):
@@ -339,32 +413,35 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 5; 1 for the long workloads c3 and c4)")
+                    help="timed steps (default 5; 2 for c3, 1 for c4)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2; 1 for c3 and c4)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5"])
-    ap.add_argument("--variants", default="all", help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct")
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5"])
+    ap.add_argument("--t5-errors", action="store_true",
+                    help="t5: also run tau/2 (N = 40000) and report the L2 errors of Table 5's protocol")
+    ap.add_argument("--variants", default="default",
+                    help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct timed in a step "
+                         "(default: bdf2_fast,bdf2_direct for c3, all four otherwise)")
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-prof", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--no-prof", action="store_true",
+                    help="skip the serial pass (kernel timings, the untimed variants)")
     ap.add_argument("--serial", action="store_true",
-                    help="run the variants one after another (default: one stream each, concurrently)")
+                    help="run the timed variants one after another (default: one stream each, concurrently)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer 4 times (a plain copy kernel of "
                          "known size that scales the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
-    long_run = args.workload in ("c3", "c4")
     if args.steps is None:
-        args.steps = 1 if long_run else 5
+        args.steps = {"c3": 2, "c4": 1}.get(args.workload, 5)
     if args.warmup is None:
-        args.warmup = 1 if long_run else 2
+        args.warmup = 1 if args.workload in ("c3", "c4") else 2
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this solver has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: this solver has no multi-GPU path (the modal solver would "
+              "shard by sine mode with no per-step exchange); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1901_05128_amd as cq
@@ -376,15 +453,20 @@ def main():
     w = WORKLOADS[args.workload]
     desc, dim, nx, ny, a1, a2, m, T, N, seed = w
     M = nx * ny
-    variants = VARIANTS if args.variants == "all" else \
-        [v for v in VARIANTS if VNAME[v] in args.variants.split(",")]
+    if args.variants == "default":
+        timed = TIMED.get(args.workload, VARIANTS)
+    else:
+        timed = [v for v in VARIANTS if VNAME[v] in args.variants.split(",")]
+    # the serial pass runs every variant of the workload unless it is skipped
+    variants = SERIAL.get(args.workload, VARIANTS) if not args.no_prof else timed
+    variants = variants + [v for v in timed if v not in variants]
     torch.cuda.set_device(0)
     G0 = torch.tensor(g0_for(w), dtype=torch.float64, device="cuda")
     grid = cq.make_grid(dim, nx, ny)
     solvers, streams = {}, {}
     for v in variants:
-        # each variant on its own stream (default priority) unless --serial
-        streams[v] = torch.cuda.current_stream() if args.serial else torch.cuda.Stream()
+        # each timed variant on its own stream (default priority) unless --serial
+        streams[v] = torch.cuda.Stream() if (v in timed and not args.serial) else torch.cuda.current_stream()
         with torch.cuda.stream(streams[v]):
             solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1],
                                                         solver=SOLVERS[args.solver]), G0)
@@ -392,7 +474,7 @@ def main():
     outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
 
     def one_step(events=None):
-        for v in variants:
+        for v in timed:
             s = solvers[v]
             with torch.cuda.stream(streams[v]):
                 if events is not None:
@@ -403,41 +485,51 @@ def main():
                 if events is not None:
                     events[v][1].record()
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         one_step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"# warmup step {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     ev = {v: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)] for v in variants}
-    per_var_ms = {v: 0.0 for v in variants}
+              for _ in range(args.steps)] for v in timed}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        one_step({v: ev[v][k] for v in variants})
+        one_step({v: ev[v][k] for v in timed})
+        if args.workload == "c3":
+            # a progress line per step (each takes seconds); the wait only
+            # follows work already queued, so the timed work is unchanged
+            ev[timed[-1]][k][1].synchronize()
+            print(f"# timed step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for v in variants:
-        per_var_ms[v] = sum(a.elapsed_time(b) for a, b in ev[v]) / args.steps
+    per_var_ms = {v: sum(a.elapsed_time(b) for a, b in ev[v]) / args.steps for v in timed}
     elapsed = t1 - t0
-    dofsteps = args.steps * len(variants) * 2 * M * N
+    dofsteps = args.steps * len(timed) * 2 * M * N
     value = dofsteps / elapsed
 
-    # Kernel timing and the dominant kernel's roofline come from one more
-    # step outside the timed region, with the variants run one after another
-    # on one stream, so that each launch's duration is its own and not
-    # stretched by kernels of other variants sharing the GPU.
+    # Serial pass outside the timed region: every variant once, one after
+    # another on one stream, with HIP events around every kernel launch, so
+    # that each launch's duration is its own and not stretched by kernels of
+    # other variants sharing the GPU.
     kinds = ["hist_fast", "hist_direct", "far_toeplitz", "solve_1d", "prep_2d", "dst_gemm", "modal_fast",
              "modal_near", "reduce_far"]
     ktime = {}
+    serial_ms = {}
     if not args.no_prof:
         torch.cuda.synchronize()
         cq.prof_enable(True)
         for v in variants:
             s = solvers[v]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             with torch.cuda.stream(streams[v]):
+                e0.record()
                 s.reset(G0)
                 s.step(N)
                 s.current(outs[v])
+                e1.record()
             torch.cuda.synchronize()
+            serial_ms[v] = e0.elapsed_time(e1)
+            print(f"# serial pass {VNAME[v]} {serial_ms[v]:.1f} ms", file=sys.stderr, flush=True)
         for kname in kinds:
             n_l, ms = cq.prof_read(kname)
             if n_l:
@@ -468,7 +560,9 @@ def main():
         roofline["kernel"] = dom
         roofline["avg_launch_us"] = avg_s * 1e6
         roofline["launches"] = n_l
-        roofline["timed"] = "one extra serial step after the timed region, HIP events per launch"
+        roofline["algorithmic_per_launch"] = (tot_f if f_frac >= b_frac else tot_b) / n_l
+        roofline["timed"] = ("serial pass after the timed region (variants " +
+                             ", ".join(VNAME[v] for v in variants) + "), HIP events per launch")
         roofline["traffic"] = load_traffic(dom)
 
     # fast vs direct on the GPU (the metric's accuracy side)
@@ -479,8 +573,12 @@ def main():
             fvd[f"scheme{scheme}"] = float(torch.linalg.norm(f - d) / torch.linalg.norm(d))
 
     info_np = {VNAME[v]: solvers[v].info().np_total for v in variants if v[1] == 1}
-    breakdown = {VNAME[v]: {"ms": per_var_ms[v], "dofsteps_per_s": 2 * M * N / (per_var_ms[v] / 1e3)}
-                 for v in variants}
+    breakdown = {VNAME[v]: {"ms": per_var_ms[v], "dofsteps_per_s": 2 * M * N / (per_var_ms[v] / 1e3),
+                            "where": "timed step (concurrent)"} for v in timed}
+    for v, ms in serial_ms.items():
+        ent = breakdown.setdefault(VNAME[v], {})
+        ent["serial_ms"] = ms
+        ent["serial_dofsteps_per_s"] = 2 * M * N / (ms / 1e3)
     for s in solvers.values():
         s.close()
 
@@ -499,13 +597,33 @@ def main():
         "data": "synthetic (seeded indicator initial data)",
         "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
                    "solver": args.solver, "streams": "serial" if args.serial else "one per variant",
-                   "variants": [VNAME[v] for v in variants], "dof": 2 * M, "N": N,
+                   "timed_variants": [VNAME[v] for v in timed], "dof": 2 * M, "N": N,
                    "fast_nodes": info_np},
         "breakdown": breakdown,
         "fast_vs_direct_rel_l2": fvd,
         "kernels_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in ktime.items()},
         "roofline": roofline,
     }
+    if args.workload == "t5":
+        # vs_baseline: the paper's Table 5 CPU times for the same workload and
+        # step (BDF2 direct + fast at (0.3, 0.8)) as DOF*steps/s
+        paper_rate = 2 * 2 * M * N / (T5_PAPER["direct_s"][0] + T5_PAPER["fast_s"][0])
+        rec["vs_baseline"] = value / paper_rate
+        rec["baseline"] = {"value": paper_rate, "unit": "DOF*steps/s",
+                           "source": "Table 5 CPU times 870.13 s (SBD) + 209.44 s (FSBD) at (0.3, 0.8), "
+                                     "2 x 1023 DOF x 20000 steps each; the paper names no machine"}
+        if args.t5_errors:
+            # the paper's protocol: E_k = ||G_k^N(tau) - G_k^N(tau/2)||_L2, h = 1/1024
+            ref = cq.fp_solve(grid, cq.make_params(a1, a2, m, T, 2 * N, 2, 0, solver=SOLVERS[args.solver]), G0)
+            h = 1.0 / (nx + 1)
+            errs = {}
+            for v in timed:
+                dlt = (outs[v] - ref).cpu()
+                errs[VNAME[v]] = [float((h * (dlt[k] ** 2).sum()) ** 0.5) for k in range(2)]
+            rec["t5_errors"] = {"ours": errs, "paper": {"bdf2_direct": T5_PAPER["direct_E"][0],
+                                                          "bdf2_fast": T5_PAPER["fast_E"][0]},
+                                "note": "reference run at tau/2 (the paper used tau = 1/4000 too); "
+                                        "the paper's spatial scheme is unstated"}
     if args.copy_probe:
         nel = args.copy_probe * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -515,7 +633,7 @@ def main():
         torch.cuda.synchronize()
         rec["copy_probe_bytes_each_way"] = nel * 8
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w)
+        rec["cpu_baseline"] = cpu_baseline(w, timed)
     print(json.dumps(rec), flush=True)
 
 

@@ -8,8 +8,9 @@
  *   dG1/dt + a D^{1-alpha1} G1 + D^{1-alpha1} A G1 = a D^{1-alpha2} G2,
  *   dG2/dt + a D^{1-alpha2} G2 + D^{1-alpha2} A G2 = a D^{1-alpha1} G1,
  * with a = (1-m)/(2m-1) (m of the transition matrix (1.2)), A = -Laplacian
- * with zero Dirichlet data, discretised in space by the 3-point (1D) or
- * 5-point (2D) finite-difference stencil on a uniform grid of interior nodes.
+ * with zero Dirichlet data, discretised in space by the 3-point (1D),
+ * 5-point (2D) or 7-point (3D) finite-difference stencil on a uniform grid of
+ * interior nodes.
  * Time: backward-Euler CQ, scheme (4.1), or BDF2 (SBD) CQ with the starting
  * correction, scheme (4.7); the CQ history is summed directly (O(N^2)) or by
  * the fast sum-of-geometric-sequences form, schemes (4.3) and (4.8).
@@ -18,7 +19,7 @@
  *  - All arrays are IEEE fp64, contiguous, owned by the caller. "dev" marks a
  *    device pointer on the current HIP device, "host" a host pointer.
  *  - A field G is laid out [2][M]: component 1 then component 2, each with
- *    M = nx*ny nodes, x fastest (node (i,j) at index j*nx + i).
+ *    M = nx*ny*nz nodes, x fastest (node (i,j,k) at index (k*ny + j)*nx + i).
  *  - Device work is enqueued on the caller's hipStream_t (passed as void*;
  *    NULL means the default stream). Entry points that return data to the
  *    host synchronise that stream.
@@ -45,12 +46,18 @@ extern "C" {
 #define CQ_ETOL -5        /* the fast rule cannot reach fast_tol within np_max   */
 #define CQ_ENONFINITE -6  /* G0 holds a NaN or an infinity                       */
 
-/* Grid: Omega = (0,lx) (dim 1) or (0,lx)x(0,ly) (dim 2); nx, ny interior
- * nodes; h = l/(n+1). For dim 1, ny must be 1. */
+/* Grid: Omega = (0,lx) (dim 1), (0,lx)x(0,ly) (dim 2) or (0,lx)x(0,ly)x(0,lz)
+ * (dim 3; the problem (1.1) is posed for d = 1, 2, 3); nx, ny, nz interior
+ * nodes per direction, h = l/(n+1); A is the 3-, 5- or 7-point
+ * finite-difference Laplacian. For dim 1, ny must be 1; for dims 1 and 2,
+ * nz must be 0 or 1 (lz is ignored). 3D grids need ny * nz <= 2^20. Nodes are
+ * ordered x fastest, then y, then z. */
 typedef struct {
     int32_t dim;
     int32_t nx, ny;
     double lx, ly;
+    int32_t nz;
+    double lz;
 } cq_grid;
 
 /* Problem and method parameters (Sections 3-4).
@@ -137,10 +144,14 @@ int cq_fast_rule(int32_t scheme, double beta, double tau, int64_t N, double tol,
  * (3.8)/(3.17) without the i = 0 term and without G^0, as it enters the
  * schemes (4.1) and (4.7)), with d_i the weights of cq_weights(scheme, beta,
  * tau, .). G_hist: dev [n][M] time-major (level 0 is G^0, unused);
- * S_out: dev [M]. n >= 1, M >= 1. The sum runs as one row of the blocked
- * Toeplitz product (FP64 MFMA) on the device. Synchronises the stream. */
+ * S_out: dev [M]. n >= 1, M >= 1 (n = 1 gives zeros). The weights are
+ * computed on the host; the sum streams every level once on the device
+ * (a weighted sum over levels, split into level slices whose partial sums
+ * are added in slice order). Allocates a device workspace (the weights and
+ * the partial sums) for the call and frees it; synchronises the stream. */
 int cq_history(int32_t scheme, double beta, double tau, const double* G_hist,
                int64_t n, int64_t M, double* S_out, void* hip_stream);
+
 
 /* Create a solver for one problem, starting from G0 (dev [2][M], copied).
  * Allocates every device buffer the run needs (the full history [N+1][2][M]

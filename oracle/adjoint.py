@@ -187,21 +187,22 @@ def adjoint(ops, alpha1, alpha2, m, T, N, G0, gN, scheme, method, np_=None, np1=
     return gG0, -gb[0], -gb[1], gm, G[N].copy()
 
 
-def adjoint_nodal(dim, nx, ny, alpha1, alpha2, m, T, N, G0, gN, scheme, method, np_=None, np1=16, ns=30):
+def adjoint_nodal(dim, nx, ny, alpha1, alpha2, m, T, N, G0, gN, scheme, method, np_=None, np1=16, ns=30,
+                  nz=1):
     """adjoint() on the finite-difference grid (sparse nodal operators)."""
-    ops = NodalOps(grid.laplacian(dim, nx, ny))
+    ops = NodalOps(grid.laplacian(dim, nx, ny, nz))
     return adjoint(ops, alpha1, alpha2, m, T, N, G0, gN, scheme, method, np_, np1, ns)
 
 
 def adjoint_reference(dim, nx, ny, alpha1, alpha2, m, T, N, G0, gN, scheme, method, np_=None, np1=16,
-                      ns=30):
+                      ns=30, nz=1):
     """adjoint() mode by mode over every sine mode: the same numbers as
     adjoint_nodal in exact arithmetic. G0 enters through the coefficient
     map c0 = P G0 (modal.to_modes) and G^N = Q cN (modal.from_modes); both
     matrices are symmetric, so dl/dcN = Q gN and dl/dG0 = P dl/dc0."""
-    lam = modal.all_eigenvalues(dim, nx, ny)
-    c0 = modal.to_modes(G0, dim, nx, ny)
-    gc = modal.from_modes(gN, dim, nx, ny)
+    lam = modal.all_eigenvalues(dim, nx, ny, nz)
+    c0 = modal.to_modes(G0, dim, nx, ny, nz)
+    gc = modal.from_modes(gN, dim, nx, ny, nz)
     g0c, ga1, ga2, gm, cN = adjoint(ModalOps(lam), alpha1, alpha2, m, T, N, c0, gc, scheme, method, np_,
                                     np1, ns)
-    return modal.to_modes(g0c, dim, nx, ny), ga1, ga2, gm, modal.from_modes(cN, dim, nx, ny)
+    return modal.to_modes(g0c, dim, nx, ny, nz), ga1, ga2, gm, modal.from_modes(cN, dim, nx, ny, nz)

@@ -169,9 +169,9 @@ def run(ops, alpha1, alpha2, m, T, N, G0, scheme, method, np_=None, np1=16, ns=3
 
 
 def solve(dim, nx, ny, alpha1, alpha2, m, T, N, G0, scheme, method, np_=None, np1=16, ns=30,
-          keep=False):
-    """Nodal solve on the FD grid; G0 is [2][nx*ny] (x fastest)."""
-    ops = NodalOps(grid.laplacian(dim, nx, ny))
+          keep=False, nz=1):
+    """Nodal solve on the FD grid; G0 is [2][nx*ny*nz] (x fastest)."""
+    ops = NodalOps(grid.laplacian(dim, nx, ny, nz))
     return run(ops, alpha1, alpha2, m, T, N, G0, scheme, method, np_, np1, ns, keep)
 
 

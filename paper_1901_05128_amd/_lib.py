@@ -37,7 +37,8 @@ class CQError(RuntimeError):
 
 
 class Grid(C.Structure):
-    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("lx", C.c_double), ("ly", C.c_double)]
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("lx", C.c_double), ("ly", C.c_double),
+                ("nz", C.c_int32), ("lz", C.c_double)]
 
 
 class Params(C.Structure):
@@ -108,8 +109,13 @@ def _check(rc: int):
         raise CQError(rc, lib().cq_last_error().decode())
 
 
-def make_grid(dim: int, nx: int, ny: int = 1, lx: float = 1.0, ly: float = 1.0) -> Grid:
-    return Grid(dim, nx, ny if dim == 2 else 1, lx, ly)
+def make_grid(dim: int, nx: int, ny: int = 1, lx: float = 1.0, ly: float = 1.0, nz: int = 1,
+              lz: float = 1.0) -> Grid:
+    return Grid(dim, nx, ny if dim >= 2 else 1, lx, ly, nz if dim == 3 else 1, lz)
+
+
+def grid_nodes(grid: Grid) -> int:
+    return grid.nx * (grid.ny if grid.dim >= 2 else 1) * (grid.nz if grid.dim == 3 else 1)
 
 
 SOLVER_NODAL, SOLVER_MODAL = 0, 1
@@ -172,7 +178,7 @@ class Solver:
     def __init__(self, grid: Grid, params: Params, G0):
         self._h = C.c_void_p()
         self.grid, self.params = grid, params
-        self.M = grid.nx * (grid.ny if grid.dim == 2 else 1)
+        self.M = grid_nodes(grid)
         if tuple(G0.shape) not in ((2, self.M), (2 * self.M,)):
             raise CQError(CQ_EINVAL, f"G0 must have shape [2][{self.M}]")
         _check(lib().fp_create(C.byref(grid), C.byref(params), _dev(G0, "G0"), _stream(), C.byref(self._h)))
@@ -239,7 +245,7 @@ def prof_read(kind) -> tuple:
 
 def fp_solve(grid: Grid, params: Params, G0, GN=None):
     import torch
-    M = grid.nx * (grid.ny if grid.dim == 2 else 1)
+    M = grid_nodes(grid)
     if GN is None:
         GN = torch.empty((2, M), dtype=torch.float64, device=G0.device)
     _check(lib().fp_solve(C.byref(grid), C.byref(params), _dev(G0, "G0"), _dev(GN, "GN"), _stream()))
@@ -265,7 +271,7 @@ class Adjoint:
 
     def __init__(self, grid: Grid, params: Params):
         self._h = C.c_void_p()
-        self.M = grid.nx * (grid.ny if grid.dim == 2 else 1)
+        self.M = grid_nodes(grid)
         _check(lib().fp_adjoint_create(C.byref(grid), C.byref(params), _stream(), C.byref(self._h)))
 
     def run(self, G0, gN, gG0=None, GN=None):

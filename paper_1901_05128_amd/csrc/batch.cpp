@@ -26,11 +26,11 @@ using namespace cqfp;
 namespace {
 
 struct HostProblem {
-    int dim = 1, nx = 1, ny = 1;
+    int dim = 1, nx = 1, ny = 1, nz = 1;
     int64_t M = 0, N = 0;
     int np = 0, L = 0, scheme = 2;
     double tau = 0, a = 0, c = 0;
-    double lx = 1, ly = 1;
+    double lx = 1, ly = 1, lz = 1;
     std::vector<double> d[2];  // weights 0..N
     FastRule rule[2];
     int rc = CQ_OK;
@@ -57,10 +57,12 @@ std::vector<double> sine_tab(int n) {
 void prepare(const cq_grid& g, const cq_params& p, HostProblem& h) {
     h.dim = g.dim;
     h.nx = g.nx;
-    h.ny = g.dim == 2 ? g.ny : 1;
+    h.ny = g.dim >= 2 ? g.ny : 1;
+    h.nz = g.dim == 3 ? g.nz : 1;
     h.lx = g.lx;
     h.ly = g.ly;
-    h.M = int64_t(h.nx) * h.ny;
+    h.lz = g.lz;
+    h.M = int64_t(h.nx) * h.ny * h.nz;
     h.N = p.N;
     h.scheme = p.scheme;
     h.tau = p.T / double(p.N);
@@ -148,8 +150,9 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     for (int i = 0; i < count; ++i) {
         const cq_grid& g = grids[i];
         const cq_params& p = params[i];
-        if (!(g.dim == 1 || g.dim == 2) || g.nx < 1 || g.ny < 1 || (g.dim == 1 && g.ny != 1) || !(g.lx > 0) ||
-            (g.dim == 2 && !(g.ly > 0)))
+        if (g.dim < 1 || g.dim > 3 || g.nx < 1 || g.ny < 1 || (g.dim == 1 && g.ny != 1) || !(g.lx > 0) ||
+            (g.dim >= 2 && !(g.ly > 0)) || (g.dim < 3 && g.nz != 0 && g.nz != 1) ||
+            (g.dim == 3 && (g.nz < 1 || !(g.lz > 0) || int64_t(g.ny) * g.nz > (int64_t(1) << 20))))
             return fail(CQ_EINVAL, "batched solve: problem %d has a bad grid", i);
         if (!(p.alpha1 > 0 && p.alpha1 < 1 && p.alpha2 > 0 && p.alpha2 < 1) || !(p.m >= 0 && p.m <= 1) ||
             p.m == 0.5 || !(p.T > 0) || p.N < 1 || (p.scheme != 1 && p.scheme != 2) || p.method != 1 ||
@@ -177,7 +180,8 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         const double K[2][2] = {{h.c / d10 + h.a, -h.a * d20 / d10}, {-h.a * d10 / d20, h.c / d20 + h.a}};
         double th[2], V[2][2], Vi[2][2];
         eig2(K, th, V, Vi);
-        double lmin = lam1d(h.nx, h.lx, 1) + (h.dim == 2 ? lam1d(h.ny, h.ly, 1) : 0.0);
+        double lmin = lam1d(h.nx, h.lx, 1) + (h.dim >= 2 ? lam1d(h.ny, h.ly, 1) : 0.0) +
+                      (h.dim == 3 ? lam1d(h.nz, h.lz, 1) : 0.0);
         if (!(th[0] + lmin > 0 && th[1] + lmin > 0))
             return fail(CQ_ESINGULAR, "batched solve: problem %d: step operator not positive definite", i);
     }
@@ -208,9 +212,11 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         I.a = h.a;
         I.d00 = h.d[0][0];
         I.d01 = h.d[1][0];
-        for (int j = 0; j < h.ny; ++j)
-            for (int q = 0; q < h.nx; ++q)
-                lam.push_back(lam1d(h.nx, h.lx, q + 1) + (h.dim == 2 ? lam1d(h.ny, h.ly, j + 1) : 0.0));
+        for (int r = 0; r < h.nz; ++r)
+            for (int j = 0; j < h.ny; ++j)
+                for (int q = 0; q < h.nx; ++q)
+                    lam.push_back(lam1d(h.nx, h.lx, q + 1) + (h.dim >= 2 ? lam1d(h.ny, h.ly, j + 1) : 0.0) +
+                                  (h.dim == 3 ? lam1d(h.nz, h.lz, r + 1) : 0.0));
         modes += h.M;
     }
     hipStream_t user = static_cast<hipStream_t>(hip_stream);
@@ -233,7 +239,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     // sine tables per distinct size
     std::map<int, double*> sines;
     for (auto& h : hp)
-        for (int n : {h.nx, h.dim == 2 ? h.ny : 0}) {
+        for (int n : {h.nx, h.dim >= 2 ? h.ny : 0, h.dim == 3 ? h.nz : 0}) {
             if (n <= 0 || sines.count(n)) continue;
             double* q;
             if ((rc = buf.alloc(&q, size_t(n) * size_t(n)))) return rc;
@@ -317,32 +323,17 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     auto transforms = [&](bool forward) {
         for (int i = 0; i < count; ++i) {
             const HostProblem& h = hp[size_t(i)];
-            const int64_t M = h.M;
             const int64_t off = 2 * inst[size_t(i)].mode_off;
             const double* in = forward ? G0[i] : d_gN + off;
             double* out = forward ? d_g0 + off : GN[i];
-            if (h.dim == 1) {
-                GemmArgs ga{};
-                ga.R = 1; ga.C = h.nx; ga.K = h.nx; ga.lda = h.nx; ga.ldb = h.nx; ga.ldc = h.nx;
-                ga.A_shared = 0; ga.B_shared = 1;
-                ga.A0 = in; ga.A1 = in + M; ga.B0 = sines[h.nx]; ga.B1 = sines[h.nx]; ga.C0 = out; ga.C1 = out + M;
-                ga.scale = forward ? 2.0 / double(h.nx + 1) : 1.0;
-                launch_gemm(ga, 3, st);
-            } else {
-                GemmArgs ga{};
-                ga.R = h.ny; ga.C = h.nx; ga.K = h.nx; ga.lda = h.nx; ga.ldb = h.nx; ga.ldc = h.nx;
-                ga.A_shared = 0; ga.B_shared = 1;
-                ga.A0 = in; ga.A1 = in + M; ga.B0 = sines[h.nx]; ga.B1 = sines[h.nx];
-                ga.C0 = d_tmp; ga.C1 = d_tmp + M;
-                launch_gemm(ga, 0, st);
-                GemmArgs gb{};
-                gb.R = h.ny; gb.C = h.nx; gb.K = h.ny; gb.lda = h.ny; gb.ldb = h.nx; gb.ldc = h.nx;
-                gb.A_shared = 1; gb.B_shared = 0;
-                gb.A0 = sines[h.ny]; gb.A1 = sines[h.ny]; gb.B0 = d_tmp; gb.B1 = d_tmp + M;
-                gb.C0 = out; gb.C1 = out + M;
-                gb.scale = forward ? 4.0 / (double(h.nx + 1) * double(h.ny + 1)) : 1.0;
-                launch_gemm(gb, 3, st);
+            double scale = 1.0;
+            if (forward) {
+                scale = 2.0 / double(h.nx + 1);
+                if (h.dim >= 2) scale *= 2.0 / double(h.ny + 1);
+                if (h.dim == 3) scale *= 2.0 / double(h.nz + 1);
             }
+            launch_sine_transform(h.dim, h.nx, h.ny, h.nz, sines[h.nx], h.dim >= 2 ? sines[h.ny] : nullptr,
+                                  h.dim == 3 ? sines[h.nz] : nullptr, in, d_tmp, out, scale, st);
         }
     };
     transforms(true);

@@ -87,6 +87,11 @@ struct GemmArgs {
     double dd0[2];
     // epilogue 2: C_k = A_k B_k - sub_k
     const double *sub0, *sub1;
+    // batch of GEMMs (blockIdx.z): operand b of a per-component A, B or C
+    // (and sub) starts sA, sB or sC elements after operand 0; shared
+    // operands are not offset
+    int batch = 1;
+    int64_t sA = 0, sB = 0, sC = 0;
 };
 
 struct ModalFastArgs {
@@ -260,12 +265,22 @@ int launch_beta_dot(const BetaDotArgs& a, hipStream_t st);  // returns blocks pe
 void launch_hist_block(const HistBlockArgs& a, int lanes, hipStream_t st);
 void launch_hist_direct(const HistDirectArgs& a, hipStream_t st);
 void launch_far(const FarArgs& a, hipStream_t st);
-// F[0][e] = sum_q F[q][e], e < per (q < ks slices, per apart)
-// out[x] = sum_q F[q][0][0][x] (one history row of a single component)
-void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st);
+// One direct history row S[x] = sum_{l=1}^{n-1} d[n-l] G[l*M + x] (x < M),
+// the levels split into ks slices (hist_row_slices); with more than one slice
+// part holds [ks][M] partial sums (summed in slice order into out). n <= 1
+// writes zeros. part_cap: most doubles part may hold (-1: no limit).
+int hist_row_slices(int64_t n, int64_t M, int64_t part_cap);
+void launch_hist_row(const double* G, int64_t n, int64_t M, const double* d, int ks, double* part, double* out,
+                     hipStream_t st);
 void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st);
 void launch_prep_2d(const StepArgs& a, hipStream_t st);
 void launch_gemm(const GemmArgs& a, int epi, hipStream_t st);
+// Separable sine transform of both components of G ([2][M], M = nx ny nz, x
+// fastest) on a grid of dim 1, 2 or 3: out = scale * (S_z (x) S_y (x) S_x) G,
+// as GEMMs along x (one), y (one per z-plane, batched) and z (one). tmp:
+// [2][M] scratch (dim >= 2). S_k: the n_k x n_k sine matrices.
+void launch_sine_transform(int dim, int nx, int ny, int nz, const double* Sx, const double* Sy, const double* Sz,
+                           const double* G, double* tmp, double* out, double scale, hipStream_t st);
 const void* kernel_step_1d(int R);
 
 // kernel timing (runtime.cpp): no-ops unless cq_prof_enable(1)

@@ -12,6 +12,7 @@
 // fast form).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include <cstdint>
@@ -1864,6 +1865,23 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ acc
 template <int EPI>
 __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
     __shared__ double red[4][2][16][17];
+    if (blockIdx.z) {  // operand set of this GEMM of the batch
+        const int64_t b = blockIdx.z;
+        if (!p.A_shared) {
+            p.A0 += b * p.sA;
+            p.A1 += b * p.sA;
+        }
+        if (!p.B_shared) {
+            p.B0 += b * p.sB;
+            p.B1 += b * p.sB;
+        }
+        p.C0 += b * p.sC;
+        p.C1 += b * p.sC;
+        if (EPI == 2) {
+            p.sub0 += b * p.sC;
+            p.sub1 += b * p.sC;
+        }
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
@@ -1965,18 +1983,81 @@ void launch_hist_direct(const HistDirectArgs& a, hipStream_t st) {
     prof_end(1, st);
 }
 
-__global__ __launch_bounds__(256) void k_reduce_row(const double* __restrict__ F, int ks, int B, int64_t M,
-                                                    double* __restrict__ out) {
+// ---------------------------------------------------------------------------
+// One direct history row (cq_history and its allocation-free variant), the
+// convolution of (3.8)/(3.17) at a single step n:
+//   S[x] = sum_{l=1}^{n-1} d[n-l] G^l[x],   G^l[x] at G[l*M + x].
+// A weighted sum over stored levels: every level is read once, so the kernel
+// streams HBM (8 bytes per DOF and level). One DOF per lane (a wave reads 64
+// consecutive doubles of a level); blockIdx.y = slice q of the levels
+// 1 + q*lchunk .. min(n-1, (q+1)*lchunk), so that a short row still fills the
+// GPU. The weights are wave-uniform scalar loads. A single slice writes
+// out[x]; several write part[q][x] and k_row_sum adds them in slice order.
+__global__ __launch_bounds__(256) void k_hist_row(const double* __restrict__ G, int64_t n, int64_t M,
+                                                  const double* __restrict__ d, int64_t lchunk,
+                                                  double* __restrict__ out) {
     const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (x >= M) return;
-    double s = 0.0;
-    for (int q = 0; q < ks; ++q) s += F[int64_t(q) * B * M + x];
+    const int64_t lb = 1 + int64_t(blockIdx.y) * lchunk;
+    const int64_t le = (lb + lchunk - 1 < n - 1) ? lb + lchunk - 1 : n - 1;  // inclusive
+    const cdouble* dd = (const cdouble*)(d);
+    const double* __restrict__ g = G + x;
+    double acc = 0.0;
+    int64_t l = lb;
+    // eight levels per round: the loads are independent, the sum is not
+    for (; l + 8 <= le + 1; l += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = g[(l + u) * M];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(dd[n - l - u], v[u], acc);
+    }
+    for (; l <= le; ++l) acc = fma(dd[n - l], g[l * M], acc);
+    out[int64_t(blockIdx.y) * M + x] = acc;
+}
+
+// out[x] = sum_{q < ks} part[q*M + x], q ascending
+__global__ __launch_bounds__(256) void k_row_sum(const double* __restrict__ part, int ks, int64_t M,
+                                                 double* __restrict__ out) {
+    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= M) return;
+    double s = part[x];
+    for (int q = 1; q < ks; ++q) s += part[int64_t(q) * M + x];
     out[x] = s;
 }
 
-void launch_reduce_row(const double* F, int ks, int B, int64_t M, double* out, hipStream_t st) {
+// out[x] = 0 (a kernel, not a memset, so that the call can sit in a captured graph)
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ out, int64_t M) {
+    const int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (x < M) out[x] = 0.0;
+}
+
+int hist_row_slices(int64_t n, int64_t M, int64_t part_cap) {
+    if (n <= 2) return 1;
+    // about 8192 waves (32 per CU) so that enough level loads are in flight
+    const int64_t wg = (M + 255) / 256;
+    int64_t ks = (2048 + wg - 1) / wg;
+    ks = std::min<int64_t>(ks, std::min<int64_t>(1024, (n - 1 + 15) / 16));  // >= 16 levels per slice
+    if (part_cap >= 0) ks = std::min<int64_t>(ks, part_cap / M);
+    return int(std::max<int64_t>(1, ks));
+}
+
+void launch_hist_row(const double* G, int64_t n, int64_t M, const double* d, int ks, double* part, double* out,
+                     hipStream_t st) {
+    const unsigned gx = unsigned((M + 255) / 256);
     prof_begin(6, st);
-    hipLaunchKernelGGL(k_reduce_row, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, F, ks, B, M, out);
+    if (n <= 1) {
+        hipLaunchKernelGGL(k_fill_zero, dim3(gx), dim3(256), 0, st, out, M);
+    } else {
+        const int64_t lchunk = (n - 1 + ks - 1) / ks;
+        const int64_t slices = (n - 1 + lchunk - 1) / lchunk;
+        if (slices == 1) {
+            hipLaunchKernelGGL(k_hist_row, dim3(gx, 1), dim3(256), 0, st, G, n, M, d, lchunk, out);
+        } else {
+            hipLaunchKernelGGL(k_hist_row, dim3(gx, unsigned(slices)), dim3(256), 0, st, G, n, M, d, lchunk, part);
+            hipLaunchKernelGGL(k_row_sum, dim3(gx), dim3(256), 0, st, part, int(slices), M, out);
+        }
+    }
     prof_end(6, st);
 }
 
@@ -2019,7 +2100,7 @@ void launch_prep_2d(const StepArgs& a, hipStream_t st) {
 }
 
 void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
-    dim3 grid(unsigned((a.C + 15) / 16), unsigned((a.R + 15) / 16));
+    dim3 grid(unsigned((a.C + 15) / 16), unsigned((a.R + 15) / 16), unsigned(a.batch > 1 ? a.batch : 1));
     prof_begin(5, st);
     if (epi == 1)
         hipLaunchKernelGGL(k_dst_gemm<1>, grid, dim3(256), 0, st, a);
@@ -2030,6 +2111,50 @@ void launch_gemm(const GemmArgs& a, int epi, hipStream_t st) {
     else
         hipLaunchKernelGGL(k_dst_gemm<0>, grid, dim3(256), 0, st, a);
     prof_end(5, st);
+}
+
+void launch_sine_transform(int dim, int nx, int ny, int nz, const double* Sx, const double* Sy, const double* Sz,
+                           const double* G, double* tmp, double* out, double scale, hipStream_t st) {
+    const int64_t M = int64_t(nx) * (dim >= 2 ? ny : 1) * (dim == 3 ? nz : 1);
+    if (dim == 1) {
+        GemmArgs ga{};
+        ga.R = 1; ga.C = nx; ga.K = nx; ga.lda = nx; ga.ldb = nx; ga.ldc = nx;
+        ga.A_shared = 0; ga.B_shared = 1;
+        ga.A0 = G; ga.A1 = G + M; ga.B0 = Sx; ga.B1 = Sx; ga.C0 = out; ga.C1 = out + M;
+        ga.scale = scale;
+        launch_gemm(ga, 3, st);
+        return;
+    }
+    const int planes = dim == 3 ? nz : 1;
+    // along x: every row of nx values (ny * planes rows) times S_x
+    // (2D: into tmp, then y into out; 3D: into out, y into tmp, z into out)
+    double* xo = dim == 2 ? tmp : out;
+    double* yo = dim == 2 ? out : tmp;
+    GemmArgs ga{};
+    ga.R = ny * planes; ga.C = nx; ga.K = nx; ga.lda = nx; ga.ldb = nx; ga.ldc = nx;
+    ga.A_shared = 0; ga.B_shared = 1;
+    ga.A0 = G; ga.A1 = G + M; ga.B0 = Sx; ga.B1 = Sx; ga.C0 = xo; ga.C1 = xo + M;
+    launch_gemm(ga, 0, st);
+    // along y: S_y times each z-plane (ny x nx)
+    GemmArgs gb{};
+    gb.R = ny; gb.C = nx; gb.K = ny; gb.lda = ny; gb.ldb = nx; gb.ldc = nx;
+    gb.A_shared = 1; gb.B_shared = 0;
+    gb.A0 = Sy; gb.A1 = Sy; gb.B0 = xo; gb.B1 = xo + M; gb.C0 = yo; gb.C1 = yo + M;
+    gb.batch = planes;
+    gb.sB = gb.sC = int64_t(ny) * nx;
+    gb.scale = scale;
+    if (dim == 2) {
+        launch_gemm(gb, 3, st);
+        return;
+    }
+    launch_gemm(gb, 0, st);
+    // along z: S_z times the (nz) x (ny nx) matrix
+    GemmArgs gc{};
+    gc.R = nz; gc.C = ny * nx; gc.K = nz; gc.lda = nz; gc.ldb = ny * nx; gc.ldc = ny * nx;
+    gc.A_shared = 1; gc.B_shared = 0;
+    gc.A0 = Sz; gc.A1 = Sz; gc.B0 = yo; gc.B1 = yo + M; gc.C0 = out; gc.C1 = out + M;
+    gc.scale = scale;
+    launch_gemm(gc, 3, st);
 }
 
 // time-blocked where the lag allows blocks of 8..32 steps and the nodes fit

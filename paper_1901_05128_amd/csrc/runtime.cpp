@@ -50,9 +50,9 @@ struct AdjBufs {
 struct Solver {
     cq_grid g{};
     cq_params p{};
-    int dim = 1, nx = 1, ny = 1;
+    int dim = 1, nx = 1, ny = 1, nz = 1;
     int64_t M = 0, N = 0, n = 0;
-    double tau = 0, a = 0, beta[2] = {0, 0}, c = 0, hx = 0, hy = 0;
+    double tau = 0, a = 0, beta[2] = {0, 0}, c = 0, hx = 0, hy = 0, hz = 0;
     hipStream_t st = nullptr;
     // fast
     int L = 2, np = 0, hlanes = 1, chunk = 0, Bt = 1, BTt = 8;
@@ -80,6 +80,9 @@ struct Solver {
            *H = nullptr, *Spart = nullptr, *F = nullptr, *rhs = nullptr, *T1 = nullptr, *T2 = nullptr,
            *Sx = nullptr, *Sy = nullptr, *lamx = nullptr, *lamy = nullptr, *qbuf = nullptr, *Sf = nullptr, *PF = nullptr, *PG = nullptr, *PRB = nullptr, *lam = nullptr,
            *g0c = nullptr, *ring = nullptr;
+    // 3D: sine matrix and eigenvalues along z; the eigenvalues of the (y, x)
+    // modes of one z-plane (the nodal solve's epilogue adds lamz[r])
+    double *Sz = nullptr, *lamz = nullptr, *lamxy = nullptr;
     int levels_pcr = 0;
     bool modal_blocked = false;  // modal fast form with the state streamed in time blocks
     // gradient runs (modal): forward history sums, adjoint sweep
@@ -143,11 +146,16 @@ double lambda_1d(int n, double len, int p) {  // p = 1..n
 
 int validate(const cq_grid* g, const cq_params* p) {
     if (!g || !p) return fail(CQ_EINVAL, "grid and params must not be NULL");
-    if (g->dim != 1 && g->dim != 2) return fail(CQ_EINVAL, "dim must be 1 or 2 (got %d)", g->dim);
+    if (g->dim < 1 || g->dim > 3) return fail(CQ_EINVAL, "dim must be 1, 2 or 3 (got %d)", g->dim);
     if (g->nx < 1 || g->ny < 1) return fail(CQ_EINVAL, "nx, ny must be >= 1");
     if (g->dim == 1 && g->ny != 1) return fail(CQ_EINVAL, "dim 1 needs ny = 1");
+    if (g->dim < 3 && g->nz != 0 && g->nz != 1) return fail(CQ_EINVAL, "dim %d needs nz = 0 or 1", g->dim);
+    if (g->dim == 3 && g->nz < 1) return fail(CQ_EINVAL, "nz must be >= 1");
     if (g->dim == 1 && g->nx > 4096) return fail(CQ_EINVAL, "1D grids are limited to 4096 nodes (got %d)", g->nx);
-    if (!(g->lx > 0) || (g->dim == 2 && !(g->ly > 0))) return fail(CQ_EINVAL, "domain lengths must be > 0");
+    if (g->dim == 3 && int64_t(g->ny) * g->nz > (int64_t(1) << 20))
+        return fail(CQ_EINVAL, "3D grids are limited to ny * nz <= 2^20 (got %d x %d)", g->ny, g->nz);
+    if (!(g->lx > 0) || (g->dim >= 2 && !(g->ly > 0)) || (g->dim == 3 && !(g->lz > 0)))
+        return fail(CQ_EINVAL, "domain lengths must be > 0");
     if (!(p->alpha1 > 0 && p->alpha1 < 1 && p->alpha2 > 0 && p->alpha2 < 1))
         return fail(CQ_EINVAL, "alpha1, alpha2 must lie in (0,1)");
     if (!(p->m >= 0 && p->m <= 1) || p->m == 0.5) return fail(CQ_EINVAL, "m must lie in [0,1] without 1/2");
@@ -215,8 +223,9 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     s.p = *p;
     s.dim = g->dim;
     s.nx = g->nx;
-    s.ny = g->dim == 2 ? g->ny : 1;
-    s.M = int64_t(s.nx) * s.ny;
+    s.ny = g->dim >= 2 ? g->ny : 1;
+    s.nz = g->dim == 3 ? g->nz : 1;
+    s.M = int64_t(s.nx) * s.ny * s.nz;
     s.N = p->N;
     s.st = st;
     s.tau = p->T / double(p->N);
@@ -225,7 +234,8 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     s.beta[1] = 1.0 - p->alpha2;
     s.c = (p->scheme == 1 ? 1.0 : 1.5) / s.tau;
     s.hx = g->lx / (s.nx + 1);
-    s.hy = s.dim == 2 ? g->ly / (s.ny + 1) : 1.0;
+    s.hy = s.dim >= 2 ? g->ly / (s.ny + 1) : 1.0;
+    s.hz = s.dim == 3 ? g->lz / (s.nz + 1) : 1.0;
     const int ns = p->ns ? p->ns : 30;
     const int np1 = p->np1 ? p->np1 : 16;
     const int np_max = p->np_max ? p->np_max : 1024;
@@ -251,7 +261,8 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     const double K[2][2] = {{s.c / d10 + s.a, -s.a * d20 / d10}, {-s.a * d10 / d20, s.c / d20 + s.a}};
     eig2(K, s.theta, s.V, s.Vinv);
     double lam_min = lambda_1d(s.nx, g->lx, 1);
-    if (s.dim == 2) lam_min += lambda_1d(s.ny, g->ly, 1);
+    if (s.dim >= 2) lam_min += lambda_1d(s.ny, g->ly, 1);
+    if (s.dim == 3) lam_min += lambda_1d(s.nz, g->lz, 1);
     for (int k = 0; k < 2; ++k)
         if (!(s.theta[k] + lam_min > 0))
             return fail(CQ_ESINGULAR,
@@ -344,8 +355,8 @@ int setup_tables(Solver& s) {
     for (int q = 0; q < s.nx; ++q) lx[size_t(q)] = lambda_1d(s.nx, g->lx, q + 1);
     if ((rc = upload(s.Sx, sine_matrix(s.nx)))) return rc;
     if ((rc = upload(s.lamx, lx))) return rc;
-    std::vector<double> ly(1, 0.0);
-    if (s.dim == 2) {
+    std::vector<double> ly(1, 0.0), lz(1, 0.0);
+    if (s.dim >= 2) {
         if ((rc = dev_alloc(s, &s.Sy, size_t(s.ny) * s.ny))) return rc;
         if ((rc = dev_alloc(s, &s.lamy, size_t(s.ny)))) return rc;
         ly.assign(size_t(s.ny), 0.0);
@@ -353,40 +364,43 @@ int setup_tables(Solver& s) {
         if ((rc = upload(s.Sy, sine_matrix(s.ny)))) return rc;
         if ((rc = upload(s.lamy, ly))) return rc;
     }
-    if (s.p.solver == 1) {  // eigenvalue of every mode, layout [ny][nx] (row y-mode, column x-mode)
+    if (s.dim == 3) {
+        if ((rc = dev_alloc(s, &s.Sz, size_t(s.nz) * s.nz))) return rc;
+        if ((rc = dev_alloc(s, &s.lamz, size_t(s.nz)))) return rc;
+        lz.assign(size_t(s.nz), 0.0);
+        for (int r = 0; r < s.nz; ++r) lz[size_t(r)] = lambda_1d(s.nz, g->lz, r + 1);
+        if ((rc = upload(s.Sz, sine_matrix(s.nz)))) return rc;
+        if ((rc = upload(s.lamz, lz))) return rc;
+        std::vector<double> lxy(size_t(s.ny) * size_t(s.nx));
+        for (int j = 0; j < s.ny; ++j)
+            for (int i = 0; i < s.nx; ++i) lxy[size_t(j) * size_t(s.nx) + size_t(i)] = ly[size_t(j)] + lx[size_t(i)];
+        if ((rc = dev_alloc(s, &s.lamxy, lxy.size()))) return rc;
+        if ((rc = upload(s.lamxy, lxy))) return rc;
+    }
+    if (s.p.solver == 1) {  // eigenvalue of every mode, layout [nz][ny][nx] (x-mode fastest)
         if ((rc = dev_alloc(s, &s.lam, size_t(s.M)))) return rc;
         std::vector<double> lm(size_t(s.M));
-        for (int j = 0; j < s.ny; ++j)
-            for (int i = 0; i < s.nx; ++i) lm[size_t(j) * size_t(s.nx) + size_t(i)] = ly[size_t(j)] + lx[size_t(i)];
+        for (int r = 0; r < s.nz; ++r)
+            for (int j = 0; j < s.ny; ++j)
+                for (int i = 0; i < s.nx; ++i)
+                    lm[(size_t(r) * size_t(s.ny) + size_t(j)) * size_t(s.nx) + size_t(i)] =
+                        lz[s.dim == 3 ? size_t(r) : 0] + ly[s.dim >= 2 ? size_t(j) : 0] + lx[size_t(i)];
         if ((rc = upload(s.lam, lm))) return rc;
     }
     return CQ_OK;
 }
 
-// sine coefficients: out = S G (1D, scaled 2/(n+1)) or S_y G S_x (2D, scaled
-// 4/((nx+1)(ny+1))); both components. tmp: [2][M] (2D).
+// sine coefficients of both components: out = S G (1D, scaled 2/(n+1)),
+// S_y G S_x (2D, scaled 4/((nx+1)(ny+1))) or the same along z as well (3D,
+// scaled 8/((nx+1)(ny+1)(nz+1))); the inverse is unscaled. tmp: s.T1.
 void transform(Solver& s, const double* G, double* out, bool forward) {
-    const int64_t M = s.M;
-    if (s.dim == 1) {
-        GemmArgs ga{};
-        ga.R = 1; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
-        ga.A_shared = 0; ga.B_shared = 1;
-        ga.A0 = G; ga.A1 = G + M; ga.B0 = s.Sx; ga.B1 = s.Sx; ga.C0 = out; ga.C1 = out + M;
-        ga.scale = forward ? 2.0 / double(s.nx + 1) : 1.0;
-        launch_gemm(ga, 3, s.st);
-        return;
+    double scale = 1.0;
+    if (forward) {
+        scale = 2.0 / double(s.nx + 1);
+        if (s.dim >= 2) scale *= 2.0 / double(s.ny + 1);
+        if (s.dim == 3) scale *= 2.0 / double(s.nz + 1);
     }
-    GemmArgs ga{};
-    ga.R = s.ny; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
-    ga.A_shared = 0; ga.B_shared = 1;
-    ga.A0 = G; ga.A1 = G + M; ga.B0 = s.Sx; ga.B1 = s.Sx; ga.C0 = s.T1; ga.C1 = s.T1 + M;
-    launch_gemm(ga, 0, s.st);
-    GemmArgs gb{};
-    gb.R = s.ny; gb.C = s.nx; gb.K = s.ny; gb.lda = s.ny; gb.ldb = s.nx; gb.ldc = s.nx;
-    gb.A_shared = 1; gb.B_shared = 0;
-    gb.A0 = s.Sy; gb.A1 = s.Sy; gb.B0 = s.T1; gb.B1 = s.T1 + M; gb.C0 = out; gb.C1 = out + M;
-    gb.scale = forward ? 4.0 / (double(s.nx + 1) * double(s.ny + 1)) : 1.0;
-    launch_gemm(gb, 3, s.st);
+    launch_sine_transform(s.dim, s.nx, s.ny, s.nz, s.Sx, s.Sy, s.Sz, G, s.T1, out, scale, s.st);
 }
 
 // (re)start a modal solver from G0 (already in s.G0): coefficients of G0,
@@ -450,7 +464,7 @@ int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
         if ((rc = setup_tables(s))) return rc;
         if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
         if ((rc = dev_alloc(s, &s.Sscratch, size_t(twoM)))) return rc;
-        if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
+        if (s.dim >= 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
         if (p->method == 1) {
             // many modes: stream the state in time blocks (thread per mode);
             // few modes: keep each mode's state in the registers of one wave
@@ -677,6 +691,52 @@ void modal_steps(Solver& s, int64_t nsteps) {
     }
 }
 
+// 3D nodal solve of one step: sine transform of w along x, y and z, the
+// per-mode 2x2 solve in the z-pass's epilogue (eigenvalue lamz[r] +
+// lamxy[(y, x) mode]), inverse transform, minus q.
+void step_solve_3d(Solver& s, double* out) {
+    const int64_t M = s.M;
+    const int nx = s.nx, ny = s.ny, nz = s.nz;
+    const int64_t plane = int64_t(ny) * nx;
+    // along x: rows of nx values, ny*nz rows
+    GemmArgs gx{};
+    gx.R = ny * nz; gx.C = nx; gx.K = nx; gx.lda = nx; gx.ldb = nx; gx.ldc = nx;
+    gx.A_shared = 0; gx.B_shared = 1;
+    gx.B0 = s.Sx; gx.B1 = s.Sx;
+    // along y: S_y times each z-plane
+    GemmArgs gy{};
+    gy.R = ny; gy.C = nx; gy.K = ny; gy.lda = ny; gy.ldb = nx; gy.ldc = nx;
+    gy.A_shared = 1; gy.B_shared = 0;
+    gy.A0 = s.Sy; gy.A1 = s.Sy;
+    gy.batch = nz;
+    gy.sB = gy.sC = plane;
+    // along z: S_z times the nz x (ny nx) matrix
+    GemmArgs gz{};
+    gz.R = nz; gz.C = int(plane); gz.K = nz; gz.lda = nz; gz.ldb = int(plane); gz.ldc = int(plane);
+    gz.A_shared = 1; gz.B_shared = 0;
+    gz.A0 = s.Sz; gz.A1 = s.Sz;
+    // forward: rhs -> T1 -> T2 -> T1 (solved coefficients)
+    gx.A0 = s.rhs; gx.A1 = s.rhs + M; gx.C0 = s.T1; gx.C1 = s.T1 + M;
+    launch_gemm(gx, 0, s.st);
+    gy.B0 = s.T1; gy.B1 = s.T1 + M; gy.C0 = s.T2; gy.C1 = s.T2 + M;
+    launch_gemm(gy, 0, s.st);
+    GemmArgs gs = gz;
+    gs.B0 = s.T2; gs.B1 = s.T2 + M; gs.C0 = s.T1; gs.C1 = s.T1 + M;
+    gs.lamy = s.lamz; gs.lamx = s.lamxy; gs.cdiag = s.c; gs.a = s.a;
+    gs.scale = 8.0 / (double(nx + 1) * double(ny + 1) * double(nz + 1));
+    gs.dd0[0] = s.dh[0][0]; gs.dd0[1] = s.dh[1][0];
+    launch_gemm(gs, 1, s.st);
+    // inverse: T1 -> T2 -> T1 -> out - q
+    gx.A0 = s.T1; gx.A1 = s.T1 + M; gx.C0 = s.T2; gx.C1 = s.T2 + M;
+    launch_gemm(gx, 0, s.st);
+    gy.B0 = s.T2; gy.B1 = s.T2 + M; gy.C0 = s.T1; gy.C1 = s.T1 + M;
+    launch_gemm(gy, 0, s.st);
+    GemmArgs gi = gz;
+    gi.B0 = s.T1; gi.B1 = s.T1 + M; gi.C0 = out; gi.C1 = out + M;
+    gi.sub0 = s.qbuf; gi.sub1 = s.qbuf + M;
+    launch_gemm(gi, 2, s.st);
+}
+
 // one time step n = s.n + 1
 void step_once(Solver& s) {
     const int64_t n = ++s.n;
@@ -759,6 +819,10 @@ void step_once(Solver& s) {
     sa.w = s.rhs;
     sa.q = s.qbuf;
     launch_prep_2d(sa, s.st);
+    if (s.dim == 3) {
+        step_solve_3d(s, s.levels + (n % s.Lr) * 2 * M);
+        return;
+    }
     GemmArgs ga{};
     // forward: T1 = w Sx ; T2 = solve(Sy T1)
     ga.R = s.ny; ga.C = s.nx; ga.K = s.nx; ga.lda = s.nx; ga.ldb = s.nx; ga.ldc = s.nx;
@@ -948,53 +1012,29 @@ int cq_history(int32_t scheme, double beta, double tau, const double* G_hist, in
     if (n < 1 || M < 1) return fail(CQ_EINVAL, "n and M must be >= 1");
     if (!G_hist || !S_out) return fail(CQ_EINVAL, "NULL array");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const int B = 64;
-    const int64_t tiles = (M + 63) / 64;
-    const int ks = int(std::min<int64_t>(64, std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles,
-                                                                                     (n + 3) / 4))));
-    const int64_t dstride = n + B + 1;
-    std::vector<double> dh(static_cast<size_t>(dstride));
-    weights(scheme, beta, tau, dstride - 1, dh.data());
-    double *dd = nullptr, *F = nullptr;
-    HIPCHK(hipMalloc(&dd, size_t(dstride) * sizeof(double)));
-    hipError_t e = hipMalloc(&F, size_t(ks) * B * size_t(M) * sizeof(double));
+    const int ks = hist_row_slices(n, M, -1);
+    std::vector<double> dh(static_cast<size_t>(n));  // d_0 .. d_{n-1}
+    weights(scheme, beta, tau, n - 1, dh.data());
+    // workspace of this call: the weights and the slices' partial sums
+    const size_t nd = size_t(n), npart = ks > 1 ? size_t(ks) * size_t(M) : 0;
+    double* ws = nullptr;
+    hipError_t e = hipMalloc(&ws, (nd + npart) * sizeof(double));
     if (e != hipSuccess) {
-        (void)hipFree(dd);
-        return fail(CQ_ENOMEM, "hipMalloc for history partials: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? CQ_ENOMEM : CQ_EHIP, "hipMalloc for the history workspace: %s",
+                    hipGetErrorString(e));
     }
     int rc = CQ_OK;
     do {
-        e = hipMemcpyAsync(dd, dh.data(), size_t(dstride) * sizeof(double), hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(ws, dh.data(), nd * sizeof(double), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) { rc = fail(CQ_EHIP, "copy weights: %s", hipGetErrorString(e)); break; }
-        if (n == 1) {
-            e = hipMemsetAsync(S_out, 0, size_t(M) * sizeof(double), st);
-            if (e != hipSuccess) { rc = fail(CQ_EHIP, "memset: %s", hipGetErrorString(e)); break; }
-        } else {
-            FarArgs fa{};
-            fa.n0 = n - 1;
-            fa.nl = n - 1;
-            fa.M = M;
-            fa.dstride = dstride;
-            fa.lstride = M;
-            fa.B = B;
-            fa.ks = ks;
-            fa.ncomp = 1;
-            const int64_t mc = (fa.n0 + ks - 1) / ks;
-            fa.mchunk = ((mc + 3) / 4) * 4;
-            fa.levels = G_hist;
-            fa.d = dd;
-            fa.F = F;
-            fa.reduce = 0;
-            launch_far(fa, st);
-            launch_reduce_row(F, ks, B, M, S_out, st);
-            e = hipGetLastError();
-            if (e != hipSuccess) { rc = fail(CQ_EHIP, "launch: %s", hipGetErrorString(e)); break; }
-        }
+        launch_hist_row(G_hist, n, M, ws, ks, ws + nd, S_out, st);
+        e = hipGetLastError();
+        if (e != hipSuccess) { rc = fail(CQ_EHIP, "launch: %s", hipGetErrorString(e)); break; }
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = fail(CQ_EHIP, "sync: %s", hipGetErrorString(e));
     } while (0);
-    (void)hipFree(dd);
-    (void)hipFree(F);
+    (void)hipFree(ws);
     return rc;
 }
 
@@ -1006,7 +1046,7 @@ int fp_create(const cq_grid* grid, const cq_params* prm, const double* G0, void*
     if (rc) return rc;
     if (!G0) return fail(CQ_EINVAL, "G0 is NULL");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const int64_t M = int64_t(grid->nx) * (grid->dim == 2 ? grid->ny : 1);
+    const int64_t M = int64_t(grid->nx) * (grid->dim >= 2 ? grid->ny : 1) * (grid->dim == 3 ? grid->nz : 1);
     Solver* s = new (std::nothrow) Solver();
     if (!s) return fail(CQ_ENOMEM, "host allocation failed");
     try {
@@ -1230,7 +1270,7 @@ static int adjoint_setup(Solver& s) {
     if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.Sscratch, size_t(twoM)))) return rc;
-    if (s.dim == 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
+    if (s.dim >= 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
     if ((rc = setup_tables(s))) return rc;
     if ((rc = dev_alloc(s, &A.traj, lev))) return rc;
     if ((rc = dev_alloc(s, &A.Sx, lev))) return rc;

@@ -6,8 +6,9 @@ CPU oracle may take their inputs from it.
 
 Domain and data follow the paper's experiments (Section 5): Omega is the unit
 interval or the unit square, the Laplacian carries zero Dirichlet data, and the
-initial values are nonsmooth indicator functions (the paper's data (b) family)
-or, for the smallest case, an indicator plus smooth data with seeded noise.
+initial values are nonsmooth indicator functions (the paper's data (b) family),
+the paper's smooth data (a) for the Table 5 workload, or, for the smallest
+case, an indicator plus smooth data with seeded noise.
 Grid nodes are x_i = i*h, h = 1/(n+1), i = 1..n (interior nodes only).
 """
 from __future__ import annotations
@@ -103,6 +104,44 @@ def g0_rectangle(nx: int, ny: int, seed: int) -> np.ndarray:
     return np.stack([f, f.copy()])
 
 
+def g0_smooth(nx: int, ny: int = 1) -> np.ndarray:
+    """The paper's smooth initial data (a) of Section 5: G1 = x(1-x),
+    G2 = sin(x) at the interior nodes (1D). In 2D (not in the paper) the
+    same profiles in x times y(1-y)."""
+    x = nodes_1d(nx)
+    g1, g2 = x * (1.0 - x), np.sin(x)
+    if ny > 1:
+        y = nodes_1d(ny)
+        f = y * (1.0 - y)
+        g1 = (f[:, None] * g1[None, :]).reshape(-1)
+        g2 = (f[:, None] * g2[None, :]).reshape(-1)
+    return np.stack([g1, g2])
+
+
+def g0_nonsmooth_b(nx: int) -> np.ndarray:
+    """The paper's nonsmooth data (b) of Section 5 (1D): G1 = (1-x) on (1/2, 1),
+    G2 = x on (0, 1/2), zero elsewhere (open intervals: the node x = 1/2 is 0)."""
+    x = nodes_1d(nx)
+    return np.stack([np.where(x > 0.5, 1.0 - x, 0.0), np.where(x < 0.5, x, 0.0)])
+
+
+def g0_box(nx: int, ny: int, nz: int, seed: int) -> np.ndarray:
+    """G1 = G2 = indicator of one closed box [u1,v1] x [u2,v2] x [u3,v3] from
+    sorted U(0,1) pairs (drawn again until it covers a grid node). Layout
+    [2][nz][ny][nx] flattened (x fastest)."""
+    rng = np.random.default_rng(seed)
+    x, y, z = nodes_1d(nx), nodes_1d(ny), nodes_1d(nz)
+    while True:
+        b = [np.sort(rng.uniform(0.0, 1.0, size=2)) for _ in range(3)]
+        ind = ((z[:, None, None] >= b[2][0]) & (z[:, None, None] <= b[2][1])
+               & (y[None, :, None] >= b[1][0]) & (y[None, :, None] <= b[1][1])
+               & (x[None, None, :] >= b[0][0]) & (x[None, None, :] <= b[0][1]))
+        if ind.any():
+            break
+    f = ind.astype(np.float64).reshape(-1)
+    return np.stack([f, f.copy()])
+
+
 def g0_random(M: int, seed: int) -> np.ndarray:
     """Plain seeded U(-1,1) data on every node (for operator-level tests)."""
     rng = np.random.default_rng(seed)
@@ -114,6 +153,8 @@ def g0_for(p: Problem) -> np.ndarray:
         return g0_c1(p.nx, p.seed)
     if p.g0_kind == "random":
         return g0_random(p.M, p.seed)
+    if p.g0_kind == "smooth":
+        return g0_smooth(p.nx, p.ny)
     if p.dim == 1:
         return g0_intervals(p.nx, p.seed)
     return g0_rectangle(p.nx, p.ny, p.seed)
@@ -124,6 +165,11 @@ C1 = Problem("c1_1d127_be_direct", 1, 127, 1, 0.3, 0.7, 0.3, 1.0, 1000, 1, 0, 1,
 C2 = Problem("c2_1d1023", 1, 1023, 1, 0.4, 0.8, 0.45, 1.0, 2 ** 14, 1, 1, 2)
 C3 = Problem("c3_2d255", 2, 255, 255, 0.2, 0.6, 0.55, 1.0, 2 ** 16, 2, 1, 3)
 C5 = Problem("c5_adjoint_2d127", 2, 127, 127, 0.2, 0.6, 0.55, 1.0, 4096, 2, 1, 5, np_=192, ns=30)
+# The paper's Table 5 problem: 1D h = 1/1024, T = 10, tau = 1/2000 (N = 20000),
+# a = -1 (m = 0), BDF2 (SBD) direct and fast, smooth data (a); the three order
+# pairs of the table.
+T5 = Problem("t5_1d1023_T10", 1, 1023, 1, 0.3, 0.8, 0.0, 10.0, 20000, 2, 1, 0, g0_kind="smooth")
+T5_ORDERS = [(0.3, 0.8), (0.4, 0.7), (0.5, 0.6)]
 
 
 def batched_instances(count: int = 256, seed: int = 4, scale: float = 1.0):

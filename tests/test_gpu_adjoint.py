@@ -148,6 +148,70 @@ def test_full_size_parameter_gradients_match_finite_differences():
         assert abs(grads[i] - fd) <= 1e-6 * abs(fd) + 1e-9 * L0
 
 
+def test_full_size_parameter_gradients_match_central_differences():
+    """The same loss; central differences with h = 1e-6 of the GPU forward
+    in alpha_1, alpha_2 and m (truncation O(h^2) ~ 1e-12 relative; the
+    loss's rounding, ~1e-14 of it, divided by 2h sets the floor)."""
+    nx, ny, G0, G0t = _c5()
+    g = cq.make_grid(2, nx, ny)
+    target = cq.fp_solve(g, _params(0.25, 0.55, 0.55), dev(G0t)).cpu().numpy()
+    base = [0.2, 0.6, 0.55]
+
+    def loss(q):
+        GN = cq.fp_solve(g, _params(*q), dev(G0)).cpu().numpy()
+        return 0.5 * float(np.sum((GN - target) ** 2)), GN
+
+    L0, GN = loss(base)
+    _, grads = cq.fp_adjoint(g, _params(*base), dev(G0), dev(GN - target))
+    h = 1e-6
+    for i in range(3):
+        qp, qm = list(base), list(base)
+        qp[i] += h
+        qm[i] -= h
+        fd = (loss(qp)[0] - loss(qm)[0]) / (2 * h)
+        print(f"  param {i}: adjoint {grads[i]:.10e}  central fd {fd:.10e}  "
+              f"rel {abs(grads[i] - fd) / max(abs(fd), 1e-300):.2e}", flush=True)
+        assert abs(grads[i] - fd) <= 1e-5 * abs(fd) + 1e-8 * L0
+
+
+def test_full_size_adjoint_matches_oracle_on_sampled_modes():
+    """The adjoint workload at full size (2D 127^2, BDF2 fast with 16 + 192
+    nodes and N_s = 30, N = 4096) against the oracle adjoint. The cotangent
+    is supported on a few sine modes (dl/dc^N zero elsewhere); the modes
+    decouple, so dl/dG0 lives on those modes and only they contribute to
+    the scalar gradients: the oracle's adjoint run over those modes alone
+    (oracle.adjoint.adjoint with the modes' eigenvalues) is the exact
+    reference. Bars as the small cases: dl/dG0 1e-10 (L2), alpha 1e-8, m
+    1e-10."""
+    from oracle import modal
+    from oracle.stepper import ModalOps
+    nx, ny, G0, _ = _c5()
+    M = nx * ny
+    modes = [(1, 1), (2, 3), (17, 40), (64, 64), (127, 1), (1, 127), (127, 127)]
+    idx = [(q - 1) * nx + (p - 1) for (p, q) in modes]
+    rng = np.random.default_rng(61)
+    gcK = rng.standard_normal((2, len(modes)))
+    gc = np.zeros((2, M))
+    gc[:, idx] = gcK
+    gN = modal.to_modes(gc, 2, nx, ny)        # from_modes(gN) = gc: the cotangent of the coefficients
+    p = _params(0.2, 0.6, 0.55)
+    print("full-size adjoint on sampled modes: GPU", flush=True)
+    gG0, grads = cq.fp_adjoint(cq.make_grid(2, nx, ny), p, dev(G0), dev(gN))
+    print("full-size adjoint on sampled modes: oracle", flush=True)
+    lam = modal.mode_eigenvalues(2, nx, ny, modes)
+    c0 = modal.project(G0, 2, nx, ny, modes)
+    g0K, ga1, ga2, gm, _cN = adj.adjoint(ModalOps(lam), 0.2, 0.6, 0.55, 1.0, 4096, c0, gcK, 2, 1, np_=192,
+                                         np1=16, ns=30)
+    g0c = np.zeros((2, M))
+    g0c[:, idx] = g0K
+    ref0 = modal.to_modes(g0c, 2, nx, ny)     # dl/dG0 = P dl/dc0
+    e0 = rel(gG0.cpu().numpy(), ref0)
+    print(f"  dl/dG0 rel L2 {e0:.3e}; scalars {list(grads)} vs {[ga1, ga2, gm]}", flush=True)
+    assert e0 <= 1e-10, e0
+    for k, (got, ref, tol) in enumerate(zip(grads, (ga1, ga2, gm), (1e-8, 1e-8, 1e-10))):
+        assert abs(got - ref) <= tol * abs(ref), (k, got, ref)
+
+
 def test_handle_matches_one_shot_and_is_reusable():
     """fp_adjoint_create once, fp_adjoint_run twice (different cotangents):
     each run equals the one-shot fp_adjoint bit for bit; the stepping calls
@@ -228,3 +292,24 @@ def test_alpha_contraction_dft_matches_toeplitz(case, scheme, method, monkeypatc
     scale = abs(tg[0]) + abs(tg[1])
     for i in (0, 1):
         assert abs(sg[i] - tg[i]) <= 1e-9 * scale, (i, sg[i], tg[i])
+
+
+def test_autograd_wrapper_float_and_cpu_scalars():
+    """Python-number orders and m receive no gradient (backprop to G0 only);
+    a 0-dim CPU tensor receives its gradient on the CPU."""
+    from paper_1901_05128_amd import autograd as ag
+    nx = 31
+    G0n = wl.g0_random(nx, 53).reshape(2, nx)
+    tgt = torch.tensor(np.random.default_rng(54).standard_normal((2, nx)), device="cuda")
+    G0 = dev(G0n).requires_grad_()
+    GN = ag.solve(G0, 0.3, 0.7, 0.35, 1, nx, 1, T=1.0, N=80, scheme=2, method=1, np_=12, np1=8, ns=10)
+    (0.5 * ((GN - tgt) ** 2).sum()).backward()
+    p = cq.make_params(0.3, 0.7, 0.35, 1.0, 80, 2, 1, np_=12, np1=8, ns=10, solver=cq.SOLVER_MODAL)
+    gG0, grads = cq.fp_adjoint(cq.make_grid(1, nx), p, dev(G0n), (GN - tgt).detach().contiguous())
+    assert torch.equal(G0.grad, gG0)
+    a1 = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)   # CPU
+    G0b = dev(G0n)                                                      # no grad wanted
+    GN = ag.solve(G0b, a1, 0.7, 0.35, 1, nx, 1, T=1.0, N=80, scheme=2, method=1, np_=12, np1=8, ns=10)
+    (0.5 * ((GN - tgt) ** 2).sum()).backward()
+    assert a1.grad.device.type == "cpu" and a1.grad.dtype == torch.float64
+    assert a1.grad.item() == grads[0]

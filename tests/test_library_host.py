@@ -116,8 +116,10 @@ def test_fp_create_rejects_bad_params(bad):
     assert rc == _lib.CQ_EINVAL and not h.value
 
 
-@pytest.mark.parametrize("grid", [cq.make_grid(3, 4), cq.make_grid(1, 0), cq.make_grid(1, 5000),
-                                  cq.Grid(1, 4, 2, 1.0, 1.0), cq.make_grid(2, 4, 4, lx=0.0)])
+@pytest.mark.parametrize("grid", [cq.make_grid(4, 4), cq.make_grid(1, 0), cq.make_grid(1, 5000),
+                                  cq.Grid(1, 4, 2, 1.0, 1.0), cq.make_grid(2, 4, 4, lx=0.0),
+                                  cq.Grid(3, 2, 2, 1.0, 1.0, 0, 1.0), cq.Grid(2, 2, 2, 1.0, 1.0, 3, 1.0),
+                                  cq.Grid(3, 2, 2, 1.0, 1.0, 2, 0.0), cq.Grid(3, 2, 2048, 1.0, 1.0, 1024, 1.0)])
 def test_fp_create_rejects_bad_grid(grid):
     rc, h = _create(grid, cq.make_params(0.3, 0.7, 0.3, 1.0, 10, 1, 0))
     assert rc == _lib.CQ_EINVAL
@@ -170,3 +172,4 @@ def test_handle_calls_reject_null():
     assert L.fp_step(None, 1) == _lib.CQ_EINVAL
     assert L.fp_adjoint_run(None, None, None, None, None, None) == _lib.CQ_EINVAL
     assert L.fp_destroy(None) == _lib.CQ_OK
+
