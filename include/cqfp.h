@@ -152,6 +152,21 @@ int cq_fast_rule(int32_t scheme, double beta, double tau, int64_t N, double tol,
 int cq_history(int32_t scheme, double beta, double tau, const double* G_hist,
                int64_t n, int64_t M, double* S_out, void* hip_stream);
 
+/* The same history sum for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Arguments, layout and result as cq_history; the weights are
+ * computed on the device by the same recurrences (so they can differ from
+ * cq_history's host weights in the last bits). Calls no hipMalloc, hipFree or
+ * other allocating routine: its workspace (the weights and partial sums) is
+ * a static device array of 16 MiB that each GPU the library runs on holds
+ * until the process ends. Limit: n <= 2^20 levels (CQ_EINVAL beyond); any M.
+ * Asynchronous: the work is only enqueued on hip_stream (no synchronisation,
+ * no memset). Every call on one GPU shares that GPU's workspace, which keeps
+ * the last call's contents: calls whose device work can overlap on one GPU
+ * (other streams without ordering, other threads) race and must be
+ * serialised by the caller. */
+int cq_history_noalloc(int32_t scheme, double beta, double tau, const double* G_hist,
+                       int64_t n, int64_t M, double* S_out, void* hip_stream);
 
 /* Create a solver for one problem, starting from G0 (dev [2][M], copied).
  * Allocates every device buffer the run needs (the full history [N+1][2][M]

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "CQ_OK", -1: "CQ_EINVAL", -2: "CQ_ESINGULAR", -3: "CQ_ENOMEM"
                 -5: "CQ_ETOL", -6: "CQ_ENONFINITE"}
 
 # every entry point the header declares
-EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "fp_create", "fp_step", "fp_current", "fp_info",
+EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "cq_history_noalloc", "fp_create", "fp_step", "fp_current", "fp_info",
            "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "fp_solve_batched",
            "fp_adjoint", "fp_adjoint_create", "fp_adjoint_run", "cq_prof_enable", "cq_prof_read",
            "cq_last_error"]
@@ -80,6 +80,7 @@ def lib() -> C.CDLL:
     L.cq_weights.argtypes = [I32, D, D, I64, P(D)]
     L.cq_fast_rule.argtypes = [I32, D, D, I64, D, I32, I32, I32, I32, I32, P(D), P(D), P(I32), P(I32), P(D)]
     L.cq_history.argtypes = [I32, D, D, VP, I64, I64, VP, VP]
+    L.cq_history_noalloc.argtypes = [I32, D, D, VP, I64, I64, VP, VP]
     L.fp_create.argtypes = [P(Grid), P(Params), VP, VP, P(VP)]
     L.fp_step.argtypes = [VP, I64]
     L.fp_current.argtypes = [VP, VP, P(I64)]
@@ -169,6 +170,15 @@ def cq_history(scheme, beta, tau, G_hist, S_out=None):
     if S_out is None:
         S_out = torch.empty(M, dtype=torch.float64, device=G_hist.device)
     _check(lib().cq_history(scheme, beta, tau, _dev(G_hist, "G_hist"), n, M, _dev(S_out, "S_out"), _stream()))
+    return S_out
+
+
+def cq_history_noalloc(scheme, beta, tau, G_hist, S_out):
+    """cq_history without device allocation (S_out is required); enqueued on
+    torch's current stream without synchronising it."""
+    n, M = G_hist.shape
+    _check(lib().cq_history_noalloc(scheme, beta, tau, _dev(G_hist, "G_hist"), n, M, _dev(S_out, "S_out"),
+                                    _stream()))
     return S_out
 
 

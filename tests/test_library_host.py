@@ -173,3 +173,15 @@ def test_handle_calls_reject_null():
     assert L.fp_adjoint_run(None, None, None, None, None, None) == _lib.CQ_EINVAL
     assert L.fp_destroy(None) == _lib.CQ_OK
 
+
+def test_history_noalloc_host_checks():
+    """The allocation-free history row rejects sizes beyond its static
+    workspace (2^20 levels) and bad arguments before any device call."""
+    L = cq.lib()
+    fake = C.c_void_p(16)  # never dereferenced: every case fails its checks first
+    assert L.cq_history_noalloc(1, 0.4, 1e-3, fake, (1 << 20) + 1, 10, fake, None) == _lib.CQ_EINVAL
+    assert "2^20" in cq.lib().cq_last_error().decode() or "1048576" in cq.lib().cq_last_error().decode()
+    assert L.cq_history_noalloc(3, 0.4, 1e-3, fake, 10, 10, fake, None) == _lib.CQ_EINVAL
+    assert L.cq_history_noalloc(1, 1.0, 1e-3, fake, 10, 10, fake, None) == _lib.CQ_EINVAL
+    assert L.cq_history_noalloc(1, 0.4, 1e-3, fake, 0, 10, fake, None) == _lib.CQ_EINVAL
+    assert L.cq_history_noalloc(1, 0.4, 1e-3, None, 10, 10, fake, None) == _lib.CQ_EINVAL
