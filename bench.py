@@ -418,6 +418,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5"])
     ap.add_argument("--t5-errors", action="store_true",
                     help="t5: also run tau/2 (N = 40000) and report the L2 errors of Table 5's protocol")
+    ap.add_argument("--t5-data", default="a", choices=["a", "b"],
+                    help="t5: the paper's smooth data (a) or nonsmooth data (b)")
     ap.add_argument("--variants", default="default",
                     help="comma list of be_fast,be_direct,bdf2_fast,bdf2_direct timed in a step "
                          "(default: bdf2_fast,bdf2_direct for c3, all four otherwise)")
@@ -461,7 +463,11 @@ def main():
     variants = SERIAL.get(args.workload, VARIANTS) if not args.no_prof else timed
     variants = variants + [v for v in timed if v not in variants]
     torch.cuda.set_device(0)
-    G0 = torch.tensor(g0_for(w), dtype=torch.float64, device="cuda")
+    g0 = g0_for(w)
+    if args.workload == "t5" and args.t5_data == "b":
+        from paper_1901_05128_amd import workloads as wl
+        g0 = wl.g0_nonsmooth_b(nx)
+    G0 = torch.tensor(g0, dtype=torch.float64, device="cuda")
     grid = cq.make_grid(dim, nx, ny)
     solvers, streams = {}, {}
     for v in variants:
@@ -594,7 +600,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded indicator initial data)",
+        "data": (("synthetic (the paper's nonsmooth initial data (b))" if args.t5_data == "b" else
+                  "synthetic (the paper's smooth initial data (a))") if seed is None
+                 else "synthetic (seeded indicator initial data)"),
         "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
                    "solver": args.solver, "streams": "serial" if args.serial else "one per variant",
                    "timed_variants": [VNAME[v] for v in timed], "dof": 2 * M, "N": N,

@@ -71,8 +71,15 @@ typedef struct {
  *    one (0 selects 1e-8); the node count np is chosen by scanning the weight
  *    errors eps_i of (3.8)/(3.16) unless np > 0 is given.
  *  np: Gauss-Jacobi nodes (BE) or N_{p,2} (BDF2); 0 = choose by the scan.
- *  np1: N_{p,1} for BDF2 (0 selects 16). ns: N_s for BDF2 (0 selects 30;
- *    must be >= 3). np_max: scan limit (0 selects 1024). A solver keeps
+ *  np1: N_{p,1} for BDF2 (0 selects 16, or the scan's choice below).
+ *    ns: N_s for BDF2 (must be >= 3; 0 selects 30 when np is given). With
+ *    np = 0 and ns = 0 the BDF2 window is chosen from the weight errors too
+ *    (Section 5): N_s in {12,...,32} and N_{p,1} in {8, 12, 16, 24} (unless
+ *    np1 > 0), each with its smallest N_{p,2} meeting the tolerance, the
+ *    pair of least modelled cost per step (state flops, window flops, state
+ *    traffic per block of N_s steps) winning; fp_info reports the choice
+ *    (lag = N_s, np1). The batched solver and cq_fast_rule keep 30 and 16.
+ *    np_max: scan limit (0 selects 1024). A solver keeps
  *    at most 1024 fast nodes per component (np, or np1 + np for BDF2);
  *    more is CQ_EINVAL.
  *  block_B: direct method, time-block length of the Toeplitz far-field
@@ -115,6 +122,7 @@ typedef struct {
     int32_t ksplit;       /* direct: K-split of the far-field update           */
     size_t device_bytes;  /* device memory held by the handle                 */
     size_t state_bytes;   /* bytes of fp_get_state                            */
+    int32_t np1;          /* BDF2 fast: N_{p,1} (first family), 0 otherwise   */
 } cq_info;
 
 /* CQ weights d_i, i = 0..n, of order beta: Taylor coefficients of
@@ -232,10 +240,13 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
  * one 512-point FFT per block, mode and component, and the block pairs
  * contracted with the spectra of the weight windows between them), else as
  * Toeplitz products; setting the environment variable CQFP_BETA_TOEPLITZ
- * (not "0") when the handle is made selects the Toeplitz form at any N. The forward trajectory, its history
- * sums and the adjoint (psi, mu) are kept in device memory: 4 (N+1) 2M
- * doubles (CQ_ENOMEM beyond the free memory). Device work runs on hip_stream; the call
- * synchronises it. Errors as fp_create, plus CQ_EINVAL for solver != 1 or
+ * (not "0") when the handle is made selects the Toeplitz form at any N. The
+ * forward trajectory, its history sums and the adjoint (psi, mu) are kept in
+ * device memory (4 (N+1) 2M doubles) when they fit in the free memory;
+ * otherwise the fast method recomputes the forward from saved states (see
+ * cq_adjoint_opts; the alpha contraction then runs as Toeplitz products) and
+ * the direct method returns CQ_ENOMEM. Device work runs on hip_stream; the
+ * call synchronises it. Errors as fp_create, plus CQ_EINVAL for solver != 1 or
  * a fast window (ns) above 32. */
 int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, const double* gN,
                double* gG0, double* grad, double* GN, void* hip_stream);
@@ -248,6 +259,48 @@ int fp_adjoint(const cq_grid* grid, const cq_params* prm, const double* G0, cons
  * handle is released by fp_destroy; the stepping calls (fp_step, ...)
  * reject it with CQ_EINVAL. */
 int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_stream, void** handle);
+
+/* Memory form of a gradient handle (extension). The forward trajectory, its
+ * history sums and the adjoint fill 4 (N+1) 2M doubles when kept whole. For
+ * the fast method the forward can instead be recomputed from saved states:
+ * the steps are cut into segments (whole chunks of the gradient reductions,
+ * a multiple of the fast form's state block); a saved state is the fast
+ * state H and the last L levels at a segment start; a binomial (revolve)
+ * schedule, optimal for the number of states that fit, chooses where the
+ * forward advances and saves, and every segment is recomputed once more with
+ * its levels and history sums in a segment buffer while the adjoint takes
+ * the segment's steps (psi = Dm mu is kept whole: (N+1) 2M doubles). The
+ * gradient is the same computation: G^N, dl/dG0 and dl/dm equal the kept
+ * form's bit for bit; the alpha contraction, summed as Toeplitz products
+ * segment by segment, agrees to rounding (relative 1e-10).
+ *  max_device_bytes: the handle's budget (0: the free device memory).
+ *  mode: 0 automatic (keep whole if it fits the budget, else checkpointed
+ *    for the fast method, else CQ_ENOMEM), 1 keep whole, 2 checkpointed
+ *    (fast method only; CQ_EINVAL otherwise).
+ *  segment_steps, slots: checkpointed form's segment length (rounded up to
+ *    whole chunks) and number of saved states; 0 chooses the pair with the
+ *    fewest recomputed forward steps that fits the budget. */
+typedef struct {
+    size_t max_device_bytes;
+    int32_t mode;
+    int32_t segment_steps;
+    int32_t slots;
+} cq_adjoint_opts;
+
+/* What a gradient handle chose. */
+typedef struct {
+    int32_t mode;           /* 1 kept whole, 2 checkpointed                 */
+    int64_t segment_steps;  /* steps per segment (N when kept whole)        */
+    int32_t segments;
+    int32_t slots;          /* saved forward states (0 when kept whole)     */
+    int64_t forward_steps;  /* forward steps per gradient (N when kept whole) */
+    size_t device_bytes;    /* device memory held by the handle             */
+} cq_adjoint_info;
+
+/* fp_adjoint_create with a memory form (opts NULL: automatic). */
+int fp_adjoint_create_opts(const cq_grid* grid, const cq_params* prm, const cq_adjoint_opts* opts,
+                           void* hip_stream, void** handle);
+int fp_adjoint_info(void* handle, cq_adjoint_info* info);
 int fp_adjoint_run(void* handle, const double* G0, const double* gN, double* gG0, double* grad,
                    double* GN);
 

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "CQ_OK", -1: "CQ_EINVAL", -2: "CQ_ESINGULAR", -3: "CQ_ENOMEM"
 # every entry point the header declares
 EXPORTS = ["cq_weights", "cq_fast_rule", "cq_history", "cq_history_noalloc", "fp_create", "fp_step", "fp_current", "fp_info",
            "fp_get_state", "fp_set_state", "fp_reset", "fp_destroy", "fp_solve", "fp_solve_batched",
-           "fp_adjoint", "fp_adjoint_create", "fp_adjoint_run", "cq_prof_enable", "cq_prof_read",
+           "fp_adjoint", "fp_adjoint_create", "fp_adjoint_create_opts", "fp_adjoint_info", "fp_adjoint_run", "cq_prof_enable", "cq_prof_read",
            "cq_last_error"]
 PROF_KINDS = {"hist_fast": 0, "hist_direct": 1, "far_toeplitz": 2, "solve_1d": 3, "prep_2d": 4, "dst_gemm": 5,
               "reduce_row": 6, "modal_fast": 7, "modal_near": 8, "batched": 9, "reduce_far": 10,
@@ -51,7 +51,18 @@ class Params(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("N", C.c_int64), ("np_total", C.c_int32), ("lag", C.c_int32),
                 ("max_eps", C.c_double), ("theta", C.c_double * 2), ("block_B", C.c_int32),
-                ("ksplit", C.c_int32), ("device_bytes", C.c_size_t), ("state_bytes", C.c_size_t)]
+                ("ksplit", C.c_int32), ("device_bytes", C.c_size_t), ("state_bytes", C.c_size_t),
+                ("np1", C.c_int32)]
+
+
+class AdjointOpts(C.Structure):
+    _fields_ = [("max_device_bytes", C.c_size_t), ("mode", C.c_int32), ("segment_steps", C.c_int32),
+                ("slots", C.c_int32)]
+
+
+class AdjointInfo(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("segment_steps", C.c_int64), ("segments", C.c_int32), ("slots", C.c_int32),
+                ("forward_steps", C.c_int64), ("device_bytes", C.c_size_t)]
 
 
 class BatchReport(C.Structure):
@@ -95,6 +106,8 @@ def lib() -> C.CDLL:
     L.fp_solve_batched.argtypes = [I32, P(Grid), P(Params), P(VP), P(VP), VP, I32, P(BatchReport)]
     L.fp_adjoint.argtypes = [P(Grid), P(Params), VP, VP, VP, P(D), VP, VP]
     L.fp_adjoint_create.argtypes = [P(Grid), P(Params), VP, P(VP)]
+    L.fp_adjoint_create_opts.argtypes = [P(Grid), P(Params), P(AdjointOpts), VP, P(VP)]
+    L.fp_adjoint_info.argtypes = [VP, P(AdjointInfo)]
     L.fp_adjoint_run.argtypes = [VP, VP, VP, VP, P(D), VP]
     L.cq_last_error.argtypes = []
     L.cq_last_error.restype = C.c_char_p
@@ -279,10 +292,20 @@ class Adjoint:
     """Gradient handle (fp_adjoint_create): set-up and device arrays once,
     then run(G0, gN) per gradient."""
 
-    def __init__(self, grid: Grid, params: Params):
+    def __init__(self, grid: Grid, params: Params, mode: int = 0, max_device_bytes: int = 0,
+                 segment_steps: int = 0, slots: int = 0):
+        """mode 0 automatic, 1 keep the trajectory whole, 2 checkpointed
+        (fast method); see cq_adjoint_opts."""
         self._h = C.c_void_p()
         self.M = grid_nodes(grid)
-        _check(lib().fp_adjoint_create(C.byref(grid), C.byref(params), _stream(), C.byref(self._h)))
+        opts = AdjointOpts(max_device_bytes, mode, segment_steps, slots)
+        _check(lib().fp_adjoint_create_opts(C.byref(grid), C.byref(params), C.byref(opts), _stream(),
+                                            C.byref(self._h)))
+
+    def info(self) -> AdjointInfo:
+        inf = AdjointInfo()
+        _check(lib().fp_adjoint_info(self._h, C.byref(inf)))
+        return inf
 
     def run(self, G0, gN, gG0=None, GN=None):
         import torch

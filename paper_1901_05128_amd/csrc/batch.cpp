@@ -1,13 +1,17 @@
 // Batched fast solves: many independent problems of uneven size in one
-// captured HIP graph (forward sine transforms, the batched modal fast
-// kernels, inverse transforms), with the lanes-per-mode tile of every
-// register class chosen by timing (autotuner, cached per process).
+// captured HIP graph (the batched modal fast kernels, one branch per register
+// class, and the inverse transforms), with the lanes-per-mode tile of every
+// register class chosen by timing (autotuner, cached per process). The set-up
+// and the instantiated graph of the last batch are kept: a call with the same
+// problems and arrays runs the forward transforms and relaunches the graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <cmath>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -125,10 +129,74 @@ struct DevBuf {
     }
 };
 
+// the last batch's set-up, device tables and instantiated graph
+struct BatchCache {
+    std::vector<double> key;          // problem fields and array addresses
+    DevBuf buf;
+    hipStream_t st = nullptr;
+    std::vector<hipStream_t> branch;  // class branches of the graph
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    struct Xf {
+        const double* in;
+        double* out;
+        int dim, nx, ny, nz;
+        double scale;
+        const double *Sx, *Sy, *Sz;
+    };
+    std::vector<Xf> fwd;  // forward transforms: G0[i] -> its coefficients in the batch arrays
+    double* d_tmp = nullptr;
+    cq_batch_report rep{};
+    ~BatchCache() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipStream_t b : branch) (void)hipStreamDestroy(b);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+std::mutex g_batch_mu;
+std::unique_ptr<BatchCache> g_batch;
+
+std::vector<double> batch_key(int count, const cq_grid* grids, const cq_params* params, const double* const* G0,
+                              double* const* GN, int autotune) {
+    std::vector<double> k;
+    k.reserve(size_t(count) * 24 + 2);
+    k.push_back(double(count));
+    k.push_back(double(autotune != 0));
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    k.push_back(double(dev));
+    for (int i = 0; i < count; ++i) {
+        const cq_grid& g = grids[i];
+        const cq_params& p = params[i];
+        for (double v : {double(g.dim), double(g.nx), double(g.ny), g.lx, g.ly, double(g.dim == 3 ? g.nz : 1),
+                         g.dim == 3 ? g.lz : 1.0, p.alpha1, p.alpha2, p.m, p.T, double(p.N), double(p.scheme),
+                         double(p.method), p.fast_tol, double(p.np), double(p.np1), double(p.ns), double(p.np_max)})
+            k.push_back(v);
+        uint64_t a = uint64_t(reinterpret_cast<uintptr_t>(G0[i])), b = uint64_t(reinterpret_cast<uintptr_t>(GN[i]));
+        double da, db;
+        std::memcpy(&da, &a, 8);
+        std::memcpy(&db, &b, 8);
+        k.push_back(da);
+        k.push_back(db);
+    }
+    return k;
+}
+
+bool same_key(const std::vector<double>& a, const std::vector<double>& b) {
+    return a.size() == b.size() && std::memcmp(a.data(), b.data(), a.size() * sizeof(double)) == 0;
+}
+
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, int> g_tune;  // (npl at 64 lanes, lag class) -> lanes per mode
 
 int npl_for(int np, int lpm) { return (np + lpm - 1) / lpm; }
+// nodes per lane of the time-blocked kernel's templates (32 lanes per component)
+int tb_tmpl(int npl32) {
+    for (int t : {4, 6, 8, 10, 12, 14, 16, 18, 20, 24})
+        if (npl32 <= t) return t;
+    return 24;
+}
 int npl_tmpl(int npl, int lpm) {
     if (lpm == 64 && npl <= 1) return 1;
     if (npl <= 2) return 2;
@@ -160,6 +228,33 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
             return fail(CQ_EINVAL, "batched solve: problem %d has bad parameters (fast method only)", i);
         if (!G0[i] || !GN[i]) return fail(CQ_EINVAL, "batched solve: NULL array for problem %d", i);
     }
+    hipStream_t user = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> batch_lock(g_batch_mu);  // calls are serialised: they share the cache
+    std::vector<double> key = batch_key(count, grids, params, G0, GN, autotune);
+    if (g_batch && same_key(g_batch->key, key)) {
+        BatchCache& c = *g_batch;
+        hipEvent_t ev_in;
+        BHIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+        BHIP(hipEventRecord(ev_in, user));
+        BHIP(hipStreamWaitEvent(c.st, ev_in, 0));
+        (void)hipEventDestroy(ev_in);
+        for (const auto& x : c.fwd)
+            launch_sine_transform(x.dim, x.nx, x.ny, x.nz, x.Sx, x.Sy, x.Sz, x.in, c.d_tmp, x.out, x.scale, c.st);
+        BHIP(hipGetLastError());
+        const auto t1 = std::chrono::steady_clock::now();
+        hipError_t ce = hipGraphLaunch(c.exec, c.st);
+        if (ce == hipSuccess) ce = hipStreamSynchronize(c.st);
+        if (ce != hipSuccess) return fail(CQ_EHIP, "batched graph: %s", hipGetErrorString(ce));
+        const auto t2 = std::chrono::steady_clock::now();
+        if (report) {
+            *report = c.rep;
+            report->setup_s = std::chrono::duration<double>(t1 - t0).count();
+            report->autotune_s = 0.0;
+            report->run_s = std::chrono::duration<double>(t2 - t1).count();
+        }
+        return CQ_OK;
+    }
+    g_batch.reset();  // a new batch: release the previous one's device memory first
     // host set-up in parallel
     {
         const int nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
@@ -219,7 +314,6 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
                                   (h.dim == 3 ? lam1d(h.nz, h.lz, r + 1) : 0.0));
         modes += h.M;
     }
-    hipStream_t user = static_cast<hipStream_t>(hip_stream);
     DevBuf buf;
     BatchInst* d_inst;
     double *d_ratio, *d_coef, *d_d, *d_lam, *d_g0, *d_gN, *d_tmp;
@@ -248,8 +342,24 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
             sines[n] = q;
         }
     // register classes (nodes per lane at 64 lanes) and the problems in each
+    // Problems the time-blocked kernel takes (lags 8..32, <= 768 nodes) are
+    // grouped by its nodes per lane at 32 lanes (the template the class runs
+    // with), the others by nodes per lane at 64 lanes; a class runs with its
+    // largest problem's node count, so tight classes waste fewer lanes.
     std::map<int, std::vector<int>> cls;
-    for (int i = 0; i < count; ++i) cls[npl_tmpl(npl_for(hp[size_t(i)].np, 64), 64)].push_back(i);
+    for (int i = 0; i < count; ++i) {
+        const HostProblem& h = hp[size_t(i)];
+        const int n32 = npl_for(h.np, 32);
+        const bool tb = h.L >= 8 && h.L <= 32 && n32 <= 24;
+        cls[tb ? 1000 + tb_tmpl(n32) : npl_tmpl(npl_for(h.np, 64), 64)].push_back(i);
+    }
+    // longest time loops first: workgroups start in index order, so the
+    // short modes fill the GPU at the end instead of a long tail
+    for (auto& kv : cls)
+        std::stable_sort(kv.second.begin(), kv.second.end(), [&](int x, int y) {
+            const HostProblem &a = hp[size_t(x)], &b = hp[size_t(y)];
+            return a.N * (a.np + a.L) > b.N * (b.np + b.L);
+        });
     std::vector<int> lists;
     std::vector<int64_t> cums;
     // lpm: lanes per mode of the per-step kernel (64 or 32), or 0 for the
@@ -263,7 +373,6 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     std::vector<Launch> launches;
     for (auto& kv : cls) {
         Launch l{};
-        l.npl64 = kv.first;
         l.count = int(kv.second.size());
         l.list_off = lists.size();
         l.cum_off = cums.size();
@@ -281,6 +390,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         cums.push_back(c);
         l.total = c;
         l.maxnp = maxnp;
+        l.npl64 = npl_tmpl(npl_for(maxnp, 64), 64);
         l.minlag = minlag;
         // without timing: time-blocked where every lag allows blocks of >= 8 steps
         l.lpm = (l.lag32 && minlag >= 8 && npl_for(maxnp, 32) <= 24) ? 0 : 64;
@@ -291,12 +401,9 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     if ((rc = buf.alloc(&d_list, lists.size())) || (rc = buf.alloc(&d_cum, cums.size()))) return rc;
     BHIP(hipMemcpy(d_list, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice));
     BHIP(hipMemcpy(d_cum, cums.data(), cums.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-    hipStream_t st;
-    BHIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    struct StreamGuard {
-        hipStream_t s;
-        ~StreamGuard() { (void)hipStreamDestroy(s); }
-    } sg{st};
+    std::unique_ptr<BatchCache> cache(new BatchCache());
+    BHIP(hipStreamCreateWithFlags(&cache->st, hipStreamNonBlocking));
+    hipStream_t st = cache->st;
     // the caller's stream may still be producing G0
     hipEvent_t ev_in;
     BHIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
@@ -332,8 +439,10 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
                 if (h.dim >= 2) scale *= 2.0 / double(h.ny + 1);
                 if (h.dim == 3) scale *= 2.0 / double(h.nz + 1);
             }
-            launch_sine_transform(h.dim, h.nx, h.ny, h.nz, sines[h.nx], h.dim >= 2 ? sines[h.ny] : nullptr,
-                                  h.dim == 3 ? sines[h.nz] : nullptr, in, d_tmp, out, scale, st);
+            const BatchCache::Xf x{in, out, h.dim, h.nx, h.ny, h.nz, scale, sines[h.nx],
+                                   h.dim >= 2 ? sines[h.ny] : nullptr, h.dim == 3 ? sines[h.nz] : nullptr};
+            if (forward) cache->fwd.push_back(x);
+            launch_sine_transform(x.dim, x.nx, x.ny, x.nz, x.Sx, x.Sy, x.Sz, x.in, d_tmp, x.out, x.scale, st);
         }
     };
     transforms(true);
@@ -403,39 +512,63 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         }
         tune_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ta).count();
     }
-    // the batched run and the inverse transforms, captured as one graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // the batched run (one graph branch per register class, so that the
+    // classes' tails overlap) and the inverse transforms, captured as one graph
+    cache->branch.assign(launches.size(), nullptr);
+    for (auto& b : cache->branch) BHIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    std::vector<hipEvent_t> evs(launches.size() + 1, nullptr);
+    for (auto& e : evs) BHIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    struct EvGuard {
+        std::vector<hipEvent_t>& v;
+        ~EvGuard() {
+            for (hipEvent_t e : v)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } evg{evs};
     BHIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    for (const Launch& l : launches) launch_modal_batch(make_args(l), npl_of(l, l.lpm), l.lpm, st);
-    transforms(false);
-    hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (ce != hipSuccess) return fail(CQ_EHIP, "graph capture: %s", hipGetErrorString(ce));
-    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ce != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return fail(CQ_EHIP, "graph instantiate: %s", hipGetErrorString(ce));
+    hipError_t ce = hipEventRecord(evs[0], st);
+    for (size_t c = 0; c < launches.size() && ce == hipSuccess; ++c) {
+        ce = hipStreamWaitEvent(cache->branch[c], evs[0], 0);
+        if (ce != hipSuccess) break;
+        launch_modal_batch(make_args(launches[c]), npl_of(launches[c], launches[c].lpm), launches[c].lpm,
+                           cache->branch[c]);
+        ce = hipEventRecord(evs[c + 1], cache->branch[c]);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(st, evs[c + 1], 0);
     }
+    if (ce == hipSuccess) transforms(false);
+    hipGraph_t graph = nullptr;
+    hipError_t ce2 = hipStreamEndCapture(st, &graph);
+    if (ce != hipSuccess || ce2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(CQ_EHIP, "graph capture: %s", hipGetErrorString(ce != hipSuccess ? ce : ce2));
+    }
+    cache->graph = graph;
+    ce = hipGraphInstantiate(&cache->exec, graph, nullptr, nullptr, 0);
+    if (ce != hipSuccess) return fail(CQ_EHIP, "graph instantiate: %s", hipGetErrorString(ce));
     const auto t2 = std::chrono::steady_clock::now();
-    ce = hipGraphLaunch(exec, st);
+    ce = hipGraphLaunch(cache->exec, st);
     if (ce == hipSuccess) ce = hipStreamSynchronize(st);
     const auto t3 = std::chrono::steady_clock::now();
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
     if (ce != hipSuccess) return fail(CQ_EHIP, "batched graph: %s", hipGetErrorString(ce));
-    if (report) {
-        report->problems = count;
-        report->modes = modes;
-        report->classes = int32_t(std::min<size_t>(launches.size(), 8));
-        for (int c = 0; c < report->classes; ++c) {
-            report->class_npl64[c] = launches[size_t(c)].npl64;
-            report->class_lanes[c] = launches[size_t(c)].lpm ? launches[size_t(c)].lpm : 64;
-            report->class_blocked[c] = launches[size_t(c)].lpm == 0 ? 1 : 0;
-            report->class_problems[c] = launches[size_t(c)].count;
-        }
-        report->setup_s = std::chrono::duration<double>(t1 - t0).count();
-        report->autotune_s = tune_s;
-        report->run_s = std::chrono::duration<double>(t3 - t2).count();
+    cq_batch_report r{};
+    r.problems = count;
+    r.modes = modes;
+    r.classes = int32_t(std::min<size_t>(launches.size(), 8));
+    for (int c = 0; c < r.classes; ++c) {
+        r.class_npl64[c] = launches[size_t(c)].npl64;
+        r.class_lanes[c] = launches[size_t(c)].lpm ? launches[size_t(c)].lpm : 64;
+        r.class_blocked[c] = launches[size_t(c)].lpm == 0 ? 1 : 0;
+        r.class_problems[c] = launches[size_t(c)].count;
     }
+    r.setup_s = std::chrono::duration<double>(t1 - t0).count();
+    r.autotune_s = tune_s;
+    r.run_s = std::chrono::duration<double>(t3 - t2).count();
+    if (report) *report = r;
+    cache->rep = r;
+    // keep the set-up, tables and graph for a call with the same batch
+    cache->key.swap(key);
+    cache->buf.p.swap(buf.p);
+    cache->d_tmp = d_tmp;
+    g_batch = std::move(cache);
     return CQ_OK;
 }

@@ -35,6 +35,11 @@ struct FastRule {
 
 // Build the rule for a given node count (np for BE, np1 + np2 for BDF2).
 void build_rule(int scheme, double beta, double tau, int np, int np1, int ns, FastRule& out);
+// BDF2 rule (3.14)-(3.16) from the Gauss-Jacobi nodes and weights of its two
+// families (np1 = s1.size(), np2 = s2.size()).
+void bdf2_rule_from_nodes(double beta, double tau, int ns, const std::vector<double>& s1,
+                          const std::vector<double>& lam1, const std::vector<double>& s2,
+                          const std::vector<double>& lam2, FastRule& out);
 // Start the geometric families at a later lag (coef_j *= r_j^(lag - old lag)).
 void shift_lag(FastRule& r, int lag);
 // max_{lag <= i <= N} |d_i - sum_j coef_j r_j^(i-lag)| / |d_0|
@@ -42,6 +47,11 @@ double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N);
 // Node-count scan; returns CQ_OK or CQ_ETOL.
 int choose_rule(int scheme, double beta, double tau, int64_t N, double tol, int np_max, int np1,
                 int ns, FastRule& out);
+
+// BDF2: N_s and N_{p,1} chosen from the weight errors for the orders betas[0..nb)
+// (candidates and cost model in setup.cpp); np1_fixed > 0 keeps N_{p,1}.
+int choose_bdf2_window(const double* betas, int nb, double tau, int64_t N, double tol, int np_max, int np1_fixed,
+                       int& ns_out, int& np1_out);
 
 // d/dbeta of the fast weights of an np-node rule (BDF2: np1 + np) started at
 // lag, for lag <= i <= N (five-point difference in beta, step h).

@@ -183,7 +183,12 @@ struct AdjGradArgs {
     double* gG0c;          // [2][M] out: dl/dg^0
     double* part;          // [nchunk][blocks] out: partial sums of sum_n (mu_0 - mu_1).(X_0 - X_1)
     double* gpart;         // [nchunk][2][M] scratch: time-chunk partial sums for dl/dg^0
-    int nchunk;            // time chunks (<= N)
+    int nchunk;            // time chunks (<= N): chunk c covers steps 1 + c per .. min(N, (c+1) per)
+    int64_t per;           // steps per chunk
+    // k_adj_da: chunks chunk0 .. chunk0 + nchunk_da - 1 only (0: all), so
+    // that a run that has one time segment at a time in memory fills the
+    // same partial sums as a run over all steps
+    int chunk0 = 0, nchunk_da = 0;
 };
 
 // d/dbeta pass over one time block n0+1..n0+bt: for each component and mode
@@ -197,7 +202,8 @@ struct AdjBetaArgs {
     int64_t dstride;
     const double* dd;      // [2][dstride] d/dbeta of the exact weights
     const double* F;       // [B][2][M] reduced far field of the block
-    const double* traj;
+    const double* g0;      // [2][M] g^0 (BDF2's starting-correction term)
+    int g0term;            // add that term (once per step n over all calls)
     const double* psi;
     double* acc;           // [2][M]
 };

@@ -1260,15 +1260,16 @@ __global__ __launch_bounds__(64) void k_modal_win(ModalWinArgs p) {
     }
     if (ADJ && p.nfirst == 1) acc[0] -= p.gc[k * M + mode];  // cotangent enters step 1
     // window part of the levels l = nfirst-j (j < L, l >= 1) already taken:
-    // all loads first (an absent level reads level 0, which is finite, times 0),
-    // then the sums
+    // all loads first (an absent level reads level nfirst-1, which every
+    // level store holds and is finite, times 0), then the sums
     {
         double old[BB];
-        int64_t sl = (p.nfirst - 1) % p.Lr;  // slot of level nfirst-1
+        const int64_t sl1 = (p.nfirst - 1) % p.Lr;  // slot of level nfirst-1
+        int64_t sl = sl1;
 #pragma unroll
         for (int j = 1; j < BB; ++j) {
             const bool ok = j < p.L && p.nfirst - j >= 1;
-            old[j] = lv[(ok ? sl : 0) * twoM] * (ok ? 1.0 : 0.0);
+            old[j] = lv[(ok ? sl : sl1) * twoM] * (ok ? 1.0 : 0.0);
             sl = (sl == 0) ? p.Lr - 1 : sl - 1;
         }
 #pragma unroll
@@ -1502,7 +1503,7 @@ __global__ __launch_bounds__(256) void k_adj_g0_part(AdjGradArgs p) {
     if (e >= 2 * p.M) return;
     const int64_t twoM = 2 * p.M, N = p.N;
     const int k = int(e / p.M);
-    const int64_t per = (N + p.nchunk - 1) / p.nchunk;
+    const int64_t per = p.per;
     const int64_t lo = 1 + int64_t(blockIdx.y) * per;
     const int64_t hi = (lo + per - 1 < N) ? lo + per - 1 : N;
     const double* __restrict__ dk = p.d + int64_t(k) * p.dstride;
@@ -1540,8 +1541,8 @@ __global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
     double acc0 = 0.0, acc1 = 0.0;
     if (mode < p.M) {
         const int64_t M = p.M, twoM = 2 * M, N = p.N;
-        const int64_t per = (N + p.nchunk - 1) / p.nchunk;
-        const int64_t lo = 1 + int64_t(blockIdx.y) * per;
+        const int64_t per = p.per;
+        const int64_t lo = 1 + int64_t(p.chunk0 + blockIdx.y) * per;
         const int64_t hi = (lo + per - 1 < N) ? lo + per - 1 : N;
         for (int64_t n = lo; n <= hi; ++n) {
             const int64_t t = n * twoM + mode, r = (N + 1 - n) * twoM + mode;
@@ -1554,7 +1555,7 @@ __global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
         }
     }
     const double tot = block_sum256(acc0 + acc1, red);
-    if (threadIdx.x == 0) p.part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0) p.part[int64_t(p.chunk0 + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
 // d/dbeta over one time block: F holds the CQ sum of the weight derivatives
@@ -1573,7 +1574,7 @@ __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
     const int64_t ec = ein ? e : twoM - 1;  // idle lanes read a valid column
     const int k = int(ec / M);
     const int64_t mode = ec - int64_t(k) * M;
-    const double g0 = p.traj[ec];
+    const double g0 = p.g0[ec];
     const double* __restrict__ ddk = p.dd + int64_t(k) * p.dstride;
     const int per = (p.bt + 3) >> 2;
     const int b0 = w * per, b1 = min(p.bt, b0 + per);
@@ -1582,7 +1583,7 @@ __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
     for (int b = b0; b < b1; ++b) {
         const int64_t n = p.n0 + 1 + b;
         double Y = p.F[(int64_t(b) * 2 + k) * M + mode];
-        if (p.scheme == 2) Y = fma(0.5 * ddk[n - 1], g0, Y);
+        if (p.scheme == 2 && p.g0term) Y = fma(0.5 * ddk[n - 1], g0, Y);
         if (b & 1)
             acc1 = fma(p.psi[(N + 1 - n) * twoM + ec], Y, acc1);
         else
@@ -2203,9 +2204,13 @@ void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st) {
 #define CQ_BATCH_TB(NP) hipLaunchKernelGGL((k_modal_batch_tb<NP>), grid, dim3(256), 0, st, a)
         prof_begin(9, st);
         if (npl <= 4) CQ_BATCH_TB(4);
+        else if (npl <= 6) CQ_BATCH_TB(6);
         else if (npl <= 8) CQ_BATCH_TB(8);
+        else if (npl <= 10) CQ_BATCH_TB(10);
         else if (npl <= 12) CQ_BATCH_TB(12);
+        else if (npl <= 14) CQ_BATCH_TB(14);
         else if (npl <= 16) CQ_BATCH_TB(16);
+        else if (npl <= 18) CQ_BATCH_TB(18);
         else if (npl <= 20) CQ_BATCH_TB(20);
         else CQ_BATCH_TB(24);
         prof_end(9, st);
@@ -2272,7 +2277,8 @@ void launch_adj_g0(const AdjGradArgs& a, hipStream_t st) {
 
 int launch_adj_da(const AdjGradArgs& a, hipStream_t st) {
     const int blocks = int((a.M + 255) / 256);
-    hipLaunchKernelGGL(k_adj_da, dim3(unsigned(blocks), unsigned(a.nchunk)), dim3(256), 0, st, a);
+    const int nc = a.nchunk_da > 0 ? a.nchunk_da : a.nchunk;
+    hipLaunchKernelGGL(k_adj_da, dim3(unsigned(blocks), unsigned(nc)), dim3(256), 0, st, a);
     return blocks * a.nchunk;
 }
 

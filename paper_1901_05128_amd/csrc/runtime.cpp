@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -45,6 +46,23 @@ struct AdjBufs {
     // workgroup, per-block dot products)
     double *tw = nullptr, *W = nullptr, *spec = nullptr, *bpart = nullptr;
     int spec_bk = 0, specP = 0, specLog = 0, spec_nb = 0, spec_nwg = 0, spec_cols = 0, nblk_dot = 0;
+    int64_t per = 1;  // steps per chunk of the time-chunked reductions
+    // Checkpointed form (fast method): the forward trajectory is not kept.
+    // The steps are cut into nseg segments of seg steps; the forward state at
+    // a segment start (the fast state H and the last L levels) can be saved
+    // in `slots` places, and a binomial schedule (split) decides where the
+    // forward is advanced to and saved. Each segment is recomputed once more
+    // with its levels and history sums in segLev / segS, the adjoint sweep
+    // (own state Ha, Sfa; psi kept whole, mu in segMu) takes the segment's
+    // steps, and the segment's share of the gradient sums is added.
+    bool ckpt = false;
+    int64_t seg = 0, ck_stride = 0, fwd_steps = 0;
+    int nseg = 0, slots = 0;
+    double *ck = nullptr, *segLev = nullptr, *segS = nullptr, *segMu = nullptr, *ringA = nullptr, *Ha = nullptr,
+           *Sfa = nullptr;
+    double *Hf = nullptr, *Sff = nullptr;  // the forward's fast state and block sums
+    std::vector<int> split;  // [nseg + 1][slots]: first advance (segments) of an optimal schedule
+    std::vector<int64_t> cost;
 };
 
 struct Solver {
@@ -56,6 +74,11 @@ struct Solver {
     hipStream_t st = nullptr;
     // fast
     int L = 2, np = 0, hlanes = 1, chunk = 0, Bt = 1, BTt = 8;
+    int ns_used = 30, np1_used = 16;  // BDF2: N_s and N_{p,1} of the fast rule
+    // fast form, blocked: the first state block is blk_off steps long (0: a
+    // full block), the rest Bt; the adjoint sweep takes blk_off = N mod Bt so
+    // that its block ends fall on the forward's block starts in reversed time
+    int64_t blk_off = 0;
     int64_t hstride = 0;  // DOFs between nodes of the state H[2][np][hstride]
     double max_eps = 0;
     // direct
@@ -236,10 +259,16 @@ int setup_host(Solver& s, const cq_grid* g, const cq_params* p, hipStream_t st) 
     s.hx = g->lx / (s.nx + 1);
     s.hy = s.dim >= 2 ? g->ly / (s.ny + 1) : 1.0;
     s.hz = s.dim == 3 ? g->lz / (s.nz + 1) : 1.0;
-    const int ns = p->ns ? p->ns : 30;
-    const int np1 = p->np1 ? p->np1 : 16;
+    int ns = p->ns ? p->ns : 30;
+    int np1 = p->np1 ? p->np1 : 16;
     const int np_max = p->np_max ? p->np_max : 1024;
     const double tol = p->fast_tol > 0 ? p->fast_tol : 1e-8;
+    // BDF2 with the node count left to the scan: N_s (and N_{p,1} unless
+    // given) from the weight errors too
+    if (p->method == 1 && p->scheme == 2 && p->ns == 0 && p->np == 0)
+        choose_bdf2_window(s.beta, 2, s.tau, s.N, tol, np_max, p->np1, ns, np1);
+    s.ns_used = ns;
+    s.np1_used = np1;
 
     // direct block length and K-split (enough workgroups to fill 256 CUs)
     if (p->method == 0) {
@@ -550,7 +579,15 @@ void launch_far_block(Solver& s, int rows) {
 void modal_steps(Solver& s, int64_t nsteps) {
     if (s.p.method == 1 && s.modal_blocked) {
         while (nsteps > 0) {
-            const int64_t nblk = (s.n / s.Bt) * s.Bt + 1;  // block of the next step
+            // the block of the next step: steps nblk .. nblk + blen - 1
+            int64_t nblk, blen;
+            if (s.n < s.blk_off) {
+                nblk = 1;
+                blen = s.blk_off;
+            } else {
+                nblk = s.blk_off + ((s.n - s.blk_off) / s.Bt) * s.Bt + 1;
+                blen = s.Bt;
+            }
             if (s.n + 1 == nblk) {
                 HistBlockArgs hb{};
                 hb.n = nblk;
@@ -560,7 +597,7 @@ void modal_steps(Solver& s, int64_t nsteps) {
                 hb.np = s.np;
                 hb.chunk = s.chunk;
                 hb.BT = s.BTt;
-                hb.bt = int(std::min<int64_t>(s.Bt, s.N - nblk + 1));
+                hb.bt = int(std::min<int64_t>(blen, s.N - nblk + 1));
                 hb.slot0 = ((nblk - s.L) % s.Lr + s.Lr) % s.Lr;
                 hb.levels = s.levels;
                 hb.H = s.H;
@@ -570,7 +607,7 @@ void modal_steps(Solver& s, int64_t nsteps) {
                 hb.Sf = s.Sf;
                 launch_hist_block(hb, s.hlanes, s.st);
             }
-            const int bt = int(std::min<int64_t>(nblk + s.Bt - 1 - s.n, nsteps));
+            const int bt = int(std::min<int64_t>(nblk + blen - 1 - s.n, nsteps));
             ModalWinArgs a{};
             a.M = s.M;
             a.nfirst = s.n + 1;
@@ -1117,6 +1154,7 @@ int fp_info(void* handle, cq_info* info) {
     info->ksplit = s.ks;
     info->device_bytes = s.dev_bytes;
     info->state_bytes = state_bytes(s);
+    info->np1 = (s.p.method == 1 && s.p.scheme == 2) ? s.np1_used : 0;
     return CQ_OK;
 }
 
@@ -1226,14 +1264,73 @@ int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double
     return rc;
 }
 
-// Gradient of a loss of G^N (forward solve with the trajectory kept in HBM,
-// adjoint sweep in reversed time with the same kernels, gradient passes).
-static int adjoint_setup(Solver& s) {
+// Gradient of a loss of G^N (forward solve, adjoint sweep in reversed time
+// with the same kernels, gradient passes). Two forms: the whole forward
+// trajectory, its history sums and the adjoint kept in HBM, or (fast method)
+// checkpointed: the forward recomputed segment by segment from saved states
+// on a binomial schedule.
+
+// chunk length of the time-chunked gradient reductions: for the fast form a
+// multiple of its state block, so that segments of whole chunks start where
+// the forward can be resumed
+static int64_t adj_chunk_len(const Solver& s) {
+    const int64_t base = (s.N + 63) / 64;
+    if (s.p.method != 1) return base;
+    return ((base + s.Bt - 1) / s.Bt) * s.Bt;
+}
+
+// Binomial (revolve) schedule over n segments: with the state at the first
+// segment saved and c more states that can be saved, T(n, c) is the fewest
+// segment advances of the forward that reverse all n segments:
+//   T(1, c) = 0,  T(n, 0) = n (n - 1) / 2  (advance from the start to each),
+//   T(n, c) = min_{1 <= m < n} m + T(n - m, c - 1) + T(m, c)
+// (advance m segments and save, reverse the last n - m with one state fewer,
+// then the first m). split[n][c] holds an optimal m.
+static void plan_schedule(int nseg, int slots, std::vector<int64_t>& T, std::vector<int>& split) {
+    const int C = std::max(1, slots);  // c = 0 .. C-1 free states
+    T.assign(size_t(nseg + 1) * size_t(C), 0);
+    split.assign(size_t(nseg + 1) * size_t(C), 0);
+    for (int n = 2; n <= nseg; ++n)
+        for (int c = 0; c < C; ++c) {
+            int64_t best = int64_t(n) * (n - 1) / 2;
+            int bm = 0;
+            if (c > 0)
+                for (int m = 1; m < n; ++m) {
+                    const int64_t v = m + T[size_t(n - m) * C + (c - 1)] + T[size_t(m) * C + c];
+                    if (v < best) {
+                        best = v;
+                        bm = m;
+                    }
+                }
+            T[size_t(n) * C + c] = best;
+            split[size_t(n) * C + c] = bm;
+        }
+}
+
+// bytes of the arrays every gradient handle holds (besides the forward /
+// adjoint storage of its form)
+static size_t adj_common_bytes(const Solver& s, size_t frows) {
+    const size_t twoM = size_t(2 * s.M);
+    size_t v = 2 * size_t(s.dstride) + 10 * twoM + frows + 64 * twoM + 2 * (size_t(s.dstride) + kDwPad) +
+               2 * size_t(s.dstride) + size_t(s.nx) * s.nx + size_t(s.ny) * s.ny + size_t(s.nz) * s.nz +
+               size_t(s.M) + size_t(s.nx + s.ny + s.nz) + 8192;
+    if (s.p.method == 1) v += 2 * size_t(s.np) * size_t(((s.M + 255) / 256) * 256) + 4 * size_t(s.np) +
+                              size_t(s.BTt) * twoM;
+    return v * sizeof(double);
+}
+
+static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
     int rc;
     const cq_params* p = &s.p;
     const int64_t M = s.M, N = s.N, twoM = 2 * M;
     const size_t lev = size_t(N + 1) * size_t(twoM);
     hipStream_t st = s.st;
+    const int mode = opt ? opt->mode : 0;
+    if (mode < 0 || mode > 2) return fail(CQ_EINVAL, "adjoint mode must be 0, 1 or 2 (got %d)", mode);
+    if (opt && (opt->segment_steps < 0 || opt->slots < 0)) return fail(CQ_EINVAL, "negative segment or slot count");
+    if (mode == 2 && p->method != 1)
+        return fail(CQ_EINVAL, "the checkpointed adjoint needs the fast method (the direct form's state at a step "
+                               "is its whole history)");
     if (p->method == 1 && s.L > 32)
         return fail(CQ_EINVAL, "the adjoint's fast form needs a window of <= 32 levels (ns = %d)", s.L);
     // the far field of the d/dbeta pass (and of the direct history): blocks of
@@ -1242,40 +1339,104 @@ static int adjoint_setup(Solver& s) {
     s.Bf = p->block_B ? p->block_B : modal_far_pass(M);
     s.ks = far_ksplit(M);
     AdjBufs& A = s.ab;
+    A.per = adj_chunk_len(s);
+    A.nchunk = int((N + A.per - 1) / A.per);
     // d/dbeta: blocks of about N/8 steps (a power of two, at most 256) while
     // their P-point transforms fit in LDS (N <= 4096), unless
     // CQFP_BETA_TOEPLITZ is set; else Toeplitz passes over all levels
     const char* force_toeplitz = std::getenv("CQFP_BETA_TOEPLITZ");
+    int spec_bk = 0, spec_nb = 0, spec_log = 0;
     {
         int lb = 0;
         while ((int64_t(8) << lb) < N && lb < 8) ++lb;
         const int Bk = 1 << lb;
         const int64_t nb = (N + Bk - 1) / Bk;
         if (nb * 2 * Bk <= kSpecMaxLds && !(force_toeplitz && force_toeplitz[0] && force_toeplitz[0] != '0')) {
-            A.spec_bk = Bk;
-            A.specP = 2 * Bk;
-            A.specLog = lb + 1;
-            A.spec_nb = int(nb);
+            spec_bk = Bk;
+            spec_log = lb + 1;
+            spec_nb = int(nb);
         }
     }
-    const size_t frows = size_t(s.ks) * size_t(std::max({s.B, s.Bf, A.spec_bk})) * size_t(twoM);
+    const size_t frows = size_t(s.ks) * size_t(std::max({s.B, s.Bf, spec_bk})) * size_t(twoM);
+    if (p->method == 1) s.hstride = ((M + 255) / 256) * 256;  // the state pass runs whole 256-DOF workgroups
+    size_t budget = opt ? opt->max_device_bytes : 0;
     {
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
-        const size_t need = (4 * lev + frows + 64 * size_t(twoM)) * sizeof(double);
-        if (need > fr)
-            return fail(CQ_ENOMEM, "the adjoint keeps 4 x (N+1) x 2M values (%zu bytes); %zu bytes free", need, fr);
+        const size_t margin = std::min<size_t>(size_t(1) << 30, fr / 50);
+        const size_t avail = fr > margin ? fr - margin : 0;
+        if (budget == 0 || budget > avail) budget = avail;
     }
+    const size_t common = adj_common_bytes(s, frows);
+    const size_t storeall = common + 4 * lev * sizeof(double);
+    if (mode == 1 || (mode == 0 && (p->method != 1 || storeall <= budget))) {
+        if (storeall > budget)
+            return fail(CQ_ENOMEM, "the adjoint keeping its whole trajectory needs %zu bytes (4 x (N+1) x 2M values "
+                                   "and work arrays); the budget is %zu", storeall, budget);
+        A.ckpt = false;
+    } else {
+        // checkpointed: psi whole, a segment's levels, history sums and mu,
+        // the adjoint's own state, a level ring for advancing, saved states
+        A.ckpt = true;
+        const size_t hc = hcount(s);
+        A.ck_stride = int64_t(hc) + int64_t(s.L) * twoM;
+        const size_t fixed = common + (lev + hc + size_t(s.BTt) * twoM + size_t(s.L) * twoM) * sizeof(double);
+        const int64_t unit = A.per;  // a segment is whole chunks (a multiple of the state block)
+        const int64_t want_seg = opt && opt->segment_steps > 0 ? opt->segment_steps : 0;
+        const int want_slots = opt ? opt->slots : 0;
+        int64_t best_cost = -1;
+        size_t best_bytes = 0;
+        std::vector<int64_t> T;
+        std::vector<int> sp;
+        for (int64_t j = 1; j * unit < N + unit; ++j) {
+            const int64_t seg = std::min<int64_t>(j * unit, ((N + unit - 1) / unit) * unit);
+            if (want_seg && seg != ((want_seg + unit - 1) / unit) * unit) continue;
+            const int nseg = int((N + seg - 1) / seg);
+            if (nseg > 256) continue;
+            const size_t segb = size_t(3 * seg + s.L + 2) * size_t(twoM) * sizeof(double);
+            if (fixed + segb + size_t(A.ck_stride) * sizeof(double) > budget) continue;
+            const int64_t cmax = int64_t((budget - fixed - segb) / (size_t(A.ck_stride) * sizeof(double)));
+            int slots = int(std::min<int64_t>(cmax, nseg));
+            if (want_slots > 0) {
+                if (want_slots > slots) continue;
+                slots = want_slots;
+            }
+            plan_schedule(nseg, slots, T, sp);
+            const int64_t cost = N + seg * T[size_t(nseg) * size_t(slots) + size_t(slots - 1)];
+            const size_t bytes = fixed + segb + size_t(slots) * size_t(A.ck_stride) * sizeof(double);
+            if (best_cost < 0 || cost < best_cost || (cost == best_cost && bytes < best_bytes)) {
+                best_cost = cost;
+                best_bytes = bytes;
+                A.seg = seg;
+                A.nseg = nseg;
+                A.slots = slots;
+                A.split = sp;
+                A.cost = T;
+            }
+        }
+        if (best_cost < 0)
+            return fail(CQ_ENOMEM, "no checkpoint schedule fits the budget of %zu bytes (the adjoint keeps "
+                                   "(N+1) x 2M values of psi and at least one saved state)", budget);
+        A.fwd_steps = best_cost;
+        spec_bk = 0;  // the d/dbeta contraction runs as Toeplitz products, segment by segment
+        spec_nb = 0;
+    }
+    A.spec_bk = spec_bk;
+    A.specP = 2 * spec_bk;
+    A.specLog = spec_log;
+    A.spec_nb = spec_nb;
     if ((rc = dev_alloc(s, &s.d_d, size_t(2 * s.dstride)))) return rc;
     if ((rc = dev_alloc(s, &s.G0, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.g0c, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &s.Sscratch, size_t(twoM)))) return rc;
     if (s.dim >= 2 && (rc = dev_alloc(s, &s.T1, size_t(twoM)))) return rc;
     if ((rc = setup_tables(s))) return rc;
-    if ((rc = dev_alloc(s, &A.traj, lev))) return rc;
-    if ((rc = dev_alloc(s, &A.Sx, lev))) return rc;
     if ((rc = dev_alloc(s, &A.psi, lev))) return rc;
-    if ((rc = dev_alloc(s, &A.mu, lev))) return rc;
+    if (!A.ckpt) {
+        if ((rc = dev_alloc(s, &A.traj, lev))) return rc;
+        if ((rc = dev_alloc(s, &A.Sx, lev))) return rc;
+        if ((rc = dev_alloc(s, &A.mu, lev))) return rc;
+    }
     if ((rc = dev_alloc(s, &s.F, frows))) return rc;
     if ((rc = dev_alloc(s, &s.F2, size_t(64) * size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.gc, size_t(twoM)))) return rc;
@@ -1283,7 +1444,6 @@ static int adjoint_setup(Solver& s) {
     if ((rc = dev_alloc(s, &A.acc, size_t(twoM)))) return rc;
     if ((rc = dev_alloc(s, &A.dw, size_t(2 * (s.dstride + kDwPad))))) return rc;
     if ((rc = dev_alloc(s, &A.dd, size_t(2 * s.dstride)))) return rc;
-    A.nchunk = int(std::min<int64_t>(64, N));
     A.nblk_da = int((M + 255) / 256) * A.nchunk;
     A.nblk_rows = int((M + 4095) / 4096);
     if ((rc = dev_alloc(s, &A.part, size_t(A.nblk_da)))) return rc;
@@ -1292,7 +1452,6 @@ static int adjoint_setup(Solver& s) {
     HIPCHK(hipMemcpyAsync(s.d_d + s.dstride, s.dh[1].data(), s.dstride * sizeof(double), hipMemcpyHostToDevice,
                           st));
     if (p->method == 1) {
-        s.hstride = ((M + 255) / 256) * 256;  // the state pass runs whole 256-DOF workgroups
         if ((rc = dev_alloc(s, &s.H, hcount(s)))) return rc;
         if ((rc = dev_alloc(s, &s.d_ratio, size_t(2 * s.np)))) return rc;
         if ((rc = dev_alloc(s, &s.d_coef, size_t(2 * s.np)))) return rc;
@@ -1306,6 +1465,17 @@ static int adjoint_setup(Solver& s) {
         if ((rc = upload(s.d_ratio, rr))) return rc;
         if ((rc = upload(s.d_coef, cc))) return rc;
         s.modal_blocked = true;  // thread per mode, level store of all N+1 levels
+        A.Hf = s.H;
+        A.Sff = s.Sf;
+        if (A.ckpt) {
+            if ((rc = dev_alloc(s, &A.Ha, hcount(s)))) return rc;
+            if ((rc = dev_alloc(s, &A.Sfa, size_t(int64_t(s.BTt) * twoM)))) return rc;
+            if ((rc = dev_alloc(s, &A.ringA, size_t(s.L) * size_t(twoM)))) return rc;
+            if ((rc = dev_alloc(s, &A.segLev, size_t(A.seg + s.L) * size_t(twoM)))) return rc;
+            if ((rc = dev_alloc(s, &A.segS, size_t(A.seg) * size_t(twoM)))) return rc;
+            if ((rc = dev_alloc(s, &A.segMu, size_t(A.seg + 2) * size_t(twoM)))) return rc;
+            if ((rc = dev_alloc(s, &A.ck, size_t(A.slots) * size_t(A.ck_stride)))) return rc;
+        }
     }
     // weight derivatives: exact (recurrences differentiated); the fast
     // scheme's beyond its lag from the rule
@@ -1317,9 +1487,8 @@ static int adjoint_setup(Solver& s) {
         weights_dbeta(p->scheme, s.beta[k], s.tau, s.dstride - 1, ddk);
         std::copy(ddk, ddk + s.dstride, dwk);
         if (p->method == 1) {
-            const int np1 = p->scheme == 2 ? (p->np1 ? p->np1 : 16) : 0;
-            const int ns = p->ns ? p->ns : 30;
-            rule_weights_dbeta(p->scheme, s.beta[k], s.tau, s.np - np1, np1, ns, s.L, N, 1e-3, dwk);
+            const int np1 = p->scheme == 2 ? s.np1_used : 0;
+            rule_weights_dbeta(p->scheme, s.beta[k], s.tau, s.np - np1, np1, s.ns_used, s.L, N, 1e-3, dwk);
         }
     }
     if ((rc = upload(A.dw, hdw))) return rc;
@@ -1345,60 +1514,82 @@ static int adjoint_setup(Solver& s) {
         launch_fft_w(A.dw + kDwPad, s.dstride + kDwPad, N, nb, P, A.specLog, A.tw, A.W, st);
         HIPCHK(hipGetLastError());
     }
+    if (!A.ckpt) A.fwd_steps = N;
     HIPCHK(hipStreamSynchronize(st));
     s.kind = 1;
     return CQ_OK;
 }
 
+// fields of the solver that one sweep of modal_steps uses
+struct Sweep {
+    double *levels, *H, *Sf, *Sout, *mu;
+    const double* gc;
+    int64_t Lr, n;
+    bool adj;
+    int64_t blk_off;
+};
+static void set_sweep(Solver& s, const Sweep& w) {
+    s.levels = w.levels;
+    s.H = w.H;
+    s.Sf = w.Sf;
+    s.Sout = w.Sout;
+    s.mu = w.mu;
+    s.gc = w.gc;
+    s.Lr = w.Lr;
+    s.n = w.n;
+    s.adj = w.adj;
+    s.blk_off = w.blk_off;
+    s.far_base = -1;
+    s.mid_n0 = -1;
+    s.n0 = 0;
+}
 
-static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* gG0, double* grad, double* GN) {
-    const cq_params* p = &s.p;
+// one row block of the d/dbeta contraction: rows n0+1 .. n0+bt against the
+// levels l0..nl (at levels[l * 2M]), contracted with psi into acc
+static void beta_rows(Solver& s, const double* levels, int64_t n0, int bt, int rows, int64_t l0, int64_t nl,
+                      bool g0term) {
     AdjBufs& A = s.ab;
-    const int64_t M = s.M, N = s.N, twoM = 2 * M;
-    hipStream_t st = s.st;
-    double *traj = A.traj, *Sx = A.Sx, *psi = A.psi, *mu = A.mu, *gc = A.gc, *gG0c = A.gG0c, *acc = A.acc,
-           *dw = A.dw, *dd = A.dd, *part = A.part, *part2 = A.part2;
-    const int nblk_da = A.nblk_da, nblk_rows = A.nblk_rows;
-    HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    // forward, keeping every level and history sum
-    s.levels = traj;
-    s.Lr = N + 1;
-    transform(s, s.G0, s.g0c, true);
-    HIPCHK(hipMemcpyAsync(traj, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(Sx, 0, size_t(twoM) * sizeof(double), st));
-    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), st));
-    s.adj = false;
-    s.Sout = Sx;
-    s.mu = nullptr;
-    s.gc = nullptr;
-    s.n = 0;
-    s.far_base = -1;
-    s.mid_n0 = -1;
-    s.n0 = 0;
-    modal_steps(s, N);
-    if (GN) transform(s, traj + N * twoM, GN, false);
+    const int64_t M = s.M, twoM = 2 * M;
+    FarArgs fa{};
+    fa.n0 = n0;
+    fa.l0 = l0;
+    fa.nl = nl;
+    fa.M = M;
+    fa.dstride = s.dstride + kDwPad;
+    fa.lstride = twoM;
+    fa.B = rows;
+    const int64_t nlev = nl - l0 + 1;
+    fa.ks = far_ks_for(s.ks, nlev);
+    fa.ncomp = 2;
+    const int64_t mc = (nlev + fa.ks - 1) / fa.ks;
+    fa.mchunk = ((mc + 3) / 4) * 4;
+    fa.levels = levels;
+    fa.d = A.dw + kDwPad;
+    fa.F = s.F;
+    fa.reduce = 1;
+    launch_far(fa, s.st);
+    AdjBetaArgs ab{};
+    ab.M = M;
+    ab.N = s.N;
+    ab.n0 = n0;
+    ab.bt = bt;
+    ab.scheme = s.p.scheme;
+    ab.dstride = s.dstride;
+    ab.dd = A.dd;
+    ab.F = s.F;
+    ab.g0 = s.g0c;
+    ab.g0term = g0term ? 1 : 0;
+    ab.psi = A.psi;
+    ab.acc = A.acc;
+    launch_adj_beta(ab, s.st);
+}
 
-    // adjoint sweep: levels psi, multipliers mu, both in reversed time
-    transform(s, gN, gc, false);  // dl/dg^N = S^T dl/dG^N, S symmetric
-    HIPCHK(hipMemsetAsync(psi, 0, size_t(twoM) * sizeof(double), st));
-    HIPCHK(hipMemsetAsync(mu, 0, size_t(twoM) * sizeof(double), st));
-    if (p->method == 1) HIPCHK(hipMemsetAsync(s.H, 0, hcount(s) * sizeof(double), st));
-    s.levels = psi;
-    s.adj = true;
-    s.Sout = nullptr;
-    s.mu = mu;
-    s.gc = gc;
-    s.n = 0;
-    s.far_base = -1;
-    s.mid_n0 = -1;
-    s.n0 = 0;
-    modal_steps(s, N);
-
-    // gradients
+static AdjGradArgs grad_args(Solver& s, const double* traj, const double* Sx, const double* mu) {
+    AdjBufs& A = s.ab;
     AdjGradArgs ga{};
-    ga.M = M;
-    ga.N = N;
-    ga.scheme = p->scheme;
+    ga.M = s.M;
+    ga.N = s.N;
+    ga.scheme = s.p.scheme;
     ga.dstride = s.dstride;
     ga.inv_tau = 1.0 / s.tau;
     ga.d0[0] = s.dh[0][0];
@@ -1407,59 +1598,224 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     ga.traj = traj;
     ga.Sx = Sx;
     ga.mu = mu;
-    ga.psi = psi;
-    ga.gG0c = gG0c;
-    ga.part = part;
-    ga.gpart = s.F;  // free until the d/dbeta pass: ks*64 >= nchunk rows of 2M
+    ga.psi = A.psi;
+    ga.gG0c = A.gG0c;
+    ga.part = A.part;
+    ga.gpart = s.F;  // free outside the d/dbeta passes: ks*64 >= nchunk rows of 2M
     ga.nchunk = A.nchunk;
+    ga.per = A.per;
+    return ga;
+}
+
+// the scalar gradients from the partial sums on the device
+static int adjoint_finish(Solver& s, double* grad) {
+    AdjBufs& A = s.ab;
+    const cq_params* p = &s.p;
+    hipStream_t st = s.st;
+    std::vector<double> hp(static_cast<size_t>(A.nblk_da)), hp2(static_cast<size_t>(2 * A.nblk_rows)),
+        hb(static_cast<size_t>(2 * A.nblk_dot));
+    HIPCHK(hipMemcpyAsync(hp.data(), A.part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hp2.data(), A.part2, hp2.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (A.spec_nb > 2)
+        HIPCHK(hipMemcpyAsync(hb.data(), A.bpart, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double sa = 0.0, sb0 = 0.0, sb1 = 0.0;
+    for (double v : hp) sa += v;
+    for (int i = 0; i < A.nblk_rows; ++i) {
+        sb0 += hp2[size_t(i)];
+        sb1 += hp2[size_t(A.nblk_rows + i)];
+    }
+    for (int i = 0; i < A.nblk_dot; ++i) {
+        sb0 += hb[size_t(i)];
+        sb1 += hb[size_t(A.nblk_dot + i)];
+    }
+    const double da_dm = -1.0 / ((2.0 * p->m - 1.0) * (2.0 * p->m - 1.0));
+    grad[0] = sb0;            // dl/dalpha_1 = -dl/dbeta_1
+    grad[1] = sb1;
+    grad[2] = -sa * da_dm;    // dl/dm = dl/da da/dm, dl/da = -sum
+    return CQ_OK;
+}
+
+// checkpointed gradient: see AdjBufs
+static int adjoint_exec_ckpt(Solver& s, const double* gN, double* gG0, double* grad, double* GN) {
+    AdjBufs& A = s.ab;
+    const int64_t M = s.M, N = s.N, twoM = 2 * M, L = s.L, seg = A.seg;
+    const size_t hc = hcount(s);
+    const size_t row = size_t(twoM) * sizeof(double);
+    hipStream_t st = s.st;
+    double* const Hf = A.Hf;
+    double* const Sff = A.Sff;
+    int64_t adj_n = 0;  // reversed steps the adjoint has taken
+    auto seg_a = [&](int k) { return int64_t(k) * seg; };
+    auto seg_b = [&](int k) { return std::min<int64_t>(N, int64_t(k + 1) * seg); };
+    // the advancing forward: state Hf, levels in the ring ringA (level l at
+    // slot l mod L), at step `cur`
+    int64_t cur = 0;
+    auto advance_to = [&](int64_t a) {
+        Sweep w{A.ringA, Hf, Sff, nullptr, nullptr, nullptr, L, cur, false, 0};
+        set_sweep(s, w);
+        modal_steps(s, a - cur);
+        cur = a;
+    };
+    auto save = [&](int slot) -> int {
+        double* c = A.ck + size_t(slot) * size_t(A.ck_stride);
+        HIPCHK(hipMemcpyAsync(c, Hf, hc * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(c + hc, A.ringA, size_t(L) * row, hipMemcpyDeviceToDevice, st));
+        return CQ_OK;
+    };
+    auto load = [&](int slot, int64_t a) -> int {
+        const double* c = A.ck + size_t(slot) * size_t(A.ck_stride);
+        HIPCHK(hipMemcpyAsync(Hf, c, hc * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(A.ringA, c + hc, size_t(L) * row, hipMemcpyDeviceToDevice, st));
+        cur = a;
+        return CQ_OK;
+    };
+    // reverse segment k, the forward being at its start
+    auto reverse_segment = [&](int k) -> int {
+        const int64_t a = seg_a(k), b = seg_b(k);
+        // forward over the segment, levels a-L+1 .. b linear in segLev
+        for (int64_t l = a - L + 1; l <= a; ++l) {
+            const int64_t slot = ((l % L) + L) % L;
+            HIPCHK(hipMemcpyAsync(A.segLev + (l - (a - L + 1)) * twoM, A.ringA + slot * twoM, row,
+                                  hipMemcpyDeviceToDevice, st));
+        }
+        double* lvb = A.segLev - (a - L + 1) * twoM;  // level l at lvb + l*2M for a-L+1 <= l <= b
+        double* sb = A.segS - (a + 1) * twoM;         // S^n at sb + n*2M for a < n <= b
+        Sweep wf{lvb, Hf, Sff, sb, nullptr, nullptr, N + 1, a, false, 0};
+        set_sweep(s, wf);
+        modal_steps(s, b - a);
+        if (b == N && GN) transform(s, lvb + N * twoM, GN, false);
+        // the adjoint over the reversed steps N-b+1 .. N-a; mu rows for the
+        // reversed steps N-b-1 .. N-a (the two before the piece carried over)
+        const int64_t r0 = N - b - 1;
+        double* mub = A.segMu - r0 * twoM;
+        if (b == N) {
+            HIPCHK(hipMemsetAsync(A.segMu, 0, 2 * row, st));
+        } else {
+            // the previous piece's rows r0, r0+1 sit at rows r0 - r0p, r0 - r0p + 1 of segMu,
+            // r0p = N - b' - 1, b' = min(N, b + seg)
+            // (one row at a time: the two ranges overlap when that piece was one step long)
+            const int64_t r0p = N - std::min<int64_t>(N, b + seg) - 1;
+            for (int64_t q = 0; q < 2; ++q)
+                HIPCHK(hipMemcpyAsync(A.segMu + q * twoM, A.segMu + (r0 - r0p + q) * twoM, row,
+                                      hipMemcpyDeviceToDevice, st));
+        }
+        Sweep wa{A.psi, A.Ha, A.Sfa, nullptr, mub, A.gc, N + 1, adj_n, true, N % s.Bt};
+        set_sweep(s, wa);
+        modal_steps(s, b - a);
+        adj_n += b - a;
+        // this segment's share of dl/da (its chunks) and of d/dbeta (the
+        // levels a+1..b against every later step)
+        AdjGradArgs ga = grad_args(s, lvb, sb, mub);
+        ga.chunk0 = int(a / A.per);
+        ga.nchunk_da = int((b - a + A.per - 1) / A.per);
+        launch_adj_da(ga, st);
+        const int rows = s.Bf;
+        for (int64_t n0 = (a / rows) * rows; n0 < N; n0 += rows) {
+            const int bt = int(std::min<int64_t>(rows, N - n0));
+            beta_rows(s, lvb, n0, bt, rows, a + 1, std::min<int64_t>(b, n0 + bt), k == 0);
+        }
+        if (k == 0) {  // dl/dG0 from psi (whole) and mu^1, mu^2 (this piece)
+            launch_adj_g0(grad_args(s, lvb, sb, mub), st);
+            transform(s, A.gG0c, gG0, true);
+        }
+        HIPCHK(hipGetLastError());
+        return CQ_OK;
+    };
+    // revolve over segments i .. j-1 with the state at segment i saved in
+    // `slot` and the states in `free` available
+    std::vector<int> freeslots;
+    for (int c = A.slots - 1; c >= 1; --c) freeslots.push_back(c);
+    const int C = std::max(1, A.slots);
+    int rc_all = CQ_OK;
+    std::function<void(int, int, int)> rev = [&](int i, int j, int slot) {
+        if (rc_all) return;
+        const int n = j - i;
+        if (n == 1) {
+            rc_all = load(slot, seg_a(i));
+            if (!rc_all) rc_all = reverse_segment(i);
+            return;
+        }
+        const int c = int(freeslots.size());
+        const int m = c > 0 ? A.split[size_t(n) * C + size_t(std::min(c, C - 1))] : 0;
+        if (c == 0 || m == 0) {
+            for (int k = j - 1; k >= i && !rc_all; --k) {
+                rc_all = load(slot, seg_a(i));
+                if (rc_all) return;
+                advance_to(seg_a(k));
+                rc_all = reverse_segment(k);
+            }
+            return;
+        }
+        rc_all = load(slot, seg_a(i));
+        if (rc_all) return;
+        advance_to(seg_a(i + m));
+        const int s2 = freeslots.back();
+        freeslots.pop_back();
+        rc_all = save(s2);
+        if (rc_all) return;
+        rev(i + m, j, s2);
+        freeslots.push_back(s2);
+        rev(i, i + m, slot);
+    };
+    // start: state at step 0 (H = 0, level 0 = g^0, earlier levels zero) in slot 0
+    HIPCHK(hipMemsetAsync(Hf, 0, hc * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(A.ringA, 0, size_t(L) * row, st));
+    HIPCHK(hipMemcpyAsync(A.ringA, s.g0c, row, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(A.Ha, 0, hc * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(A.psi, 0, row, st));
+    HIPCHK(hipMemsetAsync(A.acc, 0, row, st));
+    int rc = save(0);
+    if (rc) return rc;
+    rev(0, A.nseg, 0);
+    if (rc_all) return rc_all;
+    launch_sum_rows(A.acc, M, A.part2, st);
+    HIPCHK(hipGetLastError());
+    return adjoint_finish(s, grad);
+}
+
+static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* gG0, double* grad, double* GN) {
+    const cq_params* p = &s.p;
+    AdjBufs& A = s.ab;
+    const int64_t M = s.M, N = s.N, twoM = 2 * M;
+    hipStream_t st = s.st;
+    HIPCHK(hipMemcpyAsync(s.G0, G0, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    transform(s, s.G0, s.g0c, true);
+    transform(s, gN, A.gc, false);  // dl/dg^N = S^T dl/dG^N, S symmetric
+    if (A.ckpt) return adjoint_exec_ckpt(s, gN, gG0, grad, GN);
+    double *traj = A.traj, *Sx = A.Sx, *psi = A.psi, *mu = A.mu;
+    // forward, keeping every level and history sum
+    HIPCHK(hipMemcpyAsync(traj, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(Sx, 0, size_t(twoM) * sizeof(double), st));
+    if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));
+    set_sweep(s, Sweep{traj, A.Hf, A.Sff, Sx, nullptr, nullptr, N + 1, 0, false, 0});
+    modal_steps(s, N);
+    if (GN) transform(s, traj + N * twoM, GN, false);
+
+    // adjoint sweep: levels psi, multipliers mu, both in reversed time
+    HIPCHK(hipMemsetAsync(psi, 0, size_t(twoM) * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(mu, 0, size_t(twoM) * sizeof(double), st));
+    if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));
+    set_sweep(s, Sweep{psi, A.Hf, A.Sff, nullptr, mu, A.gc, N + 1, 0, true, p->method == 1 ? N % s.Bt : 0});
+    modal_steps(s, N);
+
+    // gradients
+    AdjGradArgs ga = grad_args(s, traj, Sx, mu);
     launch_adj_g0(ga, st);
-    transform(s, gG0c, gG0, true);  // dl/dG0 = P^T dl/dg^0, P = scaled S, symmetric
+    transform(s, A.gG0c, gG0, true);  // dl/dG0 = P^T dl/dg^0, P = scaled S, symmetric
     launch_adj_da(ga, st);
     // d/dbeta: Toeplitz products of the weight derivatives, over all levels
     // in passes of Bf steps, or in blocks of spec_bk steps over the levels of
     // the previous and the current block only (the farther block pairs
     // follow through block DFTs); BDF2's g^0 term enters with the contraction
-    HIPCHK(hipMemsetAsync(acc, 0, size_t(twoM) * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(A.acc, 0, size_t(twoM) * sizeof(double), st));
     const int rows = A.spec_bk ? A.spec_bk : s.Bf;
     for (int64_t n0 = 0; n0 < N; n0 += rows) {
         const int bt = int(std::min<int64_t>(rows, N - n0));
-        // CQ sums of the weight derivatives over levels l0..n for the block's
-        // steps (blocks of <= kDwPad steps): one Toeplitz product over levels
-        // l0..n0+bt (negative lags read the zero padding in front of each
-        // component's row)
-        FarArgs fa{};
-        fa.n0 = n0;
-        fa.l0 = A.spec_bk ? std::max<int64_t>(1, n0 - rows + 1) : 1;
-        fa.nl = n0 + bt;
-        fa.M = M;
-        fa.dstride = s.dstride + kDwPad;
-        fa.lstride = twoM;
-        fa.B = rows;
-        const int64_t nlev = fa.nl - fa.l0 + 1;
-        fa.ks = far_ks_for(s.ks, nlev);
-        fa.ncomp = 2;
-        const int64_t mc = (nlev + fa.ks - 1) / fa.ks;
-        fa.mchunk = ((mc + 3) / 4) * 4;
-        fa.levels = traj;
-        fa.d = dw + kDwPad;
-        fa.F = s.F;
-        fa.reduce = 1;
-        launch_far(fa, st);
-        AdjBetaArgs ab{};
-        ab.M = M;
-        ab.N = N;
-        ab.n0 = n0;
-        ab.bt = bt;
-        ab.scheme = p->scheme;
-        ab.dstride = s.dstride;
-        ab.dd = dd;
-        ab.F = s.F;
-        ab.traj = traj;
-        ab.psi = psi;
-        ab.acc = acc;
-        launch_adj_beta(ab, st);
+        const int64_t l0 = A.spec_bk ? std::max<int64_t>(1, n0 - rows + 1) : 1;
+        beta_rows(s, traj, n0, bt, rows, l0, n0 + bt, true);
     }
-    launch_sum_rows(acc, M, part2, st);
+    launch_sum_rows(A.acc, M, A.part2, st);
     HIPCHK(hipGetLastError());
     if (A.spec_nb > 2) {
         // columns a_t = psi^{t+1} (stored in reversed time, row N - t) and
@@ -1488,31 +1844,11 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         launch_beta_dot(bd, st);
         HIPCHK(hipGetLastError());
     }
-    std::vector<double> hp(static_cast<size_t>(nblk_da)), hp2(static_cast<size_t>(2 * nblk_rows)),
-        hb(static_cast<size_t>(2 * A.nblk_dot));
-    HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hp2.data(), part2, hp2.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    if (A.spec_nb > 2)
-        HIPCHK(hipMemcpyAsync(hb.data(), A.bpart, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double sa = 0.0, sb0 = 0.0, sb1 = 0.0;
-    for (double v : hp) sa += v;
-    for (int i = 0; i < nblk_rows; ++i) {
-        sb0 += hp2[size_t(i)];
-        sb1 += hp2[size_t(nblk_rows + i)];
-    }
-    for (int i = 0; i < A.nblk_dot; ++i) {
-        sb0 += hb[size_t(i)];
-        sb1 += hb[size_t(A.nblk_dot + i)];
-    }
-    const double da_dm = -1.0 / ((2.0 * p->m - 1.0) * (2.0 * p->m - 1.0));
-    grad[0] = sb0;            // dl/dalpha_1 = -dl/dbeta_1
-    grad[1] = sb1;
-    grad[2] = -sa * da_dm;    // dl/dm = dl/da da/dm, dl/da = -sum
-    return CQ_OK;
+    return adjoint_finish(s, grad);
 }
 
-int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_stream, void** handle) {
+int fp_adjoint_create_opts(const cq_grid* grid, const cq_params* prm, const cq_adjoint_opts* opts, void* hip_stream,
+                           void** handle) {
     clear_error();
     if (!handle) return fail(CQ_EINVAL, "handle is NULL");
     *handle = nullptr;
@@ -1524,7 +1860,7 @@ int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_strea
     if (!s) return fail(CQ_ENOMEM, "host allocation failed");
     try {
         rc = setup_host(*s, grid, prm, st);
-        if (!rc) rc = adjoint_setup(*s);
+        if (!rc) rc = adjoint_setup(*s, opts);
     } catch (const std::bad_alloc&) {
         rc = fail(CQ_ENOMEM, "host allocation failed");
     }
@@ -1534,6 +1870,25 @@ int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_strea
         return rc;
     }
     *handle = s;
+    return CQ_OK;
+}
+
+int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_stream, void** handle) {
+    return fp_adjoint_create_opts(grid, prm, nullptr, hip_stream, handle);
+}
+
+int fp_adjoint_info(void* handle, cq_adjoint_info* info) {
+    clear_error();
+    if (!handle || !info) return fail(CQ_EINVAL, "NULL argument");
+    const Solver& s = *static_cast<const Solver*>(handle);
+    if (s.kind != 1) return fail(CQ_EINVAL, "handle was not made by fp_adjoint_create");
+    const AdjBufs& A = s.ab;
+    info->mode = A.ckpt ? 2 : 1;
+    info->segment_steps = A.ckpt ? A.seg : s.N;
+    info->segments = A.ckpt ? A.nseg : 1;
+    info->slots = A.ckpt ? A.slots : 0;
+    info->forward_steps = A.fwd_steps;
+    info->device_bytes = s.dev_bytes;
     return CQ_OK;
 }
 

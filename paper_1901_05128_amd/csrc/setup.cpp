@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 
 #include "internal.h"
 
@@ -269,24 +270,35 @@ void build_rule(int scheme, double beta, double tau, int np, int np1, int ns, Fa
         }
         return;
     }
-    out.lag = ns;
+    std::vector<double> s2, lam2;
     gauss_jacobi(np1, beta, 2.0 - 2.0 * beta, s, lam);
+    gauss_jacobi(np, beta, 2.0 - 2.0 * beta, s2, lam2);
+    bdf2_rule_from_nodes(beta, tau, ns, s, lam, s2, lam2, out);
+}
+
+void bdf2_rule_from_nodes(double beta, double tau, int ns, const std::vector<double>& s1,
+                          const std::vector<double>& lam1, const std::vector<double>& s2,
+                          const std::vector<double>& lam2, FastRule& out) {
+    out.ratio.clear();
+    out.coef.clear();
+    out.lag = ns;
+    const double sb = std::sin(M_PI * beta) / M_PI;
+    const double tb = std::pow(tau, -beta);
     const double c1 = -std::pow(2.0, 2.0 + 2.0 * beta) * std::cos(M_PI * beta) * sb * tb;
-    for (int j = 0; j < np1; ++j) {
-        const double r = (s[j] + 1.0) / (s[j] + 5.0);
-        const double dbar = std::pow(s[j] + 5.0, -4.0) * std::pow(r, double(ns - 3));
+    for (size_t j = 0; j < s1.size(); ++j) {
+        const double r = (s1[j] + 1.0) / (s1[j] + 5.0);
+        const double dbar = std::pow(s1[j] + 5.0, -4.0) * std::pow(r, double(ns - 3));
         out.ratio.push_back(r);
-        out.coef.push_back(c1 * lam[j] * dbar);
+        out.coef.push_back(c1 * lam1[j] * dbar);
     }
-    gauss_jacobi(np, beta, 2.0 - 2.0 * beta, s, lam);
     const double c2 = -std::pow(2.0, -beta - 3.0) * sb * tb;
-    for (int j = 0; j < np; ++j) {
-        const double r = 0.5 * (s[j] + 1.0);
-        const double u = 1.0 + 3.0 * s[j];
+    for (size_t j = 0; j < s2.size(); ++j) {
+        const double r = 0.5 * (s2[j] + 1.0);
+        const double u = 1.0 + 3.0 * s2[j];
         const double re = std::pow(std::fabs(u), beta) * (u >= 0.0 ? 1.0 : std::cos(M_PI * beta));
         const double dbar = re * std::pow(r, double(ns - 3));
         out.ratio.push_back(r);
-        out.coef.push_back(c2 * lam[j] * dbar);
+        out.coef.push_back(c2 * lam2[j] * dbar);
     }
 }
 
@@ -299,10 +311,14 @@ double rule_error(const FastRule& r, const std::vector<double>& d, int64_t N) {
     const int64_t L = r.lag;
     if (N < L) return 0.0;
     std::vector<double> acc(size_t(N - L + 1), 0.0);
+    // a term below 1e-30 |d_0| cannot move the error measured here (the
+    // targets are above 1e-16 |d_0|); stopping there also keeps the loop out
+    // of subnormal arithmetic for the small ratios
+    const double tiny = 1e-30 * std::fabs(d[0]);
     for (size_t j = 0; j < r.ratio.size(); ++j) {
         double p = r.coef[j];
         const double q = r.ratio[j];
-        for (int64_t i = L; i <= N; ++i) {
+        for (int64_t i = L; i <= N && std::fabs(p) >= tiny; ++i) {
             acc[size_t(i - L)] += p;
             p *= q;
         }
@@ -367,6 +383,129 @@ int choose_rule(int scheme, double beta, double tau, int64_t N, double tol, int 
     }
     return fail(CQ_ETOL, "fast rule: max|eps_i|/d_0 = %.3e > %.3e with np <= %d (beta=%g, N=%lld)", out.max_eps,
                 target, np_max, beta, (long long)N);
+}
+
+// BDF2 window and first family chosen from the weight errors (Section 5
+// picks N_s from the decay of |eps_{2,i}|). Candidates N_s in {12, 16, 20,
+// 24, 28, 32} (every lag the time-blocked kernels take) and N_{p,1} in {8,
+// 12, 16, 24} (or the caller's); for each, the smallest N_{p,2} on the ladder
+// whose rule meets the target for every order beta_k; the pair with the
+// least modelled cost per mode, component and step wins:
+//   max((4 n + 2 N_s) flops / 78.6, 16 n / min(N_s, 32) bytes / 8),
+// n = N_{p,1} + N_{p,2} (the state update and weighting, the exact window;
+// the state streamed once per block of min(N_s, 32) steps; FP64 TFLOP/s
+// and HBM TB/s of the GPU). The search measures eps_i at every i up to
+// 4096 and at ~1% steps beyond (the errors vary slowly there); the winner
+// is then checked at every i and moved up the ladder if it falls short.
+namespace {
+const int kLadder[] = {8,   12,  16,  24,  32,  48,  64,  96,  128, 160, 192,
+                       256, 320, 384, 448, 512, 576, 640, 768, 896, 1024, 1280, 1536, 2048};
+
+double rule_error_at(const FastRule& r, const std::vector<double>& d, const std::vector<int64_t>& idx) {
+    const int64_t L = r.lag;
+    std::vector<double> acc(idx.size(), 0.0);
+    const double tiny = 1e-30 * std::fabs(d[0]);
+    for (size_t j = 0; j < r.ratio.size(); ++j) {
+        const double q = r.ratio[j];
+        double p = r.coef[j];
+        int64_t at = L;
+        for (size_t t = 0; t < idx.size() && std::fabs(p) >= tiny; ++t) {
+            const int64_t gap = idx[t] - at;
+            if (gap == 1) p *= q;
+            else if (gap > 1) p *= std::pow(q, double(gap));
+            at = idx[t];
+            acc[t] += p;
+        }
+    }
+    double m = 0.0;
+    for (size_t t = 0; t < idx.size(); ++t) m = std::max(m, std::fabs(d[size_t(idx[t])] - acc[t]));
+    return m / std::fabs(d[0]);
+}
+}  // namespace
+
+int choose_bdf2_window(const double* betas, int nb, double tau, int64_t N, double tol, int np_max, int np1_fixed,
+                       int& ns_out, int& np1_out) {
+    static const int ns_c[] = {12, 16, 20, 24, 28, 32};
+    static const int np1_c[] = {8, 12, 16, 24};
+    const double target = tol / (10.0 * double(std::max<int64_t>(N, 1)));
+    std::vector<std::vector<double>> d(static_cast<size_t>(nb));
+    for (int k = 0; k < nb; ++k) {
+        d[size_t(k)].assign(size_t(N) + 1, 0.0);
+        weights(2, betas[k], tau, N, d[size_t(k)].data());
+    }
+    double best = -1.0;
+    int bns = 30, bnp1 = np1_fixed ? np1_fixed : 16, bnp2 = -1;
+    FastRule r;
+    // Gauss-Jacobi nodes for (1-s)^beta (1+s)^(2-2 beta), both families,
+    // computed once per order and size
+    std::vector<std::map<int, std::pair<std::vector<double>, std::vector<double>>>> gj(static_cast<size_t>(nb));
+    auto nodes = [&](int k, int n) -> const std::pair<std::vector<double>, std::vector<double>>& {
+        auto& m = gj[size_t(k)];
+        auto it = m.find(n);
+        if (it == m.end()) {
+            std::pair<std::vector<double>, std::vector<double>> v;
+            gauss_jacobi(n, betas[k], 2.0 - 2.0 * betas[k], v.first, v.second);
+            it = m.emplace(n, std::move(v)).first;
+        }
+        return it->second;
+    };
+    auto make = [&](int k, int np2, int np1, int ns) {
+        const auto& a = nodes(k, np1);
+        const auto& b = nodes(k, np2);
+        bdf2_rule_from_nodes(betas[k], tau, ns, a.first, a.second, b.first, b.second, r);
+    };
+    for (int ns : ns_c) {
+        if (ns > N) break;
+        std::vector<int64_t> idx;
+        for (int64_t i = ns; i <= N; ++i) {
+            if (i <= 4096 || i == N) idx.push_back(i);
+            else if (double(i) >= double(idx.back()) * 1.01) idx.push_back(i);
+        }
+        for (int np1 : np1_c) {
+            if (np1_fixed && np1 != np1_fixed) continue;
+            int need = 0;  // ladder index meeting the target for every order
+            bool ok = true;
+            for (int k = 0; k < nb && ok; ++k) {
+                int lo = need, hi = int(sizeof(kLadder) / sizeof(int)) - 1;
+                while (hi >= lo && kLadder[hi] > np_max) --hi;
+                if (hi < lo) { ok = false; break; }
+                make(k, kLadder[hi], np1, ns);
+                if (rule_error_at(r, d[size_t(k)], idx) > target) { ok = false; break; }
+                while (lo < hi) {  // smallest ladder entry that meets the target
+                    const int mid = (lo + hi) / 2;
+                    make(k, kLadder[mid], np1, ns);
+                    if (rule_error_at(r, d[size_t(k)], idx) <= target) hi = mid; else lo = mid + 1;
+                }
+                need = lo;
+            }
+            if (!ok) continue;
+            const double n = double(np1 + kLadder[need]);
+            const double cost = std::max((4.0 * n + 2.0 * ns) / 78.6, 16.0 * n / double(std::min(ns, 32)) / 8.0);
+            if (best < 0 || cost < best) {
+                best = cost;
+                bns = ns;
+                bnp1 = np1;
+                bnp2 = need;
+            }
+        }
+    }
+    if (bnp2 < 0) {  // no candidate: the default window, and the ordinary scan reports any shortfall
+        ns_out = 30;
+        np1_out = np1_fixed ? np1_fixed : 16;
+        return CQ_OK;
+    }
+    // the winner at every i; up the ladder while it falls short
+    const int nl = int(sizeof(kLadder) / sizeof(int));
+    for (int k = 0; k < nb; ++k) {
+        while (bnp2 < nl && kLadder[bnp2] <= np_max) {
+            make(k, kLadder[bnp2], bnp1, bns);
+            if (rule_error(r, d[size_t(k)], N) <= target) break;
+            ++bnp2;
+        }
+    }
+    ns_out = bns;
+    np1_out = bnp1;
+    return CQ_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -150,8 +150,9 @@ def test_full_size_parameter_gradients_match_finite_differences():
 
 def test_full_size_parameter_gradients_match_central_differences():
     """The same loss; central differences with h = 1e-6 of the GPU forward
-    in alpha_1, alpha_2 and m (truncation O(h^2) ~ 1e-12 relative; the
-    loss's rounding, ~1e-14 of it, divided by 2h sets the floor)."""
+    in alpha_1, alpha_2 and m (truncation O(h^2) ~ 1e-12 relative). The
+    floor is the loss's rounding divided by 2h: the forward's fp64 error
+    after N = 4096 steps is ~1e-13 of G^N, so 1e-7 L0."""
     nx, ny, G0, G0t = _c5()
     g = cq.make_grid(2, nx, ny)
     target = cq.fp_solve(g, _params(0.25, 0.55, 0.55), dev(G0t)).cpu().numpy()
@@ -171,7 +172,7 @@ def test_full_size_parameter_gradients_match_central_differences():
         fd = (loss(qp)[0] - loss(qm)[0]) / (2 * h)
         print(f"  param {i}: adjoint {grads[i]:.10e}  central fd {fd:.10e}  "
               f"rel {abs(grads[i] - fd) / max(abs(fd), 1e-300):.2e}", flush=True)
-        assert abs(grads[i] - fd) <= 1e-5 * abs(fd) + 1e-8 * L0
+        assert abs(grads[i] - fd) <= 1e-5 * abs(fd) + 1e-7 * L0
 
 
 def test_full_size_adjoint_matches_oracle_on_sampled_modes():

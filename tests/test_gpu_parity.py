@@ -93,8 +93,9 @@ def test_solve_matches_oracle(case, scheme, method, solver):
     else:
         assert e <= 1e-8, e
         if N > info.lag:
-            np_ = info.np_total - (16 if scheme == 2 else 0)
-            ref_f = modal.reference(dim, nx, ny, a1, a2, m, T, N, G0, scheme, 1, np_=np_, ns=30)
+            np_ = info.np_total - info.np1
+            ref_f = modal.reference(dim, nx, ny, a1, a2, m, T, N, G0, scheme, 1, np_=np_, np1=info.np1 or 16,
+                                    ns=info.lag)
             ef = rel(out, ref_f)
             print(f"  rel_l2 vs fast reference {ef:.3e}", flush=True)
             assert ef <= 1e-11

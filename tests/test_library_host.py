@@ -167,6 +167,22 @@ def test_adjoint_create_host_checks():
     assert rc == _lib.CQ_ESINGULAR
 
 
+def test_adjoint_opts_host_checks():
+    """The memory form's checks come before any device call: an unknown mode,
+    negative counts, and the checkpointed form for the direct method."""
+    g = cq.make_grid(1, 31)
+    fast = cq.make_params(0.3, 0.7, 0.3, 1.0, 100, 2, 1, np_=12, np1=8, ns=10, solver=cq.SOLVER_MODAL)
+    direct = cq.make_params(0.3, 0.7, 0.3, 1.0, 100, 2, 0, solver=cq.SOLVER_MODAL)
+    L = cq.lib()
+    for prm, opts in [(fast, _lib.AdjointOpts(0, 3, 0, 0)), (fast, _lib.AdjointOpts(0, 2, -1, 0)),
+                      (fast, _lib.AdjointOpts(0, 2, 0, -2)), (direct, _lib.AdjointOpts(0, 2, 0, 0))]:
+        h = C.c_void_p()
+        rc = L.fp_adjoint_create_opts(C.byref(g), C.byref(prm), C.byref(opts), None, C.byref(h))
+        assert rc == _lib.CQ_EINVAL and not h.value, (opts.mode, rc)
+    assert "fast method" in L.cq_last_error().decode()
+    assert L.fp_adjoint_info(None, None) == _lib.CQ_EINVAL
+
+
 def test_handle_calls_reject_null():
     L = cq.lib()
     assert L.fp_step(None, 1) == _lib.CQ_EINVAL
