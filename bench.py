@@ -220,15 +220,16 @@ def cpu_baseline(w, variants):
                         f"{c2_one * 1e3:.3f} ms (1 thread), timed over {nh} levels; {spent:.1f} s of CPU work"}
 
 
-def load_traffic(kernel_name):
-    """HBM traffic per launch from the committed rocprofv3 --pmc summary, or
-    None when it is missing or the kernel source changed since it was taken."""
+def load_traffic(kernel_name, workload):
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary for
+    this kernel and workload, or None when it is missing or the kernel source
+    changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1901_05128_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        ent = rec.get(kernel_name)
+        ent = rec.get(f"{kernel_name}@{workload}")
         if not ent or ent.get("kernels_hip_sha256") != sha:
             return None
         return ent.get("bytes_per_launch")
@@ -390,7 +391,7 @@ def bench_adjoint(args):
                             "frac": bf, "fp64_frac": ff}
             roofline.update({"kernel": dom, "avg_launch_us": avg * 1e6, "launches": n_l,
                              "timed": "one extra gradient after the timed region, HIP events per launch",
-                             "traffic": load_traffic(dom)})
+                             "traffic": load_traffic(dom, "c5")})
     rec = {
         "metric": "gradients/s (dl/dG0 and dl/dalpha_1, dl/dalpha_2, dl/dm)", "value": 1.0 / per,
         "unit": "grads/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": per * 1e3,
@@ -467,6 +468,7 @@ def main():
     if args.workload == "t5" and args.t5_data == "b":
         from paper_1901_05128_amd import workloads as wl
         g0 = wl.g0_nonsmooth_b(nx)
+        desc = desc.replace("data (a)", "data (b)")
     G0 = torch.tensor(g0, dtype=torch.float64, device="cuda")
     grid = cq.make_grid(dim, nx, ny)
     solvers, streams = {}, {}
@@ -569,7 +571,7 @@ def main():
         roofline["algorithmic_per_launch"] = (tot_f if f_frac >= b_frac else tot_b) / n_l
         roofline["timed"] = ("serial pass after the timed region (variants " +
                              ", ".join(VNAME[v] for v in variants) + "), HIP events per launch")
-        roofline["traffic"] = load_traffic(dom)
+        roofline["traffic"] = load_traffic(dom, args.workload)
 
     # fast vs direct on the GPU (the metric's accuracy side)
     fvd = {}

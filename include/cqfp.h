@@ -177,17 +177,27 @@ int cq_history_noalloc(int32_t scheme, double beta, double tau, const double* G_
                        int64_t n, int64_t M, double* S_out, void* hip_stream);
 
 /* Create a solver for one problem, starting from G0 (dev [2][M], copied).
- * Allocates every device buffer the run needs (the full history [N+1][2][M]
- * for method 0; the compressed state [2][np_total][M] and an N_s-level
- * window for method 1). Validates the arguments (CQ_EINVAL, CQ_ENONFINITE),
- * checks that the step operator is positive definite (CQ_ESINGULAR) and, for
- * method 1 with np == 0, that the fast rule meets fast_tol (CQ_ETOL).
- * *handle receives the solver; free it with fp_destroy. */
+ * The handle integrates the decoupled system (2.1) by the scheme prm selects:
+ * backward-Euler CQ (4.1) with its fast form (4.3), or BDF2 CQ with the
+ * starting correction (4.7) and its fast form (4.8); the history term of
+ * each step is the CQ sum (3.8) / (3.17) with the weights of (3.4) / (3.12),
+ * and the fast method replaces its far part by the geometric sums of
+ * (3.9)-(3.10) / (3.18). Allocates every device buffer the run needs (the full history
+ * [N+1][2][M] for method 0; the compressed state [2][np_total][M] and an
+ * N_s-level window for method 1). Validates the arguments (CQ_EINVAL,
+ * CQ_ENONFINITE; the finiteness check copies G0 to the host and synchronises
+ * the stream), checks that the step operator is positive definite
+ * (CQ_ESINGULAR) and, for method 1 with np == 0, that the fast rule meets
+ * fast_tol (CQ_ETOL). *handle receives the solver; free it with fp_destroy. */
 int fp_create(const cq_grid* grid, const cq_params* prm, const double* G0,
               void* hip_stream, void** handle);
 
 /* Advance by nsteps time steps (not beyond N), asynchronously on the
- * handle's stream. Allocates nothing. */
+ * handle's stream. Each step n solves the implicit 2x2-block system of
+ * (4.1) or (4.7) for G^n (for (4.7), the n = 1 step carries the starting
+ * correction) after forming the CQ history of the earlier levels (direct sum,
+ * or the fast form (4.3) / (4.8)). Allocates nothing. CQ_EINVAL if
+ * n + nsteps > N. */
 int fp_step(void* handle, int64_t nsteps);
 
 /* Copy the current solution G^n to G_out (dev [2][M]); *n_out receives n.
@@ -207,14 +217,18 @@ int fp_set_state(void* handle, const void* src, size_t bytes);
 
 /* Restart the handle at n = 0 from a new G0 (dev [2][M], copied): clears
  * the compressed history and the level store on the device, reusing every
- * buffer (allocates nothing). Asynchronous on the handle's stream. */
+ * device buffer (no device allocation). G0 is first checked for NaN and
+ * infinity (CQ_ENONFINITE): that check copies it into a temporary host
+ * buffer and synchronises the handle's stream; the restart itself is then
+ * enqueued asynchronously on that stream. */
 int fp_reset(void* handle, const double* G0);
 
 /* Release a handle and all its device memory. NULL is accepted. */
 int fp_destroy(void* handle);
 
-/* One-call solve: create, take all N steps, write G^N to GN (dev [2][M]),
- * destroy. Synchronises the stream. */
+/* One-call solve of (2.1) by the scheme prm selects ((4.1)/(4.3) or
+ * (4.7)/(4.8), as fp_create): create, take all N steps, write G^N to GN
+ * (dev [2][M]), destroy. Errors as fp_create. Synchronises the stream. */
 int fp_solve(const cq_grid* grid, const cq_params* prm, const double* G0, double* GN,
              void* hip_stream);
 
