@@ -1,8 +1,9 @@
 """Full-size parity on sampled outputs, in the launch configuration the
 benchmark times (modal solver).
 
-Configuration 2 (1D, 1023 nodes, N = 2^14) and configuration 3 (2D, 255^2,
-N = 2^16): the GPU's G^N is projected on sampled sine modes on the CPU
+Configuration 2 (1D, 1023 nodes, N = 2^14), configuration 3 (2D, 255^2,
+N = 2^16) and the paper's Table 5 problem (1D, 1023 nodes, N = 20000): the
+GPU's G^N is projected on sampled sine modes on the CPU
 (low, middle and highest modes, both sides of the 256-mode tile boundaries
 8191/8192 and 32767/32768, and the last, ragged tile's mode 65024).
 
@@ -42,11 +43,11 @@ def _gpu():
     cq.lib()
 
 
-def _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes):
+def _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T=1.0):
     """GPU G^N on the sampled modes, the largest coefficient, and the fast
     rule's node counts and window (None for direct)."""
     g = cq.make_grid(dim, nx, ny)
-    p = cq.make_params(a1, a2, m, 1.0, N, scheme, method, solver=cq.SOLVER_MODAL)
+    p = cq.make_params(a1, a2, m, T, N, scheme, method, solver=cq.SOLVER_MODAL)
     with cq.Solver(g, p, torch.tensor(G0, dtype=torch.float64, device="cuda")) as s:
         info = s.info()
         s.step(N)
@@ -74,11 +75,11 @@ def _check(got, ref, cmax, tol):
 _LD = {}
 
 
-def _ld_direct(dim, nx, ny, modes, a1, a2, m, N, G0, scheme):
-    key = (dim, nx, ny, tuple(modes), a1, a2, m, N, scheme)
+def _ld_direct(dim, nx, ny, modes, a1, a2, m, N, G0, scheme, T=1.0):
+    key = (dim, nx, ny, tuple(modes), a1, a2, m, N, scheme, T, G0.tobytes())
     if key not in _LD:
         print(f"  long-double direct reference: {len(modes)} modes, N={N}, scheme={scheme}", flush=True)
-        _LD[key] = modal_ld.run_modes_ld(dim, nx, ny, modes, a1, a2, m, 1.0, N, G0, scheme)
+        _LD[key] = modal_ld.run_modes_ld(dim, nx, ny, modes, a1, a2, m, T, N, G0, scheme)
     return _LD[key]
 
 
@@ -86,9 +87,9 @@ def _rel_l2(got, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-def _check_case(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes):
-    got, cmax, rule = _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes)
-    ld = _ld_direct(dim, nx, ny, modes, a1, a2, m, N, G0, scheme)
+def _check_case(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T=1.0):
+    got, cmax, rule = _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T)
+    ld = _ld_direct(dim, nx, ny, modes, a1, a2, m, N, G0, scheme, T)
     e = _rel_l2(got, ld)
     per = np.abs(got - ld) / np.maximum(np.abs(ld), 1e-300)
     print(f"  vs long-double direct: rel L2 {e:.3e}, max per-coefficient rel {np.max(per):.3e}", flush=True)
@@ -98,14 +99,14 @@ def _check_case(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes):
             # the lowest mode's G1 - G2 grows), fp64 cannot reach 1e-12 of
             # the exact scheme after N steps in any order: the bar is then
             # the error of the oracle's own fp64 evaluation of the recurrence
-            f64 = modal.run_modes(dim, nx, ny, modes, a1, a2, m, 1.0, N, G0, scheme, 0)
+            f64 = modal.run_modes(dim, nx, ny, modes, a1, a2, m, T, N, G0, scheme, 0)
             e_orc = _rel_l2(f64, ld)
             print(f"  oracle fp64 vs long-double direct: rel L2 {e_orc:.3e}", flush=True)
             assert e <= e_orc, (e, e_orc)
         return
     assert e <= 1e-8, e
     print(f"  oracle fp64 fast per-mode run: {len(modes)} modes, N={N}, rule={rule}", flush=True)
-    ref = modal.run_modes(dim, nx, ny, modes, a1, a2, m, 1.0, N, G0, scheme, method, **rule)
+    ref = modal.run_modes(dim, nx, ny, modes, a1, a2, m, T, N, G0, scheme, method, **rule)
     _check(got, ref, cmax, _tol(N, method))
 
 
@@ -130,6 +131,18 @@ def test_configuration3_full_size_sampled_modes(scheme, method):
     print(f"c3 full size scheme={scheme} method={method}", flush=True)
     G0 = wl.g0_rectangle(nx, ny, 3)
     _check_case(2, nx, ny, 0.2, 0.6, 0.55, N, G0, scheme, method, C3_MODES)
+
+
+@pytest.mark.parametrize("data", ["a", "b"])
+@pytest.mark.parametrize("method", [0, 1])
+def test_table5_problem_full_size_sampled_modes(data, method):
+    """The paper's Table 5 problem (Section 5): 1D, h = 1/1024 (1023 nodes),
+    T = 10, tau = 1/2000 (N = 20000), m = 0 (a = -1), (alpha1, alpha2) =
+    (0.3, 0.8), BDF2 (SBD) direct and fast, from the paper's data (a) or (b)."""
+    nx, N = 1023, 20000
+    print(f"table 5 full size data={data} method={method}", flush=True)
+    G0 = wl.g0_smooth(nx) if data == "a" else wl.g0_nonsmooth_b(nx)
+    _check_case(1, nx, 1, 0.3, 0.8, 0.0, N, G0, 2, method, C2_MODES, T=10.0)
 
 
 def test_configuration4_full_size_sampled_modes():
