@@ -640,6 +640,127 @@ __global__ __launch_bounds__(1024) void k_step_1d(StepArgs p) {
     }
 }
 
+// The same step for M <= 1024 (one row per thread), with the PCR multipliers
+// of every level held in registers (loaded once, all in flight, and used by
+// both solves) and the reduction ping-ponging between two LDS buffers (one
+// barrier per level). 32-bit indices. The arithmetic, and its order, is that
+// of k_step_1d: the results are the same bit for bit.
+constexpr int kPcrMaxLevels = 10;  // ceil(log2 1024)
+
+__device__ __forceinline__ void pcr_regs(double*& cur, double*& nxt, int M, int levels, int x,
+                                         const double (&f)[kPcrMaxLevels][2], const double (&g)[kPcrMaxLevels][2],
+                                         const double (&rb)[2], double (&out)[2]) {
+#pragma unroll
+    for (int lvl = 0; lvl < kPcrMaxLevels; ++lvl) {
+        if (lvl < levels) {  // uniform
+            const int st = 1 << lvl;
+            if (x < M) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int o = k * M;
+                    double dd = cur[o + x];
+                    if (x - st >= 0) dd = fma(-f[lvl][k], cur[o + x - st], dd);
+                    if (x + st < M) dd = fma(-g[lvl][k], cur[o + x + st], dd);
+                    nxt[o + x] = dd;
+                }
+            }
+            __syncthreads();
+            double* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    if (x < M) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            out[k] = cur[k * M + x] * rb[k];
+            nxt[k * M + x] = out[k];
+        }
+    }
+    __syncthreads();
+    // the solution now also sits in nxt, for the neighbours' reads
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+}
+
+__global__ __launch_bounds__(1024) void k_step_1d_reg(StepArgs p) {
+    extern __shared__ double sm[];
+    const int M = int(p.M);
+    const int x = threadIdx.x;
+    const int levels = p.levels_pcr;
+    double* cur = sm;          // [2][M]
+    double* nxt = sm + 2 * M;  // [2][M]
+    // 1. w = E + c S'/d0, q = S'/d0, y = h^2 V^-1 Delta^-1 w
+    double ry[2] = {0.0, 0.0}, qv[2] = {0.0, 0.0};
+    if (x < M) {
+        double u[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const double qk = history_at(p, k, x) * p.inv_d0[k];
+            qv[k] = qk;
+            u[k] = (time_part(p, k, x) + p.cdiag * qk) * p.inv_d0[k];
+        }
+        ry[0] = (p.Vinv[0] * u[0] + p.Vinv[1] * u[1]) * p.h2;
+        ry[1] = (p.Vinv[2] * u[0] + p.Vinv[3] * u[1]) * p.h2;
+        cur[x] = ry[0];
+        cur[M + x] = ry[1];
+    }
+    // multipliers of every level, all loads issued together (after the
+    // history window's registers are free)
+    double f[kPcrMaxLevels][2], g[kPcrMaxLevels][2], rb[2];
+#pragma unroll
+    for (int lvl = 0; lvl < kPcrMaxLevels; ++lvl)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const bool ok = lvl < levels && x < M;
+            f[lvl][k] = ok ? p.PF[(lvl * 2 + k) * M + x] : 0.0;
+            g[lvl][k] = ok ? p.PG[(lvl * 2 + k) * M + x] : 0.0;
+        }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) rb[k] = x < M ? p.PRB[k * M + x] : 0.0;
+    __syncthreads();
+    double z[2] = {0.0, 0.0};
+    pcr_regs(cur, nxt, M, levels, x, f, g, rb, z);
+    // 2. residual h^2 y - T z in double-double (z of the neighbours from cur)
+    double rr[2] = {0.0, 0.0};
+    if (x < M) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int o = k * M;
+            const double zl = (x > 0) ? cur[o + x - 1] : 0.0;
+            const double zr = (x + 1 < M) ? cur[o + x + 1] : 0.0;
+            double hi = ry[k], lo = 0.0;
+            dd_add(hi, lo, zl);
+            dd_add(hi, lo, zr);
+            dd_add(hi, lo, -2.0 * z[k]);
+            const double pz = p.delta[k] * z[k];
+            const double pe = fma(p.delta[k], z[k], -pz);
+            dd_add(hi, lo, -pz);
+            lo -= pe;
+            rr[k] = hi + lo;
+        }
+        nxt[x] = rr[0];
+        nxt[M + x] = rr[1];
+    }
+    __syncthreads();
+    {
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    double dz[2] = {0.0, 0.0};
+    pcr_regs(cur, nxt, M, levels, x, f, g, rb, dz);
+    // 3. G^n = V (z + dz) - Delta^-1 S'
+    if (x < M) {
+        double* out = p.levels + p.slot_out * 2 * p.M;
+        const double z0 = z[0] + dz[0];
+        const double z1 = z[1] + dz[1];
+        out[x] = p.V[0] * z0 + p.V[1] * z1 - qv[0];
+        out[M + x] = p.V[2] * z0 + p.V[3] * z1 - qv[1];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 2D: pointwise right-hand side w = E + c Delta^-1 S' and q = Delta^-1 S'
 // (the forward DST, per-mode solve and inverse DST follow; the last GEMM
@@ -2220,7 +2341,8 @@ void launch_step_1d(const StepArgs& a, size_t lds, hipStream_t st) {
     prof_begin(3, st);
     const int R = int((a.M + kNT1D - 1) / kNT1D);
     switch (R) {
-        case 1: hipLaunchKernelGGL(k_step_1d<1>, dim3(1), dim3(kNT1D), lds, st, a); break;
+        // (two LDS buffers: twice the single buffer the caller sized)
+        case 1: hipLaunchKernelGGL(k_step_1d_reg, dim3(1), dim3(kNT1D), 2 * lds, st, a); break;
         case 2: hipLaunchKernelGGL(k_step_1d<2>, dim3(1), dim3(kNT1D), lds, st, a); break;
         case 3: hipLaunchKernelGGL(k_step_1d<3>, dim3(1), dim3(kNT1D), lds, st, a); break;
         default: hipLaunchKernelGGL(k_step_1d<4>, dim3(1), dim3(kNT1D), lds, st, a); break;
