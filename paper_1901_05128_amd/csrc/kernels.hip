@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void k_reduce_far(double* __restrict__ F, int 
 // L/16 + 4i, col L%16 (checked on gfx950).
 // One weight stage of the far-field product: the levels s0 .. s1-1 (s0 < s1)
 // of the strip G (16 columns per wave) against the weights wt staged for
-// them, wt[j] = d[n0+1 - (s1-1) + j], with wt[zero] = 0, added into acc.
+// them, wt[j] = d[n0+1 - (s1-1) + j], with 16*NR zeros from wt[zero], added
+// into acc.
 template <int NR>
 __device__ __forceinline__ void far_stage(const double* __restrict__ G, int64_t ls, const double* wt, int zero,
                                           int64_t s0, int64_t s1, int li, int lk, d4 (&acc)[NR]) {
@@ -251,18 +252,18 @@ __device__ __forceinline__ void far_stage(const double* __restrict__ G, int64_t 
         }
     };
     // A fragment of row fragment r at level l: wt[(16r + li) + (s1 - 1 - l)],
-    // the zero entry for a level past the stage (index arithmetic, not a
-    // select of addresses); read from LDS just before its products, so
-    // no register buffer holds them (four waves fit on a SIMD)
+    // or, for a level past the stage, wt[zero + 16r] in the zero tail (so
+    // the row offsets 16r are constants: paired LDS reads); read from LDS
+    // just before its products, so no register buffer holds them (four
+    // waves fit on a SIMD)
     auto mma = [&](int64_t l0, const double (&b_)[U]) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t l = l0 + 4 * uu + lk;
-            const int lin = l < s1 ? 1 : 0;
-            const int base_i = lin * (li + int(s1 - 1 - l)) + (1 - lin) * zero;
+            const int base_i = l < s1 ? li + int(s1 - 1 - l) : zero;
             double a_[NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) a_[r] = wt[base_i + lin * 16 * r];
+            for (int r = 0; r < NR; ++r) a_[r] = wt[base_i + 16 * r];
 #pragma unroll
             for (int r = 0; r < NR; ++r) acc[r] = mfma16x16x4(a_[r], b_[uu], acc[r]);
         }
@@ -271,6 +272,45 @@ __device__ __forceinline__ void far_stage(const double* __restrict__ G, int64_t 
     // while the other's products run
     double bv[U], bw[U];
     loadb(s0, bv);
+    if constexpr (NR >= 16) {
+        // 256 rows: the A fragments of the next K-step are read while this
+        // K-step's products run (two register buffers; the waves per SIMD
+        // stay at two), so no product waits on the LDS
+        double a0[NR], a1[NR];
+        auto loada = [&](int64_t l, double (&a_)[NR]) {
+            const int base_i = l < s1 ? li + int(s1 - 1 - l) : zero;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) a_[r] = wt[base_i + 16 * r];
+        };
+        auto mm = [&](const double (&a_)[NR], double b) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = mfma16x16x4(a_[r], b, acc[r]);
+        };
+        // entering, a0 holds the A fragments of level l0's K-step; leaving,
+        // those of level l0 + 16's
+        auto mma_p = [&](int64_t l0, const double (&b_)[U]) {
+            loada(l0 + 4 + lk, a1);
+            mm(a0, b_[0]);
+            loada(l0 + 8 + lk, a0);
+            mm(a1, b_[1]);
+            loada(l0 + 12 + lk, a1);
+            mm(a0, b_[2]);
+            loada(l0 + 16 + lk, a0);
+            mm(a1, b_[3]);
+        };
+        loada(s0 + lk, a0);
+        for (int64_t l0 = s0; l0 < s1; l0 += 8 * U) {
+            loadb(l0 + 4 * U, bw);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_p(l0, bv);
+            __builtin_amdgcn_sched_barrier(0);
+            loadb(l0 + 8 * U, bv);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_p(l0 + 4 * U, bw);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
     for (int64_t l0 = s0; l0 < s1; l0 += 8 * U) {
         loadb(l0 + 4 * U, bw);
         __builtin_amdgcn_sched_barrier(0);
@@ -287,7 +327,8 @@ template <int NR>
 __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
     constexpr int TL = 1024;           // levels per weight stage
     constexpr int B = NR * 16;
-    __shared__ double wt[B + TL + 1];  // [B + TL] weights of a stage, then one zero
+    constexpr int WS = B + TL + B;     // [B + TL] weights of a stage, then B zeros
+    __shared__ double wt[WS];
     const int k = blockIdx.z;
     const int q = blockIdx.y;
     const int wave = threadIdx.x >> 6;
@@ -309,7 +350,7 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
         const int64_t base = p.n0 + 1 - (s1 - 1);
         const int len = int(B + (s1 - s0) - 1);
         __syncthreads();
-        for (int j = threadIdx.x; j < B + TL + 1; j += 256) wt[j] = j < len ? dk[base + j] : 0.0;
+        for (int j = threadIdx.x; j < WS; j += 256) wt[j] = j < len ? dk[base + j] : 0.0;
         __syncthreads();
         far_stage<NR>(G, p.lstride, wt, B + TL, s0, s1, li, lk, acc);
     }
@@ -335,7 +376,7 @@ template <int NR, int KW>
 __global__ __launch_bounds__(64 * KW) void k_far_toeplitz_kw(FarArgs p) {
     constexpr int TL = NR >= 12 ? 256 : 512;  // levels per weight stage of a wave (registers)
     constexpr int B = NR * 16;
-    constexpr int WS = B + TL + 1;     // a wave's stage weights, then one zero
+    constexpr int WS = B + TL + B;     // a wave's stage weights, then B zeros
     constexpr int PART = NR * 4 * 64;  // one wave's sums
     constexpr int LDSN = (KW * WS > (KW / 2) * PART) ? KW * WS : (KW / 2) * PART;
     __shared__ double sm[LDSN];
@@ -370,9 +411,10 @@ __global__ __launch_bounds__(64 * KW) void k_far_toeplitz_kw(FarArgs p) {
         const int len = int(B + (s1 - s0) - 1);
         // (every load in flight at once: the index is clamped into the stage's
         // weights, and entries past them are set to zero after the load)
-        double v[(WS + 63) / 64];
+        constexpr int WL = B + TL;  // entries that may hold weights
+        double v[(WL + 63) / 64];
 #pragma unroll
-        for (int t = 0; t < (WS + 63) / 64; ++t) {
+        for (int t = 0; t < (WL + 63) / 64; ++t) {
             const int j = lane + 64 * t;
             v[t] = dk[base + (j < len ? j : len - 1)];
         }
@@ -381,7 +423,7 @@ __global__ __launch_bounds__(64 * KW) void k_far_toeplitz_kw(FarArgs p) {
 #pragma unroll
         for (int t = 0; t < (WS + 63) / 64; ++t) {
             const int j = lane + 64 * t;
-            if (j < WS) wt[j] = j < len ? v[t] : 0.0;
+            if (j < WS) wt[j] = (t < (WL + 63) / 64 && j < len) ? v[t < (WL + 63) / 64 ? t : 0] : 0.0;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
