@@ -2,10 +2,11 @@
 """Throughput of the CQ Fokker-Planck solver on one MI355X.
 
 One bench step = full solves (all N time steps, inputs resident in HBM) of
-the workload's timed variants, run concurrently, one stream each. For the
-2D 255^2, N = 2^16 workload (the default) that is the BDF2 scheme with the
-fast history and with the direct (blocked Toeplitz) history; for the 1D
-workloads it is BE and BDF2, each fast and direct. The value is whole-job
+the workload's timed variants. For the 2D 255^2, N = 2^16 workload (the
+default) that is the BDF2 scheme with the fast history and with the direct
+(blocked Toeplitz) history, one after the other on one stream; for the 1D
+workloads it is BE and BDF2, each fast and direct, run concurrently, one
+stream each. The value is whole-job
 DOF*steps/s (DOF = 2 components x grid nodes) over the timed variants. Every
 variant (BE included) then runs once more, serially and outside the timed
 region, with HIP events around every kernel launch: that pass gives the
@@ -43,6 +44,10 @@ VARIANTS = [(1, 1), (1, 0), (2, 1), (2, 0)]  # (scheme, method)
 TIMED = {"c3": [(2, 1), (2, 0)], "t5": [(2, 1), (2, 0)]}
 # variants of the serial pass (default: all four)
 SERIAL = {"t5": [(2, 1), (2, 0)]}
+# workloads whose timed variants run one after another on one stream: at c3 the
+# far-field passes fill the chip, and the fast solve's kernels between them on a
+# second stream made the step 5.6% slower (9.04 s against 8.55 s)
+ONE_STREAM = {"c3"}
 # Table 5's CPU times (seconds, BDF2 direct / fast, order pairs (0.3,0.8),
 # (0.4,0.7), (0.5,0.6); the paper names no machine) and its L2 errors
 # E_1, E_2 against a tau/2 run
@@ -220,17 +225,21 @@ def cpu_baseline(w, variants):
                         f"{c2_one * 1e3:.3f} ms (1 thread), timed over {nh} levels; {spent:.1f} s of CPU work"}
 
 
+# source file of each kernel family whose traffic profiles/traffic.json holds
+KERNEL_SOURCE = {"far_toeplitz": "far.hip", "hist_fast": "kernels.hip"}
+
+
 def load_traffic(kernel_name, workload):
     """HBM traffic per launch from the committed rocprofv3 --pmc summary for
-    this kernel and workload, or None when it is missing or the kernel source
-    changed since it was taken."""
+    this kernel and workload, or None when it is missing or the kernel's
+    source file changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1901_05128_amd", "csrc", "kernels.hip")
     try:
+        src = os.path.join(ROOT, "paper_1901_05128_amd", "csrc", KERNEL_SOURCE[kernel_name])
         rec = json.load(open(path))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         ent = rec.get(f"{kernel_name}@{workload}")
-        if not ent or ent.get("kernels_hip_sha256") != sha:
+        if not ent or ent.get("source_sha256") != sha:
             return None
         return ent.get("bytes_per_launch")
     except Exception:
@@ -430,7 +439,7 @@ def main():
     ap.add_argument("--no-prof", action="store_true",
                     help="skip the serial pass (kernel timings, the untimed variants)")
     ap.add_argument("--serial", action="store_true",
-                    help="run the timed variants one after another (default: one stream each, concurrently)")
+                    help="run the timed variants one after another (default: one stream each, concurrently; c3 always one stream)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer 4 times (a plain copy kernel of "
                          "known size that scales the rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -463,6 +472,7 @@ def main():
     # the serial pass runs every variant of the workload unless it is skipped
     variants = SERIAL.get(args.workload, VARIANTS) if not args.no_prof else timed
     variants = variants + [v for v in timed if v not in variants]
+    serial = args.serial or args.workload in ONE_STREAM
     torch.cuda.set_device(0)
     g0 = g0_for(w)
     if args.workload == "t5" and args.t5_data == "b":
@@ -473,8 +483,8 @@ def main():
     grid = cq.make_grid(dim, nx, ny)
     solvers, streams = {}, {}
     for v in variants:
-        # each timed variant on its own stream (default priority) unless --serial
-        streams[v] = torch.cuda.Stream() if (v in timed and not args.serial) else torch.cuda.current_stream()
+        # each timed variant on its own stream (default priority) unless serial
+        streams[v] = torch.cuda.Stream() if (v in timed and not serial) else torch.cuda.current_stream()
         with torch.cuda.stream(streams[v]):
             solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1],
                                                         solver=SOLVERS[args.solver]), G0)
@@ -582,7 +592,8 @@ def main():
 
     info_np = {VNAME[v]: solvers[v].info().np_total for v in variants if v[1] == 1}
     breakdown = {VNAME[v]: {"ms": per_var_ms[v], "dofsteps_per_s": 2 * M * N / (per_var_ms[v] / 1e3),
-                            "where": "timed step (concurrent)"} for v in timed}
+                            "where": "timed step (one stream)" if serial else "timed step (concurrent)"}
+                 for v in timed}
     for v, ms in serial_ms.items():
         ent = breakdown.setdefault(VNAME[v], {})
         ent["serial_ms"] = ms
@@ -606,7 +617,7 @@ def main():
                   "synthetic (the paper's smooth initial data (a))") if seed is None
                  else "synthetic (seeded indicator initial data)"),
         "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
-                   "solver": args.solver, "streams": "serial" if args.serial else "one per variant",
+                   "solver": args.solver, "streams": "serial" if serial else "one per variant",
                    "timed_variants": [VNAME[v] for v in timed], "dof": 2 * M, "N": N,
                    "fast_nodes": info_np},
         "breakdown": breakdown,
