@@ -11,6 +11,28 @@
 
 namespace cqfp {
 
+// Workgroups are dispatched to the 8 XCDs in turn (linear id mod 8), each XCD
+// with its own L2. Neighbouring DOF tiles share the cache lines at their
+// edges (a level row of M doubles is not 128-byte aligned), so the tiles are
+// renumbered to give each XCD a contiguous range: the index that XCD x's
+// i-th workgroup takes is x*(n/8) + min(x, n mod 8) + i, a bijection of
+// [0, n). Returns the tile, slice and component of this workgroup, tile
+// fastest.
+// (32-bit arithmetic: a launch holds far fewer than 2^31 workgroups; the
+// results are wave-uniform and kept in scalar registers.)
+__device__ __forceinline__ void far_tile(int64_t& tile, int& q, int& k) {
+    const uint32_t nx = gridDim.x, ny = gridDim.y;
+    const uint32_t n = nx * ny * gridDim.z;
+    const uint32_t lin = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const uint32_t x = lin & 7u, i = lin >> 3;
+    const uint32_t g = x * (n >> 3) + (x < (n & 7u) ? x : (n & 7u)) + i;
+    const uint32_t rest = g / nx;
+    tile = int64_t(__builtin_amdgcn_readfirstlane(g - rest * nx));
+    const uint32_t qq = rest % ny;
+    q = __builtin_amdgcn_readfirstlane(int(qq));
+    k = __builtin_amdgcn_readfirstlane(int((rest - qq) / ny));
+}
+
 // Sum the K-split partials of the far field once per block, into slice 0:
 // F[0][b][k][x] = sum_q F[q][b][k][x].
 __global__ __launch_bounds__(256) void k_reduce_far(double* __restrict__ F, int ks, int64_t per) {
@@ -138,12 +160,13 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
     constexpr int B = NR * 16;
     constexpr int WS = B + TL + B;     // [B + TL] weights of a stage, then B zeros
     __shared__ double wt[WS];
-    const int k = blockIdx.z;
-    const int q = blockIdx.y;
+    int64_t tile;
+    int q, k;
+    far_tile(tile, q, k);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t xcol = int64_t(blockIdx.x) * 64 + wave * 16 + li;
+    const int64_t xcol = tile * 64 + wave * 16 + li;
     const bool xin = xcol < p.M;
     const int64_t xc = xin ? xcol : 0;
     const int64_t l_lo = p.l0 + int64_t(q) * p.mchunk;
@@ -192,7 +215,7 @@ __global__ __launch_bounds__(256) void k_far_toeplitz(FarArgs p) {
 // levels (its own weight stages), and the parts are added in LDS, pairwise
 // (waves h..2h-1 into waves 0..h-1, h = KW/2, ..., 1), before one store. The
 // split therefore costs no HBM traffic inside a workgroup; only the
-// workgroup slices along the levels (blockIdx.y, usually a few) leave
+// workgroup slices along the levels (usually a few) leave
 // partial sums for k_reduce_far.
 template <int NR, int KW>
 __global__ __launch_bounds__(64 * KW) void k_far_toeplitz_kw(FarArgs p) {
@@ -202,12 +225,13 @@ __global__ __launch_bounds__(64 * KW) void k_far_toeplitz_kw(FarArgs p) {
     constexpr int PART = NR * 4 * 64;  // one wave's sums
     constexpr int LDSN = (KW * WS > (KW / 2) * PART) ? KW * WS : (KW / 2) * PART;
     __shared__ double sm[LDSN];
-    const int k = blockIdx.z;
-    const int q = blockIdx.y;
+    int64_t tile;
+    int q, k;
+    far_tile(tile, q, k);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: the level range is scalar
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t xcol = int64_t(blockIdx.x) * 16 + li;
+    const int64_t xcol = tile * 16 + li;
     const bool xin = xcol < p.M;
     const int64_t xc = xin ? xcol : 0;
     const int64_t g_lo = p.l0 + int64_t(q) * p.mchunk;
