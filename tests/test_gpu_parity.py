@@ -240,3 +240,54 @@ def test_modal_steps_in_uneven_chunks_bitwise(method, scheme, dim):
             s.step(c)
         many = s.current()[0].cpu().numpy()
     assert np.array_equal(one, many)
+
+
+# ------------------------------------------------------------ maximum sizes
+@pytest.mark.parametrize("nx", [1024, 1025, 4096], ids=["1024-one-row-per-thread", "1025-two-rows", "4096-max"])
+@pytest.mark.parametrize("method", [0, 1])
+def test_nodal_1d_row_count_limits(nx, method):
+    """The 1D nodal step at the edges of its row-per-thread variants (1024
+    nodes: one row per thread, multipliers in registers; 1025: two rows per
+    thread; 4096: the largest 1D grid) against the per-mode reference."""
+    N = 40
+    print(f"nodal 1D nx={nx} method={method}", flush=True)
+    G0 = wl.g0_intervals(nx, 7)
+    g = cq.make_grid(1, nx, 1)
+    p = cq.make_params(0.3, 0.7, 0.6, 0.05, N, 2, method, solver=cq.SOLVER_NODAL)
+    with cq.Solver(g, p, dev(G0)) as s:
+        info = s.info()
+        s.step(N)
+        out = s.current()[0].cpu().numpy()
+    ref = modal.reference(1, nx, 1, 0.3, 0.7, 0.6, 0.05, N, G0, 2, 0)
+    e = rel(out, ref)
+    print(f"  rel_l2 vs direct reference {e:.3e}", flush=True)
+    assert e <= (1e-12 if method == 0 else 1e-8), e
+    if method == 1:
+        ref_f = modal.reference(1, nx, 1, 0.3, 0.7, 0.6, 0.05, N, G0, 2, 1, np_=info.np_total - info.np1,
+                                np1=info.np1 or 16, ns=info.lag)
+        assert rel(out, ref_f) <= 1e-11
+
+
+@pytest.mark.parametrize("scheme,np_,np1", [(1, 1024, 0), (2, 1008, 16)], ids=["BE-1024", "BDF2-16+1008"])
+@pytest.mark.parametrize("solver", [0, 1], ids=["nodal", "modal"])
+def test_fast_rule_at_the_node_limit(scheme, np_, np1, solver):
+    """The fast form with the most nodes a solver keeps per component (1024:
+    N_p = 1024 for BE, N_{p,1} + N_{p,2} = 16 + 1008 for BDF2), against the
+    oracle's fast scheme with the same node counts and the direct reference."""
+    dim, nx, ny, N = 2, 15, 9, 120
+    print(f"fast rule limit scheme={scheme} np={np_} np1={np1} solver={solver}", flush=True)
+    G0 = wl.g0_rectangle(nx, ny, 3)
+    g = cq.make_grid(dim, nx, ny)
+    p = cq.make_params(0.3, 0.6, 0.6, 1.0, N, scheme, 1, np_=np_, np1=np1, ns=30 if scheme == 2 else 0,
+                       solver=solver)
+    with cq.Solver(g, p, dev(G0)) as s:
+        info = s.info()
+        s.step(N)
+        out = s.current()[0].cpu().numpy()
+    assert info.np_total == 1024
+    ref = modal.reference(dim, nx, ny, 0.3, 0.6, 0.6, 1.0, N, G0, scheme, 0)
+    assert rel(out, ref) <= 1e-8
+    ref_f = modal.reference(dim, nx, ny, 0.3, 0.6, 0.6, 1.0, N, G0, scheme, 1, np_=np_, np1=np1 or 16, ns=info.lag)
+    ef = rel(out, ref_f)
+    print(f"  rel_l2 vs fast reference {ef:.3e}", flush=True)
+    assert ef <= 1e-11
