@@ -85,7 +85,7 @@ typedef struct {
  *  block_B: direct method, time-block length of the Toeplitz far-field
  *    update (0 = automatic; otherwise 64, 128, 192 or 256). The modal solver
  *    steps in blocks of 64 and takes block_B as the rows of one far-field
- *    pass over the stored levels (0 selects 128, or 256 from 8192 modes): the
+ *    pass over the stored levels (0 selects 192, or 256 from 8192 modes): the
  *    pass serves block_B/64 blocks, each later block adding the levels since
  *    the pass on its own.
  *  solver: 0 = nodal: every step assembles the right-hand side on the grid

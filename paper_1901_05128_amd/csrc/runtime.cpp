@@ -30,9 +30,10 @@ namespace {
 constexpr uint64_t kStateMagic = 0x43514650u;  // "CQFP"
 constexpr int64_t kModalBlockedMin = 8192;      // modes
 constexpr int64_t kDwPad = 256;                 // zero lags in front of the d/dbeta weights (>= pass rows)
-// modal direct: rows of one far-field pass. Measured: 128, 192 and 256 tie on
-// the 1D 1023-node workload; 256 is 2.5% faster than 128 on 2D 255^2.
-int modal_far_pass(int64_t M) { return M >= 8192 ? 256 : 128; }
+// modal direct: rows of one far-field pass. Measured: 192 and 256 are 4%
+// faster than 128 on the 1D 1023-node workload (the levels split over the
+// waves of a workgroup); 256 is 2.5% faster than 128 on 2D 255^2.
+int modal_far_pass(int64_t M) { return M >= 8192 ? 256 : 192; }
 
 // device arrays of a gradient handle (trajectory, history sums, adjoint)
 struct AdjBufs {
