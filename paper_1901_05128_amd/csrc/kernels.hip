@@ -794,6 +794,26 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
 // lv: lane 32k+t holds g_k^{n0-t} (zero for levels < 1); wc: lane 32k+t holds
 // d_{k,t-b} at step b (zero outside lags 1..L-1); lvnew: lane 32k+b holds
 // the block's level of step b. Needs 2 <= L <= 32 and np <= 32*NP.
+// Window weight tables of tb_steps in LDS: per wave and component kWinTab
+// entries, tab[m] = d_{k,m-32} for 1 <= m-32 <= L-1 and 0 elsewhere, so that
+// the push weight d_{k,t-b} of step b and the weight d_{k,t+1+u} of a level
+// before the block are plain reads at offsets from a per-lane base. Each wave
+// writes and reads only its own table (a wave's LDS operations complete in
+// order: wave-scope fences order the writes before the reads).
+constexpr int kWinTab = 128;
+__device__ __forceinline__ const double* tb_window_table(double* tab, const double* dk, int L, int lane) {
+    const int t = lane & 31;
+    double* tk = tab + (lane >> 5) * kWinTab;
+#pragma unroll
+    for (int q = 0; q < kWinTab / 32; ++q) {
+        const int lag = t + 32 * q - 32;
+        tk[t + 32 * q] = (lag >= 1 && lag <= L - 1) ? dk[lag] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return tk;
+}
+
 // The time-blocked steps nbeg+1..nend of one mode (one wave; lanes 0..31
 // component 0, 32..63 component 1, lane l: component k = l/32, position
 // t = l%32). The steps go in blocks of bt <= L (the lag): the levels
@@ -822,15 +842,16 @@ __global__ __launch_bounds__(256) void k_modal_batch(BatchArgs p) {
 // (lane 32k+t: g_k^{s-t}, zero for levels < 1, s the start of that block);
 // lvnew_out (lane 32k+j: the block's level of step j < e_end); P = Minv g^n,
 // R = Minv g^{n-1}, gl = g^n. dk: this component's exact weights, readable up
-// to dlast; dwin: d_{k,t} for 1 <= t < L, else 0. Needs 2 <= L <= 32,
-// np <= 32*NP.
+// to dlast; wt: this wave's table of them for this lane's component in LDS,
+// wt[m] = d_{k,m-32} for 1 <= m-32 <= L-1 and 0 elsewhere, m < kWinTab
+// (tb_window_table). Needs 2 <= L <= 32, np <= 32*NP.
 template <int NP>
 __device__ __forceinline__ void tb_steps(const int lane, const int L, const bool bdf2, const int64_t nbeg,
                                          const int64_t nend, const int64_t ntot, double* __restrict__ hsave,
                                          const int64_t hrow, const int np, int& e_end, double& lvnew_out,
                                          const double (&r_)[NP], const double (&w_)[NP],
                                          double (&h_)[NP], const double* __restrict__ dk, const int64_t dlast,
-                                         const double dwin, const double g0k, const double e1, const double e2,
+                                         const double* wt, const double g0k, const double e1, const double e2,
                                          const double s00, const double s01, const double s10, const double s11,
                                          const double i00, const double i01, const double i10, const double i11,
                                          double& P0_, double& P1_, double& R0_, double& R1_, double& gl0_,
@@ -883,23 +904,26 @@ __device__ __forceinline__ void tb_steps(const int lane, const int L, const bool
     // (C) one step of the block (lane t holds the pending sum of step
     // n0+1+t): with Minv the inverse of the step matrix, g^n = Minv (E - D S):
     // the E part is e1 P + e2 R with P = Minv g^{n-1} and R = Minv g^{n-2},
-    // the S part s.S, so a step waits on its sum and two FMAs. Returns this
-    // lane's component of the new level.
-    double acc = 0.0, wc = 0.0, lvnew = 0.0;
-    auto cstep = [&](int b) {
+    // the S part s.S, so a step waits on its sum and two FMAs. Each lane
+    // evaluates its own component (the coefficients of its row of Minv and
+    // of s) and reads the other component's new value from its half
+    // (readlane), which takes fewer instructions than both rows in every
+    // lane and gives the same values. wc: the push weight of step b for this
+    // lane's step, d_{k,t-b}, read from the LDS table. Returns this lane's
+    // component of the new level.
+    const double sk0 = hi_half ? s10 : s00, sk1 = hi_half ? s11 : s01;
+    const double ik0 = hi_half ? i10 : i00, ik1 = hi_half ? i11 : i01;
+    double Pk = hi_half ? P1 : P0, Rk = hi_half ? R1 : R0;
+    double acc = 0.0, lvnew = 0.0;
+    auto cstep = [&](int b, double wc) {
         const double S0 = lane_value(acc, b), S1 = lane_value(acc, 32 + b);
-        const double E0 = fma(e1, P0, e2 * R0), E1 = fma(e1, P1, e2 * R1);
-        const double gn0 = fma(s01, S1, fma(s00, S0, E0));
-        const double gn1 = fma(s11, S1, fma(s10, S0, E1));
-        const double gk = hi_half ? gn1 : gn0;
+        const double Ek = fma(e1, Pk, e2 * Rk);
+        const double gk = fma(sk1, S1, fma(sk0, S0, Ek));
         acc = fma(wc, gk, acc);
-        const double wsh = dpp_zero<0x138>(wc);  // wave_shr:1
-        wc = (t == 0) ? 0.0 : wsh;
         lvnew = (t == b) ? gk : lvnew;
-        R0 = P0;
-        R1 = P1;
-        P0 = fma(i01, gn1, i00 * gn0);
-        P1 = fma(i11, gn1, i10 * gn0);
+        const double gn0 = lane_value(gk, 0), gn1 = lane_value(gk, 32);
+        Rk = Pk;
+        Pk = fma(ik1, gn1, ik0 * gn0);
         gl0 = gn0;
         gl1 = gn1;
         return gk;
@@ -960,18 +984,13 @@ __device__ __forceinline__ void tb_steps(const int lane, const int L, const bool
         // step n0+1+t at lag t+1+u (groups of 8 levels; the weights of lags
         // >= L are zero, so the last group may run past L-1)
         {
-            double wl = dpp_zero<0x130>(dwin);  // wave_shl:1, lane t: d_{k,t+1}
-            wl = (t == 31) ? 0.0 : wl;
             for (int u0 = 0; u0 + 1 < L; u0 += 8) {
+                const double* wu = wt + 33 + t + u0;  // lane t, level n0-u: d_{k,t+1+u}
                 double g[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) g[u] = __shfl(lv, (lane & 32) + ((u0 + u) & 31), 64);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    acc = fma(wl, g[u], acc);
-                    const double nx = dpp_zero<0x130>(wl);
-                    wl = (t == 31) ? 0.0 : nx;
-                }
+                for (int u = 0; u < 8; ++u) acc = fma(wu[u], g[u], acc);
             }
         }
         // (C) the steps. When this block and the next are full, the next
@@ -979,16 +998,16 @@ __device__ __forceinline__ void tb_steps(const int lane, const int L, const bool
         // solved at step b (lag L), so its FMAs fill the solve's dependency
         // chain, 8 steps per group (the group count fixed at compile time,
         // a remainder group of 1..7 steps).
-        wc = dwin;
         lvnew = 0.0;
         const bool pipe = bc == L && ntot - (n0 + L) >= L && nend - (n0 + L) >= L;
         if (pipe) {
             double accn = 0.0;
             auto group = [&](auto rc, int c0) {
                 constexpr int RC = decltype(rc)::value;
+                const double* wg = wt + 25 + t - c0;  // step c0+j: d_{k,t-c0-j} at wg[7-j]
                 double a[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) a[POS[j]] = (j < RC) ? astep(cstep(c0 + j)) : 0.0;
+                for (int j = 0; j < 8; ++j) a[POS[j]] = (j < RC) ? astep(cstep(c0 + j, wg[7 - j])) : 0.0;
                 reduce8(a, c0, accn);
             };
             int c0 = 0;
@@ -1006,7 +1025,7 @@ __device__ __forceinline__ void tb_steps(const int lane, const int L, const bool
             }
             acc = accn;
         } else {
-            for (int b = 0; b < bc; ++b) cstep(b);
+            for (int b = 0; b < bc; ++b) cstep(b, wt[32 + t - b]);
         }
         have_fast = pipe;
         if (bc < bt) {  // the call ends inside this block (the last of the loop)
@@ -1023,10 +1042,10 @@ __device__ __forceinline__ void tb_steps(const int lane, const int L, const bool
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) h_[q] = h[q];
-    P0_ = P0;
-    P1_ = P1;
-    R0_ = R0;
-    R1_ = R1;
+    P0_ = lane_value(Pk, 0);
+    P1_ = lane_value(Pk, 32);
+    R0_ = lane_value(Rk, 0);
+    R1_ = lane_value(Rk, 32);
     gl0_ = gl0;
     gl1_ = gl1;
     lv_ = lv;
@@ -1062,8 +1081,9 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
         w[q] = ok ? coef[j] : 0.0;
         h[q] = 0.0;
     }
-    // window weights of this lane: d_{k,t} for 1 <= t < L (lag t of step t from the block's first level)
-    const double dwin = (t >= 1 && t < L) ? dk[t] : 0.0;
+    // window weights of this wave, d_{k,1..L-1}, in its LDS table
+    __shared__ double wtab[4][2 * kWinTab];
+    const double* wt = tb_window_table(wtab[threadIdx.x >> 6], dk, L, lane);
     const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
     const double g00 = g0[mode], g01 = g0[M + mode];
     const double g0k = hi_half ? g01 : g00;
@@ -1086,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_modal_batch_tb(BatchArgs p) {
     double lv = 0.0;                                                      // no level >= 1 yet
     int e_end;
     double lvnew;
-    tb_steps<NP>(lane, L, bdf2, 0, N, N, nullptr, 0, np, e_end, lvnew, r, w, h, dk, N, dwin, g0k, e1, e2, s00, s01,
+    tb_steps<NP>(lane, L, bdf2, 0, N, N, nullptr, 0, np, e_end, lvnew, r, w, h, dk, N, wt, g0k, e1, e2, s00, s01,
                  s10, s11, i00, i01, i10, i11, P0, P1, R0, R1, gl0, gl1, lv);
     if (lane == 0) {
         double* gN = p.gN + 2 * I.mode_off;
@@ -1123,7 +1143,8 @@ __global__ __launch_bounds__(256) void k_modal_fast_tb(ModalFastArgs p) {
         w[q] = ok ? coef[j] : 0.0;
         h[q] = ok ? H[int64_t(j) * p.hstride] : 0.0;
     }
-    const double dwin = (t >= 1 && t < L) ? dk[t] : 0.0;
+    __shared__ double wtab[4][2 * kWinTab];
+    const double* wt = tb_window_table(wtab[threadIdx.x >> 6], dk, L, lane);
     const double g00 = p.g0[mode], g01 = p.g0[M + mode];
     const double g0k = k ? g01 : g00;
     const bool bdf2 = p.scheme == 2;
@@ -1148,7 +1169,7 @@ __global__ __launch_bounds__(256) void k_modal_fast_tb(ModalFastArgs p) {
     const int64_t nend = n + p.nsteps;
     int e_end;
     double lvnew = 0.0;
-    tb_steps<NP>(lane, L, bdf2, ks, nend, p.N, H, p.hstride, np, e_end, lvnew, r, w, h, dk, p.dstride - 1, dwin,
+    tb_steps<NP>(lane, L, bdf2, ks, nend, p.N, H, p.hstride, np, e_end, lvnew, r, w, h, dk, p.dstride - 1, wt,
                  g0k, e1, e2, s00, s01, s10, s11, i00, i01, i10, i11, P0, P1, R0, R1, gl0, gl1, lv);
     if (e_end == 0) {  // ended on a block boundary: h is the next block's starting state
 #pragma unroll
