@@ -36,7 +36,23 @@ namespace cqfp {
 // meet in LDS and the slice-0 wave adds them in slice order and stores.
 // One DOF per lane; H is [2][np][M], so a wave streams 64 consecutive DOFs
 // of one node, and r_j and coef_j are wave-uniform. Output Sf[b][k][x].
-template <int BT, int S>
+// State loads and stores of the pass: non-temporal (streamed past the caches)
+// when the state is larger than the Infinity Cache can hold across passes,
+// ordinary when it fits (it then stays in the cache from one pass to the
+// next: 5% faster per pass for a 54 MB state; non-temporal 3% faster for a
+// 1.2 GB one).
+template <bool NT>
+__device__ __forceinline__ double hb_load(const double* a) {
+    if constexpr (NT) return __builtin_nontemporal_load(a);
+    else return *a;
+}
+template <bool NT>
+__device__ __forceinline__ void hb_store(double v, double* a) {
+    if constexpr (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
+}
+
+template <int BT, int S, bool NT>
 __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
     constexpr int TILES = 4 / S;  // 64-DOF tiles per workgroup
     __shared__ double red[S > 1 ? (S - 1) * TILES * BT * 64 : 1];
@@ -77,19 +93,19 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
         int j = j0;
         double hn0 = 0.0, hn1 = 0.0, hn2 = 0.0, hn3 = 0.0;
         if (j + 4 <= j1) {
-            hn0 = __builtin_nontemporal_load(h + int64_t(j) * hs);
-            hn1 = __builtin_nontemporal_load(h + int64_t(j + 1) * hs);
-            hn2 = __builtin_nontemporal_load(h + int64_t(j + 2) * hs);
-            hn3 = __builtin_nontemporal_load(h + int64_t(j + 3) * hs);
+            hn0 = hb_load<NT>(h + int64_t(j) * hs);
+            hn1 = hb_load<NT>(h + int64_t(j + 1) * hs);
+            hn2 = hb_load<NT>(h + int64_t(j + 2) * hs);
+            hn3 = hb_load<NT>(h + int64_t(j + 3) * hs);
         }
 #pragma unroll 1
         for (; j + 4 <= j1; j += 4) {
             double h0 = hn0, h1 = hn1, h2 = hn2, h3 = hn3;
             if (j + 8 <= j1) {
-                hn0 = __builtin_nontemporal_load(h + int64_t(j + 4) * hs);
-                hn1 = __builtin_nontemporal_load(h + int64_t(j + 5) * hs);
-                hn2 = __builtin_nontemporal_load(h + int64_t(j + 6) * hs);
-                hn3 = __builtin_nontemporal_load(h + int64_t(j + 7) * hs);
+                hn0 = hb_load<NT>(h + int64_t(j + 4) * hs);
+                hn1 = hb_load<NT>(h + int64_t(j + 5) * hs);
+                hn2 = hb_load<NT>(h + int64_t(j + 6) * hs);
+                hn3 = hb_load<NT>(h + int64_t(j + 7) * hs);
             }
             const double r0 = r[j], r1 = r[j + 1], r2 = r[j + 2], r3 = r[j + 3];
             const double w0 = w[j], w1 = w[j + 1], w2 = w[j + 2], w3 = w[j + 3];
@@ -106,10 +122,10 @@ __global__ __launch_bounds__(256) void k_hist_block(HistBlockArgs p) {
                     acc[b] = fma(w3, h3, acc[b]);
                 }
             }
-            __builtin_nontemporal_store(h0, h + int64_t(j) * hs);
-            __builtin_nontemporal_store(h1, h + int64_t(j + 1) * hs);
-            __builtin_nontemporal_store(h2, h + int64_t(j + 2) * hs);
-            __builtin_nontemporal_store(h3, h + int64_t(j + 3) * hs);
+            hb_store<NT>(h0, h + int64_t(j) * hs);
+            hb_store<NT>(h1, h + int64_t(j + 1) * hs);
+            hb_store<NT>(h2, h + int64_t(j + 2) * hs);
+            hb_store<NT>(h3, h + int64_t(j + 3) * hs);
         }
         for (; j < j1; ++j) {
             double h0 = h[int64_t(j) * hs];
@@ -1951,9 +1967,18 @@ __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
 
 // ---------------------------------------------------------------------------
 // launchers (optionally bracketed by timing events, see prof_begin/prof_end)
+// state sizes up to this many bytes stay cached between passes (the 256 MB
+// Infinity Cache, with room for the level window and the sums)
+constexpr int64_t kHistCachedBytes = int64_t(128) << 20;
+
 void launch_hist_block(const HistBlockArgs& a, int lanes, hipStream_t st) {
     dim3 grid(unsigned((a.M * lanes + 255) / 256), 1, 2);
-#define CQ_HB(BT, S) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hist_block<BT, S>), grid, dim3(256), 0, st, a)
+    const bool nt = int64_t(2) * a.np * a.hstride * int64_t(sizeof(double)) > kHistCachedBytes;
+#define CQ_HB(BT, S)                                                                                    \
+    if (nt)                                                                                             \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hist_block<BT, S, true>), grid, dim3(256), 0, st, a);      \
+    else                                                                                                \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hist_block<BT, S, false>), grid, dim3(256), 0, st, a)
 #define CQ_HB_S(BT)               \
     switch (lanes) {              \
         case 1: CQ_HB(BT, 1); break; \
