@@ -491,15 +491,38 @@ def main():
     torch.cuda.synchronize()
     outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
 
+    # the nodal solver launches kernels every step: enqueued whole, one
+    # variant's N steps would fill its queue and hold the host until they ran,
+    # so the variants go round-robin in chunks of steps, which keeps every
+    # stream fed (the modal solver enqueues a whole run in a few hundred
+    # launches)
+    chunk = 256 if args.solver == "nodal" and not serial else N
+
     def one_step(events=None):
+        if chunk == N:
+            for v in timed:
+                s = solvers[v]
+                with torch.cuda.stream(streams[v]):
+                    if events is not None:
+                        events[v][0].record()
+                    s.reset(G0)
+                    s.step(N)
+                    s.current(outs[v])
+                    if events is not None:
+                        events[v][1].record()
+            return
         for v in timed:
-            s = solvers[v]
             with torch.cuda.stream(streams[v]):
                 if events is not None:
                     events[v][0].record()
-                s.reset(G0)
-                s.step(N)
-                s.current(outs[v])
+                solvers[v].reset(G0)
+        for n0 in range(0, N, chunk):
+            for v in timed:
+                with torch.cuda.stream(streams[v]):
+                    solvers[v].step(min(chunk, N - n0))
+        for v in timed:
+            with torch.cuda.stream(streams[v]):
+                solvers[v].current(outs[v])
                 if events is not None:
                     events[v][1].record()
 
