@@ -12,7 +12,9 @@ variant (BE included) then runs once more, serially and outside the timed
 region, with HIP events around every kernel launch: that pass gives the
 per-variant times, the fast-vs-direct difference of both schemes and the
 dominant kernel's roofline. The CPU oracle's rate is reported beside it
-(timed on a prefix of the same workload, extrapolated to N steps).
+(timed on a prefix of the same workload, extrapolated to N steps). With the
+default workload the line also carries the adjoint rate ("adjoint": gradients
+per second of the 127^2, N = 4096 adjoint workload, measured afterwards).
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|t5]
 """
@@ -300,7 +302,7 @@ def bench_batched(args):
     print(json.dumps(rec), flush=True)
 
 
-def bench_adjoint(args):
+def bench_adjoint(args, emit=True):
     """One step = one gradient of l = 1/2 |G^N - target|^2 on the adjoint
     workload (2D 127^2, BDF2 fast, N = 4096, np = 16 + 192, ns = 30): the
     forward solve with the trajectory kept, the reversed-time adjoint sweep
@@ -416,7 +418,9 @@ def bench_adjoint(args):
         "roofline": roofline,
     }
     h.close()
-    print(json.dumps(rec), flush=True)
+    if emit:
+        print(json.dumps(rec), flush=True)
+    return rec
 
 
 def main():
@@ -436,6 +440,8 @@ def main():
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="c3: skip the adjoint rate (gradients/s on the 127^2, N = 4096 workload) added to the line")
     ap.add_argument("--no-prof", action="store_true",
                     help="skip the serial pass (kernel timings, the untimed variants)")
     ap.add_argument("--serial", action="store_true",
@@ -676,6 +682,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         rec["copy_probe_bytes_each_way"] = nel * 8
+    if args.workload == "c3" and not args.no_adjoint:
+        # the metric's second half, the adjoint rate, on its own workload (the
+        # 127^2 grid, N = 4096), measured after the timed region above (the
+        # solvers above are closed by now)
+        torch.cuda.empty_cache()
+        adj = bench_adjoint(argparse.Namespace(steps=10, warmup=2, no_prof=args.no_prof), emit=False)
+        rec["adjoint"] = {k: adj[k] for k in ("metric", "value", "unit", "steps", "warmup", "ms_per_step", "config",
+                                              "roofline")}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, timed)
     print(json.dumps(rec), flush=True)
