@@ -1904,30 +1904,43 @@ __global__ __launch_bounds__(256) void k_dst_gemm(GemmArgs p) {
     const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
     const int row = r0 + li, col = c0 + li;
     d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int kk = wave * 4; kk < p.K; kk += 16) {
-        const int kx = kk + lk;
-        const bool kin = kx < p.K;
-        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-        if (kin && row < p.R) {
-            // A is either a per-component field (row-major, lda) or a shared
-            // symmetric sine matrix (read transposed for coalescing)
-            if (p.A_shared) {
-                a0 = a1 = p.A0[int64_t(kx) * p.lda + row];
-            } else {
-                a0 = p.A0[int64_t(row) * p.lda + kx];
-                a1 = p.A1[int64_t(row) * p.lda + kx];
+    // wave w takes the K-steps kk = 4w, 4w + 16, ...; the operands of KB of
+    // them are loaded together before their products, so a wave waits for
+    // memory once per KB K-steps rather than at every one
+    constexpr int KB = 8;
+    for (int kb = wave * 4; kb < p.K; kb += 16 * KB) {
+        double a0[KB], a1[KB], b0[KB], b1[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int kx = kb + 16 * u + lk;
+            const bool kin = kx < p.K;
+            a0[u] = a1[u] = b0[u] = b1[u] = 0.0;
+            if (kin && row < p.R) {
+                // A is either a per-component field (row-major, lda) or a shared
+                // symmetric sine matrix (read transposed for coalescing)
+                if (p.A_shared) {
+                    a0[u] = a1[u] = p.A0[int64_t(kx) * p.lda + row];
+                } else {
+                    a0[u] = p.A0[int64_t(row) * p.lda + kx];
+                    a1[u] = p.A1[int64_t(row) * p.lda + kx];
+                }
+            }
+            if (kin && col < p.C) {
+                if (p.B_shared) {
+                    b0[u] = b1[u] = p.B0[int64_t(kx) * p.ldb + col];
+                } else {
+                    b0[u] = p.B0[int64_t(kx) * p.ldb + col];
+                    b1[u] = p.B1[int64_t(kx) * p.ldb + col];
+                }
             }
         }
-        if (kin && col < p.C) {
-            if (p.B_shared) {
-                b0 = b1 = p.B0[int64_t(kx) * p.ldb + col];
-            } else {
-                b0 = p.B0[int64_t(kx) * p.ldb + col];
-                b1 = p.B1[int64_t(kx) * p.ldb + col];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            if (kb + 16 * u < p.K) {  // the K-steps of this wave, as one after another
+                acc0 = mfma16x16x4(a0[u], b0[u], acc0);
+                acc1 = mfma16x16x4(a1[u], b1[u], acc1);
             }
         }
-        acc0 = mfma16x16x4(a0, b0, acc0);
-        acc1 = mfma16x16x4(a1, b1, acc1);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
