@@ -271,13 +271,15 @@ def bench_batched(args):
         g0 = wl.g0_intervals(p.nx, 1000 + i) if p.dim == 1 else wl.g0_rectangle(p.nx, p.ny, 1000 + i)
         g0s.append(torch.tensor(g0, dtype=torch.float64, device="cuda"))
     outs = [torch.empty_like(g) for g in g0s]
+    kern = {"auto": cq.BATCH_AUTOTUNE, "default": cq.BATCH_DEFAULT, "time_blocked": cq.BATCH_TIME_BLOCKED,
+            "mfma_tile": cq.BATCH_MFMA_TILE, "per_step": cq.BATCH_PER_STEP}[args.batch_kernel]
     for _ in range(args.warmup):
-        cq.fp_solve_batched(grids, params, g0s, outs)
+        cq.fp_solve_batched(grids, params, g0s, outs, autotune=kern)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
     for _ in range(args.steps):
-        reps.append(cq.fp_solve_batched(grids, params, g0s, outs)[1])
+        reps.append(cq.fp_solve_batched(grids, params, g0s, outs, autotune=kern)[1])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dofsteps = args.steps * sum(2 * p.nx * p.ny * p.N for p in inst)
@@ -287,8 +289,12 @@ def bench_batched(args):
     # exact-weight window (2 flops per lag below N_s = 30); FP64 vector bound
     flops = sum(2 * p.nx * p.ny * p.N * (4 * (16 + int(math.ceil(3 * math.sqrt(p.N)))) + 2 * 29) for p in inst)
     ach = flops / rep.run_s / 1e12
-    roofline = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS, "kernel": "k_modal_batch (all classes)",
+    kinds = list(rep.class_blocked)[:rep.classes]
+    mx = sum(1 for x in kinds if x == 2)
+    # FP64 matrix and vector peaks are the same figure on this GPU
+    roofline = {"bound": "mfma" if 2 * mx > len(kinds) else "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "kernel": "k_modal_batch_mx / k_modal_batch_tb / k_modal_batch (all classes)",
                 "timed": "graph run time of the last step (the kernels run inside one captured graph)",
                 "traffic": None}
     rec = {
@@ -299,7 +305,9 @@ def bench_batched(args):
         "config": {"workload": "c4: 256 seeded fast-BDF2 problems, 1D 127-4095 nodes / 2D 63^2-255^2, "
                                "N=2^10..2^15, np=ceil(3 sqrt N), one captured graph",
                    "modes": rep.modes, "classes": rep.classes,
-                   "lanes_per_mode": list(rep.class_lanes)[:rep.classes]},
+                   "lanes_per_mode": list(rep.class_lanes)[:rep.classes],
+                   "class_kernel": [{0: "per_step", 1: "time_blocked", 2: "mfma_tile"}[x] for x in kinds],
+                   "kernel_choice": args.batch_kernel},
         "breakdown": {"setup_s": rep.setup_s, "autotune_s": rep.autotune_s, "graph_run_s": rep.run_s},
         "roofline": roofline,
     }
@@ -444,6 +452,9 @@ def main():
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-kernel", default="auto",
+                    choices=["auto", "default", "time_blocked", "mfma_tile", "per_step"],
+                    help="c4: the batched kernel per class (auto: timed per class)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="c3: skip the adjoint rate (gradients/s on the 127^2, N = 4096 workload) added to the line")
     ap.add_argument("--no-prof", action="store_true",

@@ -324,15 +324,21 @@ int fp_adjoint_run(void* handle, const double* G0, const double* gN, double* gG0
  * work items of one persistent kernel per register class (problems grouped
  * by nodes per lane), each mode running its problem's whole time loop, so
  * problems of uneven size share the GPU without a barrier between them.
- * Two kernels: the per-step one (64 or 32 lanes per mode, each step sums
- * the state over the lanes) and the time-blocked one (one wave per mode;
+ * Three kernels: the per-step one (64 or 32 lanes per mode, each step sums
+ * the state over the lanes), the time-blocked one (one wave per mode;
  * the state advances over a block of L steps at a time, the lag of the
  * exact-weight window, before the block's steps are solved; needs every lag
- * <= 32 and <= 768 nodes per component). G0[i], GN[i]: dev [2][M_i]
- * (caller-owned, distinct). autotune != 0 times the candidates for every
+ * <= 32 and <= 768 nodes per component) and the 16-mode MFMA one (a
+ * workgroup per 16 modes of a problem: over blocks of 16 steps the state
+ * advance and its sums are FP64 matrix-core products over the modes; needs
+ * lags 16..33 and <= 576 nodes per component). G0[i], GN[i]: dev [2][M_i]
+ * (caller-owned, distinct). autotune: 1 times the candidates for every
  * class on a short run and keeps the fastest (cached for the process);
- * otherwise the time-blocked kernel where it applies, else 64 lanes per
- * mode. The caller's stream is
+ * 0 takes the 16-mode MFMA kernel where it applies, else the time-blocked
+ * one where it applies, else 64 lanes per mode; 2, 3 and 4 take the
+ * time-blocked, the 16-mode MFMA and the per-step (64 lanes) kernel where
+ * each applies (elsewhere the time-blocked one or 64 lanes per mode); other
+ * values are CQ_EINVAL. The caller's stream is
  * waited on before the solve and the call returns when every GN[i] is
  * written. Temporary device buffers are allocated and freed inside.
  * report (may be NULL) receives the classes and timings. */
@@ -343,7 +349,7 @@ typedef struct {
     int32_t class_npl64[8];   /* nodes per lane at 64 lanes of each class    */
     int32_t class_lanes[8];   /* lanes per mode chosen for each class        */
     int32_t class_problems[8];
-    int32_t class_blocked[8]; /* 1: the time-blocked kernel, 0: per-step     */
+    int32_t class_blocked[8]; /* 1 time-blocked, 2 16-mode MFMA, 0 per-step */
     double setup_s;           /* host set-up and forward transforms          */
     double autotune_s;        /* tile timing (0 when cached or disabled)     */
     double run_s;             /* the graph: time loops and inverse transforms */

@@ -7,9 +7,10 @@ from ._lib import (CQError, Grid, Info, Params, Solver, cq_fast_rule, cq_history
                    fp_solve,
                    lib, make_grid, make_params, params_of, prof_enable, prof_read, fp_solve_batched, fp_adjoint,
                    Adjoint,
-                   BatchReport, SOLVER_NODAL, SOLVER_MODAL)
+                   BatchReport, SOLVER_NODAL, SOLVER_MODAL, BATCH_DEFAULT, BATCH_AUTOTUNE, BATCH_TIME_BLOCKED,
+                   BATCH_MFMA_TILE, BATCH_PER_STEP)
 
 __all__ = ["CQError", "Grid", "Info", "Params", "Solver", "cq_fast_rule", "cq_history", "cq_history_noalloc",
            "cq_weights",
            "fp_solve", "lib", "make_grid", "make_params", "params_of", "prof_enable", "prof_read", "fp_solve_batched", "fp_adjoint", "Adjoint", "BatchReport", "SOLVER_NODAL",
-           "SOLVER_MODAL"]
+           "SOLVER_MODAL", "BATCH_DEFAULT", "BATCH_AUTOTUNE", "BATCH_TIME_BLOCKED", "BATCH_MFMA_TILE", "BATCH_PER_STEP"]

@@ -334,9 +334,14 @@ class Adjoint:
             pass
 
 
+BATCH_DEFAULT, BATCH_AUTOTUNE, BATCH_TIME_BLOCKED, BATCH_MFMA_TILE, BATCH_PER_STEP = 0, 1, 2, 3, 4
+
+
 def fp_solve_batched(grids, params, G0s, GNs=None, autotune=True):
     """Solve len(grids) independent fast problems in one batched launch.
-    Returns (list of GN tensors, BatchReport)."""
+    autotune: True (time the kernels per class), False (the default choice),
+    or one of the BATCH_* kernel choices. Returns (list of GN tensors,
+    BatchReport)."""
     import torch
     n = len(grids)
     if not (len(params) == n == len(G0s)):
@@ -348,5 +353,6 @@ def fp_solve_batched(grids, params, G0s, GNs=None, autotune=True):
     g0 = (C.c_void_p * n)(*[_dev(g, "G0").value for g in G0s])
     gn = (C.c_void_p * n)(*[_dev(g, "GN").value for g in GNs])
     rep = BatchReport()
-    _check(lib().fp_solve_batched(n, ga, pa, g0, gn, _stream(), 1 if autotune else 0, C.byref(rep)))
+    mode = int(autotune) if not isinstance(autotune, bool) else (1 if autotune else 0)
+    _check(lib().fp_solve_batched(n, ga, pa, g0, gn, _stream(), mode, C.byref(rep)))
     return GNs, rep

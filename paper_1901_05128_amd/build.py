@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcqfp.so")
-SOURCES = ["setup.cpp", "kernels.hip", "far.hip", "runtime.cpp", "batch.cpp", "noalloc.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "far.hip", "batch_mx.hip", "runtime.cpp", "batch.cpp", "noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -162,7 +162,7 @@ std::vector<double> batch_key(int count, const cq_grid* grids, const cq_params* 
     std::vector<double> k;
     k.reserve(size_t(count) * 24 + 2);
     k.push_back(double(count));
-    k.push_back(double(autotune != 0));
+    k.push_back(double(autotune));
     int dev = 0;
     (void)hipGetDevice(&dev);
     k.push_back(double(dev));
@@ -206,13 +206,82 @@ int npl_tmpl(int npl, int lpm) {
     return 16;
 }
 
+// The 16-mode MFMA kernel takes a problem with lags kMxMinLag..kMxMaxLag and
+// at most 2 kMxMaxNtw node tiles of 16 per component.
+bool mx_ok(const HostProblem& h) {
+    return h.L >= kMxMinLag && h.L <= kMxMaxLag && (h.np + 15) / 16 <= 2 * kMxMaxNtw;
+}
+// node tiles per wave of the MFMA kernel's templates (launch_modal_batch_mx)
+int mx_tmpl(int ntw) {
+    for (int t : {4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18})
+        if (ntw <= t) return t;
+    return 18;
+}
+
+// Tables of the 16-mode MFMA kernel for one problem (layout and meaning at
+// k_modal_batch_mx): fragments of the step-by-node table w_j r_j^{t+1}, the
+// node-by-step table r_j^{B-1-s}, r_j^B, the in-block Toeplitz table of
+// c_e = sum_j w_j r_j^e and the exact-window table of the earlier levels.
+void mx_tables(const HostProblem& h, double* out) {
+    const int nt = (h.np + 15) / 16, B = kMxB;
+    const int64_t t1 = int64_t(nt + 1) * 256;  // a component's W or R: nt tiles and a zero tile
+    double* W = out;
+    double* R = out + 2 * t1;
+    double* rB = out + 4 * t1;
+    double* Cf = rB + int64_t(32) * nt;
+    double* Df = Cf + 512;
+    for (int k = 0; k < 2; ++k) {
+        const std::vector<double>& r = h.rule[k].ratio;
+        const std::vector<double>& w = h.rule[k].coef;
+        // pw[j][e] = r_j^e, e <= B
+        std::vector<double> pw(size_t(nt) * 16 * (B + 1), 0.0);
+        for (int j = 0; j < h.np; ++j) {
+            double v = 1.0;
+            for (int e = 0; e <= B; ++e) {
+                pw[size_t(j) * (B + 1) + e] = v;
+                v *= r[size_t(j)];
+            }
+        }
+        auto P = [&](int j, int e) { return j < h.np ? pw[size_t(j) * (B + 1) + e] : 0.0; };
+        auto wj = [&](int j) { return j < h.np ? w[size_t(j)] : 0.0; };
+        for (int jt = 0; jt < nt; ++jt)
+            for (int i = 0; i < 4; ++i)
+                for (int L = 0; L < 64; ++L) {
+                    const size_t o = size_t(k) * size_t(t1) + (size_t(jt) * 4 + i) * 64 + L;
+                    const int t = L % 16, lk = L / 16;
+                    const int jw = 16 * jt + 4 * i + lk;
+                    W[o] = wj(jw) * P(jw, t + 1);
+                    const int jr = 16 * jt + t, s = 4 * i + lk;
+                    R[o] = P(jr, B - 1 - s);
+                }
+        for (int j = 0; j < 16 * nt; ++j) rB[size_t(k) * 16 * nt + j] = P(j, B);
+        long double c[B];
+        for (int e = 0; e < B; ++e) {
+            long double acc = 0.0L;
+            for (int j = 0; j < h.np; ++j) acc += (long double)w[size_t(j)] * (long double)P(j, e);
+            c[e] = acc;
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int L = 0; L < 64; ++L) {
+                const int t = L % 16, s = 4 * i + L / 16;
+                Cf[size_t(k) * 256 + i * 64 + L] = s <= t ? double(c[t - s]) : 0.0;
+            }
+        for (int i = 0; i < 8; ++i)
+            for (int L = 0; L < 64; ++L) {
+                const int t = L % 16, u = 4 * i + L / 16, lag = t + 1 + u;
+                Df[size_t(k) * 512 + i * 64 + L] = lag <= h.L - 1 ? h.d[k][size_t(lag)] : 0.0;
+            }
+    }
+}
+
 }  // namespace
 
 extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_params* params,
                                 const double* const* G0, double* const* GN, void* hip_stream,
                                 int32_t autotune, cq_batch_report* report) {
     clear_error();
-    if (count < 1 || !grids || !params || !G0 || !GN) return fail(CQ_EINVAL, "batched solve: bad arguments");
+    if (count < 1 || !grids || !params || !G0 || !GN || autotune < 0 || autotune > 4)
+        return fail(CQ_EINVAL, "batched solve: bad arguments");
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<HostProblem> hp(static_cast<size_t>(count));
     for (int i = 0; i < count; ++i) {
@@ -307,6 +376,8 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         I.a = h.a;
         I.d00 = h.d[0][0];
         I.d01 = h.d[1][0];
+        I.mx_off = -1;
+        I.nt = (h.np + 15) / 16;
         for (int r = 0; r < h.nz; ++r)
             for (int j = 0; j < h.ny; ++j)
                 for (int q = 0; q < h.nx; ++q)
@@ -361,15 +432,18 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
             return a.N * (a.np + a.L) > b.N * (b.np + b.L);
         });
     std::vector<int> lists;
-    std::vector<int64_t> cums;
-    // lpm: lanes per mode of the per-step kernel (64 or 32), or 0 for the
-    // time-blocked kernel (one wave per mode, needs lags <= 32 and <= 768 nodes)
+    std::vector<int64_t> cums, cumts;
+    // lpm: lanes per mode of the per-step kernel (64 or 32), 0 for the
+    // time-blocked kernel (one wave per mode, needs lags <= 32 and <= 768
+    // nodes), kLpmMx for the 16-mode MFMA kernel (mx_ok problems)
     struct Launch {
         int npl64, lpm, count, maxnp, minlag;
-        int64_t total;
+        int64_t total, tiles;
         size_t list_off, cum_off;
-        bool lag32;
+        bool lag32, canmx;
     };
+    constexpr int kLpmMx = 16;
+    constexpr bool kDefaultMx = true;  // the default (autotune 0) prefers the MFMA kernel
     std::vector<Launch> launches;
     for (auto& kv : cls) {
         Launch l{};
@@ -377,30 +451,73 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         l.list_off = lists.size();
         l.cum_off = cums.size();
         l.lag32 = true;
-        int64_t c = 0;
+        l.canmx = true;
+        int64_t c = 0, ct = 0;
         int maxnp = 0, minlag = 64;
         for (int i : kv.second) {
             lists.push_back(i);
             cums.push_back(c);
+            cumts.push_back(ct);
             c += hp[size_t(i)].M;
+            ct += (hp[size_t(i)].M + 15) / 16;
             l.lag32 = l.lag32 && hp[size_t(i)].L <= 32;
+            l.canmx = l.canmx && mx_ok(hp[size_t(i)]);
             maxnp = std::max(maxnp, hp[size_t(i)].np);
             minlag = std::min(minlag, hp[size_t(i)].L);
         }
         cums.push_back(c);
+        cumts.push_back(ct);
         l.total = c;
+        l.tiles = ct;
         l.maxnp = maxnp;
         l.npl64 = npl_tmpl(npl_for(maxnp, 64), 64);
         l.minlag = minlag;
-        // without timing: time-blocked where every lag allows blocks of >= 8 steps
-        l.lpm = (l.lag32 && minlag >= 8 && npl_for(maxnp, 32) <= 24) ? 0 : 64;
+        // without timing: the MFMA kernel where it applies, else time-blocked
+        // where every lag allows blocks of >= 8 steps; a forced kernel
+        // (autotune 2..4) where it applies
+        const bool cantb = l.lag32 && minlag >= 8 && npl_for(maxnp, 32) <= 24;
+        l.lpm = cantb ? 0 : 64;
+        if ((autotune == 3 || (autotune == 0 && kDefaultMx)) && l.canmx) l.lpm = kLpmMx;
+        if (autotune == 4) l.lpm = 64;
         launches.push_back(l);
     }
+    // tables of the MFMA kernel for the problems of the classes that may take it
+    double* d_mx = nullptr;
+    {
+        std::vector<int64_t> mxoff(size_t(count), -1);
+        int64_t mxsize = 0;
+        for (const Launch& l : launches) {
+            if (!l.canmx || !(l.lpm == kLpmMx || autotune == 1)) continue;
+            for (int c = 0; c < l.count; ++c) {
+                const int i = lists[l.list_off + size_t(c)];
+                mxoff[size_t(i)] = mxsize;
+                mxsize += mx_table_size((hp[size_t(i)].np + 15) / 16);
+            }
+        }
+        if (mxsize > 0) {
+            std::vector<double> mx(size_t(mxsize), 0.0);
+            const int nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+            std::vector<std::thread> th;
+            for (int t = 0; t < nt; ++t)
+                th.emplace_back([&, t] {
+                    for (int i = t; i < count; i += nt)
+                        if (mxoff[size_t(i)] >= 0) mx_tables(hp[size_t(i)], mx.data() + mxoff[size_t(i)]);
+                });
+            for (auto& x : th) x.join();
+            if ((rc = buf.alloc(&d_mx, mx.size()))) return rc;
+            BHIP(hipMemcpy(d_mx, mx.data(), mx.size() * sizeof(double), hipMemcpyHostToDevice));
+            for (int i = 0; i < count; ++i) inst[size_t(i)].mx_off = mxoff[size_t(i)];
+            BHIP(hipMemcpy(d_inst, inst.data(), inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
+        }
+    }
     int* d_list;
-    int64_t* d_cum;
-    if ((rc = buf.alloc(&d_list, lists.size())) || (rc = buf.alloc(&d_cum, cums.size()))) return rc;
+    int64_t *d_cum, *d_cumt;
+    if ((rc = buf.alloc(&d_list, lists.size())) || (rc = buf.alloc(&d_cum, cums.size())) ||
+        (rc = buf.alloc(&d_cumt, cumts.size())))
+        return rc;
     BHIP(hipMemcpy(d_list, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice));
     BHIP(hipMemcpy(d_cum, cums.data(), cums.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    BHIP(hipMemcpy(d_cumt, cumts.data(), cumts.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     std::unique_ptr<BatchCache> cache(new BatchCache());
     BHIP(hipStreamCreateWithFlags(&cache->st, hipStreamNonBlocking));
     hipStream_t st = cache->st;
@@ -424,7 +541,17 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         a.lam = d_lam;
         a.g0 = d_g0;
         a.gN = d_gN;
+        a.cumt = d_cumt + l.cum_off;
+        a.tiles = l.tiles;
+        a.mx = d_mx;
         return a;
+    };
+    // one class's kernel
+    auto launch_class = [&](const BatchArgs& a, const Launch& l, int lpm, int npl, hipStream_t s) {
+        if (lpm == kLpmMx)
+            launch_modal_batch_mx(a, mx_tmpl(((l.maxnp + 15) / 16 + 1) / 2), s);
+        else
+            launch_modal_batch(a, npl, lpm, s);
     };
     // forward transforms of every G0 into the concatenated coefficient array
     auto transforms = [&](bool forward) {
@@ -453,14 +580,16 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         return lpm == 0 ? npl_for(l.maxnp, 32) : npl_tmpl(npl_for(l.npl64 * 64, lpm), lpm);
     };
     // autotune per class: the time-blocked kernel, 64 and 32 lanes per mode
-    // (each where it applies), timed on the class's problems truncated to a
-    // few steps
+    // and the 16-mode MFMA kernel (each where it applies), timed on the
+    // class's problems truncated to a few steps
     double tune_s = 0.0;
     for (Launch& l : launches) {
+        if (autotune != 1) continue;
         const int npl32 = npl_for(l.npl64 * 64, 32);
         const bool can32 = l.lag32 && npl32 <= 16;
         const bool cantb = l.lag32 && npl_for(l.maxnp, 32) <= 24;
-        const std::pair<int, int> key{l.npl64 * 2048 + l.maxnp, l.lag32 ? l.minlag : 64};
+        const std::pair<int, int> key{(l.npl64 * 2048 + l.maxnp) * 2 + (l.canmx ? 1 : 0),
+                                      l.lag32 ? l.minlag : 64};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(key);
@@ -469,7 +598,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
                 continue;
             }
         }
-        if (!autotune || (!can32 && !cantb)) continue;
+        if (!can32 && !cantb && !l.canmx) continue;
         const auto ta = std::chrono::steady_clock::now();
         // short copies of the class's problems (at most 256 steps: long enough
         // for the time-blocked kernel to pass its first blocks)
@@ -488,12 +617,12 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
         hipEvent_t e0, e1;
         BHIP(hipEventCreate(&e0));
         BHIP(hipEventCreate(&e1));
-        for (int lpm : {0, 64, 32}) {
-            if ((lpm == 0 && !cantb) || (lpm == 32 && !can32)) continue;
+        for (int lpm : {0, 64, 32, kLpmMx}) {
+            if ((lpm == 0 && !cantb) || (lpm == 32 && !can32) || (lpm == kLpmMx && !l.canmx)) continue;
             const int npl = npl_of(l, lpm);
-            launch_modal_batch(a, npl, lpm, st);  // warm
+            launch_class(a, l, lpm, npl, st);  // warm
             BHIP(hipEventRecord(e0, st));
-            launch_modal_batch(a, npl, lpm, st);
+            launch_class(a, l, lpm, npl, st);
             BHIP(hipEventRecord(e1, st));
             BHIP(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -530,8 +659,8 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     for (size_t c = 0; c < launches.size() && ce == hipSuccess; ++c) {
         ce = hipStreamWaitEvent(cache->branch[c], evs[0], 0);
         if (ce != hipSuccess) break;
-        launch_modal_batch(make_args(launches[c]), npl_of(launches[c], launches[c].lpm), launches[c].lpm,
-                           cache->branch[c]);
+        launch_class(make_args(launches[c]), launches[c], launches[c].lpm, npl_of(launches[c], launches[c].lpm),
+                     cache->branch[c]);
         ce = hipEventRecord(evs[c + 1], cache->branch[c]);
         if (ce == hipSuccess) ce = hipStreamWaitEvent(st, evs[c + 1], 0);
     }
@@ -556,8 +685,9 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     r.classes = int32_t(std::min<size_t>(launches.size(), 8));
     for (int c = 0; c < r.classes; ++c) {
         r.class_npl64[c] = launches[size_t(c)].npl64;
-        r.class_lanes[c] = launches[size_t(c)].lpm ? launches[size_t(c)].lpm : 64;
-        r.class_blocked[c] = launches[size_t(c)].lpm == 0 ? 1 : 0;
+        const int lpm = launches[size_t(c)].lpm;
+        r.class_lanes[c] = (lpm == 0 || lpm == kLpmMx) ? 64 : lpm;
+        r.class_blocked[c] = lpm == 0 ? 1 : lpm == kLpmMx ? 2 : 0;
         r.class_problems[c] = launches[size_t(c)].count;
     }
     r.setup_s = std::chrono::duration<double>(t1 - t0).count();

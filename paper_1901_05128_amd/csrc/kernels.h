@@ -239,6 +239,8 @@ struct BatchInst {
     int64_t d_off;        // weights [2][dstride] at d_off
     int64_t dstride;
     double inv_tau, c, a, d00, d01;
+    int64_t mx_off;       // tables of the 16-mode MFMA kernel at mx_off (-1: none)
+    int nt, pad2;         // node tiles of 16 per component in those tables
 };
 
 struct BatchArgs {
@@ -249,10 +251,21 @@ struct BatchArgs {
     int64_t total;        // their modes
     const double *ratio, *coef, *d, *lam, *g0;
     double* gN;
+    // 16-mode MFMA kernel: cumulative 16-mode tile counts over list
+    // (cumt[0] = 0), their total, and the tables (k_modal_batch_mx)
+    const int64_t* cumt;
+    int64_t tiles;
+    const double* mx;
 };
 
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
 void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
+// 16-mode MFMA kernel: steps per block, lags it takes, node tiles per wave
+constexpr int kMxB = 16, kMxMinLag = 16, kMxMaxLag = 33, kMxMaxNtw = 18;
+// doubles of one problem's tables with nt node tiles per component
+inline int64_t mx_table_size(int nt) { return int64_t(nt + 1) * 4 * 256 + int64_t(nt) * 32 + 2 * 256 + 2 * 512; }
+// ntw: one of 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18 (others take 18)
+void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st);
 bool modal_fast_blocked(int L, int np);  // launch_modal_fast takes the time-blocked kernel
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);
 void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st);

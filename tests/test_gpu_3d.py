@@ -87,8 +87,11 @@ def test_3d_rejects_bad_grids():
             cq.Solver(g, p, G0)
 
 
-def test_3d_in_a_batch():
-    """A 3D problem solved by fp_solve_batched next to 1D and 2D ones."""
+@pytest.mark.parametrize("kernel", [cq.BATCH_DEFAULT, cq.BATCH_TIME_BLOCKED])
+def test_3d_in_a_batch(kernel):
+    """A 3D problem solved by fp_solve_batched next to 1D and 2D ones, by the
+    default choice (the 16-mode MFMA kernel for these problems) and by the
+    time-blocked kernel."""
     probs = [(3, 15, 11, 7, 0.3, 0.7, 0.4, 300), (1, 127, 1, 1, 0.6, 0.2, 0.8, 500),
              (2, 31, 29, 1, 0.45, 0.55, 0.3, 400)]
     grids, params, g0s, refs = [], [], [], []
@@ -99,7 +102,8 @@ def test_3d_in_a_batch():
         params.append(cq.make_params(a1, a2, m, 1.0, N, 2, 1, np_=24))
         g0s.append(dev(G0))
         refs.append(modal.reference(dim, nx, ny, a1, a2, m, 1.0, N, G0, 2, 1, np_=24, ns=30, nz=nz))
-    outs, _rep = cq.fp_solve_batched(grids, params, g0s, autotune=False)
+    outs, rep = cq.fp_solve_batched(grids, params, g0s, autotune=kernel)
+    assert all(x == (2 if kernel == cq.BATCH_DEFAULT else 1) for x in list(rep.class_blocked)[:rep.classes])
     for (dim, nx, ny, nz, *_r), out, ref in zip(probs, outs, refs):
         e = rel(out.cpu().numpy(), ref)
         print(f"  batch {dim}d {nx}x{ny}x{nz}: rel_l2 vs oracle fast {e:.3e}", flush=True)

@@ -70,22 +70,29 @@ def test_batched_matches_oracle_mixed():
 
 
 def test_batched_equals_single_solves_and_tiles_agree():
+    """Autotuned, default and time-blocked batches against single modal
+    solves: the time-blocked kernel runs the single solve's arithmetic
+    (1e-13); the kernel choices of the other two may sum in another order
+    (the fast scheme's 1e-11)."""
     probs = _mixed(10, 8)
     a, g0s, rep_a = _run(probs, autotune=True, seed=50)
     b, _, rep_b = _run(probs, autotune=False, seed=50)
-    for (dim, nx, ny, a1, a2, m, T, N, scheme, np_), oa, ob, g0 in zip(probs, a, b, g0s):
+    c, _, rep_c = _run(probs, autotune=cq.BATCH_TIME_BLOCKED, seed=50)
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, np_), oa, ob, oc, g0 in zip(probs, a, b, c, g0s):
         single = cq.fp_solve(cq.make_grid(dim, nx, ny),
                              cq.make_params(a1, a2, m, T, N, scheme, 1, np_=np_, solver=cq.SOLVER_MODAL),
                              torch.tensor(g0, device="cuda")).cpu().numpy()
-        assert rel(oa, single) <= 1e-13
-        assert rel(ob, single) <= 1e-13
+        assert rel(oa, single) <= 1e-11
+        assert rel(ob, single) <= 1e-11
+        assert rel(oc, single) <= 1e-13
     assert all(x in (32, 64) for x in list(rep_a.class_lanes)[:rep_a.classes])
-    assert all(x == 64 for x in list(rep_b.class_lanes)[:rep_b.classes]) or rep_b.autotune_s == 0.0
+    assert all(x in (1, 2) for x in list(rep_b.class_blocked)[:rep_b.classes])
+    assert all(x == 1 for x in list(rep_c.class_blocked)[:rep_c.classes])
 
 
 @pytest.mark.parametrize("np_", [None, 200, 380, 500, 700])
 def test_time_blocked_kernel(np_):
-    """BDF2 problems (lag 30) without autotuning take the time-blocked kernel:
+    """BDF2 problems (lag 30) with the time-blocked kernel forced:
     blocks of 30 steps, a ragged last block, runs shorter than one block or
     one half-block, and node counts up to 768 (every register class of the
     kernel), against the oracle and against single modal solves."""
@@ -96,7 +103,7 @@ def test_time_blocked_kernel(np_):
         a1, a2 = (float(v) for v in rng.uniform(0.1, 0.9, size=2))
         m = float(rng.uniform(0.55, 0.95))
         probs.append((dim, nx, ny, a1, a2, m, 1.0, N, 2, np_ or max(8, int(math.ceil(3 * math.sqrt(N))))))
-    outs, g0s, rep = _run(probs, autotune=False, seed=300)
+    outs, g0s, rep = _run(probs, autotune=cq.BATCH_TIME_BLOCKED, seed=300)
     print(f"batch classes={rep.classes} blocked={list(rep.class_blocked)[:rep.classes]}", flush=True)
     assert all(x == 1 for x in list(rep.class_blocked)[:rep.classes])
     for (dim, nx, ny, a1, a2, m, T, N, scheme, npn), out, g0 in zip(probs, outs, g0s):
@@ -110,6 +117,50 @@ def test_time_blocked_kernel(np_):
         assert e2 <= 1e-11
 
 
+@pytest.mark.parametrize("np_", [None, 100, 200, 380, 560])
+def test_mfma_tile_kernel(np_):
+    """The 16-mode MFMA kernel (forced): BDF2 problems (lag 30) and BE
+    problems (exact window of 2 np + 2 <= 32 lags) in blocks of 16 steps,
+    runs shorter than one block, a ragged last block, ragged 16-mode tiles
+    (31 and 63 modes in 1D, 99 in 2D) and node counts up to 576 per
+    component (every tile count of the kernel's templates up to 18 per
+    wave), against the oracle's fast scheme and against single modal solves
+    (the same rule; the kernel sums in another order)."""
+    rng = np.random.default_rng(29)
+    probs = []
+    for N, scheme in ((5, 2), (16, 2), (17, 1), (31, 2), (33, 1), (64, 2), (90, 1), (151, 2)):
+        dim, nx, ny = (1, int(rng.choice([31, 63])), 1) if N % 2 else (2, 9, 11)
+        a1, a2 = (float(v) for v in rng.uniform(0.1, 0.9, size=2))
+        m = float(rng.uniform(0.55, 0.95))
+        npn = np_ or max(8, int(math.ceil(3 * math.sqrt(N))))
+        probs.append((dim, nx, ny, a1, a2, m, 1.0, N, scheme, npn))
+    outs, g0s, rep = _run(probs, autotune=cq.BATCH_MFMA_TILE, seed=400)
+    print(f"batch classes={rep.classes} blocked={list(rep.class_blocked)[:rep.classes]}", flush=True)
+    assert all(x == 2 for x in list(rep.class_blocked)[:rep.classes])
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, npn), out, g0 in zip(probs, outs, g0s):
+        single = cq.fp_solve(cq.make_grid(dim, nx, ny),
+                             cq.make_params(a1, a2, m, T, N, scheme, 1, np_=npn, solver=cq.SOLVER_MODAL),
+                             torch.tensor(g0, device="cuda")).cpu().numpy()
+        ref = modal.reference(dim, nx, ny, a1, a2, m, T, N, g0, scheme, 1, np_=npn, np1=16, ns=30)
+        e1, e2 = rel(out, single), rel(out, ref)
+        print(f"  {dim}d {nx}x{ny} N={N} scheme={scheme} np={npn}: vs single {e1:.2e} vs oracle {e2:.2e}",
+              flush=True)
+        assert e1 <= 1e-11
+        assert e2 <= 1e-11
+
+
+def test_mfma_tile_kernel_falls_back_where_it_does_not_apply():
+    """Forcing the MFMA kernel leaves a class it cannot take (700 nodes per
+    component) on the time-blocked kernel, with the same results as that
+    kernel forced."""
+    probs = [(1, 31, 1, 0.3, 0.7, 0.8, 1.0, 40, 2, 700), (2, 9, 11, 0.6, 0.2, 0.7, 1.0, 37, 2, 700)]
+    a, _, rep_a = _run(probs, autotune=cq.BATCH_MFMA_TILE, seed=500)
+    b, _, rep_b = _run(probs, autotune=cq.BATCH_TIME_BLOCKED, seed=500)
+    assert all(x == 1 for x in list(rep_a.class_blocked)[:rep_a.classes])
+    for oa, ob in zip(a, b):
+        assert np.array_equal(oa, ob)
+
+
 def test_batched_rejects_direct_method_and_bad_lag():
     g = [cq.make_grid(1, 15)]
     G0 = [torch.zeros((2, 15), dtype=torch.float64, device="cuda")]
@@ -121,7 +172,8 @@ def test_batched_rejects_direct_method_and_bad_lag():
 
 def test_batched_reduced_c4_mix():
     """The seeded 256-instance mix of the batched workload, 24 of them with N
-    scaled by 1/32 and grids capped, against single modal solves."""
+    scaled by 1/32 and grids capped, autotuned, against single modal solves
+    (the fast scheme's 1e-11: the kernel chosen may sum in another order)."""
     inst = wl.batched_instances(24, seed=4, scale=1 / 32)
     probs = []
     for p in inst:
@@ -134,4 +186,6 @@ def test_batched_reduced_c4_mix():
         single = cq.fp_solve(cq.make_grid(dim, nx, ny),
                              cq.make_params(a1, a2, m, T, N, scheme, 1, np_=np_, solver=cq.SOLVER_MODAL),
                              torch.tensor(g0, device="cuda")).cpu().numpy()
-        assert rel(out, single) <= 1e-13
+        e = rel(out, single)
+        print(f"  {dim}d {nx}x{ny} N={N} np={np_}: vs single {e:.2e}", flush=True)
+        assert e <= 1e-11

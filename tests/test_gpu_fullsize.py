@@ -145,13 +145,14 @@ def test_table5_problem_full_size_sampled_modes(data, method):
     _check_case(1, nx, 1, 0.3, 0.8, 0.0, N, G0, 2, method, C2_MODES, T=10.0)
 
 
-def test_configuration4_full_size_sampled_modes():
+@pytest.mark.parametrize("kernel", ["time_blocked", "mfma_tile"])
+def test_configuration4_full_size_sampled_modes(kernel):
     """Three problems of the seeded 256-problem batch at full size (the
     largest 2D one, 255^2 with N = 2^15; the largest 1D one, 4095 nodes with
     N = 2^15; and the first problem), solved together by fp_solve_batched
-    without autotuning, which takes the time-blocked kernel for these BDF2
-    problems; sampled sine modes against the oracle's per-mode recurrence
-    with the same node counts (np = ceil(3 sqrt N), 16 + np in all, N_s = 30)."""
+    with the time-blocked or the 16-mode MFMA kernel forced; sampled sine
+    modes against the oracle's per-mode recurrence with the same node counts
+    (np = ceil(3 sqrt N), 16 + np in all, N_s = 30)."""
     import math
     inst = wl.batched_instances(256, seed=4)
     pick = [23, 44, 0]
@@ -164,8 +165,9 @@ def test_configuration4_full_size_sampled_modes():
         G0 = wl.g0_intervals(p.nx, 1000 + i) if p.dim == 1 else wl.g0_rectangle(p.nx, p.ny, 1000 + i)
         g0s.append(torch.tensor(G0, dtype=torch.float64, device="cuda"))
         probs.append((p, npn, G0))
-    outs, rep = cq.fp_solve_batched(grids, params, g0s, autotune=False)
-    assert all(x == 1 for x in list(rep.class_blocked)[:rep.classes])
+    force, want = (cq.BATCH_TIME_BLOCKED, 1) if kernel == "time_blocked" else (cq.BATCH_MFMA_TILE, 2)
+    outs, rep = cq.fp_solve_batched(grids, params, g0s, autotune=force)
+    assert all(x == want for x in list(rep.class_blocked)[:rep.classes])
     for (p, npn, G0), out in zip(probs, outs):
         print(f"c4 full size: {p.name} {p.dim}d {p.nx}x{p.ny} N={p.N} np={npn}", flush=True)
         coef = modal.to_modes(out.cpu().numpy(), p.dim, p.nx, p.ny)
