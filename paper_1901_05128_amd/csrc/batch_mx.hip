@@ -4,6 +4,8 @@
 // (4.1)-(4.3) and (4.7)-(4.8)).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     __syncthreads();
 
     for (int64_t n0 = 0; n0 < N; n0 += B) {
-        const int bt = (N - n0 < B) ? int(N - n0) : B;
+        const int bt = (N - n0 < B) ? int(N - n0) : B;  // steps of this block
         // ---- phase A: the state advanced over this block (its inputs are
         // levels <= n0) and its part of the next block's fast sums; this
         // block's in-block Toeplitz term, window of the earlier levels and
@@ -247,28 +249,34 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
                           (fT[2 * ck][b][cp] + fT[2 * ck + 1][b][cp]);
             }
             const double* dl = dtab[ck] + ce;  // dl[j]: weight of lag j + e
+            // a full block without per-step checks, the last (ragged) one with
+            auto steps = [&](auto full_t) {
+                constexpr bool FULL = decltype(full_t)::value;
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (b < bt) {
-                    // the step's sum sits in the lane of its parity; quad_perm
-                    // [0,0,2,2] / [1,1,3,3] give it to both lanes of the component
-                    const double Sk = (b & 1) ? dpp_move<0xF5, 0xF>(pend[b >> 1]) : dpp_move<0xA0, 0xF>(pend[b >> 1]);
-                    const double So = dpp_move<0x4E, 0xF>(Sk);  // the other component's
-                    const double Ek = fma(e1, Pk, e2 * Qk);
-                    const double gk = fma(s_oth, So, fma(s_own, Sk, Ek));
-                    const double go = dpp_move<0x4E, 0xF>(gk);
-                    if (ce == 0) ring[(n0 + 1 + b) & 63][ck][cp] = gk;
-                    Qk = Pk;
-                    Pk = fma(i_oth, go, i_own * gk);
-                    glast = gk;
-                    // push into the later steps b' = 2m + e > b, lag b' - b
+                for (int b = 0; b < B; ++b) {
+                    if (FULL || b < bt) {
+                        // the step's sum sits in the lane of its parity;
+                        // quad_perm [0,0,2,2] / [1,1,3,3] give it to both lanes
+                        // of the component
+                        const double Sk = (b & 1) ? dpp_zero<0xF5>(pend[b >> 1]) : dpp_zero<0xA0>(pend[b >> 1]);
+                        const double So = dpp_zero<0x4E>(Sk);  // the other component's
+                        const double Ek = fma(e1, Pk, e2 * Qk);
+                        const double gk = fma(s_oth, So, fma(s_own, Sk, Ek));
+                        const double go = dpp_zero<0x4E>(gk);
+                        if (ce == 0) ring[(n0 + 1 + b) & 63][ck][cp] = gk;
+                        Qk = Pk;
+                        Pk = fma(i_oth, go, i_own * gk);
+                        glast = gk;
+                        // push into the later steps b' = 2m + e > b, lag b' - b
 #pragma unroll
-                    for (int m = (b + 1) / 2; m < B / 2; ++m) {
-                        const int j = 2 * m - b;  // lag j + e <= B - 1
-                        pend[m] = fma(dl[j], gk, pend[m]);
+                        for (int m = (b + 1) / 2; m < B / 2; ++m) {
+                            const int j = 2 * m - b;  // lag j + e <= B - 1
+                            pend[m] = fma(dl[j], gk, pend[m]);
+                        }
                     }
                 }
-            }
+            };
+            steps(std::false_type{});
             cst[4][lane] = Pk;
             cst[5][lane] = Qk;
             cst[6][lane] = glast;
