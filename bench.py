@@ -357,7 +357,7 @@ def bench_adjoint(args, emit=True):
     oneshot_s = time.perf_counter() - ts
     M = nx * ny
     # kernel timing: one more gradient outside the timed region
-    kinds = ["hist_fast", "far_toeplitz", "reduce_far", "modal_fast", "dst_gemm", "transpose", "beta_spec"]
+    kinds = ["hist_fast", "far_toeplitz", "reduce_far", "modal_fast", "dst_gemm", "transpose", "beta_spec", "batched"]
     ktime = {}
     roofline = None
     if not args.no_prof:
@@ -377,7 +377,15 @@ def bench_adjoint(args, emit=True):
             bt = min(Bt, N - n + 1)
             b_h += twoM * 8 * (2 * npn + 2 * bt)
             f_h += twoM * 4 * npn * bt
-        work["hist_fast"] = (2 * b_h, 2 * f_h)          # forward and adjoint sweeps
+        # the forward on the 16-mode MFMA kernel (forward_kernel 2) leaves the
+        # state pass and the window steps to the adjoint sweep
+        mxf = h.info().forward_kernel == 2
+        sweeps = 1 if mxf else 2
+        work["hist_fast"] = (sweeps * b_h, sweeps * f_h)  # forward (streamed) and adjoint sweeps
+        if mxf:
+            # state update and weighting (4 flops per node), window (2 per lag
+            # below L); every level and history sum written
+            work["batched"] = (2 * N * twoM * 8, N * twoM * (4 * npn + 2 * (L - 1)))
         # the d/dalpha contraction's near field: blocks of Bk = 256 steps, each
         # step n of block i summing dw_{n-l} g^l over the levels l of blocks
         # i-1 and i up to n (2 flops per product, mode and component); a
@@ -396,9 +404,10 @@ def bench_adjoint(args, emit=True):
         nb, P = N // Bk, 2 * Bk
         work["beta_spec"] = (twoM * 2 * N * 8, twoM * (nb * 5 * P * 9 + (nb - 2) * (nb - 1) // 2 * (Bk + 1) * 8))
         work["transpose"] = (2 * 2 * N * twoM * 8, 0)
-        # window steps, both sweeps: 2 flops per lag below L, Sf read, level and
-        # S (forward) or mu (adjoint) written
-        work["modal_fast"] = (2 * N * twoM * 8 * 3, 2 * N * twoM * 2 * (L - 1))
+        # window steps, both sweeps (the adjoint's alone with the MFMA
+        # forward): 2 flops per lag below L, Sf read, level and S (forward) or
+        # mu (adjoint) written
+        work["modal_fast"] = (sweeps * N * twoM * 8 * 3, sweeps * N * twoM * 2 * (L - 1))
         dom = max(ktime, key=lambda k: ktime[k][1])
         if dom in work:
             n_l, ms = ktime[dom]
@@ -407,7 +416,8 @@ def bench_adjoint(args, emit=True):
             ff = f / n_l / avg / 1e12 / FP64_PEAK_TFLOPS
             bf = b / n_l / avg / 1e9 / HBM_PEAK_GBS
             if ff >= bf:
-                roofline = {"bound": "mfma" if dom == "far_toeplitz" else "alu", "achieved": ff * FP64_PEAK_TFLOPS,
+                roofline = {"bound": "mfma" if dom in ("far_toeplitz", "batched") else "alu",
+                            "achieved": ff * FP64_PEAK_TFLOPS,
                             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ff, "hbm_frac": bf}
             else:
                 roofline = {"bound": "hbm", "achieved": bf * HBM_PEAK_GBS, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -422,7 +432,8 @@ def bench_adjoint(args, emit=True):
         "data": "synthetic (seeded rectangle indicators)",
         "config": {"workload": "c5: adjoint, 2D 127x127 nodes, BDF2 fast (np 16+192, ns 30), N=4096, "
                                "alpha=(0.2,0.6), m=0.55, target from alpha=(0.25,0.55)",
-                   "dof": 2 * M, "N": N},
+                   "dof": 2 * M, "N": N,
+                   "forward": "16-mode MFMA kernel" if h.info().forward_kernel == 2 else "streamed state"},
         "grads": list(grads),
         "breakdown": {"handle_setup_s": setup_s, "one_shot_fp_adjoint_s": oneshot_s,
                       "note": "value times fp_adjoint_run on a handle made once (fixed grid and parameters)"},

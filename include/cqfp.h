@@ -293,12 +293,22 @@ int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_strea
  *    (fast method only; CQ_EINVAL otherwise).
  *  segment_steps, slots: checkpointed form's segment length (rounded up to
  *    whole chunks) and number of saved states; 0 chooses the pair with the
- *    fewest recomputed forward steps that fits the budget. */
+ *    fewest recomputed forward steps that fits the budget.
+ *  forward_kernel: the kept-whole fast forward. 0 automatic (2 where it
+ *    applies), 1 the streamed state (the kernels of fp_step: the gradient
+ *    then equals the checkpointed form's as stated above), 2 the batched
+ *    16-mode MFMA kernel run over all N steps with the trajectory written as
+ *    it goes (lags 16..32, <= 512 nodes per component; elsewhere 1): the same
+ *    scheme summed in another order: dl/dG0 equals 1's bit for bit (the
+ *    adjoint sweep does not read the forward), G^N and dl/dm agree to
+ *    1e-13 and 1e-12 relative, dl/dalpha_k to 1e-11 (their contraction
+ *    cancels across modes). Other values: CQ_EINVAL. */
 typedef struct {
     size_t max_device_bytes;
     int32_t mode;
     int32_t segment_steps;
     int32_t slots;
+    int32_t forward_kernel;
 } cq_adjoint_opts;
 
 /* What a gradient handle chose. */
@@ -309,6 +319,7 @@ typedef struct {
     int32_t slots;          /* saved forward states (0 when kept whole)     */
     int64_t forward_steps;  /* forward steps per gradient (N when kept whole) */
     size_t device_bytes;    /* device memory held by the handle             */
+    int32_t forward_kernel; /* 1 streamed state, 2 16-mode MFMA (see opts)  */
 } cq_adjoint_info;
 
 /* fp_adjoint_create with a memory form (opts NULL: automatic). */

@@ -57,12 +57,12 @@ class Info(C.Structure):
 
 class AdjointOpts(C.Structure):
     _fields_ = [("max_device_bytes", C.c_size_t), ("mode", C.c_int32), ("segment_steps", C.c_int32),
-                ("slots", C.c_int32)]
+                ("slots", C.c_int32), ("forward_kernel", C.c_int32)]
 
 
 class AdjointInfo(C.Structure):
     _fields_ = [("mode", C.c_int32), ("segment_steps", C.c_int64), ("segments", C.c_int32), ("slots", C.c_int32),
-                ("forward_steps", C.c_int64), ("device_bytes", C.c_size_t)]
+                ("forward_steps", C.c_int64), ("device_bytes", C.c_size_t), ("forward_kernel", C.c_int32)]
 
 
 class BatchReport(C.Structure):
@@ -293,12 +293,13 @@ class Adjoint:
     then run(G0, gN) per gradient."""
 
     def __init__(self, grid: Grid, params: Params, mode: int = 0, max_device_bytes: int = 0,
-                 segment_steps: int = 0, slots: int = 0):
+                 segment_steps: int = 0, slots: int = 0, forward_kernel: int = 0):
         """mode 0 automatic, 1 keep the trajectory whole, 2 checkpointed
-        (fast method); see cq_adjoint_opts."""
+        (fast method); forward_kernel 0 automatic, 1 streamed state, 2 the
+        16-mode MFMA kernel; see cq_adjoint_opts."""
         self._h = C.c_void_p()
         self.M = grid_nodes(grid)
-        opts = AdjointOpts(max_device_bytes, mode, segment_steps, slots)
+        opts = AdjointOpts(max_device_bytes, mode, segment_steps, slots, forward_kernel)
         _check(lib().fp_adjoint_create_opts(C.byref(grid), C.byref(params), C.byref(opts), _stream(),
                                             C.byref(self._h)))
 

@@ -206,72 +206,13 @@ int npl_tmpl(int npl, int lpm) {
     return 16;
 }
 
-// The 16-mode MFMA kernel takes a problem with lags kMxMinLag..kMxMaxLag and
-// at most 2 kMxMaxNtw node tiles of 16 per component.
-bool mx_ok(const HostProblem& h) {
-    return h.L >= kMxMinLag && h.L <= kMxMaxLag && (h.np + 15) / 16 <= 2 * kMxMaxNtw;
-}
-// node tiles per wave of the MFMA kernel's templates (launch_modal_batch_mx)
-int mx_tmpl(int ntw) {
-    for (int t : {4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18})
-        if (ntw <= t) return t;
-    return 18;
-}
+bool mx_ok(const HostProblem& h) { return mx_applies(h.L, h.np); }
 
-// Tables of the 16-mode MFMA kernel for one problem (layout and meaning at
-// k_modal_batch_mx): fragments of the step-by-node table w_j r_j^{t+1}, the
-// node-by-step table r_j^{B-1-s}, r_j^B, the in-block Toeplitz table of
-// c_e = sum_j w_j r_j^e and the exact-window table of the earlier levels.
 void mx_tables(const HostProblem& h, double* out) {
-    const int nt = (h.np + 15) / 16, B = kMxB;
-    const int64_t t1 = int64_t(nt + 1) * 256;  // a component's W or R: nt tiles and a zero tile
-    double* W = out;
-    double* R = out + 2 * t1;
-    double* rB = out + 4 * t1;
-    double* Cf = rB + int64_t(32) * nt;
-    double* Df = Cf + 512;
-    for (int k = 0; k < 2; ++k) {
-        const std::vector<double>& r = h.rule[k].ratio;
-        const std::vector<double>& w = h.rule[k].coef;
-        // pw[j][e] = r_j^e, e <= B
-        std::vector<double> pw(size_t(nt) * 16 * (B + 1), 0.0);
-        for (int j = 0; j < h.np; ++j) {
-            double v = 1.0;
-            for (int e = 0; e <= B; ++e) {
-                pw[size_t(j) * (B + 1) + e] = v;
-                v *= r[size_t(j)];
-            }
-        }
-        auto P = [&](int j, int e) { return j < h.np ? pw[size_t(j) * (B + 1) + e] : 0.0; };
-        auto wj = [&](int j) { return j < h.np ? w[size_t(j)] : 0.0; };
-        for (int jt = 0; jt < nt; ++jt)
-            for (int i = 0; i < 4; ++i)
-                for (int L = 0; L < 64; ++L) {
-                    const size_t o = size_t(k) * size_t(t1) + (size_t(jt) * 4 + i) * 64 + L;
-                    const int t = L % 16, lk = L / 16;
-                    const int jw = 16 * jt + 4 * i + lk;
-                    W[o] = wj(jw) * P(jw, t + 1);
-                    const int jr = 16 * jt + t, s = 4 * i + lk;
-                    R[o] = P(jr, B - 1 - s);
-                }
-        for (int j = 0; j < 16 * nt; ++j) rB[size_t(k) * 16 * nt + j] = P(j, B);
-        long double c[B];
-        for (int e = 0; e < B; ++e) {
-            long double acc = 0.0L;
-            for (int j = 0; j < h.np; ++j) acc += (long double)w[size_t(j)] * (long double)P(j, e);
-            c[e] = acc;
-        }
-        for (int i = 0; i < 4; ++i)
-            for (int L = 0; L < 64; ++L) {
-                const int t = L % 16, s = 4 * i + L / 16;
-                Cf[size_t(k) * 256 + i * 64 + L] = s <= t ? double(c[t - s]) : 0.0;
-            }
-        for (int i = 0; i < 8; ++i)
-            for (int L = 0; L < 64; ++L) {
-                const int t = L % 16, u = 4 * i + L / 16, lag = t + 1 + u;
-                Df[size_t(k) * 512 + i * 64 + L] = lag <= h.L - 1 ? h.d[k][size_t(lag)] : 0.0;
-            }
-    }
+    const double* ratio[2] = {h.rule[0].ratio.data(), h.rule[1].ratio.data()};
+    const double* coef[2] = {h.rule[0].coef.data(), h.rule[1].coef.data()};
+    const double* d[2] = {h.d[0].data(), h.d[1].data()};
+    build_mx_tables(h.np, h.L, ratio, coef, d, out);
 }
 
 }  // namespace
@@ -549,7 +490,7 @@ extern "C" int fp_solve_batched(int32_t count, const cq_grid* grids, const cq_pa
     // one class's kernel
     auto launch_class = [&](const BatchArgs& a, const Launch& l, int lpm, int npl, hipStream_t s) {
         if (lpm == kLpmMx)
-            launch_modal_batch_mx(a, mx_tmpl(((l.maxnp + 15) / 16 + 1) / 2), s);
+            launch_modal_batch_mx(a, mx_template(((l.maxnp + 15) / 16 + 1) / 2), s);
         else
             launch_modal_batch(a, npl, lpm, s);
     };

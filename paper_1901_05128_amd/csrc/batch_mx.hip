@@ -4,8 +4,6 @@
 // (4.1)-(4.3) and (4.7)-(4.8)).
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "device_util.h"
 #include "kernels.h"
 
@@ -49,11 +47,12 @@ namespace cqfp {
 //   C[k][i][L]     = c_{t-s} (s <= t, else 0), t = L%16, s = 4i + L/16
 //   D[k][i][L]     = d_{k,t+1+u} (t+1+u <= L-1, else 0), u = 4i + L/16, i < 8
 // (zero for nodes j >= np). Needs kMxMinLag <= L <= kMxMaxLag and
-// nt <= 2 NTW.
+// nt <= 2 NTW. TRAJ: every step's level and history sum also go to
+// p.traj / p.sx (the forward of a gradient).
 // a global-memory double (keeps global loads after an asm statement)
 typedef __attribute__((address_space(1))) const double gdouble;
 
-template <int NTW>
+template <int NTW, bool TRAJ>
 __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     constexpr int B = kMxB;
     __shared__ double fW[2][4][B][16];             // state part of the fast sums [block & 1][wave][step][mode]
@@ -249,34 +248,36 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
                           (fT[2 * ck][b][cp] + fT[2 * ck + 1][b][cp]);
             }
             const double* dl = dtab[ck] + ce;  // dl[j]: weight of lag j + e
-            // a full block without per-step checks, the last (ragged) one with
-            auto steps = [&](auto full_t) {
-                constexpr bool FULL = decltype(full_t)::value;
+            const uint32_t toff = uint32_t(2 * I.mode_off + ck * M + mode0 + cp);  // trajectory place
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    if (FULL || b < bt) {
-                        // the step's sum sits in the lane of its parity;
-                        // quad_perm [0,0,2,2] / [1,1,3,3] give it to both lanes
-                        // of the component
-                        const double Sk = (b & 1) ? dpp_zero<0xF5>(pend[b >> 1]) : dpp_zero<0xA0>(pend[b >> 1]);
-                        const double So = dpp_zero<0x4E>(Sk);  // the other component's
-                        const double Ek = fma(e1, Pk, e2 * Qk);
-                        const double gk = fma(s_oth, So, fma(s_own, Sk, Ek));
-                        const double go = dpp_zero<0x4E>(gk);
-                        if (ce == 0) ring[(n0 + 1 + b) & 63][ck][cp] = gk;
-                        Qk = Pk;
-                        Pk = fma(i_oth, go, i_own * gk);
-                        glast = gk;
-                        // push into the later steps b' = 2m + e > b, lag b' - b
+            for (int b = 0; b < B; ++b) {
+                if (b < bt) {
+                    // the step's sum sits in the lane of its parity; quad_perm
+                    // [0,0,2,2] / [1,1,3,3] give it to both lanes of the component
+                    const double Sk = (b & 1) ? dpp_zero<0xF5>(pend[b >> 1]) : dpp_zero<0xA0>(pend[b >> 1]);
+                    const double So = dpp_zero<0x4E>(Sk);  // the other component's
+                    const double Ek = fma(e1, Pk, e2 * Qk);
+                    const double gk = fma(s_oth, So, fma(s_own, Sk, Ek));
+                    const double go = dpp_zero<0x4E>(gk);
+                    if (ce == 0) ring[(n0 + 1 + b) & 63][ck][cp] = gk;
+                    if (TRAJ && ce == 0 && mode0 + cp < M) {
+                        // the step's rows at wave-uniform addresses, the lane's
+                        // place as a 32-bit offset
+                        const int64_t row = (n0 + 1 + b) * p.tstride;
+                        p.traj[row + toff] = gk;
+                        p.sx[row + toff] = Sk;
+                    }
+                    Qk = Pk;
+                    Pk = fma(i_oth, go, i_own * gk);
+                    glast = gk;
+                    // push into the later steps b' = 2m + e > b, lag b' - b
 #pragma unroll
-                        for (int m = (b + 1) / 2; m < B / 2; ++m) {
-                            const int j = 2 * m - b;  // lag j + e <= B - 1
-                            pend[m] = fma(dl[j], gk, pend[m]);
-                        }
+                    for (int m = (b + 1) / 2; m < B / 2; ++m) {
+                        const int j = 2 * m - b;  // lag j + e <= B - 1
+                        pend[m] = fma(dl[j], gk, pend[m]);
                     }
                 }
-            };
-            steps(std::false_type{});
+            }
             cst[4][lane] = Pk;
             cst[5][lane] = Qk;
             cst[6][lane] = glast;
@@ -288,7 +289,13 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
 
 void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
     const dim3 grid(unsigned(a.tiles));
-#define CQ_BATCH_MX(T) hipLaunchKernelGGL((k_modal_batch_mx<T>), grid, dim3(256), 0, st, a)
+#define CQ_BATCH_MX(T)                                                                   \
+    do {                                                                                 \
+        if (a.traj)                                                                      \
+            hipLaunchKernelGGL((k_modal_batch_mx<T, true>), grid, dim3(256), 0, st, a);  \
+        else                                                                             \
+            hipLaunchKernelGGL((k_modal_batch_mx<T, false>), grid, dim3(256), 0, st, a); \
+    } while (0)
     prof_begin(9, st);
     switch (ntw) {
         case 4: CQ_BATCH_MX(4); break;

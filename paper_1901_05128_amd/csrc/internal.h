@@ -62,6 +62,15 @@ void rule_weights_dbeta(int scheme, double beta, double tau, int np, int np1, in
 // K12*K21 >= 0): K = V diag(theta) V^{-1}.
 void eig2(const double K[2][2], double theta[2], double V[2][2], double Vinv[2][2]);
 
+// 16-mode MFMA kernel (batch_mx.hip): whether a problem's lag and node count
+// fit it, the node-tile template for ntw tiles per wave, and its tables for
+// one problem (np nodes per component, lag L; d[k] readable up to lag L - 1;
+// out holds mx_table_size((np + 15) / 16) doubles).
+bool mx_applies(int L, int np);
+int mx_template(int ntw);
+void build_mx_tables(int np, int L, const double* const ratio[2], const double* const coef[2],
+                     const double* const d[2], double* out);
+
 // ---- kernel launchers (kernels.hip) ----
 struct DevSolver;  // defined in runtime.cpp
 

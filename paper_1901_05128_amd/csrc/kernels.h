@@ -256,6 +256,11 @@ struct BatchArgs {
     const int64_t* cumt;
     int64_t tiles;
     const double* mx;
+    // optional per-step output of the MFMA kernel (NULL: none): level g^n and
+    // history sum S^n of step n at [n * tstride + 2 mode_off + k M + mode]
+    double* traj;
+    double* sx;
+    int64_t tstride;
 };
 
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);

@@ -62,6 +62,15 @@ struct AdjBufs {
     double *ck = nullptr, *segLev = nullptr, *segS = nullptr, *segMu = nullptr, *ringA = nullptr, *Ha = nullptr,
            *Sfa = nullptr;
     double *Hf = nullptr, *Sff = nullptr;  // the forward's fast state and block sums
+    // kept-whole fast forward on the 16-mode MFMA kernel (one problem): its
+    // tables, problem entry, list and tile counts
+    bool mxfwd = false;
+    double* mx = nullptr;
+    BatchInst* mxinst = nullptr;
+    int* mxlist = nullptr;
+    int64_t* mxcum = nullptr;
+    int64_t mxtiles = 0;
+    int mxntw = 0;
     std::vector<int> split;  // [nseg + 1][slots]: first advance (segments) of an optimal schedule
     std::vector<int64_t> cost;
 };
@@ -1329,6 +1338,8 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
     const int mode = opt ? opt->mode : 0;
     if (mode < 0 || mode > 2) return fail(CQ_EINVAL, "adjoint mode must be 0, 1 or 2 (got %d)", mode);
     if (opt && (opt->segment_steps < 0 || opt->slots < 0)) return fail(CQ_EINVAL, "negative segment or slot count");
+    const int fwdk = opt ? opt->forward_kernel : 0;
+    if (fwdk < 0 || fwdk > 2) return fail(CQ_EINVAL, "forward_kernel must be 0, 1 or 2 (got %d)", fwdk);
     if (mode == 2 && p->method != 1)
         return fail(CQ_EINVAL, "the checkpointed adjoint needs the fast method (the direct form's state at a step "
                                "is its whole history)");
@@ -1468,6 +1479,50 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
         s.modal_blocked = true;  // thread per mode, level store of all N+1 levels
         A.Hf = s.H;
         A.Sff = s.Sf;
+        // the kept-whole forward on the 16-mode MFMA kernel (<= 16 node tiles
+        // per wave: its trajectory variant keeps two waves per SIMD there)
+        const int nt = (s.np + 15) / 16;
+        if (!A.ckpt && fwdk != 1 && mx_applies(s.L, s.np) && nt <= 32) {
+            std::vector<double> tab(size_t(mx_table_size(nt)));
+            const double* ratio[2] = {s.rule[0].ratio.data(), s.rule[1].ratio.data()};
+            const double* coef[2] = {s.rule[0].coef.data(), s.rule[1].coef.data()};
+            const double* dk[2] = {s.dh[0].data(), s.dh[1].data()};
+            build_mx_tables(s.np, s.L, ratio, coef, dk, tab.data());
+            BatchInst I{};
+            I.mode_off = 0;
+            I.M = M;
+            I.N = N;
+            I.np = s.np;
+            I.L = s.L;
+            I.scheme = p->scheme;
+            I.d_off = 0;
+            I.dstride = s.dstride;
+            I.inv_tau = 1.0 / s.tau;
+            I.c = s.c;
+            I.a = s.a;
+            I.d00 = s.dh[0][0];
+            I.d01 = s.dh[1][0];
+            I.mx_off = 0;
+            I.nt = nt;
+            A.mxtiles = (M + 15) / 16;
+            const int list0 = 0;
+            const int64_t cum[2] = {0, A.mxtiles};
+            if ((rc = dev_alloc(s, &A.mx, tab.size()))) return rc;
+            if ((rc = upload(A.mx, tab))) return rc;
+            // the problem entry, the list and the tile counts in one small buffer
+            const size_t ninst = (sizeof(BatchInst) + sizeof(double) - 1) / sizeof(double);
+            double* small = nullptr;
+            if ((rc = dev_alloc(s, &small, ninst + 3))) return rc;
+            A.mxinst = reinterpret_cast<BatchInst*>(small);
+            A.mxcum = reinterpret_cast<int64_t*>(small + ninst);
+            A.mxlist = reinterpret_cast<int*>(small + ninst + 2);
+            HIPCHK(hipMemcpyAsync(A.mxinst, &I, sizeof(BatchInst), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(A.mxlist, &list0, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(A.mxcum, cum, sizeof(cum), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));  // the host values above go out of scope
+            A.mxntw = mx_template((nt + 1) / 2);
+            A.mxfwd = true;
+        }
         if (A.ckpt) {
             if ((rc = dev_alloc(s, &A.Ha, hcount(s)))) return rc;
             if ((rc = dev_alloc(s, &A.Sfa, size_t(int64_t(s.BTt) * twoM)))) return rc;
@@ -1789,8 +1844,30 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     HIPCHK(hipMemcpyAsync(traj, s.g0c, size_t(twoM) * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(Sx, 0, size_t(twoM) * sizeof(double), st));
     if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));
-    set_sweep(s, Sweep{traj, A.Hf, A.Sff, Sx, nullptr, nullptr, N + 1, 0, false, 0});
-    modal_steps(s, N);
+    if (A.mxfwd) {
+        // all N steps on the 16-mode MFMA kernel, levels and history sums
+        // written per step
+        BatchArgs a{};
+        a.inst = A.mxinst;
+        a.list = A.mxlist;
+        a.cumt = A.mxcum;
+        a.count = 1;
+        a.total = M;
+        a.tiles = A.mxtiles;
+        a.d = s.d_d;
+        a.lam = s.lam;
+        a.g0 = s.g0c;
+        a.gN = s.Sscratch;
+        a.mx = A.mx;
+        a.traj = traj;
+        a.sx = Sx;
+        a.tstride = twoM;
+        launch_modal_batch_mx(a, A.mxntw, st);
+        HIPCHK(hipGetLastError());
+    } else {
+        set_sweep(s, Sweep{traj, A.Hf, A.Sff, Sx, nullptr, nullptr, N + 1, 0, false, 0});
+        modal_steps(s, N);
+    }
     if (GN) transform(s, traj + N * twoM, GN, false);
 
     // adjoint sweep: levels psi, multipliers mu, both in reversed time
@@ -1890,6 +1967,7 @@ int fp_adjoint_info(void* handle, cq_adjoint_info* info) {
     info->slots = A.ckpt ? A.slots : 0;
     info->forward_steps = A.fwd_steps;
     info->device_bytes = s.dev_bytes;
+    info->forward_kernel = A.mxfwd ? 2 : 1;
     return CQ_OK;
 }
 

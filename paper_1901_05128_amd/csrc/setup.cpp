@@ -6,8 +6,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <map>
+#include <vector>
 
 #include "internal.h"
+#include "kernels.h"
 
 namespace cqfp {
 
@@ -537,6 +539,73 @@ void eig2(const double K[2][2], double theta[2], double V[2][2], double Vinv[2][
     Vinv[0][1] = -V[0][1] / det;
     Vinv[1][0] = -V[1][0] / det;
     Vinv[1][1] = V[0][0] / det;
+}
+
+
+// ---------------------------------------------------------------------------
+// Tables of the 16-mode MFMA kernel (k_modal_batch_mx) for one problem: the
+// fragments of the step-by-node table w_j r_j^{t+1}, the node-by-step table
+// r_j^{B-1-s}, r_j^B, the in-block Toeplitz table of c_e = sum_j w_j r_j^e
+// and the exact-window table of the earlier levels, in the fragment order of
+// the kernel's MFMA operands (layout at the kernel).
+bool mx_applies(int L, int np) { return L >= kMxMinLag && L <= kMxMaxLag && (np + 15) / 16 <= 2 * kMxMaxNtw; }
+
+int mx_template(int ntw) {
+    for (int t : {4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18})
+        if (ntw <= t) return t;
+    return 18;
+}
+
+void build_mx_tables(int np, int L, const double* const ratio[2], const double* const coef[2],
+                     const double* const d[2], double* out) {
+    const int nt = (np + 15) / 16, B = kMxB;
+    const int64_t t1 = int64_t(nt + 1) * 256;  // a component's W or R: nt tiles and a zero tile
+    double* W = out;
+    double* R = out + 2 * t1;
+    double* rB = out + 4 * t1;
+    double* Cf = rB + int64_t(32) * nt;
+    double* Df = Cf + 512;
+    std::fill(out, out + mx_table_size(nt), 0.0);
+    for (int k = 0; k < 2; ++k) {
+        // pw[j][e] = r_j^e, e <= B
+        std::vector<double> pw(size_t(nt) * 16 * (B + 1), 0.0);
+        for (int j = 0; j < np; ++j) {
+            double v = 1.0;
+            for (int e = 0; e <= B; ++e) {
+                pw[size_t(j) * (B + 1) + e] = v;
+                v *= ratio[k][j];
+            }
+        }
+        auto P = [&](int j, int e) { return j < np ? pw[size_t(j) * (B + 1) + e] : 0.0; };
+        auto wj = [&](int j) { return j < np ? coef[k][j] : 0.0; };
+        for (int jt = 0; jt < nt; ++jt)
+            for (int i = 0; i < 4; ++i)
+                for (int ln = 0; ln < 64; ++ln) {
+                    const size_t o = size_t(k) * size_t(t1) + (size_t(jt) * 4 + i) * 64 + ln;
+                    const int t = ln % 16, lk = ln / 16;
+                    const int jw = 16 * jt + 4 * i + lk;
+                    W[o] = wj(jw) * P(jw, t + 1);
+                    const int jr = 16 * jt + t, sidx = 4 * i + lk;
+                    R[o] = P(jr, B - 1 - sidx);
+                }
+        for (int j = 0; j < 16 * nt; ++j) rB[size_t(k) * 16 * nt + j] = P(j, B);
+        long double c[B];
+        for (int e = 0; e < B; ++e) {
+            long double acc = 0.0L;
+            for (int j = 0; j < np; ++j) acc += (long double)coef[k][j] * (long double)P(j, e);
+            c[e] = acc;
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int ln = 0; ln < 64; ++ln) {
+                const int t = ln % 16, sidx = 4 * i + ln / 16;
+                Cf[size_t(k) * 256 + i * 64 + ln] = sidx <= t ? double(c[t - sidx]) : 0.0;
+            }
+        for (int i = 0; i < 8; ++i)
+            for (int ln = 0; ln < 64; ++ln) {
+                const int t = ln % 16, u = 4 * i + ln / 16, lag = t + 1 + u;
+                Df[size_t(k) * 512 + i * 64 + ln] = lag <= L - 1 ? d[k][lag] : 0.0;
+            }
+    }
 }
 
 }  // namespace cqfp

@@ -233,6 +233,56 @@ def test_handle_matches_one_shot_and_is_reusable():
             assert cq.lib().fp_step(h._h, 1) == -1  # CQ_EINVAL: not a stepping solver
 
 
+MX_CASES = [
+    # dim, nx, ny, alpha1, alpha2, m, N, scheme, params of the rule
+    (2, 21, 13, 0.35, 0.65, 0.7, 130, 2, dict(np_=24, ns=30)),   # ragged 16-mode tiles and 16-step blocks
+    (1, 31, 1, 0.3, 0.7, 0.35, 77, 1, dict(np_=12)),             # BE: exact window of 2 np + 2 = 26 lags
+    (1, 17, 1, 0.45, 0.55, 0.8, 64, 2, dict(np_=20, ns=16)),     # the shortest lag the kernel takes
+    (2, 9, 7, 0.2, 0.6, 0.55, 45, 2, dict(np_=40, ns=32)),       # the longest lag of the adjoint
+    (2, 127, 127, 0.2, 0.6, 0.55, 4096, 2, dict(np_=192, np1=16, ns=30)),  # the adjoint workload
+]
+
+
+@pytest.mark.parametrize("case", MX_CASES, ids=lambda c: f"{c[0]}d{c[1]}x{c[2]}N{c[6]}s{c[7]}")
+def test_mfma_forward_matches_streamed_forward(case):
+    """The kept-whole forward on the 16-mode MFMA kernel (forward_kernel 2,
+    the automatic choice here) against the streamed forward (1): dl/dG0 bit
+    for bit (the adjoint sweep does not read the forward), G^N and the
+    parameter gradients within rounding (the same scheme summed in another
+    order: G^N 1e-13, dl/dm 1e-12, dl/dalpha 1e-11); on the small grids
+    against the oracle adjoint at its bars."""
+    dim, nx, ny, a1, a2, m, N, scheme, kw = case
+    print(f"mfma forward case={case}", flush=True)
+    M = nx * ny
+    G0 = dev(wl.g0_random(M, 71).reshape(2, M))
+    gN = dev(np.random.default_rng(72).standard_normal((2, M)))
+    g = cq.make_grid(dim, nx, ny)
+    p = cq.make_params(a1, a2, m, 1.0, N, scheme, 1, solver=cq.SOLVER_MODAL, **kw)
+    out = {}
+    for fk in (0, 1, 2):
+        with cq.Adjoint(g, p, mode=1, forward_kernel=fk) as h:
+            GN = torch.empty_like(G0)
+            gG0, grads = h.run(G0, gN, GN=GN)
+            out[fk] = (GN.cpu().numpy(), gG0.cpu().numpy(), list(grads), h.info().forward_kernel)
+    assert out[0][3] == 2 and out[1][3] == 1 and out[2][3] == 2
+    assert np.array_equal(out[0][1], out[2][1]) and out[0][2] == out[2][2]
+    (GN1, g01, gr1, _), (GN2, g02, gr2, _) = out[1], out[2]
+    assert np.array_equal(g01, g02)
+    e = rel(GN2, GN1)
+    print(f"  G^N {e:.2e}, grads {[abs(a - b) / abs(b) for a, b in zip(gr2, gr1)]}", flush=True)
+    assert e <= 1e-13
+    for k in range(3):
+        # the alpha contraction cancels across modes: its rounding is relative
+        # to the terms' scale, not to the sum
+        assert abs(gr2[k] - gr1[k]) <= (1e-11 if k < 2 else 1e-12) * abs(gr1[k]), (k, gr2[k], gr1[k])
+    if M <= 300:
+        ref = adj.adjoint_reference(dim, nx, ny, a1, a2, m, 1.0, N, G0.cpu().numpy(), gN.cpu().numpy(), scheme, 1,
+                                    **kw)
+        assert rel(g02, ref[0]) <= 1e-10
+        for k in range(3):
+            assert abs(gr2[k] - ref[k + 1]) <= (1e-8 if k < 2 else 1e-10) * abs(ref[k + 1])
+
+
 def test_autograd_wrapper_matches_adjoint():
     """loss.backward() through paper_1901_05128_amd.autograd.solve gives the
     gradients fp_adjoint gives for the same cotangent."""

@@ -149,6 +149,29 @@ def test_mfma_tile_kernel(np_):
         assert e2 <= 1e-11
 
 
+@pytest.mark.parametrize("ns", [16, 33])
+def test_mfma_tile_kernel_lag_limits_and_tiny_tiles(ns):
+    """The MFMA kernel at the ends of its lag range (N_s = 16: blocks as long
+    as the lag; N_s = 33: the earlier-level window reaching 32 lags back),
+    with a single mode (15 idle columns of the 16-mode tile) and exactly one
+    full tile, against the oracle's fast scheme with the same rule."""
+    probs = [(1, 1, 1, 0.3, 0.7, 0.8, 1.0, 47, 2, 40), (1, 16, 1, 0.55, 0.25, 0.7, 1.0, 64, 2, 40),
+             (2, 3, 5, 0.8, 0.4, 0.9, 1.0, 35, 2, 40)]
+    grids, params, g0s = [], [], []
+    for i, (dim, nx, ny, a1, a2, m, T, N, scheme, npn) in enumerate(probs):
+        grids.append(cq.make_grid(dim, nx, ny))
+        params.append(cq.make_params(a1, a2, m, T, N, scheme, 1, np_=npn, ns=ns))
+        g0s.append(torch.tensor(wl.g0_random(nx * ny, 600 + i), device="cuda"))
+    outs, rep = cq.fp_solve_batched(grids, params, g0s, autotune=cq.BATCH_MFMA_TILE)
+    assert all(x == 2 for x in list(rep.class_blocked)[:rep.classes])
+    for (dim, nx, ny, a1, a2, m, T, N, scheme, npn), out, g0 in zip(probs, outs, g0s):
+        g0n = g0.cpu().numpy()
+        ref = modal.reference(dim, nx, ny, a1, a2, m, T, N, g0n, scheme, 1, np_=npn, np1=16, ns=ns)
+        e = rel(out.cpu().numpy(), ref)
+        print(f"  ns={ns} {dim}d {nx}x{ny} N={N}: vs oracle {e:.2e}", flush=True)
+        assert e <= 1e-11
+
+
 def test_mfma_tile_kernel_falls_back_where_it_does_not_apply():
     """Forcing the MFMA kernel leaves a class it cannot take (700 nodes per
     component) on the time-blocked kernel, with the same results as that

@@ -1,8 +1,9 @@
 """The checkpointed gradient (fast method): the forward recomputed segment by
 segment from saved states on a binomial schedule instead of kept whole.
 
-Against the kept-whole form on the same handle parameters: G^N, dl/dG0 and
-dl/dm bit for bit (the same arithmetic in the same order); dl/dalpha_k to
+Against the kept-whole form on the same handle parameters with the streamed
+forward (forward_kernel 1): G^N, dl/dG0 and dl/dm bit for bit (the same
+arithmetic in the same order); dl/dalpha_k to
 relative 1e-10 (the contraction is summed as Toeplitz products per segment
 instead of the near-field + block-DFT form; its terms cancel across modes,
 so the difference is rounding of the terms' scale, not of the sum). Against the oracle adjoint at
@@ -81,7 +82,7 @@ def test_checkpointed_equals_kept_whole(case, slots, segment_steps):
     g = cq.make_grid(dim, nx, ny)
     kw = dict(np_=npn, np1=8, ns=10) if scheme == 2 else dict(np_=npn)
     p = cq.make_params(a1, a2, m, 1.0, N, scheme, 1, solver=cq.SOLVER_MODAL, **kw)
-    whole = _grad(g, p, G0, gN, mode=1)
+    whole = _grad(g, p, G0, gN, mode=1, forward_kernel=1)
     ck = _grad(g, p, G0, gN, mode=2, slots=slots, segment_steps=segment_steps)
     info = ck[3]
     print(f"  segments {info.segments} x {info.segment_steps} steps, {info.slots} states, "
@@ -133,7 +134,7 @@ def test_checkpointed_at_adjoint_workload_size():
     gN = dev(np.random.default_rng(93).standard_normal((2, M)))
     g = cq.make_grid(2, nx, ny)
     p = cq.make_params(0.2, 0.6, 0.55, 1.0, 4096, 2, 1, np_=192, np1=16, ns=30, solver=cq.SOLVER_MODAL)
-    whole = _grad(g, p, G0, gN, mode=1)
+    whole = _grad(g, p, G0, gN, mode=1, forward_kernel=1)
     ck = _grad(g, p, G0, gN, mode=2, slots=4)
     inf = ck[3]
     print(f"  127^2: {inf.segments} segments of {inf.segment_steps}, {inf.slots} states, "
