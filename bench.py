@@ -377,15 +377,16 @@ def bench_adjoint(args, emit=True):
             bt = min(Bt, N - n + 1)
             b_h += twoM * 8 * (2 * npn + 2 * bt)
             f_h += twoM * 4 * npn * bt
-        # the forward on the 16-mode MFMA kernel (forward_kernel 2) leaves the
-        # state pass and the window steps to the adjoint sweep
+        # with forward_kernel 2 both sweeps run on the 16-mode MFMA kernel,
+        # else on the state pass and the window steps
         mxf = h.info().forward_kernel == 2
-        sweeps = 1 if mxf else 2
-        work["hist_fast"] = (sweeps * b_h, sweeps * f_h)  # forward (streamed) and adjoint sweeps
+        sweeps = 0 if mxf else 2
+        work["hist_fast"] = (sweeps * b_h, sweeps * f_h)  # forward and adjoint sweeps
         if mxf:
-            # state update and weighting (4 flops per node), window (2 per lag
-            # below L); every level and history sum written
-            work["batched"] = (2 * N * twoM * 8, N * twoM * (4 * npn + 2 * (L - 1)))
+            # per sweep: state update and weighting (4 flops per node), window
+            # (2 per lag below L); two arrays written per step (level and
+            # history sum, or psi and mu)
+            work["batched"] = (2 * 2 * N * twoM * 8, 2 * N * twoM * (4 * npn + 2 * (L - 1)))
         # the d/dalpha contraction's near field: blocks of Bk = 256 steps, each
         # step n of block i summing dw_{n-l} g^l over the levels l of blocks
         # i-1 and i up to n (2 flops per product, mode and component); a
@@ -404,9 +405,8 @@ def bench_adjoint(args, emit=True):
         nb, P = N // Bk, 2 * Bk
         work["beta_spec"] = (twoM * 2 * N * 8, twoM * (nb * 5 * P * 9 + (nb - 2) * (nb - 1) // 2 * (Bk + 1) * 8))
         work["transpose"] = (2 * 2 * N * twoM * 8, 0)
-        # window steps, both sweeps (the adjoint's alone with the MFMA
-        # forward): 2 flops per lag below L, Sf read, level and S (forward) or
-        # mu (adjoint) written
+        # window steps, both sweeps (none with the MFMA kernel): 2 flops per
+        # lag below L, Sf read, level and S (forward) or mu (adjoint) written
         work["modal_fast"] = (sweeps * N * twoM * 8 * 3, sweeps * N * twoM * 2 * (L - 1))
         dom = max(ktime, key=lambda k: ktime[k][1])
         if dom in work:
@@ -433,7 +433,7 @@ def bench_adjoint(args, emit=True):
         "config": {"workload": "c5: adjoint, 2D 127x127 nodes, BDF2 fast (np 16+192, ns 30), N=4096, "
                                "alpha=(0.2,0.6), m=0.55, target from alpha=(0.25,0.55)",
                    "dof": 2 * M, "N": N,
-                   "forward": "16-mode MFMA kernel" if h.info().forward_kernel == 2 else "streamed state"},
+                   "sweeps": "16-mode MFMA kernel" if h.info().forward_kernel == 2 else "streamed state"},
         "grads": list(grads),
         "breakdown": {"handle_setup_s": setup_s, "one_shot_fp_adjoint_s": oneshot_s,
                       "note": "value times fp_adjoint_run on a handle made once (fixed grid and parameters)"},

@@ -294,15 +294,15 @@ int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_strea
  *  segment_steps, slots: checkpointed form's segment length (rounded up to
  *    whole chunks) and number of saved states; 0 chooses the pair with the
  *    fewest recomputed forward steps that fits the budget.
- *  forward_kernel: the kept-whole fast forward. 0 automatic (2 where it
+ *  forward_kernel: the kept-whole fast sweeps. 0 automatic (2 where it
  *    applies), 1 the streamed state (the kernels of fp_step: the gradient
- *    then equals the checkpointed form's as stated above), 2 the batched
- *    16-mode MFMA kernel run over all N steps with the trajectory written as
- *    it goes (lags 16..32, <= 512 nodes per component; elsewhere 1): the same
- *    scheme summed in another order: dl/dG0 equals 1's bit for bit (the
- *    adjoint sweep does not read the forward), G^N and dl/dm agree to
- *    1e-13 and 1e-12 relative, dl/dalpha_k to 1e-11 (their contraction
- *    cancels across modes). Other values: CQ_EINVAL. */
+ *    then equals the checkpointed form's as stated above), 2 the forward
+ *    and the adjoint sweep each in one launch of the batched 16-mode MFMA
+ *    kernel over all N steps, levels, history sums and multipliers written
+ *    as they go (lags 16..32, <= 512 nodes per component; elsewhere 1): the
+ *    same schemes summed in another order: G^N, dl/dG0 and dl/dm agree with
+ *    1's to 1e-12 relative, dl/dalpha_k to 1e-11 (their contraction cancels
+ *    across modes). Other values: CQ_EINVAL. */
 typedef struct {
     size_t max_device_bytes;
     int32_t mode;

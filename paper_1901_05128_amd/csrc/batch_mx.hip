@@ -47,13 +47,19 @@ namespace cqfp {
 //   C[k][i][L]     = c_{t-s} (s <= t, else 0), t = L%16, s = 4i + L/16
 //   D[k][i][L]     = d_{k,t+1+u} (t+1+u <= L-1, else 0), u = 4i + L/16, i < 8
 // (zero for nodes j >= np). Needs kMxMinLag <= L <= kMxMaxLag and
-// nt <= 2 NTW. TRAJ: every step's level and history sum also go to
-// p.traj / p.sx (the forward of a gradient).
+// nt <= 2 NTW. MODE 0: the final level only (batched solves); 1: every
+// step's level and history sum also go to p.traj / p.sx (the forward of a
+// gradient); 2: the adjoint sweep of a gradient in reversed time, the same
+// recurrence on the levels psi = Dm mu with the transposed step
+// mu^n = Minv^T (E^n - S^n), E^n from mu^{n-1}, mu^{n-2}, the cotangent
+// (p.g0) subtracted from S^1, no starting correction; psi^n and mu^n go to
+// p.traj / p.sx.
 // a global-memory double (keeps global loads after an asm statement)
 typedef __attribute__((address_space(1))) const double gdouble;
 
-template <int NTW, bool TRAJ>
+template <int NTW, int MODE>
 __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
+    constexpr bool TRAJ = MODE != 0, ADJ = MODE == 2;
     constexpr int B = kMxB;
     __shared__ double fW[2][4][B][16];             // state part of the fast sums [block & 1][wave][step][mode]
     __shared__ double fT[4][B][16];                // in-block Toeplitz, earlier-level window, correction
@@ -102,7 +108,24 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     const double inv_tau = I.inv_tau;
     // E = e1 g^{n-1} + e2 g^{n-2} (BE: g^{n-1}/tau; BDF2: (2 g^{n-1} - g^{n-2}/2)/tau)
     const double e1 = (bdf2 ? 2.0 : 1.0) * inv_tau, e2 = (bdf2 ? -0.5 : 0.0) * inv_tau;
-    if (wave == 0) {
+    if (wave == 0 && ADJ) {
+        // mu^n = Minv^T r: the own and the other row's entry of column k;
+        // psi = Dm mu = L1 mu_k - a mu_k'
+        const int64_t mB = (mode0 + cp < M) ? mode0 + cp : M - 1;
+        const double ca = I.a;
+        const double L1 = ca + p.lam[I.mode_off + mB];
+        const double m11 = I.c + I.d00 * L1, m22 = I.c + I.d01 * L1;
+        const double m12 = -ca * I.d01, m21 = -ca * I.d00;
+        const double idet = 1.0 / (m11 * m22 - m12 * m21);
+        const double i00 = m22 * idet, i01 = -m12 * idet, i10 = -m21 * idet, i11 = m11 * idet;
+        cst[0][lane] = ck ? i11 : i00;
+        cst[1][lane] = ck ? i01 : i10;
+        cst[2][lane] = L1;
+        cst[3][lane] = -ca;
+        cst[4][lane] = 0.0;  // mu^{n-1}
+        cst[5][lane] = 0.0;  // mu^{n-2}
+        cst[6][lane] = 0.0;  // newest level
+    } else if (wave == 0) {
         const int64_t mB = (mode0 + cp < M) ? mode0 + cp : M - 1;
         const double* __restrict__ g0 = p.g0 + 2 * I.mode_off;
         const double g00 = g0[mB], g01 = g0[M + mB];
@@ -220,7 +243,7 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
                 for (int i = 0; i < 4; ++i) cf[i] = Ck[unsigned(i * 64) + ul];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) T = mfma16x16x4(cf[i], gin[i], T);
-                if (bdf2) {
+                if (bdf2 && !ADJ) {
                     const int64_t mA = (mode0 + li < M) ? mode0 + li : M - 1;
                     const double g0A = p.g0[2 * I.mode_off + k * M + mA];
 #pragma unroll
@@ -247,6 +270,8 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
                 pend[m] = (fW[cb][2 * ck][b][cp] + fW[cb][2 * ck + 1][b][cp]) +
                           (fT[2 * ck][b][cp] + fT[2 * ck + 1][b][cp]);
             }
+            if (ADJ && n0 == 0 && ce == 0 && mode0 + cp < M)
+                pend[0] -= p.g0[2 * I.mode_off + ck * M + mode0 + cp];  // the cotangent enters step 1
             const double* dl = dtab[ck] + ce;  // dl[j]: weight of lag j + e
             const uint32_t toff = uint32_t(2 * I.mode_off + ck * M + mode0 + cp);  // trajectory place
 #pragma unroll
@@ -255,20 +280,32 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
                     // the step's sum sits in the lane of its parity; quad_perm
                     // [0,0,2,2] / [1,1,3,3] give it to both lanes of the component
                     const double Sk = (b & 1) ? dpp_zero<0xF5>(pend[b >> 1]) : dpp_zero<0xA0>(pend[b >> 1]);
-                    const double So = dpp_zero<0x4E>(Sk);  // the other component's
                     const double Ek = fma(e1, Pk, e2 * Qk);
-                    const double gk = fma(s_oth, So, fma(s_own, Sk, Ek));
-                    const double go = dpp_zero<0x4E>(gk);
+                    double gk, go, ok;  // the new level, the other component's value, this lane's output
+                    if constexpr (ADJ) {
+                        // r = E - S, mu = Minv^T r, psi = Dm mu (s_own, s_oth:
+                        // column k of Minv; i_own, i_oth: L1 and -a)
+                        const double rk = Ek - Sk;
+                        const double ro = dpp_zero<0x4E>(rk);
+                        ok = fma(s_oth, ro, s_own * rk);
+                        go = dpp_zero<0x4E>(ok);
+                        gk = fma(i_oth, go, i_own * ok);
+                    } else {
+                        const double So = dpp_zero<0x4E>(Sk);  // the other component's
+                        gk = fma(s_oth, So, fma(s_own, Sk, Ek));
+                        go = dpp_zero<0x4E>(gk);
+                        ok = Sk;
+                    }
                     if (ce == 0) ring[(n0 + 1 + b) & 63][ck][cp] = gk;
                     if (TRAJ && ce == 0 && mode0 + cp < M) {
                         // the step's rows at wave-uniform addresses, the lane's
                         // place as a 32-bit offset
                         const int64_t row = (n0 + 1 + b) * p.tstride;
                         p.traj[row + toff] = gk;
-                        p.sx[row + toff] = Sk;
+                        p.sx[row + toff] = ok;
                     }
                     Qk = Pk;
-                    Pk = fma(i_oth, go, i_own * gk);
+                    Pk = ADJ ? ok : fma(i_oth, go, i_own * gk);
                     glast = gk;
                     // push into the later steps b' = 2m + e > b, lag b' - b
 #pragma unroll
@@ -287,16 +324,10 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     if (wave == 0 && ce == 0 && mode0 + cp < M) p.gN[2 * I.mode_off + ck * M + mode0 + cp] = cst[6][lane];
 }
 
-void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
+template <int MODE>
+static void launch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
     const dim3 grid(unsigned(a.tiles));
-#define CQ_BATCH_MX(T)                                                                   \
-    do {                                                                                 \
-        if (a.traj)                                                                      \
-            hipLaunchKernelGGL((k_modal_batch_mx<T, true>), grid, dim3(256), 0, st, a);  \
-        else                                                                             \
-            hipLaunchKernelGGL((k_modal_batch_mx<T, false>), grid, dim3(256), 0, st, a); \
-    } while (0)
-    prof_begin(9, st);
+#define CQ_BATCH_MX(T) hipLaunchKernelGGL((k_modal_batch_mx<T, MODE>), grid, dim3(256), 0, st, a)
     switch (ntw) {
         case 4: CQ_BATCH_MX(4); break;
         case 5: CQ_BATCH_MX(5); break;
@@ -309,10 +340,22 @@ void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
         case 13: CQ_BATCH_MX(13); break;
         case 14: CQ_BATCH_MX(14); break;
         case 16: CQ_BATCH_MX(16); break;
-        default: CQ_BATCH_MX(18); break;
+        default:
+            if constexpr (MODE == 0) CQ_BATCH_MX(18);
+            break;
     }
-    prof_end(9, st);
 #undef CQ_BATCH_MX
+}
+
+void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
+    prof_begin(9, st);
+    if (!a.traj)
+        launch_mx<0>(a, ntw, st);
+    else if (!a.adj)
+        launch_mx<1>(a, ntw, st);
+    else
+        launch_mx<2>(a, ntw, st);
+    prof_end(9, st);
 }
 
 }  // namespace cqfp

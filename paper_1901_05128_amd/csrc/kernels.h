@@ -256,11 +256,14 @@ struct BatchArgs {
     const int64_t* cumt;
     int64_t tiles;
     const double* mx;
-    // optional per-step output of the MFMA kernel (NULL: none): level g^n and
-    // history sum S^n of step n at [n * tstride + 2 mode_off + k M + mode]
+    // optional per-step output of the MFMA kernel (NULL: none), at
+    // [n * tstride + 2 mode_off + k M + mode]: the forward's level g^n (traj)
+    // and history sum S^n (sx), or with adj the adjoint's level psi^n (traj)
+    // and multiplier mu^n (sx); then g0 holds the cotangent, not G^0
     double* traj;
     double* sx;
     int64_t tstride;
+    int adj;
 };
 
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
@@ -269,7 +272,8 @@ void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
 constexpr int kMxB = 16, kMxMinLag = 16, kMxMaxLag = 33, kMxMaxNtw = 18;
 // doubles of one problem's tables with nt node tiles per component
 inline int64_t mx_table_size(int nt) { return int64_t(nt + 1) * 4 * 256 + int64_t(nt) * 32 + 2 * 256 + 2 * 512; }
-// ntw: one of 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18 (others take 18)
+// ntw: one of 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18 (others take 18);
+// with per-step output (a.traj) at most 16
 void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st);
 bool modal_fast_blocked(int L, int np);  // launch_modal_fast takes the time-blocked kernel
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);

@@ -62,8 +62,8 @@ struct AdjBufs {
     double *ck = nullptr, *segLev = nullptr, *segS = nullptr, *segMu = nullptr, *ringA = nullptr, *Ha = nullptr,
            *Sfa = nullptr;
     double *Hf = nullptr, *Sff = nullptr;  // the forward's fast state and block sums
-    // kept-whole fast forward on the 16-mode MFMA kernel (one problem): its
-    // tables, problem entry, list and tile counts
+    // kept-whole fast sweeps (forward and adjoint) on the 16-mode MFMA
+    // kernel (one problem): its tables, problem entry, list and tile counts
     bool mxfwd = false;
     double* mx = nullptr;
     BatchInst* mxinst = nullptr;
@@ -1479,8 +1479,8 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
         s.modal_blocked = true;  // thread per mode, level store of all N+1 levels
         A.Hf = s.H;
         A.Sff = s.Sf;
-        // the kept-whole forward on the 16-mode MFMA kernel (<= 16 node tiles
-        // per wave: its trajectory variant keeps two waves per SIMD there)
+        // the kept-whole sweeps on the 16-mode MFMA kernel (<= 16 node tiles
+        // per wave: its per-step output variants keep two waves per SIMD there)
         const int nt = (s.np + 15) / 16;
         if (!A.ckpt && fwdk != 1 && mx_applies(s.L, s.np) && nt <= 32) {
             std::vector<double> tab(size_t(mx_table_size(nt)));
@@ -1846,7 +1846,7 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));
     if (A.mxfwd) {
         // all N steps on the 16-mode MFMA kernel, levels and history sums
-        // written per step
+        // written per step (the adjoint sweep below on it too)
         BatchArgs a{};
         a.inst = A.mxinst;
         a.list = A.mxlist;
@@ -1873,9 +1873,32 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     // adjoint sweep: levels psi, multipliers mu, both in reversed time
     HIPCHK(hipMemsetAsync(psi, 0, size_t(twoM) * sizeof(double), st));
     HIPCHK(hipMemsetAsync(mu, 0, size_t(twoM) * sizeof(double), st));
-    if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));
-    set_sweep(s, Sweep{psi, A.Hf, A.Sff, nullptr, mu, A.gc, N + 1, 0, true, p->method == 1 ? N % s.Bt : 0});
-    modal_steps(s, N);
+    if (A.mxfwd) {
+        // all N steps on the 16-mode MFMA kernel's adjoint variant: psi^n and
+        // mu^n written per step, the cotangent entering step 1
+        BatchArgs a{};
+        a.inst = A.mxinst;
+        a.list = A.mxlist;
+        a.cumt = A.mxcum;
+        a.count = 1;
+        a.total = M;
+        a.tiles = A.mxtiles;
+        a.d = s.d_d;
+        a.lam = s.lam;
+        a.g0 = A.gc;
+        a.gN = s.Sscratch;
+        a.mx = A.mx;
+        a.traj = psi;
+        a.sx = mu;
+        a.tstride = twoM;
+        a.adj = 1;
+        launch_modal_batch_mx(a, A.mxntw, st);
+        HIPCHK(hipGetLastError());
+    } else {
+        if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));
+        set_sweep(s, Sweep{psi, A.Hf, A.Sff, nullptr, mu, A.gc, N + 1, 0, true, p->method == 1 ? N % s.Bt : 0});
+        modal_steps(s, N);
+    }
 
     // gradients
     AdjGradArgs ga = grad_args(s, traj, Sx, mu);
