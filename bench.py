@@ -463,6 +463,9 @@ def main():
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fast-kernel", default="mfma", choices=["mfma", "streamed"],
+                    help="modal fast runs: one launch of the 16-mode MFMA kernel per whole run where it "
+                         "applies (mfma), or the state streamed in time blocks")
     ap.add_argument("--batch-kernel", default="auto",
                     choices=["auto", "default", "time_blocked", "mfma_tile", "per_step"],
                     help="c4: the batched kernel per class (auto: timed per class)")
@@ -519,7 +522,8 @@ def main():
         streams[v] = torch.cuda.Stream() if (v in timed and not serial) else torch.cuda.current_stream()
         with torch.cuda.stream(streams[v]):
             solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1],
-                                                        solver=SOLVERS[args.solver]), G0)
+                                                        solver=SOLVERS[args.solver],
+                                                        fast_kernel=1 if args.fast_kernel == "mfma" else 0), G0)
     torch.cuda.synchronize()
     outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
 
@@ -646,6 +650,8 @@ def main():
             fvd[f"scheme{scheme}"] = float(torch.linalg.norm(f - d) / torch.linalg.norm(d))
 
     info_np = {VNAME[v]: solvers[v].info().np_total for v in variants if v[1] == 1}
+    fast_kern = {VNAME[v]: ("16-mode MFMA kernel, one launch" if solvers[v].info().whole_run_kernel else "streamed state")
+                 for v in variants if v[1] == 1}
     breakdown = {VNAME[v]: {"ms": per_var_ms[v], "dofsteps_per_s": 2 * M * N / (per_var_ms[v] / 1e3),
                             "where": "timed step (one stream)" if serial else "timed step (concurrent)"}
                  for v in timed}
@@ -674,7 +680,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}, alpha=({a1},{a2}), m={m}, T={T}",
                    "solver": args.solver, "streams": "serial" if serial else "one per variant",
                    "timed_variants": [VNAME[v] for v in timed], "dof": 2 * M, "N": N,
-                   "fast_nodes": info_np},
+                   "fast_nodes": info_np, "fast_kernel": fast_kern},
         "breakdown": breakdown,
         "fast_vs_direct_rel_l2": fvd,
         "kernels_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in ktime.items()},

@@ -93,7 +93,16 @@ typedef struct {
  *    with a 2x2 solve per mode in 2D); 1 = modal: the sine transform is
  *    applied once to G0 and once per read-out, and every mode advances by
  *    its own 2x2 recurrence (same scheme, no per-step global coupling; the
- *    fast form then needs lag <= 64 and at most 1024 nodes per component). */
+ *    fast form then needs lag <= 64 and at most 1024 nodes per component).
+ *  fast_kernel (modal solver, fast method): 0 = the state streamed through
+ *    device memory in time blocks (any run, resumable anywhere, the same
+ *    levels bit for bit however the run is cut into fp_step calls); 1 = an
+ *    fp_step call that takes all N steps from step 0 (fp_solve's) runs them
+ *    in one launch of the 16-mode MFMA kernel of fp_solve_batched, the state
+ *    in registers (lags 16..33 and <= 608 nodes per component; elsewhere, and
+ *    for other calls, 0): the same scheme summed in another order, within
+ *    1e-13 relative of 0's; the handle then holds only the final level
+ *    (fp_current, fp_get_state at n = N). Other values: CQ_EINVAL. */
 typedef struct {
     double alpha1, alpha2;
     double m;
@@ -108,6 +117,7 @@ typedef struct {
     int32_t np_max;
     int32_t block_B;
     int32_t solver;
+    int32_t fast_kernel;
 } cq_params;
 
 /* What a solver handle chose (filled by fp_info). */
@@ -123,6 +133,7 @@ typedef struct {
     size_t device_bytes;  /* device memory held by the handle                 */
     size_t state_bytes;   /* bytes of fp_get_state                            */
     int32_t np1;          /* BDF2 fast: N_{p,1} (first family), 0 otherwise   */
+    int32_t whole_run_kernel; /* 1: a whole-run fp_step takes the MFMA kernel  */
 } cq_info;
 
 /* CQ weights d_i, i = 0..n, of order beta: Taylor coefficients of

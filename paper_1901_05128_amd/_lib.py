@@ -45,14 +45,14 @@ class Params(C.Structure):
     _fields_ = [("alpha1", C.c_double), ("alpha2", C.c_double), ("m", C.c_double), ("T", C.c_double),
                 ("N", C.c_int64), ("scheme", C.c_int32), ("method", C.c_int32), ("fast_tol", C.c_double),
                 ("np", C.c_int32), ("np1", C.c_int32), ("ns", C.c_int32), ("np_max", C.c_int32),
-                ("block_B", C.c_int32), ("solver", C.c_int32)]
+                ("block_B", C.c_int32), ("solver", C.c_int32), ("fast_kernel", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("N", C.c_int64), ("np_total", C.c_int32), ("lag", C.c_int32),
                 ("max_eps", C.c_double), ("theta", C.c_double * 2), ("block_B", C.c_int32),
                 ("ksplit", C.c_int32), ("device_bytes", C.c_size_t), ("state_bytes", C.c_size_t),
-                ("np1", C.c_int32)]
+                ("np1", C.c_int32), ("whole_run_kernel", C.c_int32)]
 
 
 class AdjointOpts(C.Structure):
@@ -136,8 +136,9 @@ SOLVER_NODAL, SOLVER_MODAL = 0, 1
 
 
 def make_params(alpha1, alpha2, m, T, N, scheme, method, fast_tol=0.0, np_=0, np1=0, ns=0, np_max=0,
-                block_B=0, solver=SOLVER_NODAL) -> Params:
-    return Params(alpha1, alpha2, m, T, int(N), scheme, method, fast_tol, np_, np1, ns, np_max, block_B, solver)
+                block_B=0, solver=SOLVER_NODAL, fast_kernel=0) -> Params:
+    return Params(alpha1, alpha2, m, T, int(N), scheme, method, fast_tol, np_, np1, ns, np_max, block_B, solver,
+                  fast_kernel)
 
 
 def params_of(p) -> tuple:

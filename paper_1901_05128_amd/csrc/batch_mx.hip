@@ -198,31 +198,71 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
             // compiler barriers keep later loads from moving earlier. Tile q's
             // advance is interleaved with the sums of tile q-1, whose advance
             // has completed.
-            double wp[4];
+            if constexpr (NTW > 18) {
+                // fewer registers for the largest template: the R fragments
+                // one tile ahead, the W fragments of tile q-1 loaded again
+                // (a cache hit) for its sums after the advance of tile q
+                auto ldw = [&](int q, double (&aw)[4]) {
+                    const int jt = (h + 2 * q < NT) ? h + 2 * q : NT;
+                    const gdouble* __restrict__ wt = Wq + jt * 256;
 #pragma unroll
-            for (int q = 0; q < NTW; ++q) {
-                asm volatile("" ::: "memory");
-                double w1[4], r1[4];
-                ld(q + 1 < NTW ? q + 1 : 0, w1, r1);
-                const int jt = h + 2 * q;
-                // advanced in place: h^{n0+B} = r^B h^{n0} + R Gin; the next
-                // block's sums read the new state
+                    for (int i = 0; i < 4; ++i) aw[i] = wt[unsigned(i * 64) + ul];
+                };
+                auto ldr = [&](int q, double (&ar)[4]) {
+                    const int jt = (h + 2 * q < NT) ? h + 2 * q : NT;
+                    const gdouble* __restrict__ rt = Rq + jt * 256;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) H[q][i] *= rbt[k][jt * 16 + 4 * i + lk];
+                    for (int i = 0; i < 4; ++i) ar[i] = rt[unsigned(i * 64) + ul];
+                };
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    H[q] = mfma16x16x4(r0[i], gin[i], H[q]);
-                    if (q > 0) S = mfma16x16x4(wp[i], H[q - 1][i], S);
+                for (int q = 0; q < NTW; ++q) {
+                    asm volatile("" ::: "memory");
+                    double r1[4], wq[4];
+                    ldr(q + 1 < NTW ? q + 1 : 0, r1);
+                    if (q > 0) ldw(q - 1, wq);
+                    const int jt = h + 2 * q;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) H[q][i] *= rbt[k][jt * 16 + 4 * i + lk];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) H[q] = mfma16x16x4(r0[i], gin[i], H[q]);
+                    if (q > 0) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) S = mfma16x16x4(wq[i], H[q - 1][i], S);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) r0[i] = r1[i];
                 }
+                double wq[4];
+                ldw(NTW - 1, wq);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    wp[i] = w0[i];
-                    w0[i] = w1[i];
-                    r0[i] = r1[i];
+                for (int i = 0; i < 4; ++i) S = mfma16x16x4(wq[i], H[NTW - 1][i], S);
+            } else {
+                double wp[4];
+    #pragma unroll
+                for (int q = 0; q < NTW; ++q) {
+                    asm volatile("" ::: "memory");
+                    double w1[4], r1[4];
+                    ld(q + 1 < NTW ? q + 1 : 0, w1, r1);
+                    const int jt = h + 2 * q;
+                    // advanced in place: h^{n0+B} = r^B h^{n0} + R Gin; the next
+                    // block's sums read the new state
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) H[q][i] *= rbt[k][jt * 16 + 4 * i + lk];
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        H[q] = mfma16x16x4(r0[i], gin[i], H[q]);
+                        if (q > 0) S = mfma16x16x4(wp[i], H[q - 1][i], S);
+                    }
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        wp[i] = w0[i];
+                        w0[i] = w1[i];
+                        r0[i] = r1[i];
+                    }
                 }
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) S = mfma16x16x4(wp[i], H[NTW - 1][i], S);
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) S = mfma16x16x4(wp[i], H[NTW - 1][i], S);
             const int nb = int((n0 / B + 1) & 1);  // the next block's slot
 #pragma unroll
             for (int i = 0; i < 4; ++i) fW[nb][wave][lk + 4 * i][li] = S[i];
@@ -340,8 +380,11 @@ static void launch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
         case 13: CQ_BATCH_MX(13); break;
         case 14: CQ_BATCH_MX(14); break;
         case 16: CQ_BATCH_MX(16); break;
-        default:
+        case 18:
             if constexpr (MODE == 0) CQ_BATCH_MX(18);
+            break;
+        default:
+            if constexpr (MODE == 0) CQ_BATCH_MX(19);
             break;
     }
 #undef CQ_BATCH_MX

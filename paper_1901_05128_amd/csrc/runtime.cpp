@@ -62,22 +62,27 @@ struct AdjBufs {
     double *ck = nullptr, *segLev = nullptr, *segS = nullptr, *segMu = nullptr, *ringA = nullptr, *Ha = nullptr,
            *Sfa = nullptr;
     double *Hf = nullptr, *Sff = nullptr;  // the forward's fast state and block sums
-    // kept-whole fast sweeps (forward and adjoint) on the 16-mode MFMA
-    // kernel (one problem): its tables, problem entry, list and tile counts
-    bool mxfwd = false;
-    double* mx = nullptr;
-    BatchInst* mxinst = nullptr;
-    int* mxlist = nullptr;
-    int64_t* mxcum = nullptr;
-    int64_t mxtiles = 0;
-    int mxntw = 0;
+    bool mxfwd = false;  // kept-whole fast sweeps on the 16-mode MFMA kernel (Solver::mx)
     std::vector<int> split;  // [nseg + 1][slots]: first advance (segments) of an optimal schedule
     std::vector<int64_t> cost;
+};
+
+// One problem on the 16-mode MFMA kernel (k_modal_batch_mx): its tables, the
+// problem entry, the one-problem list and tile counts (device), the template
+struct MxRun {
+    bool on = false;
+    double* tab = nullptr;
+    BatchInst* inst = nullptr;
+    int* list = nullptr;
+    int64_t* cum = nullptr;
+    int64_t tiles = 0;
+    int ntw = 0;
 };
 
 struct Solver {
     cq_grid g{};
     cq_params p{};
+    MxRun mx;  // fast form on the 16-mode MFMA kernel (whole runs, gradient sweeps)
     int dim = 1, nx = 1, ny = 1, nz = 1;
     int64_t M = 0, N = 0, n = 0;
     double tau = 0, a = 0, beta[2] = {0, 0}, c = 0, hx = 0, hy = 0, hz = 0;
@@ -203,6 +208,7 @@ int validate(const cq_grid* g, const cq_params* p) {
         return fail(CQ_EINVAL, "block_B must be 64, 128, 192 or 256 (got %d)", p->block_B);
     if (p->np > 4096 || p->np1 > 4096) return fail(CQ_EINVAL, "np, np1 must be <= 4096");
     if (p->solver != 0 && p->solver != 1) return fail(CQ_EINVAL, "solver must be 0 (nodal) or 1 (modal)");
+    if (p->fast_kernel != 0 && p->fast_kernel != 1) return fail(CQ_EINVAL, "fast_kernel must be 0 or 1");
     return CQ_OK;
 }
 
@@ -463,6 +469,68 @@ int modal_start(Solver& s) {
     }
     HIPCHK(hipGetLastError());
     return CQ_OK;
+}
+
+// Tables and the one-problem launch data of the 16-mode MFMA kernel
+// (fast method, modal solver; the caller checks mx_applies).
+static int setup_mx(Solver& s) {
+    int rc;
+    const int nt = (s.np + 15) / 16;
+    std::vector<double> tab(size_t(mx_table_size(nt)));
+    const double* ratio[2] = {s.rule[0].ratio.data(), s.rule[1].ratio.data()};
+    const double* coef[2] = {s.rule[0].coef.data(), s.rule[1].coef.data()};
+    const double* dk[2] = {s.dh[0].data(), s.dh[1].data()};
+    build_mx_tables(s.np, s.L, ratio, coef, dk, tab.data());
+    BatchInst I{};
+    I.mode_off = 0;
+    I.M = s.M;
+    I.N = s.N;
+    I.np = s.np;
+    I.L = s.L;
+    I.scheme = s.p.scheme;
+    I.d_off = 0;
+    I.dstride = s.dstride;
+    I.inv_tau = 1.0 / s.tau;
+    I.c = s.c;
+    I.a = s.a;
+    I.d00 = s.dh[0][0];
+    I.d01 = s.dh[1][0];
+    I.mx_off = 0;
+    I.nt = nt;
+    MxRun& x = s.mx;
+    x.tiles = (s.M + 15) / 16;
+    const int list0 = 0;
+    const int64_t cum[2] = {0, x.tiles};
+    if ((rc = dev_alloc(s, &x.tab, tab.size()))) return rc;
+    if ((rc = upload(x.tab, tab))) return rc;
+    // the problem entry, the list and the tile counts in one small buffer
+    const size_t ninst = (sizeof(BatchInst) + sizeof(double) - 1) / sizeof(double);
+    double* small = nullptr;
+    if ((rc = dev_alloc(s, &small, ninst + 3))) return rc;
+    x.inst = reinterpret_cast<BatchInst*>(small);
+    x.cum = reinterpret_cast<int64_t*>(small + ninst);
+    x.list = reinterpret_cast<int*>(small + ninst + 2);
+    HIPCHK(hipMemcpy(x.inst, &I, sizeof(BatchInst), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(x.list, &list0, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(x.cum, cum, sizeof(cum), hipMemcpyHostToDevice));
+    x.ntw = mx_template((nt + 1) / 2);
+    x.on = true;
+    return CQ_OK;
+}
+
+// Launch arguments of the MFMA kernel for this solver's problem.
+static BatchArgs mx_args(const Solver& s) {
+    BatchArgs a{};
+    a.inst = s.mx.inst;
+    a.list = s.mx.list;
+    a.cumt = s.mx.cum;
+    a.count = 1;
+    a.total = s.M;
+    a.tiles = s.mx.tiles;
+    a.d = s.d_d;
+    a.lam = s.lam;
+    a.mx = s.mx.tab;
+    return a;
 }
 
 int setup_device(Solver& s, const double* G0dev, hipStream_t st) {
@@ -1102,6 +1170,8 @@ int fp_create(const cq_grid* grid, const cq_params* prm, const double* G0, void*
         rc = setup_host(*s, grid, prm, st);
         if (!rc) rc = check_finite_g0(G0, 2 * M, st);
         if (!rc) rc = setup_device(*s, G0, st);
+        if (!rc && prm->solver == 1 && prm->method == 1 && prm->fast_kernel == 1 && mx_applies(s->L, s->np))
+            rc = setup_mx(*s);
     } catch (const std::bad_alloc&) {
         rc = fail(CQ_ENOMEM, "host allocation failed");
     }
@@ -1121,10 +1191,19 @@ int fp_step(void* handle, int64_t nsteps) {
     if (nsteps < 0 || s.n + nsteps > s.N)
         return fail(CQ_EINVAL, "cannot take %lld steps from n = %lld (N = %lld)", (long long)nsteps, (long long)s.n,
                     (long long)s.N);
-    if (s.p.solver == 1)
+    if (s.p.solver == 1 && s.mx.on && s.n == 0 && nsteps == s.N && nsteps > 0) {
+        // the whole run in one launch of the 16-mode MFMA kernel (fast_kernel
+        // 1): only the final level is kept, where fp_current reads it
+        BatchArgs a = mx_args(s);
+        a.g0 = s.g0c;
+        a.gN = s.modal_blocked ? s.levels + (s.N % s.Lr) * 2 * s.M : s.ring;
+        launch_modal_batch_mx(a, s.mx.ntw, s.st);
+        s.n = s.N;
+    } else if (s.p.solver == 1) {
         modal_steps(s, nsteps);
-    else
+    } else {
         for (int64_t i = 0; i < nsteps; ++i) step_once(s);
+    }
     HIPCHK(hipGetLastError());
     return CQ_OK;
 }
@@ -1165,6 +1244,7 @@ int fp_info(void* handle, cq_info* info) {
     info->device_bytes = s.dev_bytes;
     info->state_bytes = state_bytes(s);
     info->np1 = (s.p.method == 1 && s.p.scheme == 2) ? s.np1_used : 0;
+    info->whole_run_kernel = s.mx.on ? 1 : 0;
     return CQ_OK;
 }
 
@@ -1483,44 +1563,7 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
         // per wave: its per-step output variants keep two waves per SIMD there)
         const int nt = (s.np + 15) / 16;
         if (!A.ckpt && fwdk != 1 && mx_applies(s.L, s.np) && nt <= 32) {
-            std::vector<double> tab(size_t(mx_table_size(nt)));
-            const double* ratio[2] = {s.rule[0].ratio.data(), s.rule[1].ratio.data()};
-            const double* coef[2] = {s.rule[0].coef.data(), s.rule[1].coef.data()};
-            const double* dk[2] = {s.dh[0].data(), s.dh[1].data()};
-            build_mx_tables(s.np, s.L, ratio, coef, dk, tab.data());
-            BatchInst I{};
-            I.mode_off = 0;
-            I.M = M;
-            I.N = N;
-            I.np = s.np;
-            I.L = s.L;
-            I.scheme = p->scheme;
-            I.d_off = 0;
-            I.dstride = s.dstride;
-            I.inv_tau = 1.0 / s.tau;
-            I.c = s.c;
-            I.a = s.a;
-            I.d00 = s.dh[0][0];
-            I.d01 = s.dh[1][0];
-            I.mx_off = 0;
-            I.nt = nt;
-            A.mxtiles = (M + 15) / 16;
-            const int list0 = 0;
-            const int64_t cum[2] = {0, A.mxtiles};
-            if ((rc = dev_alloc(s, &A.mx, tab.size()))) return rc;
-            if ((rc = upload(A.mx, tab))) return rc;
-            // the problem entry, the list and the tile counts in one small buffer
-            const size_t ninst = (sizeof(BatchInst) + sizeof(double) - 1) / sizeof(double);
-            double* small = nullptr;
-            if ((rc = dev_alloc(s, &small, ninst + 3))) return rc;
-            A.mxinst = reinterpret_cast<BatchInst*>(small);
-            A.mxcum = reinterpret_cast<int64_t*>(small + ninst);
-            A.mxlist = reinterpret_cast<int*>(small + ninst + 2);
-            HIPCHK(hipMemcpyAsync(A.mxinst, &I, sizeof(BatchInst), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(A.mxlist, &list0, sizeof(int), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(A.mxcum, cum, sizeof(cum), hipMemcpyHostToDevice, st));
-            HIPCHK(hipStreamSynchronize(st));  // the host values above go out of scope
-            A.mxntw = mx_template((nt + 1) / 2);
+            if ((rc = setup_mx(s))) return rc;
             A.mxfwd = true;
         }
         if (A.ckpt) {
@@ -1847,22 +1890,13 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     if (A.mxfwd) {
         // all N steps on the 16-mode MFMA kernel, levels and history sums
         // written per step (the adjoint sweep below on it too)
-        BatchArgs a{};
-        a.inst = A.mxinst;
-        a.list = A.mxlist;
-        a.cumt = A.mxcum;
-        a.count = 1;
-        a.total = M;
-        a.tiles = A.mxtiles;
-        a.d = s.d_d;
-        a.lam = s.lam;
+        BatchArgs a = mx_args(s);
         a.g0 = s.g0c;
         a.gN = s.Sscratch;
-        a.mx = A.mx;
         a.traj = traj;
         a.sx = Sx;
         a.tstride = twoM;
-        launch_modal_batch_mx(a, A.mxntw, st);
+        launch_modal_batch_mx(a, s.mx.ntw, st);
         HIPCHK(hipGetLastError());
     } else {
         set_sweep(s, Sweep{traj, A.Hf, A.Sff, Sx, nullptr, nullptr, N + 1, 0, false, 0});
@@ -1876,23 +1910,14 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     if (A.mxfwd) {
         // all N steps on the 16-mode MFMA kernel's adjoint variant: psi^n and
         // mu^n written per step, the cotangent entering step 1
-        BatchArgs a{};
-        a.inst = A.mxinst;
-        a.list = A.mxlist;
-        a.cumt = A.mxcum;
-        a.count = 1;
-        a.total = M;
-        a.tiles = A.mxtiles;
-        a.d = s.d_d;
-        a.lam = s.lam;
+        BatchArgs a = mx_args(s);
         a.g0 = A.gc;
         a.gN = s.Sscratch;
-        a.mx = A.mx;
         a.traj = psi;
         a.sx = mu;
         a.tstride = twoM;
         a.adj = 1;
-        launch_modal_batch_mx(a, A.mxntw, st);
+        launch_modal_batch_mx(a, s.mx.ntw, st);
         HIPCHK(hipGetLastError());
     } else {
         if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));

@@ -551,9 +551,9 @@ void eig2(const double K[2][2], double theta[2], double V[2][2], double Vinv[2][
 bool mx_applies(int L, int np) { return L >= kMxMinLag && L <= kMxMaxLag && (np + 15) / 16 <= 2 * kMxMaxNtw; }
 
 int mx_template(int ntw) {
-    for (int t : {4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18})
+    for (int t : {4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18, 19})
         if (ntw <= t) return t;
-    return 18;
+    return 19;
 }
 
 void build_mx_tables(int np, int L, const double* const ratio[2], const double* const coef[2],

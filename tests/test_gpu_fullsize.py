@@ -43,13 +43,14 @@ def _gpu():
     cq.lib()
 
 
-def _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T=1.0):
+def _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T=1.0, fast_kernel=0):
     """GPU G^N on the sampled modes, the largest coefficient, and the fast
     rule's node counts and window (None for direct)."""
     g = cq.make_grid(dim, nx, ny)
-    p = cq.make_params(a1, a2, m, T, N, scheme, method, solver=cq.SOLVER_MODAL)
+    p = cq.make_params(a1, a2, m, T, N, scheme, method, solver=cq.SOLVER_MODAL, fast_kernel=fast_kernel)
     with cq.Solver(g, p, torch.tensor(G0, dtype=torch.float64, device="cuda")) as s:
         info = s.info()
+        assert info.whole_run_kernel == (1 if fast_kernel and method == 1 else 0)
         s.step(N)
         out = s.current()[0].cpu().numpy()
     coef = modal.to_modes(out, dim, nx, ny)
@@ -87,8 +88,8 @@ def _rel_l2(got, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-def _check_case(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T=1.0):
-    got, cmax, rule = _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T)
+def _check_case(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T=1.0, fast_kernel=0):
+    got, cmax, rule = _run(dim, nx, ny, a1, a2, m, N, G0, scheme, method, modes, T, fast_kernel)
     ld = _ld_direct(dim, nx, ny, modes, a1, a2, m, N, G0, scheme, T)
     e = _rel_l2(got, ld)
     per = np.abs(got - ld) / np.maximum(np.abs(ld), 1e-300)
@@ -124,13 +125,15 @@ def test_configuration2_full_size_sampled_modes(scheme, method):
     _check_case(1, nx, 1, 0.4, 0.8, 0.45, N, G0, scheme, method, C2_MODES)
 
 
-@pytest.mark.parametrize("scheme,method", [(1, 0), (2, 0), (1, 1), (2, 1)])
-def test_configuration3_full_size_sampled_modes(scheme, method):
+@pytest.mark.parametrize("scheme,method,fast_kernel", [(1, 0, 0), (2, 0, 0), (1, 1, 0), (2, 1, 0), (1, 1, 1), (2, 1, 1)])
+def test_configuration3_full_size_sampled_modes(scheme, method, fast_kernel):
+    """fast_kernel 1: the fast run in one launch of the 16-mode MFMA kernel
+    (the benchmark's fast variants), at the same bars."""
     nx = ny = 255
     N = 2 ** 16
-    print(f"c3 full size scheme={scheme} method={method}", flush=True)
+    print(f"c3 full size scheme={scheme} method={method} fast_kernel={fast_kernel}", flush=True)
     G0 = wl.g0_rectangle(nx, ny, 3)
-    _check_case(2, nx, ny, 0.2, 0.6, 0.55, N, G0, scheme, method, C3_MODES)
+    _check_case(2, nx, ny, 0.2, 0.6, 0.55, N, G0, scheme, method, C3_MODES, fast_kernel=fast_kernel)
 
 
 @pytest.mark.parametrize("data", ["a", "b"])

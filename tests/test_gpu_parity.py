@@ -220,6 +220,55 @@ def test_degenerate_grids_and_coupling(dim, nx, ny, m, solver):
             assert rel(out, ref) <= (1e-12 if method == 0 else 1e-8), (scheme, method, rel(out, ref))
 
 
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("dim,nx,ny", [(1, 77, 1), (2, 95, 91)], ids=["1d-77", "2d-8645"])
+def test_whole_run_on_the_mfma_kernel(scheme, dim, nx, ny):
+    """fast_kernel 1: one fp_step over all N steps runs on the 16-mode MFMA
+    kernel (few modes: the final level into the ring; from 8192 modes: into
+    the level store), the same scheme as the streamed run within 1e-13, and
+    against the oracle's fast scheme with the same rule; fp_solve takes the
+    same path; chunked calls keep the streamed path (bit for bit the same
+    chunks with fast_kernel 0); the state of the finished run moves to a new
+    handle."""
+    N = 150
+    M = nx * ny
+    G0 = wl.g0_random(M, 77)
+    g = cq.make_grid(dim, nx, ny)
+    kw = dict(np_=40, ns=30) if scheme == 2 else dict(np_=40)
+    p0 = cq.make_params(0.3, 0.75, 0.7, 1.0, N, scheme, 1, solver=cq.SOLVER_MODAL, **kw)
+    p1 = cq.make_params(0.3, 0.75, 0.7, 1.0, N, scheme, 1, solver=cq.SOLVER_MODAL, fast_kernel=1, **kw)
+    with cq.Solver(g, p0, dev(G0)) as s:
+        assert s.info().whole_run_kernel == 0
+        s.step(N)
+        streamed = s.current()[0].cpu().numpy()
+    with cq.Solver(g, p1, dev(G0)) as s:
+        assert s.info().whole_run_kernel == 1
+        s.step(N)
+        whole = s.current()[0].cpu().numpy()
+        state = s.get_state()
+        s.reset(dev(G0))
+        s.step(N)
+        assert np.array_equal(s.current()[0].cpu().numpy(), whole)
+    with cq.Solver(g, p1, dev(np.zeros_like(G0))) as s2:
+        s2.set_state(state)
+        assert np.array_equal(s2.current()[0].cpu().numpy(), whole)
+    solved = cq.fp_solve(g, p1, dev(G0)).cpu().numpy()
+    assert np.array_equal(solved, whole)
+    chunked = []
+    for p in (p0, p1):
+        with cq.Solver(g, p, dev(G0)) as s:
+            for c in (1, 31, 29, 89):
+                s.step(c)
+            chunked.append(s.current()[0].cpu().numpy())
+    assert np.array_equal(chunked[0], chunked[1])
+    e = rel(whole, streamed)
+    ref = modal.reference(dim, nx, ny, 0.3, 0.75, 0.7, 1.0, N, G0, scheme, 1, np1=16, **kw)
+    e2 = rel(whole, ref)
+    print(f"  whole run vs streamed {e:.2e}, vs oracle fast {e2:.2e}", flush=True)
+    assert e <= 1e-13
+    assert e2 <= 1e-11
+
+
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("scheme", [1, 2])
 @pytest.mark.parametrize("dim", [1, 2])
