@@ -353,7 +353,7 @@ int fp_adjoint_run(void* handle, const double* G0, const double* gN, double* gG0
  * <= 32 and <= 768 nodes per component) and the 16-mode MFMA one (a
  * workgroup per 16 modes of a problem: over blocks of 16 steps the state
  * advance and its sums are FP64 matrix-core products over the modes; needs
- * lags 16..33 and <= 576 nodes per component). G0[i], GN[i]: dev [2][M_i]
+ * lags 16..33 and <= 608 nodes per component). G0[i], GN[i]: dev [2][M_i]
  * (caller-owned, distinct). autotune: 1 times the candidates for every
  * class on a short run and keeps the fastest (cached for the process);
  * 0 takes the 16-mode MFMA kernel where it applies, else the time-blocked
