@@ -390,7 +390,8 @@ static void launch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
 #undef CQ_BATCH_MX
 }
 
-void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
+int launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
+    if (a.traj && ntw > 16) return -1;  // no per-step output template beyond 16 tiles per wave
     prof_begin(9, st);
     if (!a.traj)
         launch_mx<0>(a, ntw, st);
@@ -399,6 +400,7 @@ void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
     else
         launch_mx<2>(a, ntw, st);
     prof_end(9, st);
+    return 0;
 }
 
 }  // namespace cqfp

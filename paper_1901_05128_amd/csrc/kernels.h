@@ -273,8 +273,9 @@ constexpr int kMxB = 16, kMxMinLag = 16, kMxMaxLag = 33, kMxMaxNtw = 19;
 // doubles of one problem's tables with nt node tiles per component
 inline int64_t mx_table_size(int nt) { return int64_t(nt + 1) * 4 * 256 + int64_t(nt) * 32 + 2 * 256 + 2 * 512; }
 // ntw: one of 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18, 19 (others take 19);
-// with per-step output (a.traj) at most 16
-void launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st);
+// with per-step output (a.traj) at most 16, else nothing is launched and -1
+// returned (0 on a launch)
+int launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st);
 bool modal_fast_blocked(int L, int np);  // launch_modal_fast takes the time-blocked kernel
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);
 void launch_modal_near(const ModalNearArgs& a, int B, bool adj, hipStream_t st);

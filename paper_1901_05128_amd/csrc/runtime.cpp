@@ -1197,7 +1197,8 @@ int fp_step(void* handle, int64_t nsteps) {
         BatchArgs a = mx_args(s);
         a.g0 = s.g0c;
         a.gN = s.modal_blocked ? s.levels + (s.N % s.Lr) * 2 * s.M : s.ring;
-        launch_modal_batch_mx(a, s.mx.ntw, s.st);
+        if (launch_modal_batch_mx(a, s.mx.ntw, s.st))
+            return fail(CQ_EINVAL, "no template for %d node tiles per wave", s.mx.ntw);
         s.n = s.N;
     } else if (s.p.solver == 1) {
         modal_steps(s, nsteps);
@@ -1896,7 +1897,8 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         a.traj = traj;
         a.sx = Sx;
         a.tstride = twoM;
-        launch_modal_batch_mx(a, s.mx.ntw, st);
+        if (launch_modal_batch_mx(a, s.mx.ntw, st))
+            return fail(CQ_EINVAL, "no per-step template for %d node tiles per wave", s.mx.ntw);
         HIPCHK(hipGetLastError());
     } else {
         set_sweep(s, Sweep{traj, A.Hf, A.Sff, Sx, nullptr, nullptr, N + 1, 0, false, 0});
@@ -1917,7 +1919,8 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         a.sx = mu;
         a.tstride = twoM;
         a.adj = 1;
-        launch_modal_batch_mx(a, s.mx.ntw, st);
+        if (launch_modal_batch_mx(a, s.mx.ntw, st))
+            return fail(CQ_EINVAL, "no per-step template for %d node tiles per wave", s.mx.ntw);
         HIPCHK(hipGetLastError());
     } else {
         if (p->method == 1) HIPCHK(hipMemsetAsync(A.Hf, 0, hcount(s) * sizeof(double), st));

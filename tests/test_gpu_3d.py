@@ -87,6 +87,27 @@ def test_3d_rejects_bad_grids():
             cq.Solver(g, p, G0)
 
 
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_3d_whole_run_on_the_mfma_kernel(scheme):
+    """fast_kernel 1 on a 3D grid (ragged 16-mode tiles over x, y and z):
+    the whole run in one launch of the 16-mode MFMA kernel, within 1e-13 of
+    the streamed run and within the fast scheme's bar of the oracle."""
+    nx, ny, nz, N = 9, 7, 6, 100
+    M = nx * ny * nz
+    G0 = wl.g0_random(M, 88)
+    g = cq.make_grid(3, nx, ny, nz=nz)
+    kw = dict(np_=24, ns=30) if scheme == 2 else dict(np_=24)
+    outs = []
+    for fk in (0, 1):
+        p = cq.make_params(0.25, 0.7, 0.65, 1.0, N, scheme, 1, solver=cq.SOLVER_MODAL, fast_kernel=fk, **kw)
+        outs.append(cq.fp_solve(g, p, dev(G0)).cpu().numpy())
+    ref = modal.reference(3, nx, ny, 0.25, 0.7, 0.65, 1.0, N, G0, scheme, 1, np1=16, nz=nz, **kw)
+    e, e2 = rel(outs[1], outs[0]), rel(outs[1], ref)
+    print(f"  3d whole run scheme={scheme}: vs streamed {e:.2e}, vs oracle fast {e2:.2e}", flush=True)
+    assert e <= 1e-13
+    assert e2 <= 1e-11
+
+
 @pytest.mark.parametrize("kernel", [cq.BATCH_DEFAULT, cq.BATCH_TIME_BLOCKED])
 def test_3d_in_a_batch(kernel):
     """A 3D problem solved by fp_solve_batched next to 1D and 2D ones, by the
