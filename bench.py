@@ -463,9 +463,10 @@ def main():
     ap.add_argument("--solver", default="modal", choices=sorted(SOLVERS),
                     help="modal: sine transform once, per-mode recurrences; nodal: per-step grid solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fast-kernel", default="mfma", choices=["mfma", "streamed"],
+    ap.add_argument("--fast-kernel", default="auto", choices=["auto", "mfma", "streamed"],
                     help="modal fast runs: one launch of the 16-mode MFMA kernel per whole run where it "
-                         "applies (mfma), or the state streamed in time blocks")
+                         "applies (mfma), the state streamed in time blocks (streamed), or the first from "
+                         "8192 modes (auto: fewer modes leave the kernel's 16-mode workgroups too few)")
     ap.add_argument("--batch-kernel", default="auto",
                     choices=["auto", "default", "time_blocked", "mfma_tile", "per_step"],
                     help="c4: the batched kernel per class (auto: timed per class)")
@@ -517,13 +518,14 @@ def main():
     G0 = torch.tensor(g0, dtype=torch.float64, device="cuda")
     grid = cq.make_grid(dim, nx, ny)
     solvers, streams = {}, {}
+    fast_k = 1 if args.fast_kernel == "mfma" or (args.fast_kernel == "auto" and M >= 8192) else 0
     for v in variants:
         # each timed variant on its own stream (default priority) unless serial
         streams[v] = torch.cuda.Stream() if (v in timed and not serial) else torch.cuda.current_stream()
         with torch.cuda.stream(streams[v]):
             solvers[v] = cq.Solver(grid, cq.make_params(a1, a2, m, T, N, v[0], v[1],
                                                         solver=SOLVERS[args.solver],
-                                                        fast_kernel=1 if args.fast_kernel == "mfma" else 0), G0)
+                                                        fast_kernel=fast_k), G0)
     torch.cuda.synchronize()
     outs = {v: torch.empty((2, M), dtype=torch.float64, device="cuda") for v in variants}
 

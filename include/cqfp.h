@@ -102,7 +102,9 @@ typedef struct {
  *    in registers (lags 16..33 and <= 608 nodes per component; elsewhere, and
  *    for other calls, 0): the same scheme summed in another order, within
  *    1e-13 relative of 0's; the handle then holds only the final level
- *    (fp_current, fp_get_state at n = N). Other values: CQ_EINVAL. */
+ *    (fp_current, fp_get_state at n = N). A whole run keeps 16 modes per
+ *    workgroup, so it pays from several thousand modes (two workgroups per
+ *    compute unit from 8192). Other values: CQ_EINVAL. */
 typedef struct {
     double alpha1, alpha2;
     double m;
@@ -306,7 +308,7 @@ int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_strea
  *    whole chunks) and number of saved states; 0 chooses the pair with the
  *    fewest recomputed forward steps that fits the budget.
  *  forward_kernel: the kept-whole fast sweeps. 0 automatic (2 where it
- *    applies), 1 the streamed state (the kernels of fp_step: the gradient
+ *    applies from 8192 modes), 1 the streamed state (the kernels of fp_step: the gradient
  *    then equals the checkpointed form's as stated above), 2 the forward
  *    and the adjoint sweep each in one launch of the batched 16-mode MFMA
  *    kernel over all N steps, levels, history sums and multipliers written

@@ -1563,7 +1563,9 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
         // the kept-whole sweeps on the 16-mode MFMA kernel (<= 16 node tiles
         // per wave: its per-step output variants keep two waves per SIMD there)
         const int nt = (s.np + 15) / 16;
-        if (!A.ckpt && fwdk != 1 && mx_applies(s.L, s.np) && nt <= 32) {
+        // automatic from kModalBlockedMin modes (fewer give the kernel too few
+        // workgroups to beat the streamed sweeps); forward_kernel 2 always
+        if (!A.ckpt && (fwdk == 2 || (fwdk == 0 && M >= kModalBlockedMin)) && mx_applies(s.L, s.np) && nt <= 32) {
             if ((rc = setup_mx(s))) return rc;
             A.mxfwd = true;
         }
