@@ -1,7 +1,8 @@
-// Batched fast solves on the FP64 matrix cores: the compressed history state
-// of 16 modes of one problem advanced and summed as small GEMMs (fast sum of
-// geometric sequences, (3.9)-(3.10) and (3.18); the per-mode form of schemes
-// (4.1)-(4.3) and (4.7)-(4.8)).
+// Fast CQ on the FP64 matrix cores: the compressed history state of 16 modes
+// of one problem advanced and summed as small GEMMs (fast sum of geometric
+// sequences, (3.9)-(3.10) and (3.18); the per-mode form of schemes
+// (4.1)-(4.3) and (4.7)-(4.8)), for batched solves, whole runs of one
+// problem and the two sweeps of a gradient.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -26,14 +27,16 @@ namespace cqfp {
 //
 // Phase A (all waves, matrix cores): wave w holds the node tiles
 // jt = h, h+2, ... (h = w & 1) of component k = w >> 1 as MFMA accumulators
-// ([16 nodes][16 modes] per tile), forms its part of the block's fast sums
-// and advances its tiles; of each component, wave h = 0 adds the in-block
-// Toeplitz term and BDF2's starting correction 1/2 d_{k,n-1} g_k^0, wave
-// h = 1 the window of the earlier levels. The partial sums go to LDS.
-// Phase B (wave 0): the block's steps one by one, lane 4p + 2k + e for
-// mode p, component k, steps of parity e (the lane keeps their pending
-// sums); each new level is pushed into the later steps of the block and
-// written to the LDS level ring that phase A of the next block reads.
+// ([16 nodes][16 modes] per tile). It advances each tile over the block
+// (h^{n0+B}) and then forms from the new state its part of the next block's
+// W H sums (a double-buffered LDS slot); of each component, wave h = 0 adds
+// this block's in-block Toeplitz term and BDF2's starting correction
+// 1/2 d_{k,n-1} g_k^0, wave h = 1 the window of the earlier levels (another
+// LDS slot). Phase B (wave 0): the block's steps one by one, lane 4p + 2k + e
+// for mode p, component k, steps of parity e (the lane keeps their pending
+// sums, which start as the two slots' partial sums); each new level is
+// pushed into the later steps of the block and written to the LDS level ring
+// that phase A of the next block reads.
 //
 // MFMA 16x16x4 f64 operands: A(16x4) lane L -> (row L%16, k L/16);
 // B(4x16) lane L -> (k L/16, col L%16); C: item i of lane L is row
@@ -47,13 +50,16 @@ namespace cqfp {
 //   C[k][i][L]     = c_{t-s} (s <= t, else 0), t = L%16, s = 4i + L/16
 //   D[k][i][L]     = d_{k,t+1+u} (t+1+u <= L-1, else 0), u = 4i + L/16, i < 8
 // (zero for nodes j >= np). Needs kMxMinLag <= L <= kMxMaxLag and
-// nt <= 2 NTW. MODE 0: the final level only (batched solves); 1: every
-// step's level and history sum also go to p.traj / p.sx (the forward of a
+// nt <= 2 NTW.
+//
+// MODE 0: the final level only (batched solves, whole runs); 1: every step's
+// level and history sum also go to p.traj / p.sx (the forward of a
 // gradient); 2: the adjoint sweep of a gradient in reversed time, the same
 // recurrence on the levels psi = Dm mu with the transposed step
 // mu^n = Minv^T (E^n - S^n), E^n from mu^{n-1}, mu^{n-2}, the cotangent
 // (p.g0) subtracted from S^1, no starting correction; psi^n and mu^n go to
 // p.traj / p.sx.
+
 // a global-memory double (keeps global loads after an asm statement)
 typedef __attribute__((address_space(1))) const double gdouble;
 
