@@ -312,7 +312,9 @@ int fp_adjoint_create(const cq_grid* grid, const cq_params* prm, void* hip_strea
  *    then equals the checkpointed form's as stated above), 2 the forward
  *    and the adjoint sweep each in one launch of the batched 16-mode MFMA
  *    kernel over all N steps, levels, history sums and multipliers written
- *    as they go (lags 16..32, <= 512 nodes per component; elsewhere 1): the
+ *    as they go (lags 16..32, <= 512 nodes per component; elsewhere 1;
+ *    up to 448 nodes it also writes the levels as the d/dalpha block DFTs'
+ *    time series, 2 x N x 2M more values where the budget holds them): the
  *    same schemes summed in another order: G^N, dl/dG0 and dl/dm agree with
  *    1's to 1e-12 relative, dl/dalpha_k to 1e-11 (their contraction cancels
  *    across modes). Other values: CQ_EINVAL. */

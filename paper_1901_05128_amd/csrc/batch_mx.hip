@@ -58,7 +58,9 @@ namespace cqfp {
 // recurrence on the levels psi = Dm mu with the transposed step
 // mu^n = Minv^T (E^n - S^n), E^n from mu^{n-1}, mu^{n-2}, the cotangent
 // (p.g0) subtracted from S^1, no starting correction; psi^n and mu^n go to
-// p.traj / p.sx.
+// p.traj / p.sx. With p.tcols (modes 1, 2, NTW < kMxColsNtw) each finished
+// block's levels are also written from the ring as time series, 16 steps of
+// a place at a time.
 
 // a global-memory double (keeps global loads after an asm statement)
 typedef __attribute__((address_space(1))) const double gdouble;
@@ -66,6 +68,7 @@ typedef __attribute__((address_space(1))) const double gdouble;
 template <int NTW, int MODE>
 __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     constexpr bool TRAJ = MODE != 0, ADJ = MODE == 2;
+    constexpr bool COLS = TRAJ && NTW < kMxColsNtw;  // p.tcols taken (the widest variant has no registers left)
     constexpr int B = kMxB;
     __shared__ double fW[2][4][B][16];             // state part of the fast sums [block & 1][wave][step][mode]
     __shared__ double fT[4][B][16];                // in-block Toeplitz, earlier-level window, correction
@@ -169,8 +172,27 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     }
     __syncthreads();
 
+    // the levels of steps n0c+1..n0c+btc (ring slots that the next three
+    // blocks leave alone) to p.tcols: wave w writes modes 4w..4w+3 of both
+    // components, lane 16u + b step b of mode 4w + u (a wave-uniform base and
+    // a small lane offset keep the addresses out of the loop's registers)
+    auto put_cols = [&](int64_t n0c, int btc) {
+        const int u = lane >> 4, b = lane & 15;
+        if (b < btc && mode0 + 4 * wave + u < M) {
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                double* base = p.tcols + (2 * I.mode_off + kk * M + mode0 + 4 * wave) * p.tcn + p.tcb +
+                               p.tcd * (n0c + 1);
+                base[int64_t(u) * p.tcn + p.tcd * b] = ring[(n0c + 1 + b) & 63][kk][4 * wave + u];
+            }
+        }
+    };
+
     for (int64_t n0 = 0; n0 < N; n0 += B) {
         const int bt = (N - n0 < B) ? int(N - n0) : B;  // steps of this block
+        if constexpr (COLS) {
+            if (p.tcols && n0 > 0) put_cols(n0 - B, B);
+        }
         // ---- phase A: the state advanced over this block (its inputs are
         // levels <= n0) and its part of the next block's fast sums; this
         // block's in-block Toeplitz term, window of the earlier levels and
@@ -367,6 +389,12 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
         }
         __syncthreads();
     }
+    if constexpr (COLS) {
+        if (p.tcols) {
+            const int64_t nl = ((N - 1) / B) * B;  // the last block
+            put_cols(nl, int(N - nl));
+        }
+    }
     if (wave == 0 && ce == 0 && mode0 + cp < M) p.gN[2 * I.mode_off + ck * M + mode0 + cp] = cst[6][lane];
 }
 
@@ -397,7 +425,8 @@ static void launch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
 }
 
 int launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st) {
-    if (a.traj && ntw > 16) return -1;  // no per-step output template beyond 16 tiles per wave
+    if (a.traj && ntw > 16) return -1;
+    if (a.tcols && (!a.traj || ntw >= kMxColsNtw)) return -1;  // no per-step output template beyond 16 tiles per wave
     prof_begin(9, st);
     if (!a.traj)
         launch_mx<0>(a, ntw, st);

@@ -264,17 +264,24 @@ struct BatchArgs {
     double* sx;
     int64_t tstride;
     int adj;
+    // optional (with traj; NULL: none): the same levels as time series by
+    // place, tcols[place * tcn + tcb + tcd * n] = traj's value of step n
+    double* tcols;
+    int64_t tcn, tcb;
+    int tcd;
 };
 
 void launch_modal_fast(const ModalFastArgs& a, hipStream_t st);
 void launch_modal_batch(const BatchArgs& a, int npl, int lpm, hipStream_t st);
 // 16-mode MFMA kernel: steps per block, lags it takes, node tiles per wave
 constexpr int kMxB = 16, kMxMinLag = 16, kMxMaxLag = 33, kMxMaxNtw = 19;
+// node tiles per wave from which the per-step variants take no tcols
+constexpr int kMxColsNtw = 16;
 // doubles of one problem's tables with nt node tiles per component
 inline int64_t mx_table_size(int nt) { return int64_t(nt + 1) * 4 * 256 + int64_t(nt) * 32 + 2 * 256 + 2 * 512; }
 // ntw: one of 4, 5, 6, 7, 8, 9, 10, 12, 13, 14, 16, 18, 19 (others take 19);
-// with per-step output (a.traj) at most 16, else nothing is launched and -1
-// returned (0 on a launch)
+// with per-step output (a.traj) at most 16 and with a.tcols below
+// kMxColsNtw, else nothing is launched and -1 returned (0 on a launch)
 int launch_modal_batch_mx(const BatchArgs& a, int ntw, hipStream_t st);
 bool modal_fast_blocked(int L, int np);  // launch_modal_fast takes the time-blocked kernel
 void launch_modal_win(const ModalWinArgs& a, bool adj, hipStream_t st);

@@ -63,6 +63,10 @@ struct AdjBufs {
            *Sfa = nullptr;
     double *Hf = nullptr, *Sff = nullptr;  // the forward's fast state and block sums
     bool mxfwd = false;  // kept-whole fast sweeps on the 16-mode MFMA kernel (Solver::mx)
+    // with mxfwd and the block DFTs, where the budget holds them: the columns
+    // b_t = g^{t+1} and a_t = psi^{t+1} ([2M][N]) as the sweeps write them
+    // (else transposed into Sx and mu after the sweeps)
+    double *colG = nullptr, *colPsi = nullptr;
     std::vector<int> split;  // [nseg + 1][slots]: first advance (segments) of an optimal schedule
     std::vector<int64_t> cost;
 };
@@ -1568,6 +1572,11 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
         if (!A.ckpt && (fwdk == 2 || (fwdk == 0 && M >= kModalBlockedMin)) && mx_applies(s.L, s.np) && nt <= 32) {
             if ((rc = setup_mx(s))) return rc;
             A.mxfwd = true;
+            const size_t colb = 2 * size_t(N) * size_t(twoM) * sizeof(double);
+            if (A.spec_nb > 2 && s.mx.ntw < kMxColsNtw && storeall + colb <= budget) {
+                if ((rc = dev_alloc(s, &A.colG, size_t(N) * size_t(twoM)))) return rc;
+                if ((rc = dev_alloc(s, &A.colPsi, size_t(N) * size_t(twoM)))) return rc;
+            }
         }
         if (A.ckpt) {
             if ((rc = dev_alloc(s, &A.Ha, hcount(s)))) return rc;
@@ -1899,6 +1908,10 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         a.traj = traj;
         a.sx = Sx;
         a.tstride = twoM;
+        a.tcols = A.colG;  // b_t = g^{t+1}
+        a.tcn = N;
+        a.tcb = -1;
+        a.tcd = 1;
         if (launch_modal_batch_mx(a, s.mx.ntw, st))
             return fail(CQ_EINVAL, "no per-step template for %d node tiles per wave", s.mx.ntw);
         HIPCHK(hipGetLastError());
@@ -1921,6 +1934,10 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         a.sx = mu;
         a.tstride = twoM;
         a.adj = 1;
+        a.tcols = A.colPsi;  // a_t = psi^{t+1}, kept at row N - t
+        a.tcn = N;
+        a.tcb = N;
+        a.tcd = -1;
         if (launch_modal_batch_mx(a, s.mx.ntw, st))
             return fail(CQ_EINVAL, "no per-step template for %d node tiles per wave", s.mx.ntw);
         HIPCHK(hipGetLastError());
@@ -1950,9 +1967,12 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
     HIPCHK(hipGetLastError());
     if (A.spec_nb > 2) {
         // columns a_t = psi^{t+1} (stored in reversed time, row N - t) and
-        // b_t = g^{t+1} into mu and Sx, which the passes above were the last to read
-        launch_cols_transpose(psi, N, -1, twoM, N, mu, st);
-        launch_cols_transpose(traj, 1, 1, twoM, N, Sx, st);
+        // b_t = g^{t+1}: written by the sweeps, or transposed here into mu and
+        // Sx, which the passes above were the last to read
+        if (!A.colG) {
+            launch_cols_transpose(psi, N, -1, twoM, N, mu, st);
+            launch_cols_transpose(traj, 1, 1, twoM, N, Sx, st);
+        }
         BetaSpecArgs bs{};
         bs.N = N;
         bs.M = M;
@@ -1960,8 +1980,8 @@ static int adjoint_exec(Solver& s, const double* G0, const double* gN, double* g
         bs.P = A.specP;
         bs.logP = A.specLog;
         bs.cols = A.spec_cols;
-        bs.psiT = mu;
-        bs.gT = Sx;
+        bs.psiT = A.colG ? A.colPsi : mu;
+        bs.gT = A.colG ? A.colG : Sx;
         bs.tw = A.tw;
         bs.spec = A.spec;
         launch_beta_spec(bs, A.spec_nwg, st);

@@ -283,6 +283,45 @@ def test_mfma_sweeps_match_streamed_sweeps(case):
             assert abs(gr2[k] - ref[k + 1]) <= (1e-8 if k < 2 else 1e-10) * abs(ref[k + 1])
 
 
+def test_mfma_sweeps_without_the_time_series_buffers():
+    """The MFMA sweeps also write the levels g and psi as per-place time series
+    for the alpha contraction's block DFTs (2 x N x 2M more values) where the
+    byte budget holds them; under a smaller budget the handle keeps the
+    trajectory whole without them and transposes afterwards. The budget is
+    lowered in steps of a quarter of those bytes from the full handle's size
+    until the handle drops them: same device bytes less exactly theirs, and
+    G^N, dl/dG0 and the gradients bitwise equal (the same values reach the
+    same contraction)."""
+    dim, nx, ny, a1, a2, m, N, scheme, kw = MX_CASES[0]
+    M = nx * ny
+    G0 = dev(wl.g0_random(M, 73).reshape(2, M))
+    gN = dev(np.random.default_rng(74).standard_normal((2, M)))
+    g = cq.make_grid(dim, nx, ny)
+    p = cq.make_params(a1, a2, m, 1.0, N, scheme, 1, solver=cq.SOLVER_MODAL, **kw)
+
+    def run(budget):
+        with cq.Adjoint(g, p, mode=1, forward_kernel=2, max_device_bytes=budget) as h:
+            GN = torch.empty_like(G0)
+            gG0, grads = h.run(G0, gN, GN=GN)
+            inf = h.info()
+            assert inf.mode == 1 and inf.forward_kernel == 2
+            return inf.device_bytes, GN.cpu().numpy(), gG0.cpu().numpy(), list(grads)
+
+    full = run(0)
+    colb = 2 * N * 2 * M * 8
+    small = None
+    for i in range(9):
+        budget = full[0] - 1 - i * (colb // 4)
+        print(f"  budget {budget} (full handle {full[0]} bytes)", flush=True)
+        r = run(budget)
+        if r[0] < full[0]:
+            small = r
+            break
+    assert small is not None
+    assert small[0] == full[0] - colb
+    assert np.array_equal(small[1], full[1]) and np.array_equal(small[2], full[2]) and small[3] == full[3]
+
+
 def test_autograd_wrapper_matches_adjoint():
     """loss.backward() through paper_1901_05128_amd.autograd.solve gives the
     gradients fp_adjoint gives for the same cotangent."""
