@@ -21,6 +21,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|t5]
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -382,16 +383,20 @@ def bench_adjoint(args, emit=True):
         mxf = h.info().forward_kernel == 2
         sweeps = 0 if mxf else 2
         work["hist_fast"] = (sweeps * b_h, sweeps * f_h)  # forward and adjoint sweeps
+        # up to 448 nodes the MFMA sweeps also write their levels as the block
+        # DFTs' time series (the bench's handle has the memory for them)
+        cols = mxf and npn <= 448
         if mxf:
             # per sweep: state update and weighting (4 flops per node), window
             # (2 per lag below L); two arrays written per step (level and
-            # history sum, or psi and mu)
-            work["batched"] = (2 * 2 * N * twoM * 8, 2 * N * twoM * (4 * npn + 2 * (L - 1)))
-        # the d/dalpha contraction's near field: blocks of Bk = 256 steps, each
-        # step n of block i summing dw_{n-l} g^l over the levels l of blocks
-        # i-1 and i up to n (2 flops per product, mode and component); a
-        # block reads those levels once and writes its rows
-        Bk = 256
+            # history sum, or psi and mu), three with the time series
+            work["batched"] = (2 * (3 if cols else 2) * N * twoM * 8, 2 * N * twoM * (4 * npn + 2 * (L - 1)))
+        # the d/dalpha contraction's near field: blocks of Bk steps (the power
+        # of two nearest 2.25 sqrt(N), 128 here), each step n of block i
+        # summing dw_{n-l} g^l over the levels l of blocks i-1 and i up to n
+        # (2 flops per product, mode and component); a block reads those
+        # levels once and writes its rows
+        Bk = 1 << min(8, max(3, round(math.log2(2.25 * math.sqrt(N)))))
         f_far, b_far = 0, 0
         for n0 in range(0, N, Bk):
             bt = min(Bk, N - n0)
@@ -399,12 +404,14 @@ def bench_adjoint(args, emit=True):
             f_far += sum(2 * (n - l0 + 1) * twoM for n in range(n0 + 1, n0 + bt + 1))
             b_far += (n0 + bt - l0 + 1) * twoM * 8 + bt * twoM * 8
         work["far_toeplitz"] = (b_far, f_far)
-        # its farther block pairs: per mode and component 16 FFTs of 512 points
-        # (5 P log2 P flops each) and 105 block products of 257 frequencies
-        # (8 flops each), reading psi and g (N doubles each)
-        nb, P = N // Bk, 2 * Bk
-        work["beta_spec"] = (twoM * 2 * N * 8, twoM * (nb * 5 * P * 9 + (nb - 2) * (nb - 1) // 2 * (Bk + 1) * 8))
-        work["transpose"] = (2 * 2 * N * twoM * 8, 0)
+        # its farther block pairs: per mode and component nb FFTs of P = 2 Bk
+        # points (5 P log2 P flops each) and (nb-2)(nb-1)/2 block products of
+        # Bk + 1 frequencies (8 flops each), reading psi and g (N doubles each)
+        nb, P = -(-N // Bk), 2 * Bk
+        work["beta_spec"] = (twoM * 2 * N * 8, twoM * (nb * 5 * P * int(math.log2(P)) +
+                                                      (nb - 2) * (nb - 1) // 2 * (Bk + 1) * 8))
+        if not cols:
+            work["transpose"] = (2 * 2 * N * twoM * 8, 0)
         # window steps, both sweeps (none with the MFMA kernel): 2 flops per
         # lag below L, Sf read, level and S (forward) or mu (adjoint) written
         work["modal_fast"] = (sweeps * N * twoM * 8 * 3, sweeps * N * twoM * 2 * (L - 1))

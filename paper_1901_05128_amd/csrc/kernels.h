@@ -213,6 +213,10 @@ struct AdjBetaArgs {
 // blocks of Bk = P/2 steps
 constexpr int kSpecMaxLds = 8192;  // nb * P complex doubles (128 KB of LDS)
 constexpr int kSpecMaxP = 512;     // blocks of at most 256 steps
+// k_beta_spec: distances per thread item, items per workgroup (1024 threads);
+// ceil((nb - 2) / kSpecSD) (Bk + 1) <= kSpecItems for every nb, Bk >= 8 with
+// nb P <= kSpecMaxLds (at most 1152)
+constexpr int kSpecSD = 4, kSpecItems = 2048;
 struct BetaSpecArgs {
     int64_t N, M;
     int nb, P, logP;      // P = 2^logP = 2 Bk, nb = ceil(N / Bk), nb P <= kSpecMaxLds

@@ -1711,21 +1711,26 @@ __device__ __forceinline__ int bit_reverse(int t, int logP) {
 // per mode, load the nb blocks (a, b) into LDS in bit-reversed order, FFT
 // them, split each block's spectrum in place (A_f into slot f, B_f into slot
 // P-f for 0 < f < Bk; at f = 0 and Bk both are real and share the slot as
-// (A, B)), and add sum_j conj(A^(j+d)_f) B^(j)_f for the (d, f), d >= 2,
-// f <= Bk, that the thread owns (q = (d-2)(Bk+1) + f = tid + 1024 r) into
-// registers. Partial spectra per workgroup, summed in k_beta_dot in a fixed
-// order.
+// (A, B)), and add sum_j conj(A^(j+d)_f) B^(j)_f for d >= 2, f <= Bk into
+// registers. A thread item is one frequency f and kSpecSD consecutive
+// distances d0 .. d0+kSpecSD-1 (item = (d0-2)/kSpecSD (Bk+1) + f, tid + 1024 r):
+// it walks j upwards with B^(j) and a window of the kSpecSD values
+// A^(j+d0..), so that a step reads two LDS values for kSpecSD products
+// (blocks from nb on read as zero). Partial spectra per workgroup at
+// q = (d-2)(Bk+1) + f, summed in k_beta_dot in a fixed order.
 __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
     __shared__ double2 z[kSpecMaxLds];
     __shared__ double2 tws[kSpecMaxP / 2];
-    constexpr int QR = kSpecMaxLds / 2 / 1024 + 1;
+    constexpr int SD = kSpecSD, IR = kSpecItems / 1024;
     const int k = blockIdx.y, tid = threadIdx.x;
     const int P = p.P, logP = p.logP, Bk = P >> 1, nb = p.nb, F1 = Bk + 1;
-    const int Q = (nb - 2) * F1, NI = nb * F1;
+    const int Q = (nb - 2) * F1, NI = nb * F1, NIT = (nb - 2 + SD - 1) / SD * F1;
     for (int j = tid; j < Bk; j += 1024) tws[j] = reinterpret_cast<const double2*>(p.tw)[j];
-    double xr[QR], xi[QR];
+    double xr[IR][SD], xi[IR][SD];
 #pragma unroll
-    for (int r = 0; r < QR; ++r) xr[r] = xi[r] = 0.0;
+    for (int r = 0; r < IR; ++r)
+#pragma unroll
+        for (int dd = 0; dd < SD; ++dd) xr[r][dd] = xi[r][dd] = 0.0;
     const int64_t m0 = int64_t(blockIdx.x) * p.cols;
     const int64_t m1 = (m0 + p.cols < p.M) ? m0 + p.cols : p.M;
     // a mode's steps t = blk Bk + u < nb Bk <= kSpecMaxLds / 2, LV per thread;
@@ -1776,33 +1781,59 @@ __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < QR; ++r) {
-            const int q = tid + 1024 * r;
-            if (q < Q) {
-                const int d = 2 + q / F1, f = q % F1;
+        for (int r = 0; r < IR; ++r) {
+            const int item = tid + 1024 * r;
+            if (item < NIT) {
+                const int d0 = 2 + SD * (item / F1), f = item % F1;
                 const bool edge = f == 0 || f == Bk;
                 const int fb = edge ? f : P - f;
-                double sr = 0.0, si = 0.0;
-                for (int j = 0; j + d < nb; ++j) {
-                    const double2 za = z[(j + d) * P + f], zb = z[j * P + fb];
-                    const double2 A = edge ? make_double2(za.x, 0.0) : za;
+                // A at f (real part only at the edges), B at P - f (the
+                // imaginary part of slot f at the edges)
+                auto ldA = [&](int blk) {
+                    const double2 za = blk < nb ? z[blk * P + f] : make_double2(0.0, 0.0);
+                    return edge ? make_double2(za.x, 0.0) : za;
+                };
+                double2 win[SD];
+#pragma unroll
+                for (int dd = 0; dd < SD; ++dd) win[dd] = ldA(d0 + dd);
+                double sr[SD], si[SD];
+#pragma unroll
+                for (int dd = 0; dd < SD; ++dd) sr[dd] = si[dd] = 0.0;
+                for (int j = 0; j + d0 < nb; ++j) {
+                    const double2 zb = z[j * P + fb];
                     const double2 B = edge ? make_double2(zb.y, 0.0) : zb;
-                    sr += A.x * B.x + A.y * B.y;  // conj(A) B
-                    si += A.x * B.y - A.y * B.x;
+#pragma unroll
+                    for (int dd = 0; dd < SD; ++dd) {
+                        sr[dd] += win[dd].x * B.x + win[dd].y * B.y;  // conj(A) B
+                        si[dd] += win[dd].x * B.y - win[dd].y * B.x;
+                    }
+#pragma unroll
+                    for (int dd = 0; dd + 1 < SD; ++dd) win[dd] = win[dd + 1];
+                    win[SD - 1] = ldA(j + 1 + d0 + SD - 1);
                 }
-                xr[r] += sr;
-                xi[r] += si;
+#pragma unroll
+                for (int dd = 0; dd < SD; ++dd) {
+                    xr[r][dd] += sr[dd];
+                    xi[r][dd] += si[dd];
+                }
             }
         }
         __syncthreads();  // z is reloaded by the next mode
     }
     double* __restrict__ out = p.spec + (int64_t(k) * gridDim.x + blockIdx.x) * int64_t(Q) * 2;
 #pragma unroll
-    for (int r = 0; r < QR; ++r) {
-        const int q = tid + 1024 * r;
-        if (q < Q) {
-            out[2 * q] = xr[r];
-            out[2 * q + 1] = xi[r];
+    for (int r = 0; r < IR; ++r) {
+        const int item = tid + 1024 * r;
+        if (item < NIT) {
+            const int d0 = 2 + SD * (item / F1), f = item % F1;
+#pragma unroll
+            for (int dd = 0; dd < SD; ++dd) {
+                if (d0 + dd < nb) {
+                    const int q = (d0 + dd - 2) * F1 + f;
+                    out[2 * q] = xr[r][dd];
+                    out[2 * q + 1] = xi[r][dd];
+                }
+            }
         }
     }
 }

@@ -1438,17 +1438,20 @@ static int adjoint_setup(Solver& s, const cq_adjoint_opts* opt) {
     AdjBufs& A = s.ab;
     A.per = adj_chunk_len(s);
     A.nchunk = int((N + A.per - 1) / A.per);
-    // d/dbeta: blocks of about N/8 steps (a power of two, at most 256) while
-    // their P-point transforms fit in LDS (N <= 4096), unless
-    // CQFP_BETA_TOEPLITZ is set; else Toeplitz passes over all levels
+    // d/dbeta: blocks of Bk steps while their P-point transforms fit in LDS
+    // (N <= 4096), unless CQFP_BETA_TOEPLITZ is set; else Toeplitz passes
+    // over all levels. The exact near field costs about N Bk per mode, the
+    // block pairs N^2 / Bk: Bk is the power of two nearest 2.25 sqrt(N)
+    // (8..256), the balance measured at N = 4096 (Bk 64, 128, 256)
     const char* force_toeplitz = std::getenv("CQFP_BETA_TOEPLITZ");
     int spec_bk = 0, spec_nb = 0, spec_log = 0;
     {
-        int lb = 0;
-        while ((int64_t(8) << lb) < N && lb < 8) ++lb;
+        const int lb = int(std::min<long>(8, std::max<long>(3, std::lround(std::log2(2.25 * std::sqrt(double(N)))))));
         const int Bk = 1 << lb;
         const int64_t nb = (N + Bk - 1) / Bk;
-        if (nb * 2 * Bk <= kSpecMaxLds && !(force_toeplitz && force_toeplitz[0] && force_toeplitz[0] != '0')) {
+        const int64_t items = (nb - 2 + kSpecSD - 1) / kSpecSD * (Bk + 1);  // k_beta_spec's thread items
+        if (nb * 2 * Bk <= kSpecMaxLds && items <= kSpecItems &&
+            !(force_toeplitz && force_toeplitz[0] && force_toeplitz[0] != '0')) {
             spec_bk = Bk;
             spec_log = lb + 1;
             spec_nb = int(nb);

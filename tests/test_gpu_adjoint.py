@@ -348,6 +348,8 @@ SPEC_CASES = [
     (2, 9, 7, 0.2, 0.6, 0.55, 1.0, 150),
     (1, 1, 1, 0.45, 0.55, 0.8, 1.0, 1),       # K = 2
     (1, 1, 1, 0.45, 0.55, 0.8, 1.0, 5),
+    (1, 11, 1, 0.35, 0.65, 0.52, 1.0, 20),    # the smallest transform, 16 points (3 blocks of 8 steps)
+    (1, 9, 1, 0.3, 0.6, 0.4, 1.0, 600),       # 128 points, ragged last block (10 blocks of 64 steps)
     (1, 13, 1, 0.25, 0.75, 0.3, 1.0, 2049),   # K = 8192 with a ragged N
     (1, 7, 1, 0.4, 0.8, 0.45, 1.0, 4096),     # the largest N of the DFT form
     (2, 97, 85, 0.25, 0.65, 0.6, 1.0, 70),    # 8245 modes: 128 workgroups of 65 modes
