@@ -240,6 +240,8 @@ MX_CASES = [
     (1, 17, 1, 0.45, 0.55, 0.8, 64, 2, dict(np_=20, ns=16)),     # the shortest lag the kernel takes
     (2, 9, 7, 0.2, 0.6, 0.55, 45, 2, dict(np_=40, ns=32)),       # the longest lag of the adjoint
     (2, 127, 127, 0.2, 0.6, 0.55, 4096, 2, dict(np_=192, np1=16, ns=30)),  # the adjoint workload
+    (2, 9, 7, 0.3, 0.7, 0.6, 70, 2, dict(np_=290, ns=30)),      # 306 nodes: 10 tiles per wave, time series written
+    (1, 23, 1, 0.35, 0.6, 0.65, 50, 2, dict(np_=470, ns=30)),   # 486 nodes: 16 tiles per wave, transposed instead
 ]
 
 
