@@ -196,6 +196,7 @@ struct AdjGradArgs {
 // F[b] = sum_{l=l0}^{n} dw_{n-l} g^l from k_far_toeplitz over levels
 // l0..n0+bt (l0 = 1, or the first level of the previous block when the
 // farther levels go through block DFTs)
+constexpr int kAdjBetaWaves = 16;  // k_adj_beta: waves per 64 columns (slices of a block's steps)
 struct AdjBetaArgs {
     int64_t M, N, n0;
     int bt, scheme;

@@ -1578,11 +1578,12 @@ __global__ __launch_bounds__(256) void k_adj_da(AdjGradArgs p) {
 // over the levels l0..n of k_far_toeplitz (all levels, or those of the
 // previous and the current block); add BDF2's starting correction and
 // contract with psi. A
-// workgroup covers 64 (component, mode) pairs; its 4 waves take a quarter
-// of the block's steps each (a column of F and psi per wave and step, read
-// coalesced), and the partial sums meet in LDS in a fixed order.
-__global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
-    __shared__ double red[3][64];
+// workgroup covers 64 (component, mode) pairs; its kAdjBetaWaves waves take
+// a slice of the block's steps each (a row of 64 F and psi values per wave
+// and step, read coalesced; many waves keep enough loads in flight), and the
+// partial sums meet in LDS in a fixed order.
+__global__ __launch_bounds__(64 * kAdjBetaWaves) void k_adj_beta(AdjBetaArgs p) {
+    __shared__ double red[kAdjBetaWaves - 1][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t M = p.M, twoM = 2 * M, N = p.N;
     const int64_t e = int64_t(blockIdx.x) * 64 + lane;
@@ -1592,7 +1593,7 @@ __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
     const int64_t mode = ec - int64_t(k) * M;
     const double g0 = p.g0[ec];
     const double* __restrict__ ddk = p.dd + int64_t(k) * p.dstride;
-    const int per = (p.bt + 3) >> 2;
+    const int per = (p.bt + kAdjBetaWaves - 1) / kAdjBetaWaves;
     const int b0 = w * per, b1 = min(p.bt, b0 + per);
     double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll 4
@@ -1608,7 +1609,12 @@ __global__ __launch_bounds__(256) void k_adj_beta(AdjBetaArgs p) {
     const double v = acc0 + acc1;
     if (w) red[w - 1][lane] = v;
     __syncthreads();
-    if (w == 0 && ein) p.acc[e] += ((v + red[0][lane]) + red[1][lane]) + red[2][lane];
+    if (w == 0 && ein) {
+        double t = v;
+#pragma unroll
+        for (int i = 0; i < kAdjBetaWaves - 1; ++i) t += red[i][lane];
+        p.acc[e] += t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2334,7 +2340,7 @@ int launch_adj_da(const AdjGradArgs& a, hipStream_t st) {
 }
 
 void launch_adj_beta(const AdjBetaArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_beta, dim3(unsigned((2 * a.M + 63) / 64)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_beta, dim3(unsigned((2 * a.M + 63) / 64)), dim3(64 * kAdjBetaWaves), 0, st, a);
 }
 
 void launch_cols_transpose(const double* src, int64_t row0, int dir, int64_t ncols, int64_t nt, double* dst,
