@@ -233,7 +233,22 @@ def cpu_baseline(w, variants):
 
 
 # source file of each kernel family whose traffic profiles/traffic.json holds
-KERNEL_SOURCE = {"far_toeplitz": "far.hip", "hist_fast": "kernels.hip"}
+KERNEL_SOURCE = {"far_toeplitz": "far.hip", "hist_fast": "kernels.hip", "batched": "batch_mx.hip"}
+
+
+def copy_probe(mib):
+    """Four copies of a mib-MiB device buffer (a plain copy kernel of known
+    size) after the measured work: rocprofv3's FETCH_SIZE and WRITE_SIZE of
+    these calibrate the counters. Returns the bytes copied each way."""
+    import torch
+
+    nel = mib * (1 << 20) // 8
+    src = torch.ones(nel, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return nel * 8
 
 
 def load_traffic(kernel_name, workload):
@@ -448,6 +463,8 @@ def bench_adjoint(args, emit=True):
         "roofline": roofline,
     }
     h.close()
+    if emit and args.copy_probe:
+        rec["copy_probe_bytes_each_way"] = copy_probe(args.copy_probe)
     if emit:
         print(json.dumps(rec), flush=True)
     return rec
@@ -716,13 +733,7 @@ def main():
                                 "note": "reference run at tau/2 (the paper used tau = 1/4000 too); "
                                         "the paper's spatial scheme is unstated"}
     if args.copy_probe:
-        nel = args.copy_probe * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        rec["copy_probe_bytes_each_way"] = nel * 8
+        rec["copy_probe_bytes_each_way"] = copy_probe(args.copy_probe)
     if args.workload == "c3" and not args.no_adjoint:
         # the metric's second half, the adjoint rate, on its own workload (the
         # 127^2 grid, N = 4096), measured after the timed region above (the
