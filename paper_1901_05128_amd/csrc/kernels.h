@@ -212,7 +212,7 @@ struct AdjBetaArgs {
 // d/dbeta through block DFTs, block pairs d >= 2: per column e of [2][M]
 // (component k = e / M), a_t = psi^{t+1}, b_t = g^{t+1} for t < N, in nb > 2
 // blocks of Bk = P/2 steps
-constexpr int kSpecMaxLds = 8192;  // nb * P complex doubles (128 KB of LDS)
+constexpr int kSpecMaxLds = 8192;  // nb * P complex doubles (136 KB of LDS with one pad slot per 16)
 constexpr int kSpecMaxP = 512;     // blocks of at most 256 steps
 // k_beta_spec: distances per thread item, items per workgroup (1024 threads);
 // ceil((nb - 2) / kSpecSD) (Bk + 1) <= kSpecItems for every nb, Bk >= 8 with

@@ -1668,6 +1668,11 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 w) {
     return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
 }
 
+// LDS slot of complex point i of the transforms: one pad slot after every
+// 16 points, so that the early passes' strided accesses (points 4 or 16
+// apart) and the bit-reversed stores spread over all banks
+__device__ __forceinline__ int zp(int i) { return i + (i >> 4); }
+
 __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int logP, const double2* tw) {
     int s = 0;
     for (; s + 1 < logP; s += 2) {
@@ -1676,7 +1681,7 @@ __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int log
             const int blk = t >> (logP - 2), tt = t & (qP - 1);
             const int pos = tt & (h - 1);
             const int i = blk * P + ((tt >> s) << (s + 2)) + pos;
-            double2 a = z[i], b = z[i + h], c = z[i + 2 * h], d = z[i + 3 * h];
+            double2 a = z[zp(i)], b = z[zp(i + h)], c = z[zp(i + 2 * h)], d = z[zp(i + 3 * h)];
             const double2 w1 = tw[pos << (logP - 1 - s)];
             const double2 w2 = tw[pos << (logP - 2 - s)];
             const double2 w3 = tw[(pos + h) << (logP - 2 - s)];
@@ -1687,11 +1692,11 @@ __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int log
             d = make_double2(c.x - u.x, c.y - u.y);
             c = make_double2(c.x + u.x, c.y + u.y);
             u = cmul(c, w2);
-            z[i + 2 * h] = make_double2(a.x - u.x, a.y - u.y);
-            z[i] = make_double2(a.x + u.x, a.y + u.y);
+            z[zp(i + 2 * h)] = make_double2(a.x - u.x, a.y - u.y);
+            z[zp(i)] = make_double2(a.x + u.x, a.y + u.y);
             u = cmul(d, w3);
-            z[i + 3 * h] = make_double2(b.x - u.x, b.y - u.y);
-            z[i + h] = make_double2(b.x + u.x, b.y + u.y);
+            z[zp(i + 3 * h)] = make_double2(b.x - u.x, b.y - u.y);
+            z[zp(i + h)] = make_double2(b.x + u.x, b.y + u.y);
         }
         __syncthreads();
     }
@@ -1700,10 +1705,10 @@ __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int log
         for (int t = threadIdx.x; t < nb * hP; t += blockDim.x) {
             const int blk = t >> (logP - 1), pos = t & (hP - 1);
             const int i = blk * P + pos;
-            const double2 u = cmul(z[i + h], tw[pos]);
-            const double2 a = z[i];
-            z[i] = make_double2(a.x + u.x, a.y + u.y);
-            z[i + h] = make_double2(a.x - u.x, a.y - u.y);
+            const double2 u = cmul(z[zp(i + h)], tw[pos]);
+            const double2 a = z[zp(i)];
+            z[zp(i)] = make_double2(a.x + u.x, a.y + u.y);
+            z[zp(i + h)] = make_double2(a.x - u.x, a.y - u.y);
         }
         __syncthreads();
     }
@@ -1725,7 +1730,7 @@ __device__ __forceinline__ int bit_reverse(int t, int logP) {
 // (blocks from nb on read as zero). Partial spectra per workgroup at
 // q = (d-2)(Bk+1) + f, summed in k_beta_dot in a fixed order.
 __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
-    __shared__ double2 z[kSpecMaxLds];
+    __shared__ double2 z[kSpecMaxLds + kSpecMaxLds / 16];
     __shared__ double2 tws[kSpecMaxP / 2];
     constexpr int SD = kSpecSD, IR = kSpecItems / 1024;
     const int k = blockIdx.y, tid = threadIdx.x;
@@ -1763,8 +1768,8 @@ __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
             const int t = tid + 1024 * v;
             if (t < nb * Bk) {
                 const int blk = t >> (logP - 1), u = t & (Bk - 1);
-                z[blk * P + bit_reverse(u, logP)] = make_double2(pa[v], pb[v]);
-                z[blk * P + bit_reverse(u + Bk, logP)] = make_double2(0.0, 0.0);
+                z[zp(blk * P + bit_reverse(u, logP))] = make_double2(pa[v], pb[v]);
+                z[zp(blk * P + bit_reverse(u + Bk, logP))] = make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
@@ -1775,14 +1780,14 @@ __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
         for (int it = tid; it < NI; it += 1024) {
             const int blk = it / F1, f = it - blk * F1;
             const int i0 = blk * P + f, i1 = blk * P + ((P - f) & (P - 1));
-            const double2 zf = z[i0], zc = z[i1];
+            const double2 zf = z[zp(i0)], zc = z[zp(i1)];
             const double2 A = make_double2(0.5 * (zf.x + zc.x), 0.5 * (zf.y - zc.y));
             const double2 B = make_double2(0.5 * (zf.y + zc.y), -0.5 * (zf.x - zc.x));
             if (f == 0 || f == Bk) {
-                z[i0] = make_double2(A.x, B.x);
+                z[zp(i0)] = make_double2(A.x, B.x);
             } else {
-                z[i0] = A;
-                z[i1] = B;
+                z[zp(i0)] = A;
+                z[zp(i1)] = B;
             }
         }
         __syncthreads();
@@ -1796,7 +1801,7 @@ __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
                 // A at f (real part only at the edges), B at P - f (the
                 // imaginary part of slot f at the edges)
                 auto ldA = [&](int blk) {
-                    const double2 za = blk < nb ? z[blk * P + f] : make_double2(0.0, 0.0);
+                    const double2 za = blk < nb ? z[zp(blk * P + f)] : make_double2(0.0, 0.0);
                     return edge ? make_double2(za.x, 0.0) : za;
                 };
                 double2 win[SD];
@@ -1806,7 +1811,7 @@ __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
 #pragma unroll
                 for (int dd = 0; dd < SD; ++dd) sr[dd] = si[dd] = 0.0;
                 for (int j = 0; j + d0 < nb; ++j) {
-                    const double2 zb = z[j * P + fb];
+                    const double2 zb = z[zp(j * P + fb)];
                     const double2 B = edge ? make_double2(zb.y, 0.0) : zb;
 #pragma unroll
                     for (int dd = 0; dd < SD; ++dd) {
@@ -1851,7 +1856,7 @@ __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
 __global__ __launch_bounds__(1024) void k_fft_w(const double* __restrict__ dw, int64_t dwstride, int64_t N,
                                                 int nb, int P, int logP, const double* __restrict__ twp,
                                                 double* __restrict__ W) {
-    __shared__ double2 z[kSpecMaxLds];
+    __shared__ double2 z[kSpecMaxLds + kSpecMaxLds / 16];
     __shared__ double2 tws[kSpecMaxP / 2];
     const int Bk = P >> 1, Q = nb * (Bk + 1);
     for (int j = threadIdx.x; j < Bk; j += 1024) tws[j] = reinterpret_cast<const double2*>(twp)[j];
@@ -1859,13 +1864,14 @@ __global__ __launch_bounds__(1024) void k_fft_w(const double* __restrict__ dw, i
         const int d = t >> logP, r = t & (P - 1);
         const int64_t lag = int64_t(d) * Bk + (r < Bk ? r : r - P);
         const bool ok = r != Bk && lag >= 0 && lag < N;
-        z[d * P + bit_reverse(r, logP)] = ok ? make_double2(dw[lag], dw[dwstride + lag]) : make_double2(0.0, 0.0);
+        z[zp(d * P + bit_reverse(r, logP))] =
+            ok ? make_double2(dw[lag], dw[dwstride + lag]) : make_double2(0.0, 0.0);
     }
     __syncthreads();
     lds_fft_batch(z, nb, P, logP, tws);
     for (int q = threadIdx.x; q < Q; q += 1024) {
         const int d = q / (Bk + 1), f = q - d * (Bk + 1);
-        const double2 zf = z[d * P + f], zc = z[d * P + ((P - f) & (P - 1))];
+        const double2 zf = z[zp(d * P + f)], zc = z[zp(d * P + ((P - f) & (P - 1)))];
         W[2 * q] = 0.5 * (zf.x + zc.x);
         W[2 * q + 1] = 0.5 * (zf.y - zc.y);
         W[2 * (Q + q)] = 0.5 * (zf.y + zc.y);
