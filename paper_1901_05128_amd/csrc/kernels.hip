@@ -1668,9 +1668,10 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 w) {
     return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
 }
 
-// LDS slot of complex point i of the transforms: one pad slot after every
-// 16 points, so that the early passes' strided accesses (points 4 or 16
-// apart) and the bit-reversed stores spread over all banks
+// LDS slot of complex point i of the transforms (and of twiddle i): one pad
+// slot after every 16, so that the early passes' strided accesses (points 4
+// or 16 apart), the bit-reversed stores and the later passes' strided
+// twiddle reads spread over all banks
 __device__ __forceinline__ int zp(int i) { return i + (i >> 4); }
 
 __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int logP, const double2* tw) {
@@ -1682,9 +1683,9 @@ __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int log
             const int pos = tt & (h - 1);
             const int i = blk * P + ((tt >> s) << (s + 2)) + pos;
             double2 a = z[zp(i)], b = z[zp(i + h)], c = z[zp(i + 2 * h)], d = z[zp(i + 3 * h)];
-            const double2 w1 = tw[pos << (logP - 1 - s)];
-            const double2 w2 = tw[pos << (logP - 2 - s)];
-            const double2 w3 = tw[(pos + h) << (logP - 2 - s)];
+            const double2 w1 = tw[zp(pos << (logP - 1 - s))];
+            const double2 w2 = tw[zp(pos << (logP - 2 - s))];
+            const double2 w3 = tw[zp((pos + h) << (logP - 2 - s))];
             double2 u = cmul(b, w1);
             b = make_double2(a.x - u.x, a.y - u.y);
             a = make_double2(a.x + u.x, a.y + u.y);
@@ -1705,7 +1706,7 @@ __device__ __forceinline__ void lds_fft_batch(double2* z, int nb, int P, int log
         for (int t = threadIdx.x; t < nb * hP; t += blockDim.x) {
             const int blk = t >> (logP - 1), pos = t & (hP - 1);
             const int i = blk * P + pos;
-            const double2 u = cmul(z[zp(i + h)], tw[pos]);
+            const double2 u = cmul(z[zp(i + h)], tw[zp(pos)]);
             const double2 a = z[zp(i)];
             z[zp(i)] = make_double2(a.x + u.x, a.y + u.y);
             z[zp(i + h)] = make_double2(a.x - u.x, a.y - u.y);
@@ -1731,12 +1732,12 @@ __device__ __forceinline__ int bit_reverse(int t, int logP) {
 // q = (d-2)(Bk+1) + f, summed in k_beta_dot in a fixed order.
 __global__ __launch_bounds__(1024) void k_beta_spec(BetaSpecArgs p) {
     __shared__ double2 z[kSpecMaxLds + kSpecMaxLds / 16];
-    __shared__ double2 tws[kSpecMaxP / 2];
+    __shared__ double2 tws[kSpecMaxP / 2 + kSpecMaxP / 32];
     constexpr int SD = kSpecSD, IR = kSpecItems / 1024;
     const int k = blockIdx.y, tid = threadIdx.x;
     const int P = p.P, logP = p.logP, Bk = P >> 1, nb = p.nb, F1 = Bk + 1;
     const int Q = (nb - 2) * F1, NI = nb * F1, NIT = (nb - 2 + SD - 1) / SD * F1;
-    for (int j = tid; j < Bk; j += 1024) tws[j] = reinterpret_cast<const double2*>(p.tw)[j];
+    for (int j = tid; j < Bk; j += 1024) tws[zp(j)] = reinterpret_cast<const double2*>(p.tw)[j];
     double xr[IR][SD], xi[IR][SD];
 #pragma unroll
     for (int r = 0; r < IR; ++r)
@@ -1857,9 +1858,9 @@ __global__ __launch_bounds__(1024) void k_fft_w(const double* __restrict__ dw, i
                                                 int nb, int P, int logP, const double* __restrict__ twp,
                                                 double* __restrict__ W) {
     __shared__ double2 z[kSpecMaxLds + kSpecMaxLds / 16];
-    __shared__ double2 tws[kSpecMaxP / 2];
+    __shared__ double2 tws[kSpecMaxP / 2 + kSpecMaxP / 32];
     const int Bk = P >> 1, Q = nb * (Bk + 1);
-    for (int j = threadIdx.x; j < Bk; j += 1024) tws[j] = reinterpret_cast<const double2*>(twp)[j];
+    for (int j = threadIdx.x; j < Bk; j += 1024) tws[zp(j)] = reinterpret_cast<const double2*>(twp)[j];
     for (int t = threadIdx.x; t < nb * P; t += 1024) {
         const int d = t >> logP, r = t & (P - 1);
         const int64_t lag = int64_t(d) * Bk + (r < Bk ? r : r - P);
