@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     __shared__ double fW[2][4][B][16];             // state part of the fast sums [block & 1][wave][step][mode]
     __shared__ double fT[4][B][16];                // in-block Toeplitz, earlier-level window, correction
     __shared__ double ring[64][2][16];             // level g_k^m of the tile's modes at [m & 63][k]
-    __shared__ double rbt[2][32 * kMxMaxNtw];      // r_j^B [k][j]
+    __shared__ double rbt[2][32 * NTW];            // r_j^B [k][j] (j < 32 NTW: tiles jt <= 2 NTW - 1)
     __shared__ double dtab[2][B];                  // push weights d_{k,lag}, lag 1..B-1 (0 at lag 0)
     __shared__ double cst[7][64];                  // phase B: per-lane constants and state
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256, 2) void k_modal_batch_mx(BatchArgs p) {
     for (int e = threadIdx.x; e < 64 * 2 * 16; e += 256) (&ring[0][0][0])[e] = 0.0;
     for (int e = threadIdx.x; e < 4 * B * 16; e += 256) (&fW[0][0][0][0])[e] = 0.0;  // h^0 = 0
     const int64_t t1 = int64_t(NT + 1) * 256;  // doubles of one component's W or R table
-    for (int e = threadIdx.x; e < 2 * 32 * kMxMaxNtw; e += 256) {
-        const int kk = e / (32 * kMxMaxNtw), j = e - kk * 32 * kMxMaxNtw;
+    for (int e = threadIdx.x; e < 2 * 32 * NTW; e += 256) {
+        const int kk = e / (32 * NTW), j = e - kk * 32 * NTW;
         rbt[kk][j] = j < 16 * NT ? tab[4 * t1 + kk * 16 * NT + j] : 0.0;
     }
     if (threadIdx.x < 2 * B) {
